@@ -1,0 +1,243 @@
+/*
+ * fi.h - C ABI of the MI355X library for FEM harmonic inpainting with
+ * optimised data (Chizhov and Weickert, arXiv 2105.01586).
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950):
+ *   inpaint(f, mask, g) -> u   harmonic inpainting with P1 finite elements
+ *                              (Section 2.1 eqs. (1)-(3), Section 2.2);
+ *   error(u, f)                squared error map, MSE and per-triangle L2
+ *                              error (Section 3);
+ *   adjoint(r) -> B^T r        transpose of the inpainting map u = B g
+ *                              (Section 4);
+ *   tonal_opt(f, mask) -> g    least-squares grey values, CG on the normal
+ *                              equations B^T B g = B^T f (Section 4, eqs. (4),
+ *                              (5)), with inner solves instead of forming B.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Images are N x N with N a power of two >= 2, stored row-major: pixel
+ *   (r, c) has linear index r * N + c and sits at the mesh lattice point
+ *   (x = c, y = r). f is uint8, u and every pixel-sized vector are float64.
+ * - The mask is a host array of m >= 1 strictly ascending int32 linear pixel
+ *   indices. g (the stored values) is float64 of length m in that order.
+ * - The mesh is the 2:1 edge-balanced quadtree on [0, N]^2 refined to unit
+ *   cells at every mask pixel, each leaf cut into right isosceles triangles
+ *   (two per leaf, or a fan from the centre when a neighbour is finer). Every
+ *   mask pixel is a vertex (Section 2.2). Vertices are numbered in row-major
+ *   (y, x) order; free rows are the non-mask vertices in that order.
+ * - Pointers named *_dev are device pointers on the context's device; the
+ *   caller owns them and keeps them alive for the duration of the call. All
+ *   device work is ordered on the context's HIP stream; a call returns after
+ *   the stream work it needs for host-visible results has finished. The
+ *   library never frees caller memory.
+ * - Every call returns a status code (FI_OK = 0). On failure
+ *   fi_last_error() gives a message (per calling thread). Outputs are left
+ *   unspecified unless stated, except FI_E_NO_CONVERGENCE, where outputs hold
+ *   the last iterate and the stats report the residual reached.
+ * - One fi_mesh must not be used by two calls at the same time.
+ */
+#ifndef FI_H
+#define FI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fi_status {
+  FI_OK = 0,
+  FI_E_INVALID = 1,        /* bad argument: shape, ordering, range, NaN */
+  FI_E_EMPTY_MASK = 2,     /* m == 0: the system is singular (Section 2.2) */
+  FI_E_NO_CONVERGENCE = 3, /* iteration cap reached before the tolerance */
+  FI_E_NOMEM = 4,          /* device or host allocation failed */
+  FI_E_HIP = 5             /* a HIP runtime call failed */
+};
+
+enum fi_precision {
+  FI_PREC_FP32_IR = 0, /* FP32 Jacobi-PCG inner solves, FP64 residual and
+                          iterative refinement (default) */
+  FI_PREC_FP64 = 1     /* plain FP64 Jacobi-PCG, FP64 residual check */
+};
+
+typedef struct fi_ctx fi_ctx;
+typedef struct fi_mesh fi_mesh;
+
+/* Options of one solve of K_FF u_F = b (the harmonic extension). */
+typedef struct fi_solve_opts {
+  int precision;     /* enum fi_precision */
+  double rtol;       /* stop when ||b - K_FF x||_2 <= rtol * ||b||_2 (FP64) */
+  double inner_rtol; /* each inner solve reduces its residual by this factor */
+  int max_inner;     /* iteration cap of one inner solve */
+  int max_refine;    /* cap on refinement steps (outer FP64 residual checks) */
+  int check_every;   /* host reads the device convergence flag every this
+                        many iterations (>= 1) */
+} fi_solve_opts;
+
+typedef struct fi_solve_stats {
+  int64_t iterations;  /* CG iterations, all inner solves together */
+  int32_t refinements; /* inner solves (refinement steps) performed */
+  int32_t status;      /* FI_OK or FI_E_NO_CONVERGENCE */
+  double rel_residual; /* final ||b - K_FF x||_2 / ||b||_2 in FP64 */
+} fi_solve_stats;
+
+typedef struct fi_tonal_opts {
+  fi_solve_opts inner; /* options of every inner solve */
+  double rtol;         /* stop when ||B^T(f - B g)|| <= rtol ||B^T(f - B g0)|| */
+  int max_outer;       /* cap on outer CG iterations */
+  int start_from_g;    /* 0: start from g0 = f on the mask; 1: from g_dev */
+} fi_tonal_opts;
+
+typedef struct fi_tonal_stats {
+  int32_t outer_iterations;
+  int32_t status;         /* FI_OK or FI_E_NO_CONVERGENCE */
+  int64_t inner_iterations;
+  double rel_normal_residual; /* ||s_k|| / ||s_0|| with s = B^T (f - B g) */
+  double mse_initial;     /* MSE of B g0 against f */
+  double mse_final;       /* MSE of B g against f */
+} fi_tonal_stats;
+
+typedef struct fi_mesh_info {
+  int64_t N;      /* image side */
+  int64_t P;      /* pixels, N * N */
+  int64_t V;      /* mesh vertices */
+  int64_t T;      /* triangles */
+  int64_t L;      /* quadtree leaves */
+  int64_t n;      /* free vertices (unknowns) */
+  int64_t m;      /* mask pixels */
+  int64_t nnz_ff; /* stored entries of K_FF, diagonal included */
+  int64_t nnz_fd; /* stored entries of K_FD */
+  int64_t device_bytes; /* device memory held by the mesh */
+} fi_mesh_info;
+
+/* Default solve options: FP32 inner PCG with FP64 refinement to 1e-10. */
+void fi_solve_opts_default(fi_solve_opts* opts);
+/* Default tonal options: inner defaults, rtol 1e-8, 500 outer iterations. */
+void fi_tonal_opts_default(fi_tonal_opts* opts);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* fi_last_error(void);
+
+/* Library version string. */
+const char* fi_version(void);
+
+/* Context: binds a device and a HIP stream (hipStream_t passed as void*; NULL
+ * means the null stream). The stream is borrowed, not owned. A context must
+ * outlive every mesh built on it: destroy the meshes first. */
+int fi_ctx_create(int device, void* stream, fi_ctx** out);
+int fi_ctx_set_stream(fi_ctx* ctx, void* stream);
+int fi_ctx_destroy(fi_ctx* ctx);
+
+/* Builds the quadtree mesh for an N x N image (width == height == N) and the
+ * mask (host array, strictly ascending, in range), uploads it and assembles
+ * the stiffness matrix on the device (fi_assemble). The mesh rules are those
+ * of Section 2.2 with the quadtree reading stated above. Errors:
+ * FI_E_INVALID (shape, ordering, range), FI_E_EMPTY_MASK (m == 0). */
+int fi_mesh_build(fi_ctx* ctx, int width, int height, const int32_t* mask_idx, int64_t m,
+                  fi_mesh** out);
+int fi_mesh_destroy(fi_mesh* mesh);
+int fi_mesh_get_info(const fi_mesh* mesh, fi_mesh_info* info);
+
+/* Host-only mesh: the same quadtree mesh built on the CPU with no device
+ * work, for building meshes on worker threads (or checking them without a
+ * GPU). fi_host_mesh_info fills the geometric counts (nnz fields are 0).
+ * fi_mesh_upload moves a host mesh to the device, assembles it, and consumes
+ * the host mesh (*host is set to NULL on success). Errors as fi_mesh_build. */
+typedef struct fi_host_mesh fi_host_mesh;
+int fi_host_mesh_build(int width, int height, const int32_t* mask_idx, int64_t m,
+                       fi_host_mesh** out);
+int fi_host_mesh_info(const fi_host_mesh* host, fi_mesh_info* info);
+int fi_host_mesh_export(const fi_host_mesh* host, int32_t* vxy, int32_t* tri, int32_t* leaves,
+                        int32_t* free_vids, int32_t* mask_vids);
+int fi_host_mesh_destroy(fi_host_mesh* host);
+int fi_mesh_upload(fi_ctx* ctx, fi_host_mesh** host, fi_mesh** out);
+
+/* (Re)assembles the P1 stiffness matrix on the device: element matrices
+ * K^e_ij = (b_i b_j + c_i c_j) / (4A) summed per vertex row, split into the
+ * free block K_FF, the coupling K_FD and its transpose K_DF; exact zeros are
+ * dropped (Section 2.2). Stream-ordered; no host sync except the first call,
+ * which sizes the matrices. */
+int fi_assemble(fi_mesh* mesh);
+
+/* Inpainting u = B g (Section 2.2, Section 4): solves K_FF u_F = -K_FD g
+ * (Section 2.2: SPD with at least one mask pixel, solved by CG; here Jacobi
+ * PCG) and interpolates linearly inside each triangle to all P pixels.
+ *   f_dev:  uint8[P] image; used only when g_dev is NULL (then g = f on the
+ *           mask). May be NULL when g_dev is given.
+ *   g_dev:  float64[m] mask values, or NULL.
+ *   u_dev:  float64[P] output pixels.
+ *   opts:   NULL for defaults. stats: may be NULL. */
+int fi_inpaint(fi_mesh* mesh, const uint8_t* f_dev, const double* g_dev, double* u_dev,
+               const fi_solve_opts* opts, fi_solve_stats* stats);
+
+/* The vertex values of the last fi_inpaint on this mesh, float64[V] in
+ * vertex order, copied to a device buffer. */
+int fi_vertex_values(fi_mesh* mesh, double* u_vertex_dev);
+
+/* Error measures of Section 3: e_i = (u_i - f_i)^2, MSE = sum(e) / P, and the
+ * total e over the pixels each triangle owns (a pixel belongs to the first
+ * triangle of its quadtree leaf, in listing order, that contains it).
+ *   mse_host:    output scalar (may be NULL);
+ *   pix_err_dev: float64[P] output, or NULL;
+ *   tri_err_dev: float64[T] output, or NULL.
+ * Sums use a fixed order, so results are reproducible run to run. */
+int fi_error(fi_mesh* mesh, const double* u_dev, const uint8_t* f_dev, double* mse_host,
+             double* pix_err_dev, double* tri_err_dev);
+
+/* Adjoint of the inpainting map, s = B^T r = t_D - K_DF K_FF^{-1} t_F with
+ * t = R^T r (R: interpolation to pixels). Section 4's nested CG applies it
+ * through one more solve with the same symmetric matrix.
+ *   r_dev: float64[P]; s_dev: float64[m] output. */
+int fi_adjoint(fi_mesh* mesh, const double* r_dev, double* s_dev, const fi_solve_opts* opts,
+               fi_solve_stats* stats);
+
+/* Tonal optimisation (Section 4): g* = argmin ||B g - f||^2 by CG on the
+ * normal equations in least-squares form (CGLS): residual r = f - B g,
+ * s = B^T r; B is applied through inner solves, never formed.
+ *   f_dev: uint8[P]; g_dev: float64[m], start value if opts->start_from_g,
+ *   result on return. opts: NULL for defaults. */
+int fi_tonal_opt(fi_mesh* mesh, const uint8_t* f_dev, double* g_dev, const fi_tonal_opts* opts,
+                 fi_tonal_stats* stats);
+
+/* Export of the mesh for checking (host buffers of the stated sizes, each may
+ * be NULL): vertex lattice coordinates int32[V][2] (x, y); triangles
+ * int32[T][3] (vertex ids, positive orientation); leaves int32[L][3]
+ * (x0, y0, level) in Morton order; free vertex ids int32[n]; mask vertex ids
+ * int32[m]. Synchronous. */
+int fi_mesh_export_geometry(const fi_mesh* mesh, int32_t* vxy, int32_t* tri, int32_t* leaves,
+                            int32_t* free_vids, int32_t* mask_vids);
+
+/* Export of the assembled matrices as CSR (host buffers, each may be NULL):
+ * K_FF int32 rowptr[n+1], int32 col[nnz_ff], float64 val[nnz_ff] (diagonal
+ * included, columns ascending); K_FD int32 rowptr[n+1], col[nnz_fd] (mask
+ * slots), float64 val[nnz_fd]. Synchronous. */
+int fi_mesh_export_csr(const fi_mesh* mesh, int32_t* ff_rowptr, int32_t* ff_col, double* ff_val,
+                       int32_t* fd_rowptr, int32_t* fd_col, double* fd_val);
+
+/* Owner triangle of every pixel, int32[P] device output (the rule of
+ * fi_error). */
+int fi_owner_map(fi_mesh* mesh, int32_t* owner_dev);
+
+/* Global top-k mask growth: the k non-mask pixels with the largest e
+ * (float64[P] device input), ties broken by the lower linear index. Writes
+ * the k selected indices in ascending order to out_dev (int32[k], device).
+ * Errors: FI_E_INVALID if k exceeds the number of non-mask pixels. */
+int fi_topk_new_pixels(fi_mesh* mesh, const double* e_dev, int64_t k, int32_t* out_dev);
+
+/* Timing helper: runs `reps` iterations of the fused FP32 (precision =
+ * FI_PREC_FP32_IR) or FP64 (FI_PREC_FP64) CG iteration kernel on this mesh's
+ * current solver state between two HIP events recorded on the context
+ * stream, and returns the mean milliseconds per launch. The solver state is
+ * left undefined. */
+int fi_time_cg_kernel(fi_mesh* mesh, int precision, int reps, double* ms_per_launch);
+
+/* Algorithmic bytes one launch of the fused CG iteration kernel must move
+ * (matrix, row pointers, and each vector read or written once). */
+int fi_cg_kernel_bytes(const fi_mesh* mesh, int precision, int64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FI_H */

@@ -1,0 +1,439 @@
+"""Python binding of the MI355X FEM harmonic-inpainting library (``libfi.so``).
+
+Thin ctypes layer over the C ABI in ``include/fi.h``: it checks tensor
+shapes, dtypes and devices and passes raw pointers. Every step of the
+computation runs in the library's HIP kernels; there is no fallback. Device
+memory comes from PyTorch tensors on the GPU, and calls run on PyTorch's
+current stream of that device unless another stream is given.
+
+Names follow the paper (Chizhov and Weickert, arXiv 2105.01586): f is the
+image, the mask K is a sorted array of linear pixel indices, g holds the
+grey values stored at the mask pixels, u = B g is the inpainted image
+(Sections 2 and 4).
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import weakref
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "FIError", "NoConvergence", "library", "Context", "Mesh", "SolveOpts", "TonalOpts",
+    "PREC_FP32_IR", "PREC_FP64", "lib_path", "EXPORTED_SYMBOLS", "host_mesh",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libfi.so")
+
+OK, E_INVALID, E_EMPTY_MASK, E_NO_CONVERGENCE, E_NOMEM, E_HIP = range(6)
+PREC_FP32_IR, PREC_FP64 = 0, 1
+
+EXPORTED_SYMBOLS = (
+    "fi_solve_opts_default", "fi_tonal_opts_default", "fi_last_error", "fi_version",
+    "fi_ctx_create", "fi_ctx_set_stream", "fi_ctx_destroy", "fi_mesh_build", "fi_mesh_destroy",
+    "fi_mesh_get_info", "fi_assemble", "fi_inpaint", "fi_vertex_values", "fi_error",
+    "fi_adjoint", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
+    "fi_owner_map", "fi_topk_new_pixels", "fi_time_cg_kernel", "fi_cg_kernel_bytes",
+    "fi_host_mesh_build", "fi_host_mesh_info", "fi_host_mesh_export", "fi_host_mesh_destroy",
+    "fi_mesh_upload",
+)
+
+
+class FIError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[fi status {code}] {msg}")
+        self.code = code
+
+
+class NoConvergence(FIError):
+    pass
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("inner_rtol", ctypes.c_double), ("max_inner", ctypes.c_int),
+                ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class _SolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("refinements", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+
+
+class _TonalOpts(ctypes.Structure):
+    _fields_ = [("inner", _SolveOpts), ("rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("start_from_g", ctypes.c_int)]
+
+
+class _TonalStats(ctypes.Structure):
+    _fields_ = [("outer_iterations", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("inner_iterations", ctypes.c_int64), ("rel_normal_residual", ctypes.c_double),
+                ("mse_initial", ctypes.c_double), ("mse_final", ctypes.c_double)]
+
+
+class _MeshInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("N", "P", "V", "T", "L", "n", "m", "nnz_ff", "nnz_fd", "device_bytes")]
+
+
+_lib = None
+_live_meshes: "weakref.WeakSet" = weakref.WeakSet()
+_live_contexts: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all() -> None:
+    # Meshes first (they borrow their context), before the HIP runtime's own
+    # exit handlers run.
+    for obj in list(_live_meshes) + list(_live_contexts):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+def library() -> ctypes.CDLL:
+    """Loads libfi.so (raises if it was not built: there is no other path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise ImportError(f"{lib_path} is missing; build it with __graft_entry__.build() "
+                          "or python paper_2105_01586_amd/build.py")
+    L = ctypes.CDLL(lib_path)
+    vp, i32p, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), \
+        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "fi_solve_opts_default": (None, [ctypes.POINTER(_SolveOpts)]),
+        "fi_tonal_opts_default": (None, [ctypes.POINTER(_TonalOpts)]),
+        "fi_last_error": (ctypes.c_char_p, []),
+        "fi_version": (ctypes.c_char_p, []),
+        "fi_ctx_create": (ctypes.c_int, [ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "fi_ctx_set_stream": (ctypes.c_int, [vp, vp]),
+        "fi_ctx_destroy": (ctypes.c_int, [vp]),
+        "fi_mesh_build": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64,
+                                         ctypes.POINTER(vp)]),
+        "fi_mesh_destroy": (ctypes.c_int, [vp]),
+        "fi_mesh_get_info": (ctypes.c_int, [vp, ctypes.POINTER(_MeshInfo)]),
+        "fi_assemble": (ctypes.c_int, [vp]),
+        "fi_inpaint": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                      ctypes.POINTER(_SolveStats)]),
+        "fi_vertex_values": (ctypes.c_int, [vp, vp]),
+        "fi_error": (ctypes.c_int, [vp, vp, vp, dp, vp, vp]),
+        "fi_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                      ctypes.POINTER(_SolveStats)]),
+        "fi_tonal_opt": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_TonalOpts),
+                                        ctypes.POINTER(_TonalStats)]),
+        "fi_mesh_export_geometry": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "fi_mesh_export_csr": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "fi_owner_map": (ctypes.c_int, [vp, vp]),
+        "fi_topk_new_pixels": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp]),
+        "fi_time_cg_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp]),
+        "fi_cg_kernel_bytes": (ctypes.c_int, [vp, ctypes.c_int, i64p]),
+        "fi_host_mesh_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64,
+                                              ctypes.POINTER(vp)]),
+        "fi_host_mesh_info": (ctypes.c_int, [vp, ctypes.POINTER(_MeshInfo)]),
+        "fi_host_mesh_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "fi_host_mesh_destroy": (ctypes.c_int, [vp]),
+        "fi_mesh_upload": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    del i32p
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str) -> None:
+    if rc == OK:
+        return
+    msg = library().fi_last_error().decode(errors="replace")
+    cls = NoConvergence if rc == E_NO_CONVERGENCE else FIError
+    raise cls(rc, f"{what}: {msg}")
+
+
+@dataclass
+class SolveOpts:
+    """Options of one harmonic-extension solve (defaults as in the C library)."""
+    precision: int = PREC_FP32_IR
+    rtol: float = 1e-10
+    inner_rtol: float = 1e-4
+    max_inner: int = 20000
+    max_refine: int = 40
+    check_every: int = 32
+
+    def c(self) -> _SolveOpts:
+        return _SolveOpts(self.precision, self.rtol, self.inner_rtol, self.max_inner,
+                          self.max_refine, self.check_every)
+
+
+@dataclass
+class TonalOpts:
+    inner: SolveOpts = None
+    rtol: float = 1e-8
+    max_outer: int = 500
+    start_from_g: bool = False
+
+    def c(self) -> _TonalOpts:
+        inner = (self.inner or SolveOpts()).c()
+        return _TonalOpts(inner, self.rtol, self.max_outer, int(self.start_from_g))
+
+
+def _stats(s) -> dict:
+    return {k: getattr(s, k) for k, _ in s._fields_}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def host_mesh(side: int, mask_idx) -> dict:
+    """Builds the quadtree mesh on the host only (no GPU) and exports it.
+
+    Returns numpy arrays: vxy (V, 2), tri (T, 3), leaves (L, 3), free_vids,
+    mask_vids, plus the counts.
+    """
+    L = library()
+    mask = np.ascontiguousarray(np.asarray(mask_idx, dtype=np.int32).ravel())
+    h = ctypes.c_void_p()
+    _check(L.fi_host_mesh_build(int(side), int(side), mask.ctypes.data_as(ctypes.c_void_p),
+                                mask.size, ctypes.byref(h)), "fi_host_mesh_build")
+    try:
+        info = _MeshInfo()
+        _check(L.fi_host_mesh_info(h, ctypes.byref(info)), "fi_host_mesh_info")
+        d = _stats(info)
+        out = {"vxy": np.empty((d["V"], 2), np.int32), "tri": np.empty((d["T"], 3), np.int32),
+               "leaves": np.empty((d["L"], 3), np.int32), "free_vids": np.empty(d["n"], np.int32),
+               "mask_vids": np.empty(d["m"], np.int32)}
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(L.fi_host_mesh_export(h, c(out["vxy"]), c(out["tri"]), c(out["leaves"]),
+                                     c(out["free_vids"]), c(out["mask_vids"])),
+               "fi_host_mesh_export")
+        out.update({k: int(v) for k, v in d.items()})
+        return out
+    finally:
+        L.fi_host_mesh_destroy(h)
+
+
+class Context:
+    """Device and HIP stream binding. ``stream`` defaults to torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(library().fi_ctx_create(self.device, ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(h)), "fi_ctx_create")
+        self._h = h
+        self._meshes = weakref.WeakSet()
+        _live_contexts.add(self)
+
+    def set_stream(self, stream) -> None:
+        self.stream = stream
+        _check(library().fi_ctx_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)),
+               "fi_ctx_set_stream")
+
+    def close(self) -> None:
+        """Destroys the context after every mesh built on it."""
+        for m in list(getattr(self, "_meshes", ())):
+            m.close()
+        if getattr(self, "_h", None):
+            library().fi_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t, dtype, numel, name, device):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must live on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """Quadtree FEM mesh for one (image side, mask) pair, with its device matrices."""
+
+    def __init__(self, ctx: Context, side: int, mask_idx):
+        self.ctx = ctx
+        mask = np.ascontiguousarray(np.asarray(mask_idx, dtype=np.int32).ravel())
+        self._mask = mask
+        h = ctypes.c_void_p()
+        _check(library().fi_mesh_build(ctx._h, int(side), int(side),
+                                       mask.ctypes.data_as(ctypes.c_void_p), mask.size,
+                                       ctypes.byref(h)), "fi_mesh_build")
+        self._h = h
+        ctx._meshes.add(self)
+        _live_meshes.add(self)
+        info = _MeshInfo()
+        _check(library().fi_mesh_get_info(h, ctypes.byref(info)), "fi_mesh_get_info")
+        self.info = _stats(info)
+        for k in ("N", "P", "V", "T", "L", "n", "m"):
+            setattr(self, k, int(self.info[k]))
+
+    @property
+    def mask(self) -> np.ndarray:
+        return self._mask
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            library().fi_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self):
+        return self.ctx.device
+
+    def _empty(self, n, dtype):
+        torch = _torch()
+        return torch.empty(n, dtype=dtype, device=f"cuda:{self._dev()}")
+
+    # -- the hot path ------------------------------------------------------
+    def assemble(self) -> None:
+        _check(library().fi_assemble(self._h), "fi_assemble")
+
+    def inpaint(self, f=None, g=None, u=None, opts: SolveOpts | None = None):
+        """u = B g (g defaults to f on the mask). Returns (u, stats)."""
+        torch = _torch()
+        d = self._dev()
+        if u is None:
+            u = self._empty(self.P, torch.float64)
+        st = _SolveStats()
+        o = (opts or SolveOpts()).c()
+        rc = library().fi_inpaint(self._h, _ptr(f, torch.uint8, self.P, "f", d),
+                                  _ptr(g, torch.float64, self.m, "g", d),
+                                  _ptr(u, torch.float64, self.P, "u", d), ctypes.byref(o),
+                                  ctypes.byref(st))
+        _check(rc, "fi_inpaint")
+        return u, _stats(st)
+
+    def vertex_values(self):
+        torch = _torch()
+        out = self._empty(self.V, torch.float64)
+        _check(library().fi_vertex_values(self._h, ctypes.c_void_p(out.data_ptr())),
+               "fi_vertex_values")
+        return out
+
+    def error(self, u, f, pixel: bool = False, triangle: bool = False):
+        """Returns (mse, e or None, E_T or None)."""
+        torch = _torch()
+        d = self._dev()
+        e = self._empty(self.P, torch.float64) if pixel else None
+        E = self._empty(self.T, torch.float64) if triangle else None
+        mse = ctypes.c_double()
+        rc = library().fi_error(self._h, _ptr(u, torch.float64, self.P, "u", d),
+                                _ptr(f, torch.uint8, self.P, "f", d), ctypes.byref(mse),
+                                _ptr(e, torch.float64, self.P, "e", d),
+                                _ptr(E, torch.float64, self.T, "E", d))
+        _check(rc, "fi_error")
+        return mse.value, e, E
+
+    def adjoint(self, r, s=None, opts: SolveOpts | None = None):
+        """s = B^T r. Returns (s, stats)."""
+        torch = _torch()
+        d = self._dev()
+        if s is None:
+            s = self._empty(self.m, torch.float64)
+        st = _SolveStats()
+        o = (opts or SolveOpts()).c()
+        rc = library().fi_adjoint(self._h, _ptr(r, torch.float64, self.P, "r", d),
+                                  _ptr(s, torch.float64, self.m, "s", d), ctypes.byref(o),
+                                  ctypes.byref(st))
+        _check(rc, "fi_adjoint")
+        return s, _stats(st)
+
+    def tonal_opt(self, f, g=None, opts: TonalOpts | None = None):
+        """g* = argmin ||B g - f||^2 by CGLS. Returns (g, stats)."""
+        torch = _torch()
+        d = self._dev()
+        o = opts or TonalOpts()
+        if g is None:
+            g = self._empty(self.m, torch.float64)
+            o = TonalOpts(o.inner, o.rtol, o.max_outer, False)
+        co = o.c()
+        st = _TonalStats()
+        rc = library().fi_tonal_opt(self._h, _ptr(f, torch.uint8, self.P, "f", d),
+                                    _ptr(g, torch.float64, self.m, "g", d), ctypes.byref(co),
+                                    ctypes.byref(st))
+        _check(rc, "fi_tonal_opt")
+        return g, _stats(st)
+
+    # -- exports for checking --------------------------------------------
+    def export_geometry(self) -> dict:
+        vxy = np.empty((self.V, 2), np.int32)
+        tri = np.empty((self.T, 3), np.int32)
+        leaves = np.empty((self.L, 3), np.int32)
+        fv = np.empty(self.n, np.int32)
+        mv = np.empty(self.m, np.int32)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(library().fi_mesh_export_geometry(self._h, c(vxy), c(tri), c(leaves), c(fv), c(mv)),
+               "fi_mesh_export_geometry")
+        return {"vxy": vxy, "tri": tri, "leaves": leaves, "free_vids": fv, "mask_vids": mv}
+
+    def export_csr(self) -> dict:
+        n = self.n
+        nff, nfd = int(self.info["nnz_ff"]), int(self.info["nnz_fd"])
+        a = {"ff_rowptr": np.empty(n + 1, np.int32), "ff_col": np.empty(nff, np.int32),
+             "ff_val": np.empty(nff, np.float64), "fd_rowptr": np.empty(n + 1, np.int32),
+             "fd_col": np.empty(nfd, np.int32), "fd_val": np.empty(nfd, np.float64)}
+        c = lambda x: x.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(library().fi_mesh_export_csr(self._h, c(a["ff_rowptr"]), c(a["ff_col"]),
+                                            c(a["ff_val"]), c(a["fd_rowptr"]), c(a["fd_col"]),
+                                            c(a["fd_val"])), "fi_mesh_export_csr")
+        return a
+
+    def owner_map(self):
+        torch = _torch()
+        out = self._empty(self.P, torch.int32)
+        _check(library().fi_owner_map(self._h, ctypes.c_void_p(out.data_ptr())), "fi_owner_map")
+        return out
+
+    def topk_new_pixels(self, e, k: int):
+        torch = _torch()
+        out = self._empty(max(int(k), 1), torch.int32)
+        rc = library().fi_topk_new_pixels(self._h, _ptr(e, torch.float64, self.P, "e", self._dev()),
+                                          int(k), ctypes.c_void_p(out.data_ptr()))
+        _check(rc, "fi_topk_new_pixels")
+        return out[:int(k)]
+
+    # -- measurement ---------------------------------------------------------
+    def time_cg_kernel(self, precision: int = PREC_FP32_IR, reps: int = 200) -> float:
+        ms = ctypes.c_double()
+        _check(library().fi_time_cg_kernel(self._h, int(precision), int(reps), ctypes.byref(ms)),
+               "fi_time_cg_kernel")
+        return ms.value
+
+    def cg_kernel_bytes(self, precision: int = PREC_FP32_IR) -> int:
+        b = ctypes.c_int64()
+        _check(library().fi_cg_kernel_bytes(self._h, int(precision), ctypes.byref(b)),
+               "fi_cg_kernel_bytes")
+        return b.value

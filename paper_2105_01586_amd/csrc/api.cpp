@@ -1,0 +1,637 @@
+// C ABI of the library (declared in include/fi.h): contexts, meshes, and the
+// inpainting, error, adjoint and tonal-optimisation calls.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "internal.h"
+
+namespace fi {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int device_alloc(fi_mesh* M, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~(size_t)255;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? FI_E_NOMEM : FI_E_HIP,
+                std::string("device allocation failed: ") + hipGetErrorString(e));
+  }
+  M->allocations.push_back(*p);
+  M->device_bytes += (int64_t)bytes;
+  return FI_OK;
+}
+
+namespace {
+
+template <typename T>
+int alloc_n(fi_mesh* M, T** p, int64_t n) {
+  return device_alloc(M, (void**)p, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+}
+
+template <typename T>
+int upload(fi_mesh* M, T** p, const std::vector<T>& h) {
+  int rc = alloc_n(M, p, (int64_t)h.size());
+  if (rc) return rc;
+  if (!h.empty())
+    FI_HIP_TRY(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice,
+                              M->ctx->stream));
+  return FI_OK;
+}
+
+void free_mesh(fi_mesh* M) {
+  if (!M) return;
+  // hipFree waits for outstanding work on the device; the context (and its
+  // stream) may already be gone, so only the device id is used here.
+  (void)hipSetDevice(M->device);
+  for (void* p : M->allocations) (void)hipFree(p);
+  if (M->h_red) (void)hipHostFree(M->h_red);
+  if (M->h_ctl) (void)hipHostFree(M->h_ctl);
+  delete M;
+}
+
+int alloc_workspace(fi_mesh* M) {
+  int rc = 0;
+  const int64_t n = M->n, m = M->m, V = M->V, T = M->T;
+#define TRY(x) do { rc = (x); if (rc) return rc; } while (0)
+  TRY(alloc_n(M, &M->d_cnt, std::max(2 * (n + 1), m + 1)));
+  TRY(alloc_n(M, &M->d_scan_tmp, scan_tmp_ints(std::max(n, m) + 1)));
+  TRY(alloc_n(M, &M->d_ff_rowptr, n + 1));
+  TRY(alloc_n(M, &M->d_fd_rowptr, n + 1));
+  TRY(alloc_n(M, &M->d_df_rowptr, m + 1));
+  TRY(alloc_n(M, &M->d_diag64, n));
+  TRY(alloc_n(M, &M->d_dinv64, n));
+  TRY(alloc_n(M, &M->d_dinv32, n));
+  TRY(alloc_n(M, &M->d_b64, n));
+  TRY(alloc_n(M, &M->d_x64, n));
+  TRY(alloc_n(M, &M->d_r64, n));
+  float* f32[8];
+  double* f64[8];
+  for (int k = 0; k < 8; ++k) TRY(alloc_n(M, &f32[k], n));
+  for (int k = 0; k < 8; ++k) TRY(alloc_n(M, &f64[k], n));
+  M->cg32 = CGState{f32[0], f32[1], {f32[2], f32[3]}, {f32[4], f32[5]}, {f32[6], f32[7]}};
+  M->cg64 = CGState{f64[0], f64[1], {f64[2], f64[3]}, {f64[4], f64[5]}, {f64[6], f64[7]}};
+  TRY(alloc_n(M, &M->d_part, 2 * 4 * kMaxGrid));
+  TRY(alloc_n(M, &M->d_scal, 8));
+  TRY(alloc_n(M, &M->d_ctl, 4));
+  TRY(alloc_n(M, &M->d_red, kMaxGrid));
+  TRY(alloc_n(M, &M->d_red_out, 8));
+  TRY(alloc_n(M, &M->d_uvert, V));
+  TRY(alloc_n(M, &M->d_g, m));
+  TRY(alloc_n(M, &M->d_tpart, 3 * T));
+  TRY(alloc_n(M, &M->d_tF, n));
+  TRY(alloc_n(M, &M->d_tD, m));
+  TRY(alloc_n(M, &M->d_rpart, raster_blocks(M)));
+#undef TRY
+  FI_HIP_TRY(hipHostMalloc((void**)&M->h_red, 8 * sizeof(double), hipHostMallocDefault));
+  FI_HIP_TRY(hipHostMalloc((void**)&M->h_ctl, 4 * sizeof(int32_t), hipHostMallocDefault));
+  int64_t g = (n + kBlock - 1) / kBlock;
+  M->cg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxGrid));
+  return FI_OK;
+}
+
+int read_total(fi_mesh* M, const int32_t* dptr, int64_t* out) {
+  int32_t v = 0;
+  FI_HIP_TRY(hipMemcpyAsync(M->h_ctl + 3, dptr, sizeof(int32_t), hipMemcpyDeviceToHost,
+                            M->ctx->stream));
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  v = M->h_ctl[3];
+  *out = v;
+  return FI_OK;
+}
+
+int sync_read_scalar(fi_mesh* M, const double* dptr, double* out) {
+  FI_HIP_TRY(hipMemcpyAsync(M->h_red, dptr, sizeof(double), hipMemcpyDeviceToHost,
+                            M->ctx->stream));
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  *out = M->h_red[0];
+  return FI_OK;
+}
+
+int check_mesh(const fi_mesh* M) {
+  if (!M || !M->ctx) return fail(FI_E_INVALID, "mesh is NULL");
+  return FI_OK;
+}
+
+fi_solve_opts resolve_opts(const fi_solve_opts* o) {
+  fi_solve_opts d;
+  fi_solve_opts_default(&d);
+  if (!o) return d;
+  fi_solve_opts r = *o;
+  if (r.rtol <= 0) r.rtol = d.rtol;
+  if (r.inner_rtol <= 0 || r.inner_rtol >= 1) r.inner_rtol = d.inner_rtol;
+  if (r.max_inner <= 0) r.max_inner = d.max_inner;
+  if (r.max_refine <= 0) r.max_refine = d.max_refine;
+  if (r.check_every <= 0) r.check_every = d.check_every;
+  return r;
+}
+
+// u = B g for g on the device (vertex values kept in d_uvert).
+int apply_B(fi_mesh* M, const double* g, double* u_out, const fi_solve_opts* o,
+            fi_solve_stats* st) {
+  int rc = launch_lift(M, g, M->d_b64);
+  if (rc) return rc;
+  rc = solve_free(M, o, st);
+  if (rc) return rc;
+  rc = launch_vertex_values(M, M->d_x64, g, M->d_uvert);
+  if (rc) return rc;
+  return launch_raster(M, M->d_uvert, nullptr, nullptr, u_out, nullptr, nullptr, nullptr,
+                       nullptr);
+}
+
+// s = B^T r for r on the device.
+int apply_BT(fi_mesh* M, const double* r, double* s, const fi_solve_opts* o, fi_solve_stats* st) {
+  int rc = launch_raster_transpose(M, r, M->d_tpart);
+  if (rc) return rc;
+  rc = launch_gather_vertex(M, M->d_tpart, M->d_tF, M->d_tD);
+  if (rc) return rc;
+  FI_HIP_TRY(hipMemcpyAsync(M->d_b64, M->d_tF, (size_t)M->n * sizeof(double),
+                            hipMemcpyDeviceToDevice, M->ctx->stream));
+  rc = solve_free(M, o, st);
+  if (rc) return rc;
+  return launch_adjoint_tail(M, M->d_tD, M->d_x64, s);
+}
+
+int dot_host(fi_mesh* M, const double* a, const double* b, int64_t n, double* out) {
+  int rc = launch_dot(M, a, b, n, M->d_red_out);
+  if (rc) return rc;
+  return sync_read_scalar(M, M->d_red_out, out);
+}
+
+int mse_of(fi_mesh* M, const double* u, const uint8_t* f, double* mse) {
+  int rc = launch_raster(M, nullptr, u, f, nullptr, nullptr, nullptr, nullptr, M->d_rpart);
+  if (rc) return rc;
+  rc = launch_reduce(M, M->d_rpart, raster_blocks(M), 1, M->d_red_out);
+  if (rc) return rc;
+  double s = 0;
+  rc = sync_read_scalar(M, M->d_red_out, &s);
+  if (rc) return rc;
+  *mse = s / (double)M->P;
+  return FI_OK;
+}
+
+}  // namespace
+}  // namespace fi
+
+using namespace fi;
+
+extern "C" {
+
+void fi_solve_opts_default(fi_solve_opts* o) {
+  if (!o) return;
+  o->precision = FI_PREC_FP32_IR;
+  o->rtol = 1e-10;
+  o->inner_rtol = 1e-4;
+  o->max_inner = 20000;
+  o->max_refine = 40;
+  o->check_every = 32;
+}
+
+void fi_tonal_opts_default(fi_tonal_opts* o) {
+  if (!o) return;
+  fi_solve_opts_default(&o->inner);
+  o->rtol = 1e-8;
+  o->max_outer = 500;
+  o->start_from_g = 0;
+}
+
+const char* fi_last_error(void) { return g_last_error.c_str(); }
+
+const char* fi_version(void) { return "fem-inpaint-mi355x 0.1.0 (gfx950)"; }
+
+int fi_ctx_create(int device, void* stream, fi_ctx** out) {
+  if (!out) return fail(FI_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  FI_HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(FI_E_INVALID, "no such device");
+  FI_HIP_TRY(hipSetDevice(device));
+  fi_ctx* c = new fi_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return FI_OK;
+}
+
+int fi_ctx_set_stream(fi_ctx* ctx, void* stream) {
+  if (!ctx) return fail(FI_E_INVALID, "ctx is NULL");
+  ctx->stream = (hipStream_t)stream;
+  return FI_OK;
+}
+
+int fi_ctx_destroy(fi_ctx* ctx) {
+  delete ctx;
+  return FI_OK;
+}
+
+int fi_host_mesh_build(int width, int height, const int32_t* mask_idx, int64_t m,
+                       fi_host_mesh** out) {
+  if (!out) return fail(FI_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (width != height) return fail(FI_E_INVALID, "image must be square");
+  fi_host_mesh* h = new fi_host_mesh();
+  int rc = build_host_mesh(width, mask_idx, m, h->mesh);
+  if (rc) { delete h; return rc; }
+  *out = h;
+  return FI_OK;
+}
+
+int fi_host_mesh_info(const fi_host_mesh* h, fi_mesh_info* info) {
+  if (!h || !info) return fail(FI_E_INVALID, "NULL argument");
+  const HostMesh& H = h->mesh;
+  std::memset(info, 0, sizeof(*info));
+  info->N = H.N;
+  info->P = (int64_t)H.N * H.N;
+  info->V = H.V();
+  info->T = H.T();
+  info->L = H.L();
+  info->n = (int64_t)H.free_vids.size();
+  info->m = (int64_t)H.mask_vids.size();
+  return FI_OK;
+}
+
+int fi_host_mesh_export(const fi_host_mesh* h, int32_t* vxy, int32_t* tri, int32_t* leaves,
+                        int32_t* free_vids, int32_t* mask_vids) {
+  if (!h) return fail(FI_E_INVALID, "host mesh is NULL");
+  const HostMesh& H = h->mesh;
+  if (vxy) std::memcpy(vxy, H.vxy.data(), H.vxy.size() * sizeof(int32_t));
+  if (tri) std::memcpy(tri, H.tri.data(), H.tri.size() * sizeof(int32_t));
+  if (leaves) {
+    for (int64_t i = 0; i < H.L(); ++i) {
+      leaves[3 * i] = H.leaves[4 * i];
+      leaves[3 * i + 1] = H.leaves[4 * i + 1];
+      leaves[3 * i + 2] = H.leaves[4 * i + 2];
+    }
+  }
+  if (free_vids) std::memcpy(free_vids, H.free_vids.data(), H.free_vids.size() * sizeof(int32_t));
+  if (mask_vids) std::memcpy(mask_vids, H.mask_vids.data(), H.mask_vids.size() * sizeof(int32_t));
+  return FI_OK;
+}
+
+int fi_host_mesh_destroy(fi_host_mesh* h) {
+  delete h;
+  return FI_OK;
+}
+
+int fi_mesh_build(fi_ctx* ctx, int width, int height, const int32_t* mask_idx, int64_t m,
+                  fi_mesh** out) {
+  if (!ctx || !out) return fail(FI_E_INVALID, "ctx or out is NULL");
+  *out = nullptr;
+  fi_host_mesh* h = nullptr;
+  int rc = fi_host_mesh_build(width, height, mask_idx, m, &h);
+  if (rc) return rc;
+  rc = fi_mesh_upload(ctx, &h, out);
+  if (h) fi_host_mesh_destroy(h);
+  return rc;
+}
+
+int fi_mesh_upload(fi_ctx* ctx, fi_host_mesh** host, fi_mesh** out) {
+  if (!ctx || !out || !host || !*host) return fail(FI_E_INVALID, "NULL argument");
+  *out = nullptr;
+  FI_HIP_TRY(hipSetDevice(ctx->device));
+  fi_mesh* M = new fi_mesh();
+  M->ctx = ctx;
+  M->device = ctx->device;
+  M->host = std::move((*host)->mesh);
+  int rc = FI_OK;
+  const HostMesh& H = M->host;
+  M->N = H.N;
+  M->P = (int64_t)H.N * H.N;
+  M->V = H.V();
+  M->T = H.T();
+  M->L = H.L();
+  M->n = (int64_t)H.free_vids.size();
+  M->m = (int64_t)H.mask_vids.size();
+  if ((rc = upload(M, &M->d_vxy, H.vxy)) || (rc = upload(M, &M->d_tri, H.tri)) ||
+      (rc = upload(M, &M->d_leaves, H.leaves)) || (rc = upload(M, &M->d_vmap, H.vmap)) ||
+      (rc = upload(M, &M->d_free_vids, H.free_vids)) ||
+      (rc = upload(M, &M->d_mask_vids, H.mask_vids)) ||
+      (rc = upload(M, &M->d_mask_pix, H.mask_pix)) || (rc = upload(M, &M->d_vt_ptr, H.vt_ptr)) ||
+      (rc = upload(M, &M->d_vt_idx, H.vt_idx)) || (rc = alloc_workspace(M)) ||
+      (rc = fi_assemble(M))) {
+    std::string keep = g_last_error;
+    (*host)->mesh = std::move(M->host);
+    free_mesh(M);
+    g_last_error = keep;
+    return rc;
+  }
+  fi_host_mesh_destroy(*host);
+  *host = nullptr;
+  *out = M;
+  return FI_OK;
+}
+
+int fi_mesh_destroy(fi_mesh* M) {
+  free_mesh(M);
+  return FI_OK;
+}
+
+int fi_mesh_get_info(const fi_mesh* M, fi_mesh_info* info) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!info) return fail(FI_E_INVALID, "info is NULL");
+  info->N = M->N;
+  info->P = M->P;
+  info->V = M->V;
+  info->T = M->T;
+  info->L = M->L;
+  info->n = M->n;
+  info->m = M->m;
+  info->nnz_ff = M->nnz_off + M->n;
+  info->nnz_fd = M->nnz_fd;
+  info->device_bytes = M->device_bytes;
+  return FI_OK;
+}
+
+int fi_assemble(fi_mesh* M) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  const int64_t n = M->n, m = M->m;
+  int32_t* cnt_ff = M->d_cnt;
+  int32_t* cnt_fd = M->d_cnt + (n + 1);
+  if ((rc = launch_assemble_count(M, true))) return rc;
+  if ((rc = scan_counts(M, cnt_ff, M->d_ff_rowptr, n + 1))) return rc;
+  if ((rc = scan_counts(M, cnt_fd, M->d_fd_rowptr, n + 1))) return rc;
+  if (!M->assembled_once) {
+    if ((rc = read_total(M, M->d_ff_rowptr + n, &M->nnz_off))) return rc;
+    if ((rc = read_total(M, M->d_fd_rowptr + n, &M->nnz_fd))) return rc;
+    if ((rc = alloc_n(M, &M->d_ff_col, M->nnz_off)) || (rc = alloc_n(M, &M->d_ff_val64, M->nnz_off)) ||
+        (rc = alloc_n(M, &M->d_ff_val32, M->nnz_off)) || (rc = alloc_n(M, &M->d_fd_col, M->nnz_fd)) ||
+        (rc = alloc_n(M, &M->d_fd_val, M->nnz_fd)))
+      return rc;
+  }
+  if ((rc = launch_assemble_fill(M, true))) return rc;
+  // mask rows: K_DF (reuses the count scratch after the fill above is queued)
+  if ((rc = launch_assemble_count(M, false))) return rc;
+  if ((rc = scan_counts(M, M->d_cnt, M->d_df_rowptr, m + 1))) return rc;
+  if (!M->assembled_once) {
+    if ((rc = read_total(M, M->d_df_rowptr + m, &M->nnz_df))) return rc;
+    if ((rc = alloc_n(M, &M->d_df_col, M->nnz_df)) || (rc = alloc_n(M, &M->d_df_val, M->nnz_df)))
+      return rc;
+  }
+  if ((rc = launch_assemble_fill(M, false))) return rc;
+  if (!M->assembled_once) FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  M->assembled_once = true;
+  return FI_OK;
+}
+
+int fi_inpaint(fi_mesh* M, const uint8_t* f_dev, const double* g_dev, double* u_dev,
+               const fi_solve_opts* opts, fi_solve_stats* stats) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_dev) return fail(FI_E_INVALID, "u_dev is NULL");
+  if (!g_dev && !f_dev) return fail(FI_E_INVALID, "need f_dev or g_dev");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  const fi_solve_opts o = resolve_opts(opts);
+  fi_solve_stats st{};
+  const double* g = g_dev;
+  if (!g) {
+    if ((rc = launch_gather_mask(M, f_dev, M->d_g))) return rc;
+    g = M->d_g;
+  }
+  rc = apply_B(M, g, u_dev, &o, &st);
+  if (stats) *stats = st;
+  if (rc) return rc;
+  if (st.status != FI_OK)
+    return fail(FI_E_NO_CONVERGENCE, "inpainting solve did not reach the tolerance");
+  return FI_OK;
+}
+
+int fi_vertex_values(fi_mesh* M, double* u_vertex_dev) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_vertex_dev) return fail(FI_E_INVALID, "output is NULL");
+  FI_HIP_TRY(hipMemcpyAsync(u_vertex_dev, M->d_uvert, (size_t)M->V * sizeof(double),
+                            hipMemcpyDeviceToDevice, M->ctx->stream));
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  return FI_OK;
+}
+
+int fi_error(fi_mesh* M, const double* u_dev, const uint8_t* f_dev, double* mse_host,
+             double* pix_err_dev, double* tri_err_dev) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_dev || !f_dev) return fail(FI_E_INVALID, "u_dev and f_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  rc = launch_raster(M, nullptr, u_dev, f_dev, nullptr, pix_err_dev, tri_err_dev, nullptr,
+                     M->d_rpart);
+  if (rc) return rc;
+  rc = launch_reduce(M, M->d_rpart, raster_blocks(M), 1, M->d_red_out);
+  if (rc) return rc;
+  double s = 0.0;
+  rc = sync_read_scalar(M, M->d_red_out, &s);
+  if (rc) return rc;
+  if (mse_host) *mse_host = s / (double)M->P;
+  return FI_OK;
+}
+
+int fi_adjoint(fi_mesh* M, const double* r_dev, double* s_dev, const fi_solve_opts* opts,
+               fi_solve_stats* stats) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!r_dev || !s_dev) return fail(FI_E_INVALID, "r_dev and s_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  const fi_solve_opts o = resolve_opts(opts);
+  fi_solve_stats st{};
+  rc = apply_BT(M, r_dev, s_dev, &o, &st);
+  if (stats) *stats = st;
+  if (rc) return rc;
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  if (st.status != FI_OK)
+    return fail(FI_E_NO_CONVERGENCE, "adjoint solve did not reach the tolerance");
+  return FI_OK;
+}
+
+int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev, const fi_tonal_opts* opts,
+                 fi_tonal_stats* stats) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!f_dev || !g_dev) return fail(FI_E_INVALID, "f_dev and g_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  fi_tonal_opts o;
+  fi_tonal_opts_default(&o);
+  if (opts) {
+    o = *opts;
+    if (o.rtol <= 0) o.rtol = 1e-8;
+    if (o.max_outer <= 0) o.max_outer = 500;
+  }
+  const fi_solve_opts io = resolve_opts(opts ? &opts->inner : nullptr);
+  fi_tonal_stats ts{};
+  const int64_t m = M->m, P = M->P;
+  if (!M->d_tg) {
+    if ((rc = alloc_n(M, &M->d_tg, m)) || (rc = alloc_n(M, &M->d_ts, m)) ||
+        (rc = alloc_n(M, &M->d_tr, P)) || (rc = alloc_n(M, &M->d_tq, P)))
+      return rc;
+  }
+  double* p = M->d_tg;
+  double* s = M->d_ts;
+  double* r = M->d_tr;
+  double* q = M->d_tq;
+  fi_solve_stats st{};
+  auto acc = [&](const fi_solve_stats& x) -> int {
+    ts.inner_iterations += x.iterations;
+    if (x.status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");
+    return FI_OK;
+  };
+  if (!o.start_from_g) {
+    if ((rc = launch_gather_mask(M, f_dev, g_dev))) return rc;
+  }
+  // r = f - B g
+  if ((rc = apply_B(M, g_dev, q, &io, &st)) || (rc = acc(st))) return rc;
+  if ((rc = launch_pixel_residual(M, f_dev, q, r))) return rc;
+  double rr = 0;
+  if ((rc = dot_host(M, r, r, P, &rr))) return rc;
+  ts.mse_initial = rr / (double)P;
+  // s = B^T r, p = s
+  if ((rc = apply_BT(M, r, s, &io, &st)) || (rc = acc(st))) return rc;
+  FI_HIP_TRY(hipMemcpyAsync(p, s, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice,
+                            M->ctx->stream));
+  double gamma = 0;
+  if ((rc = dot_host(M, s, s, m, &gamma))) return rc;
+  const double s0 = std::sqrt(gamma);
+  if (!std::isfinite(s0)) return fail(FI_E_INVALID, "non-finite normal residual");
+  ts.rel_normal_residual = s0 > 0 ? 1.0 : 0.0;
+  ts.status = FI_OK;
+  int it = 0;
+  if (s0 > 0) {
+    ts.status = FI_E_NO_CONVERGENCE;
+    while (it < o.max_outer) {
+      if ((rc = apply_B(M, p, q, &io, &st)) || (rc = acc(st))) return rc;
+      double qq = 0;
+      if ((rc = dot_host(M, q, q, P, &qq))) return rc;
+      if (!(qq > 0)) break;
+      const double alpha = gamma / qq;
+      if ((rc = launch_axpy(M, m, alpha, p, g_dev))) return rc;
+      if ((rc = launch_axpy(M, P, -alpha, q, r))) return rc;
+      if ((rc = apply_BT(M, r, s, &io, &st)) || (rc = acc(st))) return rc;
+      double gnew = 0;
+      if ((rc = dot_host(M, s, s, m, &gnew))) return rc;
+      ++it;
+      ts.rel_normal_residual = std::sqrt(gnew) / s0;
+      if (ts.rel_normal_residual <= o.rtol) { ts.status = FI_OK; break; }
+      const double beta = gnew / gamma;
+      if ((rc = launch_xpby(M, m, s, beta, p))) return rc;
+      gamma = gnew;
+    }
+  }
+  ts.outer_iterations = it;
+  double mse = 0;
+  if ((rc = apply_B(M, g_dev, q, &io, &st)) || (rc = acc(st))) return rc;
+  if ((rc = mse_of(M, q, f_dev, &mse))) return rc;
+  ts.mse_final = mse;
+  if (stats) *stats = ts;
+  if (ts.status != FI_OK)
+    return fail(FI_E_NO_CONVERGENCE, "tonal optimisation reached the outer iteration cap");
+  return FI_OK;
+}
+
+int fi_mesh_export_geometry(const fi_mesh* M, int32_t* vxy, int32_t* tri, int32_t* leaves,
+                            int32_t* free_vids, int32_t* mask_vids) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  fi_host_mesh view;
+  view.mesh = M->host;  // copy: exports are for checking, not the hot path
+  return fi_host_mesh_export(&view, vxy, tri, leaves, free_vids, mask_vids);
+}
+
+int fi_mesh_export_csr(const fi_mesh* Mc, int32_t* ff_rowptr, int32_t* ff_col, double* ff_val,
+                       int32_t* fd_rowptr, int32_t* fd_col, double* fd_val) {
+  int rc = check_mesh(Mc);
+  if (rc) return rc;
+  fi_mesh* M = const_cast<fi_mesh*>(Mc);
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  const int64_t n = M->n;
+  std::vector<int32_t> rp(n + 1), col(M->nnz_off), frp(n + 1), fcol(M->nnz_fd);
+  std::vector<double> val(M->nnz_off), diag(n), fval(M->nnz_fd);
+  FI_HIP_TRY(hipMemcpy(rp.data(), M->d_ff_rowptr, (n + 1) * 4, hipMemcpyDeviceToHost));
+  if (M->nnz_off) {
+    FI_HIP_TRY(hipMemcpy(col.data(), M->d_ff_col, M->nnz_off * 4, hipMemcpyDeviceToHost));
+    FI_HIP_TRY(hipMemcpy(val.data(), M->d_ff_val64, M->nnz_off * 8, hipMemcpyDeviceToHost));
+  }
+  FI_HIP_TRY(hipMemcpy(diag.data(), M->d_diag64, n * 8, hipMemcpyDeviceToHost));
+  FI_HIP_TRY(hipMemcpy(frp.data(), M->d_fd_rowptr, (n + 1) * 4, hipMemcpyDeviceToHost));
+  if (M->nnz_fd) {
+    FI_HIP_TRY(hipMemcpy(fcol.data(), M->d_fd_col, M->nnz_fd * 4, hipMemcpyDeviceToHost));
+    FI_HIP_TRY(hipMemcpy(fval.data(), M->d_fd_val, M->nnz_fd * 8, hipMemcpyDeviceToHost));
+  }
+  // K_FF with its diagonal merged in column order
+  int64_t pos = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (ff_rowptr) ff_rowptr[i] = (int32_t)pos;
+    bool placed = false;
+    for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+      if (!placed && col[j] > i) {
+        if (ff_col) ff_col[pos] = (int32_t)i;
+        if (ff_val) ff_val[pos] = diag[i];
+        ++pos;
+        placed = true;
+      }
+      if (ff_col) ff_col[pos] = col[j];
+      if (ff_val) ff_val[pos] = val[j];
+      ++pos;
+    }
+    if (!placed) {
+      if (ff_col) ff_col[pos] = (int32_t)i;
+      if (ff_val) ff_val[pos] = diag[i];
+      ++pos;
+    }
+  }
+  if (ff_rowptr) ff_rowptr[n] = (int32_t)pos;
+  if (fd_rowptr) std::memcpy(fd_rowptr, frp.data(), (n + 1) * 4);
+  if (fd_col) std::memcpy(fd_col, fcol.data(), fcol.size() * 4);
+  if (fd_val) std::memcpy(fd_val, fval.data(), fval.size() * 8);
+  return FI_OK;
+}
+
+int fi_owner_map(fi_mesh* M, int32_t* owner_dev) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!owner_dev) return fail(FI_E_INVALID, "owner_dev is NULL");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  rc = launch_raster(M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, owner_dev, nullptr);
+  if (rc) return rc;
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  return FI_OK;
+}
+
+int fi_topk_new_pixels(fi_mesh* M, const double* e_dev, int64_t k, int32_t* out_dev) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!e_dev || (!out_dev && k > 0)) return fail(FI_E_INVALID, "e_dev and out_dev are required");
+  if (k < 0 || k > M->P - M->m) return fail(FI_E_INVALID, "k out of range");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  return topk_new_pixels(M, e_dev, k, out_dev);
+}
+
+int fi_time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms_per_launch) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!ms_per_launch) return fail(FI_E_INVALID, "output is NULL");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  return time_cg_kernel(M, precision, reps, ms_per_launch);
+}
+
+int fi_cg_kernel_bytes(const fi_mesh* M, int precision, int64_t* bytes) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!bytes) return fail(FI_E_INVALID, "output is NULL");
+  *bytes = cg_kernel_bytes(M, precision);
+  return FI_OK;
+}
+
+}  // extern "C"

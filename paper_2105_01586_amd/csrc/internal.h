@@ -1,0 +1,196 @@
+// Internal declarations shared by the host code and the HIP kernels of the
+// library. Nothing here is part of the C ABI (see include/fi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fi.h"
+
+namespace fi {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define FI_HIP_TRY(expr)                                                                 \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::fi::fail(FI_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ------------------------------------------------------------- host mesh --
+// The quadtree mesh as built on the host (integer data only).
+struct HostMesh {
+  int N = 0;                       // image side (power of two)
+  int levels = 0;                  // log2(N)
+  std::vector<int32_t> leaves;     // (L+1) x 4: x0, y0, level, first triangle;
+                                   // the extra row holds (0, 0, 0, T)
+  std::vector<int32_t> vxy;        // V x 2: x, y
+  std::vector<int32_t> tri;        // T x 3 vertex ids, positive orientation
+  std::vector<int32_t> vmap;       // V: free row (>= 0) or -(mask slot + 1)
+  std::vector<int32_t> free_vids;  // n
+  std::vector<int32_t> mask_vids;  // m
+  std::vector<int32_t> mask_pix;   // m: linear pixel index of each mask slot
+  std::vector<int32_t> vt_ptr;     // V+1: incident (triangle, corner) lists
+  std::vector<int32_t> vt_idx;     // 3T: 3 * triangle + corner, ascending
+  int max_incident = 0;            // largest incident-triangle count
+
+  int64_t L() const { return (int64_t)leaves.size() / 4 - 1; }
+  int64_t V() const { return (int64_t)vxy.size() / 2; }
+  int64_t T() const { return (int64_t)tri.size() / 3; }
+};
+
+// Builds the balanced quadtree mesh. Returns FI_OK or an error code (with
+// set_error). Checks: N power of two >= 2, mask strictly ascending in range.
+int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& out);
+
+// Incident triangles per vertex never exceed this on a 2:1 balanced quadtree
+// with centre fans (four leaves meet at a point, each gives at most two).
+constexpr int kMaxIncident = 8;
+
+// ----------------------------------------------------------- device mesh --
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  int64_t n = 0;
+};
+
+struct CGState {  // state of one fused-CG inner solver in precision T
+  void* x = nullptr;
+  void* p = nullptr;
+  void* r[2] = {nullptr, nullptr};
+  void* s[2] = {nullptr, nullptr};
+  void* q[2] = {nullptr, nullptr};
+};
+
+}  // namespace fi
+
+struct fi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+};
+
+struct fi_host_mesh {
+  fi::HostMesh mesh;
+};
+
+struct fi_mesh {
+  fi_ctx* ctx = nullptr;  // borrowed: the context outlives the mesh
+  int device = 0;         // copy of ctx->device, used on destruction
+  fi::HostMesh host;
+  int N = 0;
+  int64_t P = 0, V = 0, T = 0, L = 0, n = 0, m = 0;
+  int64_t nnz_off = 0;  // off-diagonal entries of K_FF
+  int64_t nnz_fd = 0;   // entries of K_FD
+  int64_t nnz_df = 0;   // entries of K_DF
+  int64_t device_bytes = 0;
+  std::vector<void*> allocations;
+
+  // geometry (device)
+  int32_t* d_vxy = nullptr;
+  int32_t* d_tri = nullptr;
+  int32_t* d_leaves = nullptr;
+  int32_t* d_vmap = nullptr;
+  int32_t* d_free_vids = nullptr;
+  int32_t* d_mask_vids = nullptr;
+  int32_t* d_mask_pix = nullptr;
+  int32_t* d_vt_ptr = nullptr;
+  int32_t* d_vt_idx = nullptr;
+
+  // matrices (device)
+  bool assembled_once = false;
+  int32_t* d_ff_rowptr = nullptr;  // off-diagonal part of K_FF
+  int32_t* d_ff_col = nullptr;
+  double* d_ff_val64 = nullptr;
+  float* d_ff_val32 = nullptr;
+  double* d_diag64 = nullptr;
+  double* d_dinv64 = nullptr;
+  float* d_dinv32 = nullptr;
+  int32_t* d_fd_rowptr = nullptr;
+  int32_t* d_fd_col = nullptr;
+  double* d_fd_val = nullptr;
+  int32_t* d_df_rowptr = nullptr;
+  int32_t* d_df_col = nullptr;
+  double* d_df_val = nullptr;
+  int32_t* d_cnt = nullptr;       // counts scratch (max(n, m) + 1)
+  int32_t* d_scan_tmp = nullptr;  // scan scratch
+
+  // solver workspace (device)
+  double* d_b64 = nullptr;
+  double* d_x64 = nullptr;
+  double* d_r64 = nullptr;
+  fi::CGState cg32, cg64;
+  double* d_part = nullptr;   // 2 x kMaxGrid x 4 partial sums
+  double* d_scal = nullptr;   // scalar slots of the fused CG kernel
+  int32_t* d_ctl = nullptr;   // control words: done flag, iterations, ...
+  double* d_red = nullptr;    // reduction scratch (kMaxGrid doubles)
+  double* d_red_out = nullptr;  // final reduced scalars (8 doubles)
+  double* h_red = nullptr;    // pinned host mirror of d_red_out / d_ctl
+  int32_t* h_ctl = nullptr;
+  int cg_grid = 0;            // blocks of the fused CG kernel
+
+  // pixel / vertex work vectors (device)
+  double* d_uvert = nullptr;  // V
+  double* d_g = nullptr;      // m (working copy of g)
+  double* d_tpart = nullptr;  // 3T adjoint partials
+  double* d_tF = nullptr;     // n
+  double* d_tD = nullptr;     // m
+  double* d_rpart = nullptr;  // raster partial sums (one per leaf block)
+
+  // tonal workspace (device, allocated on first use)
+  double* d_tg = nullptr;  // m: p
+  double* d_ts = nullptr;  // m: s
+  double* d_tr = nullptr;  // P: r
+  double* d_tq = nullptr;  // P: q
+
+  // top-k workspace (device, allocated on first use)
+  void* d_topk = nullptr;
+  int64_t topk_bytes = 0;
+};
+
+namespace fi {
+
+constexpr int kBlock = 256;      // threads per block of the vector kernels
+constexpr int kMaxGrid = 1024;   // cap on blocks of the fused CG kernel
+
+int device_alloc(fi_mesh* M, void** p, size_t bytes);
+
+// Kernel launchers (kernels.hip). All stream-ordered, no host sync.
+int launch_assemble_count(fi_mesh* M, bool free_rows);
+int launch_assemble_fill(fi_mesh* M, bool free_rows);
+int scan_counts(fi_mesh* M, const int32_t* cnt, int32_t* rowptr, int64_t n);
+// Exclusive prefix sum of n ints with caller scratch of scan_tmp_ints(n) ints.
+int scan_exclusive(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* tmp);
+int64_t scan_tmp_ints(int64_t n);
+int launch_lift(fi_mesh* M, const double* g, double* b);
+int launch_gather_mask(fi_mesh* M, const uint8_t* f, double* g);
+int launch_vertex_values(fi_mesh* M, const double* xF, const double* g, double* uvert);
+// Leaf-major interpolation / error pass. Pixel values come from u_in when
+// given, else from interpolating the vertex values uvert (NULL: zeros).
+int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uint8_t* f,
+                  double* u_out, double* e_out, double* tri_err_out, int32_t* owner_out,
+                  double* partial_out);
+int raster_blocks(const fi_mesh* M);
+int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart);
+int launch_gather_vertex(fi_mesh* M, const double* tpart, double* tF, double* tD);
+int launch_adjoint_tail(fi_mesh* M, const double* tD, const double* y, double* s);
+int launch_reduce(fi_mesh* M, const double* part, int nparts, int ncomp, double* out);
+int launch_dot(fi_mesh* M, const double* a, const double* b, int64_t n, double* out_dev);
+int launch_axpy(fi_mesh* M, int64_t n, double alpha, const double* x, double* y);
+int launch_xpby(fi_mesh* M, int64_t n, const double* x, double beta, double* y);
+int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r);
+
+// Solver pieces (solver.hip).
+int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats);
+int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms);
+int64_t cg_kernel_bytes(const fi_mesh* M, int precision);
+
+// Top-k (topk.hip).
+int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out);
+
+}  // namespace fi

@@ -1,0 +1,637 @@
+// HIP kernels for gfx950: stiffness assembly, Dirichlet lift, interpolation
+// to pixels with error measures, its transpose, and vector reductions.
+//
+// Assembly is vertex-centric: one thread owns one matrix row and visits the
+// triangles incident to its vertex, so rows are written without atomics and
+// the result is bitwise reproducible. Rasterisation is leaf-centric: one
+// thread owns one quadtree leaf, whose half-open box holds exactly its own
+// pixels, so per-triangle sums are private to the thread.
+#include <cstdint>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace fi {
+
+namespace {
+
+inline int grid_for(int64_t n, int per_block = kBlock) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (int)(g < 1 ? 1 : g);
+}
+
+// ------------------------------------------------------------ assembly ----
+// Row of the stiffness matrix at vertex v: K_vw = sum over triangles holding
+// v and w of (b_v b_w + c_v c_w) / (4A), with b_i = y_j - y_k, c_i = x_k - x_j
+// for (i, j, k) cyclic (Section 2.2, P1 elements). Returns the distinct
+// neighbours with non-zero weight, sorted by vertex id, and the diagonal.
+__device__ __forceinline__ int stiffness_row(int v, const int32_t* __restrict__ vxy,
+                                             const int32_t* __restrict__ tri,
+                                             const int32_t* __restrict__ vt_ptr,
+                                             const int32_t* __restrict__ vt_idx,
+                                             int32_t (&nb)[2 * kMaxIncident],
+                                             double (&w)[2 * kMaxIncident], double& diag) {
+  int cnt = 0;
+  double d = 0.0;
+  const int64_t xa = vxy[2 * v], ya = vxy[2 * v + 1];
+  const int e1 = vt_ptr[v + 1];
+  for (int e = vt_ptr[v]; e < e1; ++e) {
+    const int code = vt_idx[e];
+    const int t = code / 3;
+    const int k = code - 3 * t;
+    const int b = tri[3 * t + (k + 1) % 3];
+    const int c = tri[3 * t + (k + 2) % 3];
+    const int64_t xb = vxy[2 * b], yb = vxy[2 * b + 1];
+    const int64_t xc = vxy[2 * c], yc = vxy[2 * c + 1];
+    const int64_t ba = yb - yc, ca = xc - xb;
+    const int64_t bb = yc - ya, cb = xa - xc;
+    const int64_t bc = ya - yb, cc = xb - xa;
+    const int64_t twoA = (xb - xa) * (yc - ya) - (yb - ya) * (xc - xa);
+    const double inv = 1.0 / (2.0 * (double)twoA);
+    d += (double)(ba * ba + ca * ca) * inv;
+    const double wb = (double)(ba * bb + ca * cb) * inv;
+    const double wc = (double)(ba * bc + ca * cc) * inv;
+    int fb = -1, fc = -1;
+    for (int q = 0; q < cnt; ++q) {
+      if (nb[q] == b) fb = q;
+      if (nb[q] == c) fc = q;
+    }
+    if (fb >= 0) w[fb] += wb; else { nb[cnt] = b; w[cnt] = wb; ++cnt; }
+    if (fc >= 0) w[fc] += wc; else { nb[cnt] = c; w[cnt] = wc; ++cnt; }
+  }
+  // drop exact zeros (hypotenuse couplings), then insertion sort by id
+  int k2 = 0;
+  for (int q = 0; q < cnt; ++q) {
+    if (w[q] != 0.0) { nb[k2] = nb[q]; w[k2] = w[q]; ++k2; }
+  }
+  for (int q = 1; q < k2; ++q) {
+    const int32_t kn = nb[q];
+    const double kw = w[q];
+    int r = q - 1;
+    while (r >= 0 && nb[r] > kn) { nb[r + 1] = nb[r]; w[r + 1] = w[r]; --r; }
+    nb[r + 1] = kn;
+    w[r + 1] = kw;
+  }
+  diag = d;
+  return k2;
+}
+
+// Rows of the free vertices: count entries of K_FF (off-diagonal) and K_FD.
+__global__ __launch_bounds__(kBlock) void k_asm_free_count(
+    int n, const int32_t* __restrict__ free_vids, const int32_t* __restrict__ vxy,
+    const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_idx, const int32_t* __restrict__ vmap,
+    int32_t* __restrict__ cnt_ff, int32_t* __restrict__ cnt_fd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == n) { cnt_ff[n] = 0; cnt_fd[n] = 0; }
+  if (i >= n) return;
+  int32_t nb[2 * kMaxIncident];
+  double w[2 * kMaxIncident];
+  double d;
+  const int k = stiffness_row(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  int cf = 0, cd = 0;
+  for (int q = 0; q < k; ++q) {
+    if (vmap[nb[q]] >= 0) ++cf; else ++cd;
+  }
+  cnt_ff[i] = cf;
+  cnt_fd[i] = cd;
+}
+
+__global__ __launch_bounds__(kBlock) void k_asm_free_fill(
+    int n, const int32_t* __restrict__ free_vids, const int32_t* __restrict__ vxy,
+    const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_idx, const int32_t* __restrict__ vmap,
+    const int32_t* __restrict__ ff_ptr, int32_t* __restrict__ ff_col,
+    double* __restrict__ ff_val64, float* __restrict__ ff_val32,
+    const int32_t* __restrict__ fd_ptr, int32_t* __restrict__ fd_col,
+    double* __restrict__ fd_val, double* __restrict__ diag64, double* __restrict__ dinv64,
+    float* __restrict__ dinv32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t nb[2 * kMaxIncident];
+  double w[2 * kMaxIncident];
+  double d;
+  const int k = stiffness_row(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  int pf = ff_ptr[i], pd = fd_ptr[i];
+  for (int q = 0; q < k; ++q) {
+    const int32_t mv = vmap[nb[q]];
+    if (mv >= 0) {
+      ff_col[pf] = mv;
+      ff_val64[pf] = w[q];
+      ff_val32[pf] = (float)w[q];
+      ++pf;
+    } else {
+      fd_col[pd] = -mv - 1;
+      fd_val[pd] = w[q];
+      ++pd;
+    }
+  }
+  diag64[i] = d;
+  dinv64[i] = 1.0 / d;
+  dinv32[i] = (float)(1.0 / d);
+}
+
+// Rows of the mask vertices: K_DF (free columns only).
+__global__ __launch_bounds__(kBlock) void k_asm_mask_count(
+    int m, const int32_t* __restrict__ mask_vids, const int32_t* __restrict__ vxy,
+    const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_idx, const int32_t* __restrict__ vmap,
+    int32_t* __restrict__ cnt_df) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == m) cnt_df[m] = 0;
+  if (j >= m) return;
+  int32_t nb[2 * kMaxIncident];
+  double w[2 * kMaxIncident];
+  double d;
+  const int k = stiffness_row(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  int cf = 0;
+  for (int q = 0; q < k; ++q) cf += vmap[nb[q]] >= 0;
+  cnt_df[j] = cf;
+}
+
+__global__ __launch_bounds__(kBlock) void k_asm_mask_fill(
+    int m, const int32_t* __restrict__ mask_vids, const int32_t* __restrict__ vxy,
+    const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_idx, const int32_t* __restrict__ vmap,
+    const int32_t* __restrict__ df_ptr, int32_t* __restrict__ df_col,
+    double* __restrict__ df_val) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  int32_t nb[2 * kMaxIncident];
+  double w[2 * kMaxIncident];
+  double d;
+  const int k = stiffness_row(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  int p = df_ptr[j];
+  for (int q = 0; q < k; ++q) {
+    const int32_t mv = vmap[nb[q]];
+    if (mv >= 0) { df_col[p] = mv; df_val[p] = w[q]; ++p; }
+  }
+}
+
+// ---------------------------------------------------------------- scan ----
+// Exclusive prefix sum, 2048 items per block (256 threads x 8).
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ __launch_bounds__(kBlock) void k_scan_tile(const int32_t* __restrict__ in,
+                                                      int32_t* __restrict__ out, int64_t n,
+                                                      int32_t* __restrict__ tile_sums) {
+  __shared__ int32_t sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+  int32_t tsum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    tsum += v[k];
+  }
+  sh[threadIdx.x] = tsum;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int32_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int32_t run = sh[threadIdx.x] - tsum;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kBlock - 1) tile_sums[blockIdx.x] = sh[kBlock - 1];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(int32_t* __restrict__ out, int64_t n,
+                                                     const int32_t* __restrict__ offs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += offs[i / kScanTile];
+}
+
+int scan_rec(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* tmp) {
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  int32_t* sums = tmp;
+  int32_t* sums_scanned = tmp + tiles;
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)tiles), dim3(kBlock), 0, st, in, out, n, sums);
+  if (tiles > 1) {
+    int rc = scan_rec(st, sums, sums_scanned, tiles, tmp + 2 * tiles);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n)), dim3(kBlock), 0, st, out, n, sums_scanned);
+  }
+  FI_HIP_TRY(hipGetLastError());
+  return FI_OK;
+}
+
+// ------------------------------------------------------ lift and gathers --
+// b = -K_FD g (Section 2.2: mask values prescribed, moved to the right side).
+__global__ __launch_bounds__(kBlock) void k_lift(int n, const int32_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ g,
+                                                 double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = ptr[i]; j < ptr[i + 1]; ++j) acc += val[j] * g[col[j]];
+  b[i] = -acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_mask(int m, const int32_t* __restrict__ pix,
+                                                        const uint8_t* __restrict__ f,
+                                                        double* __restrict__ g) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) g[j] = (double)f[pix[j]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_vertex_values(int V, const int32_t* __restrict__ vmap,
+                                                          const double* __restrict__ xF,
+                                                          const double* __restrict__ g,
+                                                          double* __restrict__ uv) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int32_t mv = vmap[v];
+  uv[v] = mv >= 0 ? xF[mv] : g[-mv - 1];
+}
+
+// ------------------------------------------------------- rasterisation ----
+// Linear interpolation inside the owner triangle (Section 2.2). A pixel at
+// point (x, y) belongs to the leaf whose half-open box holds it, and to the
+// first triangle of that leaf (listing order) that contains it, boundary
+// included. Weights are orient(p, b, c) / orient(a, b, c) and cyclic; the
+// denominators are powers of two, so the weights are exact.
+constexpr int kMaxLeafTri = 8;
+
+struct LeafTris {
+  int nt;
+  int t0;
+  int ax[kMaxLeafTri], ay[kMaxLeafTri], bx[kMaxLeafTri], by[kMaxLeafTri], cx[kMaxLeafTri],
+      cy[kMaxLeafTri];
+  int va[kMaxLeafTri], vb[kMaxLeafTri], vc[kMaxLeafTri];
+  double inv[kMaxLeafTri];
+};
+
+__device__ __forceinline__ void load_leaf(const int32_t* __restrict__ leaves, int64_t i,
+                                          const int32_t* __restrict__ tri,
+                                          const int32_t* __restrict__ vxy, LeafTris& L) {
+  L.t0 = leaves[4 * i + 3];
+  L.nt = leaves[4 * i + 7] - L.t0;
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) {
+    if (k < L.nt) {
+      const int t = L.t0 + k;
+      L.va[k] = tri[3 * t];
+      L.vb[k] = tri[3 * t + 1];
+      L.vc[k] = tri[3 * t + 2];
+      L.ax[k] = vxy[2 * L.va[k]]; L.ay[k] = vxy[2 * L.va[k] + 1];
+      L.bx[k] = vxy[2 * L.vb[k]]; L.by[k] = vxy[2 * L.vb[k] + 1];
+      L.cx[k] = vxy[2 * L.vc[k]]; L.cy[k] = vxy[2 * L.vc[k] + 1];
+      const int den = (L.bx[k] - L.ax[k]) * (L.cy[k] - L.ay[k]) - (L.by[k] - L.ay[k]) * (L.cx[k] - L.ax[k]);
+      L.inv[k] = 1.0 / (double)den;
+    }
+  }
+}
+
+// orientation numerators of point (x, y) against triangle k; owner is the
+// first k with all three >= 0
+__device__ __forceinline__ int locate(const LeafTris& L, int x, int y, int& oa, int& ob, int& oc) {
+  int own = -1;
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) {
+    if (own < 0 && k < L.nt) {
+      const int a = (L.bx[k] - x) * (L.cy[k] - y) - (L.by[k] - y) * (L.cx[k] - x);
+      const int b = (L.cx[k] - x) * (L.ay[k] - y) - (L.cy[k] - y) * (L.ax[k] - x);
+      const int c = (L.ax[k] - x) * (L.by[k] - y) - (L.ay[k] - y) * (L.bx[k] - x);
+      if (a >= 0 && b >= 0 && c >= 0) { own = k; oa = a; ob = b; oc = c; }
+    }
+  }
+  return own;
+}
+
+__global__ __launch_bounds__(kBlock) void k_raster(
+    int64_t nleaves, int N, const int32_t* __restrict__ leaves, const int32_t* __restrict__ tri,
+    const int32_t* __restrict__ vxy, const double* __restrict__ uv, const double* __restrict__ u_in,
+    const uint8_t* __restrict__ f, double* __restrict__ u_out, double* __restrict__ e_out, double* __restrict__ tri_err,
+    int32_t* __restrict__ owner_out, double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < nleaves) {
+    LeafTris L;
+    load_leaf(leaves, i, tri, vxy, L);
+    double ua[kMaxLeafTri], ub[kMaxLeafTri], uc[kMaxLeafTri], E[kMaxLeafTri];
+#pragma unroll
+    for (int k = 0; k < kMaxLeafTri; ++k) {
+      E[k] = 0.0;
+      if (k < L.nt && uv) { ua[k] = uv[L.va[k]]; ub[k] = uv[L.vb[k]]; uc[k] = uv[L.vc[k]]; }
+      else { ua[k] = ub[k] = uc[k] = 0.0; }
+    }
+    const int x0 = leaves[4 * i], y0 = leaves[4 * i + 1];
+    const int s = 1 << leaves[4 * i + 2];
+    for (int dy = 0; dy < s; ++dy) {
+      for (int dx = 0; dx < s; ++dx) {
+        const int x = x0 + dx, y = y0 + dy;
+        int oa = 0, ob = 0, oc = 0;
+        const int own = locate(L, x, y, oa, ob, oc);
+        double u = 0.0, ia = 0.0;
+        int tk = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxLeafTri; ++k) {
+          if (k == own) {
+            ia = L.inv[k];
+            u = ((double)oa * ia) * ua[k] + ((double)ob * ia) * ub[k] + ((double)oc * ia) * uc[k];
+            tk = k;
+          }
+        }
+        const int64_t pix = (int64_t)y * N + x;
+        if (u_in) u = u_in[pix];
+        if (u_out) u_out[pix] = u;
+        if (owner_out) owner_out[pix] = L.t0 + tk;
+        if (f) {
+          const double dlt = u - (double)f[pix];
+          const double e = dlt * dlt;
+          if (e_out) e_out[pix] = e;
+          acc[0] += e;
+#pragma unroll
+          for (int k = 0; k < kMaxLeafTri; ++k)
+            if (k == tk) E[k] += e;
+        }
+      }
+    }
+    if (f && tri_err) {
+#pragma unroll
+      for (int k = 0; k < kMaxLeafTri; ++k)
+        if (k < L.nt) tri_err[L.t0 + k] = E[k];
+    }
+  }
+  block_sum<1>(acc, lds);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+}
+
+// Transposed interpolation: per triangle and corner, sum over the pixels the
+// triangle owns of weight * r (t = R^T r before the per-vertex gather).
+__global__ __launch_bounds__(kBlock) void k_raster_T(int64_t nleaves, int N,
+                                                     const int32_t* __restrict__ leaves,
+                                                     const int32_t* __restrict__ tri,
+                                                     const int32_t* __restrict__ vxy,
+                                                     const double* __restrict__ r,
+                                                     double* __restrict__ tpart) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nleaves) return;
+  LeafTris L;
+  load_leaf(leaves, i, tri, vxy, L);
+  double Sa[kMaxLeafTri], Sb[kMaxLeafTri], Sc[kMaxLeafTri];
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) Sa[k] = Sb[k] = Sc[k] = 0.0;
+  const int x0 = leaves[4 * i], y0 = leaves[4 * i + 1];
+  const int s = 1 << leaves[4 * i + 2];
+  for (int dy = 0; dy < s; ++dy) {
+    for (int dx = 0; dx < s; ++dx) {
+      const int x = x0 + dx, y = y0 + dy;
+      int oa = 0, ob = 0, oc = 0;
+      const int own = locate(L, x, y, oa, ob, oc);
+      const double rv = r[(int64_t)y * N + x];
+#pragma unroll
+      for (int k = 0; k < kMaxLeafTri; ++k) {
+        if (k == own) {
+          const double ia = L.inv[k];
+          Sa[k] += ((double)oa * ia) * rv;
+          Sb[k] += ((double)ob * ia) * rv;
+          Sc[k] += ((double)oc * ia) * rv;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) {
+    if (k < L.nt) {
+      const int64_t t = L.t0 + k;
+      tpart[3 * t] = Sa[k];
+      tpart[3 * t + 1] = Sb[k];
+      tpart[3 * t + 2] = Sc[k];
+    }
+  }
+}
+
+// t_v = sum over (triangle, corner) pairs at v of the partial sums, in the
+// fixed ascending order of the adjacency list; split into free and mask parts.
+__global__ __launch_bounds__(kBlock) void k_gather_vertex(int V, const int32_t* __restrict__ vt_ptr,
+                                                          const int32_t* __restrict__ vt_idx,
+                                                          const int32_t* __restrict__ vmap,
+                                                          const double* __restrict__ tpart,
+                                                          double* __restrict__ tF,
+                                                          double* __restrict__ tD) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  double acc = 0.0;
+  for (int e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) acc += tpart[vt_idx[e]];
+  const int32_t mv = vmap[v];
+  if (mv >= 0) tF[mv] = acc; else tD[-mv - 1] = acc;
+}
+
+// s = t_D - K_DF y
+__global__ __launch_bounds__(kBlock) void k_adjoint_tail(int m, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ tD,
+                                                         const double* __restrict__ y,
+                                                         double* __restrict__ s) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double acc = 0.0;
+  for (int q = ptr[j]; q < ptr[j + 1]; ++q) acc += val[q] * y[col[q]];
+  s[j] = tD[j] - acc;
+}
+
+// ------------------------------------------------------ vector kernels ----
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, int nparts,
+                                                   int ncomp, double* __restrict__ out) {
+  __shared__ double lds[4];
+  for (int c = 0; c < ncomp; ++c) {
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j < nparts; j += kBlock) v[0] += part[(int64_t)j * ncomp + c];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[c] = v[0];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_part(const double* __restrict__ a,
+                                                     const double* __restrict__ b, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double lds[4];
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    v[0] += a[i] * b[i];
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, double alpha,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] += alpha * x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_xpby(int64_t n, const double* __restrict__ x,
+                                                 double beta, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = x[i] + beta * y[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pixel_residual(int64_t P, const uint8_t* __restrict__ f,
+                                                           const double* __restrict__ u,
+                                                           double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < P) r[i] = (double)f[i] - u[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers ----
+#define FI_LAUNCH_CHECK() FI_HIP_TRY(hipGetLastError())
+
+int launch_assemble_count(fi_mesh* M, bool free_rows) {
+  hipStream_t st = M->ctx->stream;
+  if (free_rows) {
+    hipLaunchKernelGGL(k_asm_free_count, dim3(grid_for(M->n + 1)), dim3(kBlock), 0, st, (int)M->n,
+                       M->d_free_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
+                       M->d_cnt, M->d_cnt + (M->n + 1));
+  } else {
+    hipLaunchKernelGGL(k_asm_mask_count, dim3(grid_for(M->m + 1)), dim3(kBlock), 0, st, (int)M->m,
+                       M->d_mask_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
+                       M->d_cnt);
+  }
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_assemble_fill(fi_mesh* M, bool free_rows) {
+  hipStream_t st = M->ctx->stream;
+  if (free_rows) {
+    hipLaunchKernelGGL(k_asm_free_fill, dim3(grid_for(M->n)), dim3(kBlock), 0, st, (int)M->n,
+                       M->d_free_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
+                       M->d_ff_rowptr, M->d_ff_col, M->d_ff_val64, M->d_ff_val32, M->d_fd_rowptr,
+                       M->d_fd_col, M->d_fd_val, M->d_diag64, M->d_dinv64, M->d_dinv32);
+  } else {
+    hipLaunchKernelGGL(k_asm_mask_fill, dim3(grid_for(M->m)), dim3(kBlock), 0, st, (int)M->m,
+                       M->d_mask_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
+                       M->d_df_rowptr, M->d_df_col, M->d_df_val);
+  }
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int scan_counts(fi_mesh* M, const int32_t* cnt, int32_t* rowptr, int64_t n_plus_1) {
+  return scan_rec(M->ctx->stream, cnt, rowptr, n_plus_1, M->d_scan_tmp);
+}
+
+int scan_exclusive(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* tmp) {
+  return scan_rec(st, in, out, n, tmp);
+}
+
+int64_t scan_tmp_ints(int64_t n) {
+  int64_t total = 0, t = n;
+  for (;;) {
+    t = (t + kScanTile - 1) / kScanTile;
+    total += 2 * t + 2;
+    if (t <= 1) break;
+  }
+  return total + 16;
+}
+
+int launch_lift(fi_mesh* M, const double* g, double* b) {
+  if (M->n == 0) return FI_OK;
+  hipLaunchKernelGGL(k_lift, dim3(grid_for(M->n)), dim3(kBlock), 0, M->ctx->stream, (int)M->n,
+                     M->d_fd_rowptr, M->d_fd_col, M->d_fd_val, g, b);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_gather_mask(fi_mesh* M, const uint8_t* f, double* g) {
+  hipLaunchKernelGGL(k_gather_mask, dim3(grid_for(M->m)), dim3(kBlock), 0, M->ctx->stream,
+                     (int)M->m, M->d_mask_pix, f, g);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_vertex_values(fi_mesh* M, const double* xF, const double* g, double* uvert) {
+  hipLaunchKernelGGL(k_vertex_values, dim3(grid_for(M->V)), dim3(kBlock), 0, M->ctx->stream,
+                     (int)M->V, M->d_vmap, xF, g, uvert);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uint8_t* f,
+                  double* u_out, double* e_out, double* tri_err_out, int32_t* owner_out,
+                  double* partial_out) {
+  hipLaunchKernelGGL(k_raster, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L, M->N,
+                     M->d_leaves, M->d_tri, M->d_vxy, uvert, u_in, f, u_out, e_out, tri_err_out,
+                     owner_out, partial_out);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart) {
+  hipLaunchKernelGGL(k_raster_T, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L,
+                     M->N, M->d_leaves, M->d_tri, M->d_vxy, r, tpart);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_gather_vertex(fi_mesh* M, const double* tpart, double* tF, double* tD) {
+  hipLaunchKernelGGL(k_gather_vertex, dim3(grid_for(M->V)), dim3(kBlock), 0, M->ctx->stream,
+                     (int)M->V, M->d_vt_ptr, M->d_vt_idx, M->d_vmap, tpart, tF, tD);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_adjoint_tail(fi_mesh* M, const double* tD, const double* y, double* s) {
+  hipLaunchKernelGGL(k_adjoint_tail, dim3(grid_for(M->m)), dim3(kBlock), 0, M->ctx->stream,
+                     (int)M->m, M->d_df_rowptr, M->d_df_col, M->d_df_val, tD, y, s);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_reduce(fi_mesh* M, const double* part, int nparts, int ncomp, double* out) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, M->ctx->stream, part, nparts, ncomp, out);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_dot(fi_mesh* M, const double* a, const double* b, int64_t n, double* out_dev) {
+  int g = grid_for(n);
+  if (g > kMaxGrid) g = kMaxGrid;
+  hipLaunchKernelGGL(k_dot_part, dim3(g), dim3(kBlock), 0, M->ctx->stream, a, b, n, M->d_red);
+  FI_LAUNCH_CHECK();
+  return launch_reduce(M, M->d_red, g, 1, out_dev);
+}
+
+int launch_axpy(fi_mesh* M, int64_t n, double alpha, const double* x, double* y) {
+  if (n == 0) return FI_OK;
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, alpha, x, y);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_xpby(fi_mesh* M, int64_t n, const double* x, double beta, double* y) {
+  if (n == 0) return FI_OK;
+  hipLaunchKernelGGL(k_xpby, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, x, beta, y);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r) {
+  hipLaunchKernelGGL(k_pixel_residual, dim3(grid_for(M->P)), dim3(kBlock), 0, M->ctx->stream,
+                     M->P, f, u, r);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+}  // namespace fi
+
+namespace fi {
+int raster_blocks(const fi_mesh* M) {
+  const int64_t g = (M->L + kBlock - 1) / kBlock;
+  return (int)(g < 1 ? 1 : g);
+}
+}  // namespace fi

@@ -1,0 +1,95 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and its host-side mesh builder matches the oracle bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2105_01586_amd as fi
+import synth
+from oracle import mesh as om
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(fi_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fi.library()
+    decl = declared_symbols()
+    assert len(decl) >= 20
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(fi.EXPORTED_SYMBOLS)
+
+
+def test_version_and_defaults():
+    lib = fi.library()
+    assert b"gfx950" in lib.fi_version()
+    o = fi._SolveOpts()
+    lib.fi_solve_opts_default(o)
+    assert o.rtol == 1e-10 and o.precision == fi.PREC_FP32_IR
+    t = fi._TonalOpts()
+    lib.fi_tonal_opts_default(t)
+    assert t.rtol == 1e-8 and t.inner.rtol == 1e-10
+
+
+def rand_mask(N, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(N * N, size=k, replace=False))
+
+
+CASES = [(2, 1, 0), (2, 4, 1), (4, 1, 2), (8, 3, 3), (16, 10, 4), (32, 1, 5), (64, 205, 6),
+         (128, 655, 7), (256, 2621, 8)]
+
+
+@pytest.mark.parametrize("N,k,seed", CASES)
+def test_host_mesh_bit_exact(N, k, seed):
+    m = rand_mask(N, k, seed)
+    h = fi.host_mesh(N, m)
+    o = om.build_mesh(N, m)
+    assert np.array_equal(h["leaves"], o.leaves)
+    assert np.array_equal(h["vxy"], o.vxy)
+    assert np.array_equal(h["tri"], o.tri)
+    assert np.array_equal(h["free_vids"], o.free_vids)
+    assert np.array_equal(h["mask_vids"], o.mask_vids)
+
+
+def test_host_mesh_workload_512():
+    w = synth.WORKLOADS["tonal512"]
+    m = w.mask()
+    h = fi.host_mesh(w.side, m)
+    o = om.build_mesh(w.side, m)
+    assert np.array_equal(h["tri"], o.tri) and np.array_equal(h["vxy"], o.vxy)
+
+
+def test_host_mesh_full_and_edge_masks():
+    N = 16
+    for m in (np.arange(N * N), np.array([0]), np.array([N * N - 1]), np.array([N - 1, N * (N - 1)])):
+        h = fi.host_mesh(N, m)
+        o = om.build_mesh(N, m)
+        assert np.array_equal(h["tri"], o.tri)
+
+
+@pytest.mark.parametrize("side,mask,code", [
+    (16, [], fi.E_EMPTY_MASK),
+    (16, [3, 3], fi.E_INVALID),
+    (16, [5, 2], fi.E_INVALID),
+    (16, [256], fi.E_INVALID),
+    (16, [-1], fi.E_INVALID),
+    (12, [1], fi.E_INVALID),
+    (1, [0], fi.E_INVALID),
+])
+def test_host_mesh_errors(side, mask, code):
+    with pytest.raises(fi.FIError) as ei:
+        fi.host_mesh(side, mask)
+    assert ei.value.code == code

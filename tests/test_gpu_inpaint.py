@@ -1,0 +1,158 @@
+"""GPU parity of the inpainting path against the FP64 oracle.
+
+Integer work (mesh, CSR pattern, 2K values, owner triangles) must match
+bit for bit; inpainted pixels within 1e-6 absolute on the 0-255 scale in both
+FP32+refinement and plain FP64 modes; error measures within rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2105_01586_amd as fi
+from gpu_common import SMALL_CASES, case, oracle_inpaint, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+NAMES = [c[0] for c in SMALL_CASES] + ["c2"]
+PIX_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fi.Context(0)
+    yield c
+    c.close()
+
+
+_meshes = {}
+
+
+def gpu_mesh(ctx, name):
+    if name not in _meshes:
+        side, mask, _ = case(name)
+        _meshes[name] = fi.Mesh(ctx, side, mask)
+    return _meshes[name]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_geometry_and_matrices_bit_exact(ctx, name):
+    print(f"case {name}", flush=True)
+    M = gpu_mesh(ctx, name)
+    pr = oracle_problem(name)
+    g = M.export_geometry()
+    assert np.array_equal(g["vxy"], pr.mesh.vxy)
+    assert np.array_equal(g["tri"], pr.mesh.tri)
+    assert np.array_equal(g["leaves"], pr.mesh.leaves)
+    c = M.export_csr()
+    K = pr.sys.K_FF
+    assert np.array_equal(c["ff_rowptr"], K.indptr)
+    assert np.array_equal(c["ff_col"], K.indices)
+    assert np.array_equal(c["ff_val"], K.data)          # exact dyadic values
+    assert np.array_equal((2 * c["ff_val"]).astype(np.int64), 2 * K.data)
+    KD = pr.sys.K_FD
+    assert np.array_equal(c["fd_rowptr"], KD.indptr)
+    assert np.array_equal(c["fd_col"], KD.indices)
+    assert np.array_equal(c["fd_val"], KD.data)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_owner_map_bit_exact(ctx, name):
+    print(f"case {name}", flush=True)
+    M = gpu_mesh(ctx, name)
+    own = M.owner_map().cpu().numpy()
+    assert np.array_equal(own, oracle_problem(name).rast.owner)
+
+
+@pytest.mark.parametrize("precision", [fi.PREC_FP32_IR, fi.PREC_FP64])
+@pytest.mark.parametrize("name", NAMES)
+def test_inpaint_parity(ctx, name, precision):
+    print(f"case {name} precision {precision}", flush=True)
+    M = gpu_mesh(ctx, name)
+    _, _, f = case(name)
+    u, st = M.inpaint(f=dev(f), opts=fi.SolveOpts(precision=precision))
+    u = u.cpu().numpy()
+    ref = oracle_inpaint(name)
+    err = np.max(np.abs(u - ref))
+    print(f"  max abs err {err:.3e}, iters {st['iterations']}, refinements {st['refinements']}, "
+          f"rel residual {st['rel_residual']:.3e}")
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-10
+    assert err <= PIX_TOL
+    # mask pixels carry g exactly
+    _, mask, _ = case(name)
+    assert np.array_equal(u[mask], f[mask].astype(np.float64))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_error_measures(ctx, name):
+    print(f"case {name}", flush=True)
+    M = gpu_mesh(ctx, name)
+    _, _, f = case(name)
+    pr = oracle_problem(name)
+    ref = oracle_inpaint(name)
+    u = dev(ref)   # same pixels on both sides: compare the error kernels alone
+    mse, e, E = M.error(u, dev(f), pixel=True, triangle=True)
+    e_ref = (ref - f.astype(np.float64)) ** 2
+    assert np.array_equal(e.cpu().numpy(), e_ref)
+    E_ref = pr.triangle_error(ref, f)
+    assert np.allclose(E.cpu().numpy(), E_ref, rtol=1e-12, atol=1e-12)
+    mse_ref = pr.mse(ref, f)
+    assert abs(mse - mse_ref) <= 1e-12 * max(mse_ref, 1e-300) + 1e-300
+
+
+def test_determinism(ctx):
+    M = gpu_mesh(ctx, "c2")
+    _, _, f = case("c2")
+    u1, _ = M.inpaint(f=dev(f))
+    u2, _ = M.inpaint(f=dev(f))
+    assert torch.equal(u1, u2)
+    m1 = M.error(u1, dev(f))[0]
+    m2 = M.error(u2, dev(f))[0]
+    assert m1 == m2
+
+
+def test_given_g_and_constant(ctx):
+    M = gpu_mesh(ctx, "n256_k2000")
+    g = torch.full((M.m,), 77.5, dtype=torch.float64, device="cuda:0")
+    u, _ = M.inpaint(g=g)
+    # constants are harmonic: exact up to the solve tolerance
+    assert torch.max(torch.abs(u - 77.5)).item() <= PIX_TOL
+    pr = oracle_problem("n256_k2000")
+    rng = np.random.default_rng(3)
+    gv = rng.uniform(-100, 300, size=M.m)
+    u, _ = M.inpaint(g=dev(gv))
+    assert np.max(np.abs(u.cpu().numpy() - pr.B(gv))) <= PIX_TOL
+
+
+def test_reassemble_is_identical(ctx):
+    M = gpu_mesh(ctx, "n128_k300")
+    before = M.export_csr()
+    M.assemble()
+    after = M.export_csr()
+    for k in before:
+        assert np.array_equal(before[k], after[k])
+
+
+def test_error_paths(ctx):
+    with pytest.raises(fi.FIError) as ei:
+        fi.Mesh(ctx, 16, [])
+    assert ei.value.code == fi.E_EMPTY_MASK
+    with pytest.raises(fi.FIError) as ei:
+        fi.Mesh(ctx, 16, [9, 3])
+    assert ei.value.code == fi.E_INVALID
+    M = gpu_mesh(ctx, "n16_k7")
+    g = torch.zeros(M.m, dtype=torch.float64, device="cuda:0")
+    g[0] = float("nan")
+    with pytest.raises(fi.FIError) as ei:
+        M.inpaint(g=g)
+    assert ei.value.code == fi.E_INVALID
+    with pytest.raises(ValueError):
+        M.inpaint(g=torch.zeros(M.m + 1, dtype=torch.float64, device="cuda:0"))
+    # iteration cap forced from the host: one CG iteration, one refinement
+    Mc = gpu_mesh(ctx, "c2")
+    _, _, f = case("c2")
+    with pytest.raises(fi.NoConvergence):
+        Mc.inpaint(f=dev(f), opts=fi.SolveOpts(max_inner=1, max_refine=1))

@@ -1,0 +1,121 @@
+"""GPU parity of the adjoint, the autograd gradient and tonal optimisation.
+
+Adjoint B^T r against the oracle (relative 1e-8) and the dot-product
+identity; d(MSE)/dg from autograd against the oracle gradient and central
+finite differences on 16 random mask coordinates (eps = 1e-3); tonal MSE
+within 1e-6 relative of the oracle's least-squares optimum, whose normal
+residual the GPU result also drives near zero.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2105_01586_amd as fi
+from paper_2105_01586_amd import autograd as fa
+from gpu_common import case, oracle_problem, oracle_tonal
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fi.Context(0)
+    yield c
+    c.close()
+
+
+_meshes = {}
+
+
+def gpu_mesh(ctx, name):
+    if name not in _meshes:
+        side, mask, _ = case(name)
+        _meshes[name] = fi.Mesh(ctx, side, mask)
+    return _meshes[name]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("precision", [fi.PREC_FP32_IR, fi.PREC_FP64])
+@pytest.mark.parametrize("name", ["n16_k7", "n64_c1", "n256_k2000", "c2"])
+def test_adjoint_parity(ctx, name, precision):
+    print(f"case {name} precision {precision}", flush=True)
+    M = gpu_mesh(ctx, name)
+    pr = oracle_problem(name)
+    rng = np.random.default_rng(5)
+    r = rng.normal(size=M.P)
+    s, st = M.adjoint(dev(r), opts=fi.SolveOpts(precision=precision))
+    s = s.cpu().numpy()
+    ref = pr.BT(r)
+    rel = np.linalg.norm(s - ref) / np.linalg.norm(ref)
+    print(f"  rel err {rel:.3e}, iters {st['iterations']}")
+    assert rel <= 1e-8
+    g = rng.normal(size=M.m)
+    u, _ = M.inpaint(g=dev(g), opts=fi.SolveOpts(precision=precision))
+    lhs = float(u.cpu().numpy() @ r)
+    rhs = float(g @ s)
+    assert abs(lhs - rhs) <= 1e-8 * (np.linalg.norm(g) * np.linalg.norm(r))
+
+
+@pytest.mark.parametrize("name", ["n64_c1", "c2"])
+def test_autograd_gradient_and_fd(ctx, name):
+    print(f"case {name}", flush=True)
+    M = gpu_mesh(ctx, name)
+    pr = oracle_problem(name)
+    _, _, f = case(name)
+    rng = np.random.default_rng(7)
+    g0 = pr.default_g(f) + rng.normal(scale=2.0, size=M.m)
+    g = dev(g0).requires_grad_(True)
+    fd_t = dev(f)
+    loss = fa.mse_loss(g, fd_t, M)
+    loss.backward()
+    grad = g.grad.cpu().numpy()
+    ref = pr.mse_grad(g0, f)
+    rel = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
+    print(f"  gradient rel err vs oracle {rel:.3e}")
+    assert rel <= 1e-8
+    # The MSE is quadratic in g, so central differences carry no truncation
+    # error: what is left is the rounding of the two losses and the error of
+    # their solves, divided by 2 eps. The losses are solved tightly (1e-12).
+    eps = 1e-3
+    tight = fi.SolveOpts(rtol=1e-12)
+    scale = np.max(np.abs(grad))
+    worst = 0.0
+    for j in rng.integers(0, M.m, size=16):
+        gp = g0.copy()
+        gm = g0.copy()
+        gp[j] += eps
+        gm[j] -= eps
+        with torch.no_grad():
+            lp = fa.mse_loss(dev(gp), fd_t, M, tight).item()
+            lm = fa.mse_loss(dev(gm), fd_t, M, tight).item()
+        fd = (lp - lm) / (2 * eps)
+        dev_j = abs(fd - grad[j])
+        worst = max(worst, dev_j / (abs(grad[j]) + 1e-3 * scale))
+        assert dev_j <= 1e-4 * abs(grad[j]) + 1e-6 * scale, (j, fd, grad[j])
+    print(f"  worst FD deviation (relative) {worst:.3e}")
+
+
+@pytest.mark.parametrize("precision", [fi.PREC_FP32_IR, fi.PREC_FP64])
+@pytest.mark.parametrize("name", ["n16_k7", "n64_c1", "n256_k2000", "c2"])
+def test_tonal_parity(ctx, name, precision):
+    print(f"case {name} precision {precision}", flush=True)
+    M = gpu_mesh(ctx, name)
+    pr = oracle_problem(name)
+    _, _, f = case(name)
+    g, st = M.tonal_opt(dev(f), opts=fi.TonalOpts(inner=fi.SolveOpts(precision=precision)))
+    g = g.cpu().numpy()
+    g_ref, it_ref, _ = oracle_tonal(name)
+    mse_gpu_by_oracle = pr.mse_of_g(g, f)
+    mse_ref = pr.mse_of_g(g_ref, f)
+    mse0 = pr.mse_of_g(pr.default_g(f), f)
+    print(f"  outer {st['outer_iterations']} (oracle {it_ref}), inner {st['inner_iterations']}, "
+          f"mse {st['mse_final']:.9f} oracle {mse_ref:.9f} (untuned {mse0:.6f})")
+    assert st["status"] == 0 and st["rel_normal_residual"] <= 1e-8
+    assert abs(st["mse_final"] - mse_ref) <= 1e-6 * mse_ref
+    assert abs(mse_gpu_by_oracle - mse_ref) <= 1e-6 * mse_ref
+    assert mse_ref <= mse0 + 1e-12 and st["mse_final"] <= st["mse_initial"]
+    s0 = np.linalg.norm(pr.normal_residual(pr.default_g(f), f))
+    assert np.linalg.norm(pr.normal_residual(g, f)) <= 1e-6 * s0
