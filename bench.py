@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one 256 MiB device-to-device copy (a kernel of known "
+                         "traffic, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -75,6 +78,12 @@ def main():
     import paper_2105_01586_amd as fi
     import synth
 
+    if args.copy_calibration:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = synth.WORKLOADS[args.workload]
     f_np = w.image()
     mask = w.mask()
