@@ -57,6 +57,8 @@ void free_mesh(fi_mesh* M) {
   // hipFree waits for outstanding work on the device; the context (and its
   // stream) may already be gone, so only the device id is used here.
   (void)hipSetDevice(M->device);
+  (void)hipDeviceSynchronize();
+  solver_release(M);
   for (void* p : M->allocations) (void)hipFree(p);
   if (M->h_red) (void)hipHostFree(M->h_red);
   if (M->h_ctl) (void)hipHostFree(M->h_ctl);
@@ -76,7 +78,9 @@ int alloc_workspace(fi_mesh* M) {
   TRY(alloc_n(M, &M->d_dinv64, n));
   TRY(alloc_n(M, &M->d_dinv32, n));
   TRY(alloc_n(M, &M->d_b64, n));
-  TRY(alloc_n(M, &M->d_x64, n));
+  TRY(alloc_n(M, &M->d_x64buf[0], n));
+  TRY(alloc_n(M, &M->d_x64buf[1], n));
+  M->d_x64 = M->d_x64buf[0];
   TRY(alloc_n(M, &M->d_r64, n));
   float* f32[8];
   double* f64[8];
@@ -384,6 +388,7 @@ int fi_assemble(fi_mesh* M) {
       return rc;
   }
   if ((rc = launch_assemble_fill(M, false))) return rc;
+  if ((rc = solver_setup(M))) return rc;
   if (!M->assembled_once) FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
   M->assembled_once = true;
   return FI_OK;

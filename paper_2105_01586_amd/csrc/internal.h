@@ -122,8 +122,11 @@ struct fi_mesh {
 
   // solver workspace (device)
   double* d_b64 = nullptr;
-  double* d_x64 = nullptr;
+  double* d_x64 = nullptr;        // the last solve's result (one of d_x64buf)
+  double* d_x64buf[2] = {nullptr, nullptr};
   double* d_r64 = nullptr;
+  void* d_rec = nullptr;          // solver state records, two by launch parity
+  void* h_rec = nullptr;          // pinned ring of two record copies
   fi::CGState cg32, cg64;
   double* d_part = nullptr;   // 2 x kMaxGrid x 4 partial sums
   double* d_scal = nullptr;   // scalar slots of the fused CG kernel
@@ -133,6 +136,22 @@ struct fi_mesh {
   double* h_red = nullptr;    // pinned host mirror of d_red_out / d_ctl
   int32_t* h_ctl = nullptr;
   int cg_grid = 0;            // blocks of the fused CG kernel
+  int cg_bs = 512;            // threads per block of the fused CG kernel
+  // ELL copy of the off-diagonal part of K_FF, column-major by row: slot k of
+  // row i at d_ell[k * n_pad + i]; each entry is the column (bits 0-29), bit
+  // 30 for an empty slot (weight 0, column = the row), bit 31 for weight -1
+  // (clear: -1/2). ell_w == 0: CSR is used.
+  int32_t* d_ell = nullptr;
+  int ell_w = 0;
+  int64_t n_pad = 0;
+  bool large_mode = false;    // n too large for in-kernel partial re-reduction
+  double* d_red4 = nullptr;   // reduced partial sums (large mode)
+  double* d_prm = nullptr;    // inner-solve parameters read by the CG kernels
+  int32_t* d_flag = nullptr;  // packing flags
+  hipEvent_t ring_ev[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // [0] FP32, [1] FP64
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  int graph_chunk = 0;
 
   // pixel / vertex work vectors (device)
   double* d_uvert = nullptr;  // V
@@ -186,6 +205,9 @@ int launch_xpby(fi_mesh* M, int64_t n, const double* x, double beta, double* y);
 int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r);
 
 // Solver pieces (solver.hip).
+constexpr int kMaxEll = 8;
+int solver_setup(fi_mesh* M);      // after assembly: ELL packing, mode, graphs reset
+void solver_release(fi_mesh* M);   // graphs and events
 int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats);
 int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms);
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision);

@@ -1,25 +1,49 @@
-// Jacobi-preconditioned CG for K_FF x = b with FP64 iterative refinement.
+// Jacobi-preconditioned CG for K_FF x = b with FP64 iterative refinement,
+// driven by the device.
 //
-// Section 2.2 solves the SPD FEM system with conjugate gradients. Here each
-// CG iteration is ONE kernel launch: the Chronopoulos-Gear form of PCG needs
-// a single global reduction per iteration (the dots (r, z), (z, A z) and
-// (r, r) are taken together), and the next iteration's SpMV input is
-// recomputed on the fly from the previous vectors, so one launch covers
-//     p = z + beta p,   q = s + beta q,   x += alpha p,   r -= alpha q,
-//     z = D^-1 r,       s = A z,          partial dots of the new state.
-// r, s and q are double-buffered because neighbours read the old values
-// while their owners write the new ones; x and p are only touched by their
-// owner. Every block reduces the previous kernel's per-block partial sums
-// itself, in a fixed order, so no atomics and no extra reduction launch are
-// needed, and results are reproducible bit for bit.
+// Section 2.2 solves the SPD FEM system with conjugate gradients. The whole
+// solve is a sequence of launches of ONE "step" kernel; each launch reads a
+// small state record, does the work of the current phase, and writes the
+// next record:
+//   INIT  start an inner solve: r0 = r64 / ||r64||, s0 = A D^-1 r0, or stop
+//         the solve when ||r64|| <= rtol ||b|| (or on stagnation / cap);
+//   ITER  one Jacobi-PCG iteration in the Chronopoulos-Gear form: a single
+//         global reduction per iteration (the dots (r, z), (z, A z), (r, r)
+//         together), the next SpMV input recomputed from the previous
+//         vectors, so one launch covers
+//            p = z + beta p,  q = s + beta q,  x += alpha p,  r -= alpha q,
+//            z = D^-1 r,      s = A z,         partial dots of the new state;
+//         when the inner solve has converged the same launch instead adds
+//         the correction in FP64 and forms the FP64 residual b - K x;
+//   DONE  nothing.
+// Every per-launch quantity (state record, partial sums, r, s, q) is double
+// buffered by launch parity: launch k reads slot k % 2 and writes the other,
+// so blocks of one launch never see each other's writes. The host only
+// replays a recorded HIP graph of step launches and polls a copy of the
+// record one chunk behind; it makes no decision between refinements.
 //
-// Precision (mixed mode): the inner iterations run in FP32 with FP32
-// SpMV accumulation (dots accumulate in FP64); the outer loop forms the true
-// residual b - K x in FP64 on the GPU, solves for a correction in FP32 and
-// adds it in FP64 until ||b - K x|| <= rtol ||b||. In FP64 mode the same
-// kernel runs in double and the FP64 residual check confirms the result.
+// Matrix layout: the off-diagonal part of K_FF in column-major ELL (slot k of
+// row i at ell[k * n_pad + i], coalesced across a wavefront); on the
+// quadtree mesh every off-diagonal entry is -1/2 or -1, so an entry is the
+// column with the sign bit marking -1 and a padding bit for empty slots
+// (which point at the row itself with weight 0, so every load is
+// unconditional: no divergent branches between the loads). The diagonal
+// enters through K_ii z_i = r_i. A CSR path covers other matrices.
+//
+// All loads of an iteration that do not depend on alpha and beta (the
+// previous partial sums, the thread's row, its neighbours' values) are
+// issued before the block reduction. When the rows fit in at most kMaxGrid
+// blocks, every block re-reduces the previous launch's per-block partial sums
+// in a fixed order; larger systems put a one-block reduction launch between
+// steps. No atomics: results are reproducible bit for bit.
+//
+// Precision: in mixed mode the iterations run in FP32 with FP32 SpMV
+// accumulation (dots accumulate in FP64); corrections, residuals and the
+// iterate are FP64. FP64 mode runs the same kernel in double.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "internal.h"
 #include "reduce.h"
@@ -33,6 +57,30 @@ inline int grid_for(int64_t n) {
   return (int)(g < 1 ? 1 : g);
 }
 
+enum Phase : int32_t { kInit = 1, kIter = 2, kDoneOk = 3, kDoneNoConv = 4, kDoneBad = 5 };
+
+// Solver state, one record per launch parity.
+struct Rec {
+  int32_t phase;
+  int32_t iter;       // iteration within the current inner solve
+  int32_t total;      // iterations over all inner solves
+  int32_t ninner;     // inner solves started
+  int32_t stagnant;   // consecutive refinements that did not halve ||r||
+  int32_t xp;         // x64 buffer holding the iterate
+  int32_t pad0, pad1;
+  double gamma_prev, alpha_prev, rho_ref;
+  double tol2;        // inner tolerance, squared
+  double rnorm;       // FP64 residual norm at the start of this inner solve
+  double bnorm;
+  double pad2, pad3;
+};
+static_assert(sizeof(Rec) == 96, "record layout");
+
+// Constant parameters of a solve (written by the start launch).
+struct Params {
+  double rtol, inner_rtol, max_inner, max_refine, mixed, pad[3];
+};
+
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -43,49 +91,80 @@ __device__ __forceinline__ T next_r(T r, T s, T q, T a, T b) {
   return fmaT(-a, fmaT(b, q, s), r);
 }
 
-// Reads the per-block partial sums of the previous launch and reduces them
-// in a fixed order (strided per thread, then the block tree).
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int G,
-                                                double (&v)[3], double* lds) {
-  v[0] = v[1] = v[2] = 0.0;
-  for (int j = threadIdx.x; j < G; j += kBlock) {
-    v[0] += part[4 * j];
-    v[1] += part[4 * j + 1];
-    v[2] += part[4 * j + 2];
-  }
-  block_sum<3>(v, lds);
+// ELL entry: bits 0-29 column, bit 30 set for padding (weight 0; the column
+// is then the row itself, so every gather stays in bounds and unconditional),
+// bit 31 set for weight -1, clear for weight -1/2.
+constexpr int32_t kColMask = 0x3FFFFFFF;
+constexpr int32_t kPadBit = 0x40000000;
+
+__device__ __forceinline__ int ell_col(int32_t e) { return e & kColMask; }
+
+template <typename T>
+__device__ __forceinline__ T ell_weight(int32_t e) {
+  return (e & kPadBit) ? T(0) : (e < 0 ? T(-1) : T(-0.5));
 }
 
-// State 0 of an inner solve: x = 0, p = 0, q_prev = 0, r = rhs * scale (rhs
-// in FP64), s = A D^-1 r, and the partial dots of that state.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_init(
-    int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, const T* __restrict__ dinv, const double* __restrict__ rhs,
-    double scale, T* __restrict__ x, T* __restrict__ p, T* __restrict__ r0,
-    T* __restrict__ s0, T* __restrict__ q0, double* __restrict__ part_out,
-    int32_t* __restrict__ ctl) {
-  __shared__ double lds[12];
-  if (blockIdx.x == 0 && threadIdx.x == 0) { ctl[0] = 0; ctl[1] = 0; }
-  double v[3] = {0.0, 0.0, 0.0};
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const T ri = (T)(rhs[i] * scale);
-    const T zi = dinv[i] * ri;
-    T acc = ri;  // diagonal term: K_ii z_i = r_i
-    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j) {
-      const int c = col[j];
-      acc = fmaT(val[j], dinv[c] * (T)(rhs[c] * scale), acc);
-    }
-    x[i] = (T)0;
-    p[i] = (T)0;
-    q0[i] = (T)0;
-    r0[i] = ri;
-    s0[i] = acc;
-    v[0] += (double)ri * (double)zi;
-    v[1] += (double)zi * (double)acc;
-    v[2] += (double)ri * (double)ri;
-  }
-  block_sum<3>(v, lds);
+struct StepArgs {
+  int n;
+  int n_pad;
+  int W;                  // ELL slots (0: CSR)
+  const int32_t* ell;
+  const int32_t* rowptr;  // CSR (always present; used when W == 0)
+  const int32_t* col;
+  const T* val;
+  const double* val64;
+  const T* dinv;
+  const double* diag64;
+  T* x;                   // the correction of the current inner solve
+  T* p;
+  const T* r_in;
+  const T* s_in;
+  const T* q_in;
+  T* r_out;
+  T* s_out;
+  T* q_out;
+  const double* part_in;
+  int nparts_in;
+  double* part_out;
+  const Rec* rec_in;
+  Rec* rec_out;
+  const Params* prm;
+  const double* b64;
+  double* r64;
+  double* x64a;           // x64 buffers; rec.xp selects the current one
+  double* x64b;
+  int force;              // timing only: always iterate, ignore stop tests
+};
+
+// Builds a record from explicit fields (no copy of an input record, whose
+// unused bytes the compiler would otherwise carry through the kernel).
+__device__ __forceinline__ void put_rec(Rec* out, int phase, int iter, int total, int ninner,
+                                        int stagnant, int xp, double gamma_prev,
+                                        double alpha_prev, double rho_ref, double tol2,
+                                        double rnorm, double bnorm) {
+  Rec r;
+  r.phase = phase;
+  r.iter = iter;
+  r.total = total;
+  r.ninner = ninner;
+  r.stagnant = stagnant;
+  r.xp = xp;
+  r.pad0 = 0;
+  r.pad1 = 0;
+  r.gamma_prev = gamma_prev;
+  r.alpha_prev = alpha_prev;
+  r.rho_ref = rho_ref;
+  r.tol2 = tol2;
+  r.rnorm = rnorm;
+  r.bnorm = bnorm;
+  r.pad2 = 0.0;
+  r.pad3 = 0.0;
+  *out = r;
+}
+
+template <int BS>
+__device__ __forceinline__ void store_partials_bs(double* part_out, double (&v)[3]) {
   if (threadIdx.x == 0) {
     part_out[4 * blockIdx.x] = v[0];
     part_out[4 * blockIdx.x + 1] = v[1];
@@ -94,322 +173,615 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(
   }
 }
 
-// One fused Chronopoulos-Gear PCG iteration (state `iter` -> iter + 1).
-// ctl[0]: 0 running, 1 converged, 2 breakdown, 3 iteration cap; ctl[1]:
-// iterations done. scal_in/out: gamma_prev, alpha_prev, rho_ref.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_iter(
-    int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ p,
-    const T* __restrict__ r_in, const T* __restrict__ s_in, const T* __restrict__ q_in,
-    T* __restrict__ r_out, T* __restrict__ s_out, T* __restrict__ q_out,
-    const double* __restrict__ part_in, double* __restrict__ part_out,
-    const double* __restrict__ scal_in, double* __restrict__ scal_out, int32_t* __restrict__ ctl,
-    int iter, double tol2, int maxit, int force) {
-  __shared__ double lds[12];
-  __shared__ int done;
-  // One read per block, so the whole block takes the same branch (the flag
-  // can change while this launch runs, but only to stop a solve that every
-  // block is about to stop anyway).
-  if (threadIdx.x == 0) done = force ? 0 : ctl[0];
-  __syncthreads();
-  if (done) return;
-  double red[3];
-  reduce_partials(part_in, gridDim.x, red, lds);
+// Start of a solve: x64 = 0, r64 = b, partial ||b||^2, first record.
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, Params* prm_out) {
+  __shared__ double lds[3 * (BS / 64)];
+  double v[3] = {0.0, 0.0, 0.0};
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < A.n) {
+    const double bi = A.b64[i];
+    A.x64a[i] = 0.0;
+    A.r64[i] = bi;
+    v[0] = bi * bi;
+  }
+  block_sum_w<3, BS / 64>(v, lds);
+  store_partials_bs<BS>(A.part_out, v);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *prm_out = prm;
+    Rec r{};
+    r.phase = kInit;
+    *A.rec_out = r;
+  }
+}
+
+// One step of the solve (see the file comment). One thread per row, BS
+// threads per block.
+template <typename T, bool ELL, int BS>
+__global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
+  __shared__ double lds[3 * (BS / 64)];
+  // The record slot read here is written only by the next launch, so every
+  // thread reads it directly: uniform scalar loads, values kept read-only.
+  const Rec Rin = *A.rec_in;
+  const Params P = *A.prm;
+  // ---- loads that do not depend on the phase or on alpha, beta --------
+  double red[3] = {0.0, 0.0, 0.0};
+  constexpr int kPer = (kMaxGrid + BS - 1) / BS;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int j = threadIdx.x + u * BS;
+    const bool in = j < A.nparts_in;
+    const int jc = in ? j : 0;  // unconditional loads; out-of-range slots add 0
+    const double a0 = A.part_in[4 * jc], a1 = A.part_in[4 * jc + 1], a2 = A.part_in[4 * jc + 2];
+    red[0] += in ? a0 : 0.0;
+    red[1] += in ? a1 : 0.0;
+    red[2] += in ? a2 : 0.0;
+  }
+  const int i = blockIdx.x * BS + threadIdx.x;
+  const bool live = i < A.n;
+  const int ic = live ? i : A.n - 1;  // the tail loads a valid row, stores nothing
+  const T r0 = A.r_in[ic], s0 = A.s_in[ic], q0 = A.q_in[ic], d0 = A.dinv[ic];
+  const T p0 = A.p[ic], x0 = A.x[ic];
+  T nr[kMaxEll], ns[kMaxEll], nq[kMaxEll], nd[kMaxEll], nw[kMaxEll];
+  int32_t e[kMaxEll];
+  if constexpr (ELL) {
+#pragma unroll
+    for (int k = 0; k < kMaxEll; ++k)
+      e[k] = k < A.W ? A.ell[(int64_t)k * A.n_pad + ic] : (kPadBit | ic);
+#pragma unroll
+    for (int k = 0; k < kMaxEll; ++k) {
+      const int c = ell_col(e[k]);
+      nr[k] = A.r_in[c];
+      ns[k] = A.s_in[c];
+      nq[k] = A.q_in[c];
+      nd[k] = A.dinv[c];
+      nw[k] = ell_weight<T>(e[k]);
+    }
+  }
+  block_sum_w<3, BS / 64>(red, lds);
+  const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+  const int phase = A.force ? (int)kIter : Rin.phase;
+  double v[3] = {0.0, 0.0, 0.0};
+
+  if (phase >= kDoneOk) {  // finished: carry the record forward
+    if (writer)
+      put_rec(A.rec_out, Rin.phase, Rin.iter, Rin.total, Rin.ninner, Rin.stagnant, Rin.xp,
+              Rin.gamma_prev, Rin.alpha_prev, Rin.rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
+    return;
+  }
+
+  if (phase == kInit) {
+    // red[0] = ||r64||^2 from the start or refinement launch
+    const double rnorm = sqrt(red[0]);
+    const double bnorm = Rin.ninner == 0 ? rnorm : Rin.bnorm;
+    int stagnant = Rin.stagnant;
+    int next = 0;
+    if (!isfinite(rnorm)) next = kDoneBad;
+    else if (rnorm <= P.rtol * bnorm) next = kDoneOk;
+    else if ((double)Rin.ninner >= P.max_refine) next = kDoneNoConv;
+    else if (Rin.ninner > 0) {
+      stagnant = rnorm > 0.5 * Rin.rnorm ? stagnant + 1 : 0;
+      if (stagnant >= 3) next = kDoneNoConv;
+    }
+    if (next) {
+      if (writer)
+        put_rec(A.rec_out, next, Rin.iter, Rin.total, Rin.ninner, stagnant, Rin.xp,
+                Rin.gamma_prev, Rin.alpha_prev, Rin.rho_ref, Rin.tol2, rnorm, bnorm);
+      return;
+    }
+    // Inner target: what the outer tolerance still needs, never looser than
+    // inner_rtol in mixed mode.
+    const double want = 0.5 * P.rtol * bnorm / rnorm;
+    const double itol = P.mixed != 0.0 ? fmax(P.inner_rtol, want) : fmax(want, 1e-15);
+    const double scale = 1.0 / rnorm;
+    if (live) {
+      const T ri = (T)(A.r64[i] * scale);
+      const T zi = d0 * ri;
+      T acc = ri;  // diagonal term: K_ii z_i = r_i
+      if constexpr (ELL) {
+#pragma unroll
+        for (int k = 0; k < kMaxEll; ++k) {
+          const T rc = (T)(A.r64[ell_col(e[k])] * scale);
+          acc = fmaT(nw[k], nd[k] * rc, acc);
+        }
+      } else {
+        for (int j = A.rowptr[i]; j < A.rowptr[i + 1]; ++j) {
+          const int c = A.col[j];
+          acc = fmaT(A.val[j], A.dinv[c] * (T)(A.r64[c] * scale), acc);
+        }
+      }
+      A.x[i] = T(0);
+      A.p[i] = T(0);
+      A.q_out[i] = T(0);
+      A.r_out[i] = ri;
+      A.s_out[i] = acc;
+      v[0] = (double)ri * (double)zi;
+      v[1] = (double)zi * (double)acc;
+      v[2] = (double)ri * (double)ri;
+    }
+    block_sum_w<3, BS / 64>(v, lds);
+    store_partials_bs<BS>(A.part_out, v);
+    if (writer)
+      put_rec(A.rec_out, kIter, 0, Rin.total, Rin.ninner + 1, stagnant, Rin.xp, 0.0, 0.0, 0.0,
+              itol * itol, rnorm, bnorm);
+    return;
+  }
+
+  // ---- kIter --------------------------------------------------------------
+  const int iter = Rin.iter;
   const double gamma = red[0], delta = red[1], rho = red[2];
-  const double rho_ref = iter == 0 ? rho : scal_in[2];
+  const double rho_ref = iter == 0 ? rho : Rin.rho_ref;
   double alpha, beta;
   if (iter == 0) {
     beta = 0.0;
     alpha = gamma / delta;
   } else {
-    beta = gamma / scal_in[0];
-    alpha = gamma / (delta - beta * gamma / scal_in[1]);
+    beta = gamma / Rin.gamma_prev;
+    alpha = gamma / (delta - beta * gamma / Rin.alpha_prev);
   }
-  if (!force) {
-    int stop = 0;
-    if (!(rho > tol2 * rho_ref)) stop = 1;            // converged (also rho == 0)
-    else if (!(alpha > 0.0) || !isfinite(alpha)) stop = 2;  // breakdown / loss of SPD-ness
-    else if (iter >= maxit) stop = 3;
-    if (stop) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) { ctl[0] = stop; ctl[1] = iter; }
-      return;
+  bool stop = false;
+  if (!A.force) {
+    stop = !(rho > Rin.tol2 * rho_ref)          // converged (also rho == 0)
+           || !(alpha > 0.0) || !isfinite(alpha)  // breakdown
+           || (double)iter >= P.max_inner;        // iteration cap
+  }
+  if (stop) {
+    // Inner solve over: x64 += rnorm * d (d = the correction in x),
+    // r64 = b - K_FF x64, partial ||r64||^2. Neighbours' new x64 values are
+    // recomputed from their old value and correction.
+    const double* xo = Rin.xp ? A.x64b : A.x64a;
+    double* xn = Rin.xp ? A.x64a : A.x64b;
+    const double sc = Rin.rnorm;
+    if (live) {
+      const double xi = xo[i] + sc * (double)x0;
+      double acc = A.diag64[i] * xi;
+      if constexpr (ELL) {
+#pragma unroll
+        for (int k = 0; k < kMaxEll; ++k) {
+          const int c = ell_col(e[k]);
+          acc += ell_weight<double>(e[k]) * (xo[c] + sc * (double)A.x[c]);
+        }
+      } else {
+        for (int j = A.rowptr[i]; j < A.rowptr[i + 1]; ++j) {
+          const int c = A.col[j];
+          acc += A.val64[j] * (xo[c] + sc * (double)A.x[c]);
+        }
+      }
+      const double ri = A.b64[i] - acc;
+      xn[i] = xi;
+      A.r64[i] = ri;
+      v[0] = ri * ri;
     }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal_out[0] = gamma;
-    scal_out[1] = alpha;
-    scal_out[2] = rho_ref;
+    block_sum_w<3, BS / 64>(v, lds);
+    store_partials_bs<BS>(A.part_out, v);
+    if (writer)
+      put_rec(A.rec_out, kInit, iter, Rin.total + iter, Rin.ninner, Rin.stagnant, Rin.xp ^ 1,
+              gamma, alpha, rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
+    return;
   }
   const T a = (T)alpha, b = (T)beta;
-  double v[3] = {0.0, 0.0, 0.0};
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const T ri0 = r_in[i], si0 = s_in[i], qi0 = q_in[i], di = dinv[i];
-    const T pi = fmaT(b, p[i], di * ri0);
-    const T qi = fmaT(b, qi0, si0);
-    x[i] = fmaT(a, pi, x[i]);
-    p[i] = pi;
-    const T ri = next_r(ri0, si0, qi0, a, b);
-    const T zi = di * ri;
-    T acc = ri;  // diagonal term
-    const int j1 = rowptr[i + 1];
-    for (int j = rowptr[i]; j < j1; ++j) {
-      const int c = col[j];
-      const T rc = next_r(r_in[c], s_in[c], q_in[c], a, b);
-      acc = fmaT(val[j], dinv[c] * rc, acc);
+  if (live) {
+    const T pi = fmaT(b, p0, d0 * r0);
+    const T qi = fmaT(b, q0, s0);
+    A.x[i] = fmaT(a, pi, x0);
+    A.p[i] = pi;
+    const T ri = next_r(r0, s0, q0, a, b);
+    const T zi = d0 * ri;
+    T acc = ri;  // diagonal term: K_ii z_i = r_i
+    if constexpr (ELL) {
+#pragma unroll
+      for (int k = 0; k < kMaxEll; ++k) {
+        const T rc = next_r(nr[k], ns[k], nq[k], a, b);
+        acc = fmaT(nw[k], nd[k] * rc, acc);
+      }
+    } else {
+      const int j1 = A.rowptr[i + 1];
+      for (int j = A.rowptr[i]; j < j1; ++j) {
+        const int c = A.col[j];
+        const T rc = next_r(A.r_in[c], A.s_in[c], A.q_in[c], a, b);
+        acc = fmaT(A.val[j], A.dinv[c] * rc, acc);
+      }
     }
-    r_out[i] = ri;
-    q_out[i] = qi;
-    s_out[i] = acc;
-    v[0] += (double)ri * (double)zi;
-    v[1] += (double)zi * (double)acc;
-    v[2] += (double)ri * (double)ri;
+    A.r_out[i] = ri;
+    A.q_out[i] = qi;
+    A.s_out[i] = acc;
+    v[0] = (double)ri * (double)zi;
+    v[1] = (double)zi * (double)acc;
+    v[2] = (double)ri * (double)ri;
+  }
+  block_sum_w<3, BS / 64>(v, lds);
+  store_partials_bs<BS>(A.part_out, v);
+  if (writer)
+    put_rec(A.rec_out, kIter, iter + 1, Rin.total, Rin.ninner, Rin.stagnant, Rin.xp, gamma, alpha,
+            rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
+}
+
+// Large systems: one block sums the per-block partials between steps.
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __restrict__ part,
+                                                            int nparts, double* __restrict__ out) {
+  __shared__ double lds[12];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < nparts; j += kBlock) {
+    v[0] += part[4 * j];
+    v[1] += part[4 * j + 1];
+    v[2] += part[4 * j + 2];
   }
   block_sum<3>(v, lds);
   if (threadIdx.x == 0) {
-    part_out[4 * blockIdx.x] = v[0];
-    part_out[4 * blockIdx.x + 1] = v[1];
-    part_out[4 * blockIdx.x + 2] = v[2];
-    part_out[4 * blockIdx.x + 3] = 0.0;
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    out[3] = 0.0;
   }
 }
 
-// r = b - K_FF x in FP64 (diagonal separate), with per-block partial ||r||^2.
-__global__ __launch_bounds__(kBlock) void k_residual64(
-    int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, const double* __restrict__ diag, const double* __restrict__ b,
-    const double* __restrict__ x, double* __restrict__ r, double* __restrict__ part) {
-  __shared__ double lds[4];
-  double v[1] = {0.0};
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    double acc = diag[i] * x[i];
-    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j) acc += val[j] * x[col[j]];
-    const double ri = b[i] - acc;
-    r[i] = ri;
-    v[0] += ri * ri;
-  }
-  block_sum<1>(v, lds);
-  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_refine(int n, double scale, const T* __restrict__ d,
-                                                   double* __restrict__ x) {
+// ELL packing of the CSR off-diagonal part; flags values other than -1/2, -1.
+__global__ __launch_bounds__(kBlock) void k_pack_ell(int n, int n_pad, int W,
+                                                     const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     int32_t* __restrict__ ell,
+                                                     int32_t* __restrict__ flag) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] += scale * (double)d[i];
+  if (i >= n_pad) return;
+  const int j0 = i < n ? rowptr[i] : 0, j1 = i < n ? rowptr[i + 1] : 0;
+  for (int k = 0; k < W; ++k) {
+    int32_t e = kPadBit | (i < n ? i : 0);
+    if (j0 + k < j1) {
+      const double w = val[j0 + k];
+      e = col[j0 + k];
+      if (w == -1.0) e |= (int32_t)0x80000000;
+      else if (w != -0.5) atomicOr(flag, 1);
+    }
+    ell[(int64_t)k * n_pad + i] = e;
+  }
+  if (i < n && j1 - j0 > W) atomicOr(flag, 2);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double v, double* __restrict__ x) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] = v;
+__global__ __launch_bounds__(kBlock) void k_max_rowlen(int n, const int32_t* __restrict__ rowptr,
+                                                       int32_t* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) atomicMax(out, rowptr[i + 1] - rowptr[i]);
 }
 
-struct InnerArgs {
-  const int32_t* rowptr;
-  const int32_t* col;
-  const void* val;
-  const void* dinv;
-  CGState st;
+__global__ void k_zero_flag(int32_t* f) { f[0] = 0; f[1] = 0; }
+
+// ---------------------------------------------------------------- host ----
+template <typename T>
+struct Prec;
+template <>
+struct Prec<float> {
+  static constexpr int idx = 0;
+  static const float* val(fi_mesh* M) { return M->d_ff_val32; }
+  static const float* dinv(fi_mesh* M) { return M->d_dinv32; }
+  static CGState& st(fi_mesh* M) { return M->cg32; }
+};
+template <>
+struct Prec<double> {
+  static constexpr int idx = 1;
+  static const double* val(fi_mesh* M) { return M->d_ff_val64; }
+  static const double* dinv(fi_mesh* M) { return M->d_dinv64; }
+  static CGState& st(fi_mesh* M) { return M->cg64; }
 };
 
-template <typename T>
-InnerArgs inner_args(fi_mesh* M);
+Rec* rec_slot(fi_mesh* M, int k) { return (Rec*)M->d_rec + k; }
 
-template <>
-InnerArgs inner_args<float>(fi_mesh* M) {
-  return InnerArgs{M->d_ff_rowptr, M->d_ff_col, M->d_ff_val32, M->d_dinv32, M->cg32};
+// Arguments of the launch of parity `par` (reads slot par, writes slot par^1).
+template <typename T>
+StepArgs<T> make_args(fi_mesh* M, int par, int force) {
+  CGState& S = Prec<T>::st(M);
+  const int a = par, b = par ^ 1;
+  StepArgs<T> A;
+  A.n = (int)M->n;
+  A.n_pad = (int)M->n_pad;
+  A.W = M->ell_w;
+  A.ell = M->d_ell;
+  A.rowptr = M->d_ff_rowptr;
+  A.col = M->d_ff_col;
+  A.val = Prec<T>::val(M);
+  A.val64 = M->d_ff_val64;
+  A.dinv = Prec<T>::dinv(M);
+  A.diag64 = M->d_diag64;
+  A.x = (T*)S.x;
+  A.p = (T*)S.p;
+  A.r_in = (const T*)S.r[a];
+  A.s_in = (const T*)S.s[a];
+  A.q_in = (const T*)S.q[a];
+  A.r_out = (T*)S.r[b];
+  A.s_out = (T*)S.s[b];
+  A.q_out = (T*)S.q[b];
+  if (M->large_mode) {
+    A.part_in = M->d_red4;
+    A.nparts_in = 1;
+  } else {
+    A.part_in = M->d_part + (size_t)a * 4 * M->cg_grid;
+    A.nparts_in = M->cg_grid;
+  }
+  A.part_out = M->d_part + (size_t)b * 4 * M->cg_grid;
+  A.rec_in = rec_slot(M, a);
+  A.rec_out = rec_slot(M, b);
+  A.prm = (const Params*)M->d_prm;
+  A.b64 = M->d_b64;
+  A.r64 = M->d_r64;
+  A.x64a = M->d_x64buf[0];
+  A.x64b = M->d_x64buf[1];
+  A.force = force;
+  return A;
 }
-template <>
-InnerArgs inner_args<double>(fi_mesh* M) {
-  return InnerArgs{M->d_ff_rowptr, M->d_ff_col, M->d_ff_val64, M->d_dinv64, M->cg64};
+
+template <typename T, bool ELL>
+void* step_ptr(int bs) {
+  switch (bs) {
+    case 256: return (void*)k_step<T, ELL, 256>;
+    default: return (void*)k_step<T, ELL, 512>;
+  }
 }
 
 template <typename T>
-int launch_init(fi_mesh* M, const double* rhs, double scale) {
-  InnerArgs A = inner_args<T>(M);
-  hipLaunchKernelGGL(k_cg_init<T>, dim3(M->cg_grid), dim3(kBlock), 0, M->ctx->stream, (int)M->n,
-                     A.rowptr, A.col, (const T*)A.val, (const T*)A.dinv, rhs, scale, (T*)A.st.x,
-                     (T*)A.st.p, (T*)A.st.r[0], (T*)A.st.s[0], (T*)A.st.q[0], M->d_part, M->d_ctl);
+void* step_kernel(fi_mesh* M) {
+  return M->ell_w > 0 ? step_ptr<T, true>(M->cg_bs) : step_ptr<T, false>(M->cg_bs);
+}
+
+template <typename T>
+void* start_kernel(fi_mesh* M) {
+  switch (M->cg_bs) {
+    case 256: return (void*)k_solve_start<T, 256>;
+    default: return (void*)k_solve_start<T, 512>;
+  }
+}
+
+int launch_reduce_after(fi_mesh* M, int par) {
+  // the step of parity `par` wrote partial slot par^1
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, M->ctx->stream,
+                     M->d_part + (size_t)(par ^ 1) * 4 * M->cg_grid, M->cg_grid, M->d_red4);
   FI_HIP_TRY(hipGetLastError());
   return FI_OK;
 }
 
 template <typename T>
-int launch_iter(fi_mesh* M, int iter, double tol2, int maxit, int force) {
-  InnerArgs A = inner_args<T>(M);
-  const int a = iter & 1, b = a ^ 1;
-  double* part_in = M->d_part + (size_t)a * 4 * kMaxGrid;
-  double* part_out = M->d_part + (size_t)b * 4 * kMaxGrid;
-  double* scal_in = M->d_scal + 4 * a;
-  double* scal_out = M->d_scal + 4 * b;
-  hipLaunchKernelGGL(k_cg_iter<T>, dim3(M->cg_grid), dim3(kBlock), 0, M->ctx->stream, (int)M->n,
-                     A.rowptr, A.col, (const T*)A.val, (const T*)A.dinv, (T*)A.st.x, (T*)A.st.p,
-                     (const T*)A.st.r[a], (const T*)A.st.s[a], (const T*)A.st.q[a],
-                     (T*)A.st.r[b], (T*)A.st.s[b], (T*)A.st.q[b], part_in, part_out, scal_in,
-                     scal_out, M->d_ctl, iter, tol2, maxit, force);
-  FI_HIP_TRY(hipGetLastError());
+int launch_step(fi_mesh* M, int par, int force) {
+  StepArgs<T> A = make_args<T>(M, par, force);
+  void* args[1] = {&A};
+  FI_HIP_TRY(hipLaunchKernel(step_kernel<T>(M), dim3(M->cg_grid), dim3(M->cg_bs), args, 0,
+                             M->ctx->stream));
+  if (M->large_mode) return launch_reduce_after(M, par);
   return FI_OK;
 }
 
-// Runs one inner solve of K d = rhs * scale to relative residual `rtol`
-// (FP(T) recurrence residual); returns iterations used and the stop code.
 template <typename T>
-int inner_solve(fi_mesh* M, const double* rhs, double scale, double rtol, int maxit,
-                int check_every, int64_t* iters, int* stop_code) {
-  int rc = launch_init<T>(M, rhs, scale);
-  if (rc) return rc;
-  const double tol2 = rtol * rtol;
-  int it = 0;
-  for (;;) {
-    const int chunk = check_every;
-    for (int k = 0; k < chunk; ++k) {
-      rc = launch_iter<T>(M, it + k, tol2, maxit, 0);
-      if (rc) return rc;
+int launch_start(fi_mesh* M, const fi_solve_opts* o) {
+  StepArgs<T> A = make_args<T>(M, 1, 0);  // writes record and partials of slot 0
+  Params prm{};
+  prm.rtol = o->rtol;
+  prm.inner_rtol = o->inner_rtol;
+  prm.max_inner = o->max_inner;
+  prm.max_refine = o->max_refine;
+  prm.mixed = sizeof(T) == sizeof(float) ? 1.0 : 0.0;
+  Params* pout = (Params*)M->d_prm;
+  void* args[3] = {&A, &prm, &pout};
+  FI_HIP_TRY(hipLaunchKernel(start_kernel<T>(M), dim3(M->cg_grid), dim3(M->cg_bs), args, 0,
+                             M->ctx->stream));
+  if (M->large_mode) return launch_reduce_after(M, 1);
+  return FI_OK;
+}
+
+constexpr int kChunk = 8;  // step launches per recorded graph (even)
+
+template <typename T>
+int get_graph(fi_mesh* M, hipGraphExec_t* out) {
+  const int pi = Prec<T>::idx;
+  if (M->graph_exec[pi]) {
+    *out = M->graph_exec[pi];
+    return FI_OK;
+  }
+  hipGraph_t g = nullptr;
+  FI_HIP_TRY(hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  for (int k = 0; k < kChunk; ++k) {
+    const int par = k & 1;  // chunks start on parity 0: the start launch wrote slot 0
+    StepArgs<T> A = make_args<T>(M, par, 0);
+    void* params[1] = {&A};
+    hipKernelNodeParams kp{};
+    kp.func = step_kernel<T>(M);
+    kp.gridDim = dim3(M->cg_grid);
+    kp.blockDim = dim3(M->cg_bs);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    FI_HIP_TRY(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+    prev = node;
+    if (M->large_mode) {
+      const double* pin = M->d_part + (size_t)(par ^ 1) * 4 * M->cg_grid;
+      int np = M->cg_grid;
+      double* pout = M->d_red4;
+      void* rp[3] = {&pin, &np, &pout};
+      hipKernelNodeParams rk{};
+      rk.func = (void*)k_reduce_partials;
+      rk.gridDim = dim3(1);
+      rk.blockDim = dim3(kBlock);
+      rk.sharedMemBytes = 0;
+      rk.kernelParams = rp;
+      rk.extra = nullptr;
+      hipGraphNode_t rnode;
+      FI_HIP_TRY(hipGraphAddKernelNode(&rnode, g, &prev, 1, &rk));
+      prev = rnode;
     }
-    it += chunk;
-    FI_HIP_TRY(hipMemcpyAsync(M->h_ctl, M->d_ctl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                              M->ctx->stream));
-    FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
-    if (M->h_ctl[0] != 0) {
-      *iters = M->h_ctl[1];
-      *stop_code = M->h_ctl[0];
+  }
+  hipGraphExec_t ex = nullptr;
+  FI_HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  M->graph[pi] = g;
+  M->graph_exec[pi] = ex;
+  *out = ex;
+  return FI_OK;
+}
+
+template <typename T>
+int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
+  hipStream_t st = M->ctx->stream;
+  int rc = launch_start<T>(M, o);
+  if (rc) return rc;
+  hipGraphExec_t ex = nullptr;
+  rc = get_graph<T>(M, &ex);
+  if (rc) return rc;
+  // Upper bound on launches: every inner solve takes at most max_inner + 2.
+  const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
+  const int64_t max_chunks = max_launch / kChunk + 2;
+  Rec* ring = (Rec*)M->h_rec;
+  // Chunk c: replay, copy the record it ends with (slot 0) to ring c % 2 and
+  // record an event; the host checks chunk c - 1 while chunk c runs.
+  for (int64_t c = 0;; ++c) {
+    if (c < max_chunks) {
+      FI_HIP_TRY(hipGraphLaunch(ex, st));
+      FI_HIP_TRY(hipMemcpyAsync(ring + (c & 1), rec_slot(M, 0), sizeof(Rec), hipMemcpyDeviceToHost,
+                                st));
+      FI_HIP_TRY(hipEventRecord(M->ring_ev[c & 1], st));
+    }
+    const int64_t prev = c - 1;
+    if (prev < 0) continue;
+    FI_HIP_TRY(hipEventSynchronize(M->ring_ev[prev & 1]));
+    const Rec R = ring[prev & 1];
+    if (R.phase >= kDoneOk) {
+      stats->iterations = R.total;
+      stats->refinements = R.ninner;
+      stats->rel_residual = R.bnorm > 0 ? R.rnorm / R.bnorm : 0.0;
+      stats->status = R.phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
+      M->d_x64 = M->d_x64buf[R.xp];
+      if (R.phase == kDoneBad) return fail(FI_E_INVALID, "right-hand side or residual not finite");
       return FI_OK;
     }
-    if (it > maxit + chunk) {  // cannot happen: the kernel stops at maxit
-      return fail(FI_E_HIP, "inner solver did not report termination");
-    }
+    if (prev >= max_chunks - 1) return fail(FI_E_HIP, "solver did not report termination");
   }
-}
-
-template <typename T>
-int refine_update(fi_mesh* M, double scale) {
-  InnerArgs A = inner_args<T>(M);
-  hipLaunchKernelGGL(k_refine<T>, dim3(grid_for(M->n)), dim3(kBlock), 0, M->ctx->stream, (int)M->n,
-                     scale, (const T*)A.st.x, M->d_x64);
-  FI_HIP_TRY(hipGetLastError());
-  return FI_OK;
-}
-
-int residual64(fi_mesh* M, double* rnorm2_host) {
-  hipLaunchKernelGGL(k_residual64, dim3(M->cg_grid), dim3(kBlock), 0, M->ctx->stream, (int)M->n,
-                     M->d_ff_rowptr, M->d_ff_col, M->d_ff_val64, M->d_diag64, M->d_b64, M->d_x64,
-                     M->d_r64, M->d_red);
-  FI_HIP_TRY(hipGetLastError());
-  int rc = launch_reduce(M, M->d_red, M->cg_grid, 1, M->d_red_out);
-  if (rc) return rc;
-  FI_HIP_TRY(hipMemcpyAsync(M->h_red, M->d_red_out, sizeof(double), hipMemcpyDeviceToHost,
-                            M->ctx->stream));
-  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
-  *rnorm2_host = M->h_red[0];
-  return FI_OK;
-}
-
-template <typename T>
-int solve_ir(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
-  const int64_t n = M->n;
-  stats->iterations = 0;
-  stats->refinements = 0;
-  stats->status = FI_OK;
-  stats->rel_residual = 0.0;
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, 0.0, M->d_x64);
-  FI_HIP_TRY(hipGetLastError());
-  int rc = launch_dot(M, M->d_b64, M->d_b64, n, M->d_red_out);
-  if (rc) return rc;
-  FI_HIP_TRY(hipMemcpyAsync(M->h_red, M->d_red_out, sizeof(double), hipMemcpyDeviceToHost,
-                            M->ctx->stream));
-  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
-  const double bnorm = std::sqrt(M->h_red[0]);
-  if (!std::isfinite(bnorm)) return fail(FI_E_INVALID, "right-hand side is not finite");
-  if (bnorm == 0.0) return FI_OK;  // x = 0 solves it exactly
-  double rnorm = bnorm;
-  const double* rhs = M->d_b64;  // residual of x = 0
-  const bool mixed = sizeof(T) == sizeof(float);
-  int stagnant = 0;
-  for (int step = 0;; ++step) {
-    const double rel = rnorm / bnorm;
-    stats->rel_residual = rel;
-    if (rel <= o->rtol) return FI_OK;
-    if (step >= o->max_refine) break;
-    // Inner target: what the outer tolerance still needs, never looser than
-    // inner_rtol in mixed mode.
-    const double want = 0.5 * o->rtol * bnorm / rnorm;
-    const double itol = mixed ? std::max(o->inner_rtol, want) : std::max(want, 1e-15);
-    int64_t its = 0;
-    int code = 0;
-    rc = inner_solve<T>(M, rhs, 1.0 / rnorm, itol, o->max_inner, std::max(1, o->check_every), &its,
-                        &code);
-    if (rc) return rc;
-    stats->iterations += its;
-    rc = refine_update<T>(M, rnorm);
-    if (rc) return rc;
-    double r2 = 0.0;
-    rc = residual64(M, &r2);
-    if (rc) return rc;
-    stats->refinements += 1;
-    const double rnew = std::sqrt(r2);
-    if (!std::isfinite(rnew)) return fail(FI_E_HIP, "non-finite residual in refinement");
-    stagnant = (rnew > 0.5 * rnorm) ? stagnant + 1 : 0;
-    rnorm = rnew;
-    rhs = M->d_r64;
-    if (stagnant >= 3) break;
-  }
-  stats->rel_residual = rnorm / bnorm;
-  stats->status = FI_E_NO_CONVERGENCE;
-  return FI_OK;
 }
 
 }  // namespace
 
-// Solves K_FF x64 = b64 (both in the mesh workspace).
-int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats) {
-  if (M->n == 0) {
-    stats->iterations = 0;
-    stats->refinements = 0;
-    stats->status = FI_OK;
-    stats->rel_residual = 0.0;
-    return FI_OK;
+void solver_release(fi_mesh* M) {
+  for (int k = 0; k < 2; ++k) {
+    if (M->graph_exec[k]) (void)hipGraphExecDestroy(M->graph_exec[k]);
+    if (M->graph[k]) (void)hipGraphDestroy(M->graph[k]);
+    M->graph_exec[k] = nullptr;
+    M->graph[k] = nullptr;
+    if (M->ring_ev[k]) (void)hipEventDestroy(M->ring_ev[k]);
+    M->ring_ev[k] = nullptr;
   }
-  if (opts->precision == FI_PREC_FP64) return solve_ir<double>(M, opts, stats);
-  return solve_ir<float>(M, opts, stats);
+  if (M->h_rec) (void)hipHostFree(M->h_rec);
+  M->h_rec = nullptr;
 }
 
+// Called after every assembly: picks the launch shape and packs the ELL copy.
+int solver_setup(fi_mesh* M) {
+  hipStream_t st = M->ctx->stream;
+  const int64_t n = M->n;
+  const bool first = M->d_flag == nullptr;
+  if (first) {
+    // Block size of the step kernel: fewer, larger blocks cut the partial
+    // sums every block re-reads (G^2 traffic); FI_CG_BLOCK overrides.
+    int bs = 512;
+    if (const char* env = std::getenv("FI_CG_BLOCK")) bs = std::atoi(env);
+    if (bs != 256 && bs != 512) bs = 512;  // 1024 would spill the ELL kernel
+    M->cg_bs = bs;
+  }
+  const int64_t blocks = (n + M->cg_bs - 1) / M->cg_bs;
+  if (first) {
+    M->large_mode = blocks > kMaxGrid;
+    M->cg_grid = (int)std::max<int64_t>(1, blocks);
+    M->n_pad = (n + 63) / 64 * 64;
+    int rc = 0;
+    if ((rc = device_alloc(M, (void**)&M->d_flag, 4 * sizeof(int32_t)))) return rc;
+    if ((rc = device_alloc(M, (void**)&M->d_red4, 4 * sizeof(double)))) return rc;
+    if ((rc = device_alloc(M, (void**)&M->d_prm, sizeof(Params)))) return rc;
+    if ((rc = device_alloc(M, &M->d_rec, 2 * sizeof(Rec)))) return rc;
+    if ((rc = device_alloc(M, (void**)&M->d_part, (size_t)2 * 4 * M->cg_grid * sizeof(double))))
+      return rc;
+    FI_HIP_TRY(hipHostMalloc(&M->h_rec, 2 * sizeof(Rec), hipHostMallocDefault));
+    for (int k = 0; k < 2; ++k)
+      FI_HIP_TRY(hipEventCreateWithFlags(&M->ring_ev[k], hipEventDisableTiming));
+    // widest row decides the ELL width
+    hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, st, M->d_flag);
+    if (n > 0)
+      hipLaunchKernelGGL(k_max_rowlen, dim3(grid_for(n)), dim3(kBlock), 0, st, (int)n,
+                         M->d_ff_rowptr, M->d_flag);
+    FI_HIP_TRY(hipGetLastError());
+    FI_HIP_TRY(hipMemcpyAsync(M->h_ctl, M->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FI_HIP_TRY(hipStreamSynchronize(st));
+    const int32_t w = M->h_ctl[0];
+    M->ell_w = (w <= kMaxEll) ? std::max(w, 1) : 0;
+    if (M->ell_w > 0) {
+      if ((rc = device_alloc(M, (void**)&M->d_ell, (size_t)M->ell_w * M->n_pad * sizeof(int32_t))))
+        return rc;
+    }
+  }
+  if (M->ell_w > 0) {
+    hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, st, M->d_flag);
+    hipLaunchKernelGGL(k_pack_ell, dim3(grid_for(M->n_pad)), dim3(kBlock), 0, st, (int)n,
+                       (int)M->n_pad, M->ell_w, M->d_ff_rowptr, M->d_ff_col, M->d_ff_val64,
+                       M->d_ell, M->d_flag);
+    FI_HIP_TRY(hipGetLastError());
+    if (first) {
+      FI_HIP_TRY(hipMemcpyAsync(M->h_ctl, M->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      FI_HIP_TRY(hipStreamSynchronize(st));
+      if (M->h_ctl[0] != 0) M->ell_w = 0;  // values other than -1/2, -1: use CSR
+    }
+  }
+  return FI_OK;
+}
+
+// Solves K_FF x = b64 (both in the mesh workspace); the result is in d_x64.
+int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats) {
+  stats->iterations = 0;
+  stats->refinements = 0;
+  stats->status = FI_OK;
+  stats->rel_residual = 0.0;
+  if (M->n == 0) return FI_OK;
+  if (opts->precision == FI_PREC_FP64) return solve_dev<double>(M, opts, stats);
+  return solve_dev<float>(M, opts, stats);
+}
+
+// Times `reps` CG iterations (step launches forced into the iteration
+// phase) between two HIP events on the context stream.
 int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
   if (M->n == 0 || reps < 1) return fail(FI_E_INVALID, "nothing to time");
   hipStream_t st = M->ctx->stream;
-  // a fresh state from the current right-hand side
-  int rc = precision == FI_PREC_FP64 ? launch_init<double>(M, M->d_b64, 1.0)
-                                     : launch_init<float>(M, M->d_b64, 1.0);
+  const bool d = precision == FI_PREC_FP64;
+  fi_solve_opts o;
+  fi_solve_opts_default(&o);
+  // a start launch plus one init step give a valid state to iterate from
+  int rc = d ? launch_start<double>(M, &o) : launch_start<float>(M, &o);
+  if (rc) return rc;
+  rc = d ? launch_step<double>(M, 0, 0) : launch_step<float>(M, 0, 0);
   if (rc) return rc;
   hipEvent_t e0, e1;
   FI_HIP_TRY(hipEventCreate(&e0));
   FI_HIP_TRY(hipEventCreate(&e1));
   for (int k = 0; k < 4; ++k) {
-    rc = precision == FI_PREC_FP64 ? launch_iter<double>(M, k, 0.0, 1 << 30, 1)
-                                   : launch_iter<float>(M, k, 0.0, 1 << 30, 1);
+    rc = d ? launch_step<double>(M, (k + 1) & 1, 1) : launch_step<float>(M, (k + 1) & 1, 1);
     if (rc) return rc;
   }
   FI_HIP_TRY(hipEventRecord(e0, st));
   for (int k = 0; k < reps; ++k) {
-    rc = precision == FI_PREC_FP64 ? launch_iter<double>(M, 4 + k, 0.0, 1 << 30, 1)
-                                   : launch_iter<float>(M, 4 + k, 0.0, 1 << 30, 1);
+    rc = d ? launch_step<double>(M, (k + 1) & 1, 1) : launch_step<float>(M, (k + 1) & 1, 1);
     if (rc) return rc;
   }
   FI_HIP_TRY(hipEventRecord(e1, st));
   FI_HIP_TRY(hipEventSynchronize(e1));
   float t = 0.f;
   FI_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *ms = (double)t / reps;
   return FI_OK;
 }
 
-// Bytes one fused iteration must move: matrix (column index + value per
-// off-diagonal entry), row pointers, and per row the reads of r, s, q, D^-1,
-// x, p and the writes of x, p, r, s, q.
+// Bytes one CG iteration must move: the matrix (one int32 per stored
+// off-diagonal entry in the encoded layout, or column + value per CSR entry
+// plus row pointers), and per row the reads of r, s, q, D^-1, x, p and the
+// writes of x, p, r, s, q.
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision) {
   const int64_t w = precision == FI_PREC_FP64 ? 8 : 4;
-  return M->nnz_off * (4 + w) + (M->n + 1) * 4 + M->n * w * 11;
+  const int64_t mat = M->ell_w > 0 ? M->nnz_off * 4  // encoded entries; padding not counted
+                                   : M->nnz_off * (4 + w) + (M->n + 1) * 4;
+  return mat + M->n * w * 11;
 }
 
 }  // namespace fi
