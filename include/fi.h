@@ -225,6 +225,26 @@ int fi_owner_map(fi_mesh* mesh, int32_t* owner_dev);
  * Errors: FI_E_INVALID if k exceeds the number of non-mask pixels. */
 int fi_topk_new_pixels(fi_mesh* mesh, const double* e_dev, int64_t k, int32_t* out_dev);
 
+/* Error-driven mask growth (Section 3: densification on the inpainting
+ * error map, here its global top-k form): starting from mask0, for `rounds`
+ * rounds rebuild the mesh on the current mask, inpaint with g = f on the
+ * mask, compute e_i = (u_i - f_i)^2 and add the k_add non-mask pixels with
+ * the largest e_i (ties to the lower index); finally inpaint once more.
+ *   f_dev:     uint8[side * side] device image;
+ *   mask0:     host int32[m0], strictly ascending;
+ *   mask_out:  host int32[m0 + rounds * k_add]: mask0, then each round's
+ *              additions in ascending order, round after round;
+ *   mse_out:   host float64[rounds + 1], MSE after each round's inpainting
+ *              (index r: the mask of round r; index rounds: the final mask);
+ *   gpu_ms_out: host float64[rounds + 1] or NULL: milliseconds of device
+ *              time for the solve, interpolation and error of each round
+ *              (HIP events on the context stream; mesh building excluded).
+ * Errors as fi_mesh_build / fi_inpaint; FI_E_INVALID if a round cannot add
+ * k_add pixels. */
+int fi_grow_mask(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0, int64_t m0,
+                 int64_t k_add, int rounds, const fi_solve_opts* opts, int32_t* mask_out,
+                 double* mse_out, double* gpu_ms_out);
+
 /* Timing helper: runs `reps` iterations of the fused FP32 (precision =
  * FI_PREC_FP32_IR) or FP64 (FI_PREC_FP64) CG iteration kernel on this mesh's
  * current solver state between two HIP events recorded on the context

@@ -6,14 +6,14 @@ CG. The oracle instead computes the exact discrete solution with a direct
 Cholesky factorisation, so that an iterative GPU answer can be measured
 against it.
 
-Two factorisations are provided, both plain library steps:
+Two factorisations are provided:
 
 * ``BandedCholesky``: reverse Cuthill-McKee ordering, then LAPACK's banded
-  Cholesky (``scipy.linalg.cholesky_banded``). Used up to a few hundred
-  thousand unknowns.
+  Cholesky (``scipy.linalg.cholesky_banded``), a library step. Used up to
+  20,000 unknowns.
 * ``SparseCholesky`` (in ``oracle.sparse_chol``): a plain C left-looking
-  sparse Cholesky with a geometric nested-dissection order, for the largest
-  crops, where the band would not fit in memory.
+  sparse Cholesky with a geometric nested-dissection order, for larger
+  systems, where the band is wide.
 """
 from __future__ import annotations
 
@@ -58,14 +58,19 @@ class BandedCholesky:
         return x
 
 
-def factorise(A: sp.spmatrix, method: str = "auto"):
-    """Direct Cholesky factor object with a ``solve(b)`` method."""
+def factorise(A: sp.spmatrix, method: str = "auto", coords: np.ndarray | None = None,
+              side: int | None = None):
+    """Direct Cholesky factor object with a ``solve(b)`` method.
+
+    ``auto`` takes the banded factorisation up to 20,000 unknowns and the
+    sparse one (nested dissection on ``coords`` when given) above.
+    """
     n = A.shape[0]
     if method == "auto":
-        method = "banded" if n <= 150_000 else "sparse"
+        method = "banded" if n <= 20_000 else "sparse"
     if method == "banded":
         return BandedCholesky(A)
     if method == "sparse":
         from .sparse_chol import SparseCholesky
-        return SparseCholesky(A)
+        return SparseCholesky(A, coords, side)
     raise ValueError(method)

@@ -39,7 +39,8 @@ class Problem:
         self.R_D = R[:, self.mesh.mask_vids].tocsr()
         self.R_FT = self.R_F.T.tocsr()
         self.R_DT = self.R_D.T.tocsr()
-        self.factor = solve.factorise(self.sys.K_FF, factor_method)
+        self.factor = solve.factorise(self.sys.K_FF, factor_method,
+                                      self.mesh.vxy[self.mesh.free_vids], N)
         self.N = N
         self.P = N * N
 

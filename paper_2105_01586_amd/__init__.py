@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "FIError", "NoConvergence", "library", "Context", "Mesh", "SolveOpts", "TonalOpts",
-    "PREC_FP32_IR", "PREC_FP64", "lib_path", "EXPORTED_SYMBOLS", "host_mesh",
+    "PREC_FP32_IR", "PREC_FP64", "lib_path", "EXPORTED_SYMBOLS", "host_mesh", "grow_mask",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +39,7 @@ EXPORTED_SYMBOLS = (
     "fi_adjoint", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
     "fi_owner_map", "fi_topk_new_pixels", "fi_time_cg_kernel", "fi_cg_kernel_bytes",
     "fi_host_mesh_build", "fi_host_mesh_info", "fi_host_mesh_export", "fi_host_mesh_destroy",
-    "fi_mesh_upload",
+    "fi_mesh_upload", "fi_grow_mask",
 )
 
 
@@ -140,6 +140,8 @@ def library() -> ctypes.CDLL:
         "fi_host_mesh_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "fi_host_mesh_destroy": (ctypes.c_int, [vp]),
         "fi_mesh_upload": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "fi_grow_mask": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int, ctypes.POINTER(_SolveOpts), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -437,3 +439,27 @@ class Mesh:
         _check(library().fi_cg_kernel_bytes(self._h, int(precision), ctypes.byref(b)),
                "fi_cg_kernel_bytes")
         return b.value
+
+
+def grow_mask(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
+              opts: SolveOpts | None = None):
+    """Error-driven mask growth (fi_grow_mask).
+
+    Returns (mask_order, mse, gpu_ms): the int32 pixel indices in order of
+    addition (mask0 first, then each round's additions), the MSE after each
+    of the rounds + 1 inpaintings, and the device milliseconds of each
+    round's solve, interpolation and error.
+    """
+    torch = _torch()
+    mask0 = np.ascontiguousarray(np.asarray(mask0, dtype=np.int32).ravel())
+    P = int(side) * int(side)
+    out = np.empty(mask0.size + int(rounds) * int(k_add), np.int32)
+    mse = np.empty(int(rounds) + 1, np.float64)
+    ms = np.empty(int(rounds) + 1, np.float64)
+    o = (opts or SolveOpts()).c()
+    c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    rc = library().fi_grow_mask(ctx._h, int(side), _ptr(f, torch.uint8, P, "f", ctx.device),
+                                c(mask0), mask0.size, int(k_add), int(rounds), ctypes.byref(o),
+                                c(out), c(mse), c(ms))
+    _check(rc, "fi_grow_mask")
+    return out, mse, ms

@@ -684,7 +684,10 @@ int solver_setup(fi_mesh* M) {
   }
   const int64_t blocks = (n + M->cg_bs - 1) / M->cg_bs;
   if (first) {
-    M->large_mode = blocks > kMaxGrid;
+    // FI_CG_LARGE=1 forces the separate-reduction launch shape (tests use it
+    // to check that path on systems small enough for the oracle).
+    const char* force_large = std::getenv("FI_CG_LARGE");
+    M->large_mode = blocks > kMaxGrid || (force_large && std::atoi(force_large) == 1);
     M->cg_grid = (int)std::max<int64_t>(1, blocks);
     M->n_pad = (n + 63) / 64 * 64;
     int rc = 0;

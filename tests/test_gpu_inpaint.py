@@ -156,3 +156,33 @@ def test_error_paths(ctx):
     _, _, f = case("c2")
     with pytest.raises(fi.NoConvergence):
         Mc.inpaint(f=dev(f), opts=fi.SolveOpts(max_inner=1, max_refine=1))
+
+
+@pytest.mark.parametrize("precision", [fi.PREC_FP32_IR, fi.PREC_FP64])
+def test_large_launch_shape_parity(ctx, precision, monkeypatch):
+    """The launch shape used above 524288 unknowns (a one-block reduction
+    launch between solver steps), forced on the 512^2 case for the oracle."""
+    monkeypatch.setenv("FI_CG_LARGE", "1")
+    side, mask, f = case("c2")
+    M = fi.Mesh(ctx, side, mask)
+    monkeypatch.delenv("FI_CG_LARGE")
+    u, st = M.inpaint(f=dev(f), opts=fi.SolveOpts(precision=precision))
+    err = np.max(np.abs(u.cpu().numpy() - oracle_inpaint("c2")))
+    print(f"  large shape: max abs err {err:.3e}, iters {st['iterations']}")
+    assert st["status"] == 0 and err <= PIX_TOL
+    r = np.random.default_rng(9).normal(size=M.P)
+    s, _ = M.adjoint(dev(r), opts=fi.SolveOpts(precision=precision))
+    ref = oracle_problem("c2").BT(r)
+    assert np.linalg.norm(s.cpu().numpy() - ref) <= 1e-8 * np.linalg.norm(ref)
+    M.close()
+
+
+@pytest.mark.parametrize("bs", ["256", "512"])
+def test_block_sizes_agree(ctx, bs, monkeypatch):
+    monkeypatch.setenv("FI_CG_BLOCK", bs)
+    side, mask, f = case("n256_k2000")
+    M = fi.Mesh(ctx, side, mask)
+    monkeypatch.delenv("FI_CG_BLOCK")
+    u, _ = M.inpaint(f=dev(f))
+    assert np.max(np.abs(u.cpu().numpy() - oracle_inpaint("n256_k2000"))) <= PIX_TOL
+    M.close()

@@ -117,3 +117,42 @@ def test_constant_and_maximum_principle(N, k, seed):
     u = pr.vertex_solution(g)
     assert u.min() >= g.min() - 1e-9 and u.max() <= g.max() + 1e-9
     assert np.array_equal(u[pr.mesh.mask_vids], g)
+
+
+@pytest.mark.parametrize("N,k,seed", [(8, 3, 0), (16, 10, 1), (32, 25, 2), (64, 205, 3)])
+def test_sparse_cholesky_matches_dense(N, k, seed):
+    from oracle.sparse_chol import SparseCholesky, nested_dissection
+    rng = np.random.default_rng(seed)
+    M = mesh_mod.build_mesh(N, random_mask(rng, N, k))
+    S = fem.assemble(M)
+    b = rng.normal(size=M.n)
+    x_dense = np.linalg.solve(S.K_FF.toarray(), b)
+    for c in (SparseCholesky(S.K_FF, M.vxy[M.free_vids], N), SparseCholesky(S.K_FF)):
+        assert np.allclose(c.solve(b), x_dense, rtol=1e-12, atol=1e-11)
+    order = nested_dissection(M.vxy[M.free_vids], N)
+    assert np.array_equal(np.sort(order), np.arange(M.n))
+    # the factor itself: L L^T reproduces the permuted matrix
+    c = SparseCholesky(S.K_FF, M.vxy[M.free_vids], N)
+    e = np.zeros(M.n)
+    e[3] = 1.0
+    assert np.allclose(S.K_FF @ c.solve(e), e, atol=1e-12)
+
+
+def test_sparse_cholesky_rejects_indefinite():
+    from oracle.sparse_chol import SparseCholesky
+    import scipy.sparse as sp
+    A = sp.csc_matrix(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    with pytest.raises(np.linalg.LinAlgError):
+        SparseCholesky(A)
+
+
+def test_sparse_and_banded_agree_on_workload():
+    import synth
+    from oracle.sparse_chol import SparseCholesky
+    w = synth.WORKLOADS["plain64"]
+    M = mesh_mod.build_mesh(w.side, w.mask())
+    S = fem.assemble(M)
+    b = np.random.default_rng(1).normal(size=M.n)
+    x1 = SparseCholesky(S.K_FF, M.vxy[M.free_vids], w.side).solve(b)
+    x2 = solve.BandedCholesky(S.K_FF).solve(b)
+    assert np.allclose(x1, x2, rtol=1e-12, atol=1e-11)
