@@ -82,12 +82,14 @@ int alloc_workspace(fi_mesh* M) {
   TRY(alloc_n(M, &M->d_x64buf[1], n));
   M->d_x64 = M->d_x64buf[0];
   TRY(alloc_n(M, &M->d_r64, n));
-  float* f32[8];
-  double* f64[8];
-  for (int k = 0; k < 8; ++k) TRY(alloc_n(M, &f32[k], n));
-  for (int k = 0; k < 8; ++k) TRY(alloc_n(M, &f64[k], n));
-  M->cg32 = CGState{f32[0], f32[1], {f32[2], f32[3]}, {f32[4], f32[5]}, {f32[6], f32[7]}};
-  M->cg64 = CGState{f64[0], f64[1], {f64[2], f64[3]}, {f64[4], f64[5]}, {f64[6], f64[7]}};
+  float* f32[4];
+  double* f64[4];
+  for (int k = 0; k < 2; ++k) TRY(alloc_n(M, &f32[k], n));
+  for (int k = 2; k < 4; ++k) TRY(alloc_n(M, &f32[k], 4 * n));  // (r, s, q, D^-1) records
+  for (int k = 0; k < 2; ++k) TRY(alloc_n(M, &f64[k], n));
+  for (int k = 2; k < 4; ++k) TRY(alloc_n(M, &f64[k], 4 * n));
+  M->cg32 = CGState{f32[0], f32[1], {f32[2], f32[3]}};
+  M->cg64 = CGState{f64[0], f64[1], {f64[2], f64[3]}};
   TRY(alloc_n(M, &M->d_part, 2 * 4 * kMaxGrid));
   TRY(alloc_n(M, &M->d_scal, 8));
   TRY(alloc_n(M, &M->d_ctl, 4));

@@ -63,9 +63,7 @@ struct DevBuf {
 struct CGState {  // state of one fused-CG inner solver in precision T
   void* x = nullptr;
   void* p = nullptr;
-  void* r[2] = {nullptr, nullptr};
-  void* s[2] = {nullptr, nullptr};
-  void* q[2] = {nullptr, nullptr};
+  void* rq[2] = {nullptr, nullptr};  // per-row (r, s, q, D^-1), by launch parity
 };
 
 }  // namespace fi

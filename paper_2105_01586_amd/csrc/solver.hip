@@ -35,7 +35,9 @@
 // issued before the block reduction. When the rows fit in at most kMaxGrid
 // blocks, every block re-reduces the previous launch's per-block partial sums
 // in a fixed order; larger systems put a one-block reduction launch between
-// steps. No atomics: results are reproducible bit for bit.
+// steps. No atomics: results are reproducible bit for bit. Each row's r, s,
+// q and D^-1 sit together (one load per neighbour), and blocks are mapped to
+// rows so that every XCD works on one contiguous slab of rows.
 //
 // Precision: in mixed mode the iterations run in FP32 with FP32 SpMV
 // accumulation (dots accumulate in FP64); corrections, residuals and the
@@ -104,6 +106,22 @@ __device__ __forceinline__ T ell_weight(int32_t e) {
   return (e & kPadBit) ? T(0) : (e < 0 ? T(-1) : T(-0.5));
 }
 
+// Per-row solver values (r, s, q, D^-1) side by side: a neighbour costs
+// one aligned load instead of four.
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+  T r, s, q, d;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs (hardware block b runs on
+// XCD b % 8; the grid is a multiple of 8). Logical block (b % 8) * (G / 8) +
+// b / 8 gives each XCD one contiguous slab of rows, so the neighbour values a
+// block gathers mostly sit in its own XCD's L2.
+__device__ __forceinline__ int logical_block() {
+  const int b = blockIdx.x, per = gridDim.x >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
 template <typename T>
 struct StepArgs {
   int n;
@@ -118,12 +136,8 @@ struct StepArgs {
   const double* diag64;
   T* x;                   // the correction of the current inner solve
   T* p;
-  const T* r_in;
-  const T* s_in;
-  const T* q_in;
-  T* r_out;
-  T* s_out;
-  T* q_out;
+  const Quad<T>* rq_in;
+  Quad<T>* rq_out;
   const double* part_in;
   int nparts_in;
   double* part_out;
@@ -178,7 +192,7 @@ template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, Params* prm_out) {
   __shared__ double lds[3 * (BS / 64)];
   double v[3] = {0.0, 0.0, 0.0};
-  const int i = blockIdx.x * BS + threadIdx.x;
+  const int i = logical_block() * BS + threadIdx.x;
   if (i < A.n) {
     const double bi = A.b64[i];
     A.x64a[i] = 0.0;
@@ -217,10 +231,11 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
     red[1] += in ? a1 : 0.0;
     red[2] += in ? a2 : 0.0;
   }
-  const int i = blockIdx.x * BS + threadIdx.x;
+  const int i = logical_block() * BS + threadIdx.x;
   const bool live = i < A.n;
   const int ic = live ? i : A.n - 1;  // the tail loads a valid row, stores nothing
-  const T r0 = A.r_in[ic], s0 = A.s_in[ic], q0 = A.q_in[ic], d0 = A.dinv[ic];
+  const Quad<T> own = A.rq_in[ic];
+  const T r0 = own.r, s0 = own.s, q0 = own.q, d0 = own.d;
   const T p0 = A.p[ic], x0 = A.x[ic];
   T nr[kMaxEll], ns[kMaxEll], nq[kMaxEll], nd[kMaxEll], nw[kMaxEll];
   int32_t e[kMaxEll];
@@ -230,11 +245,11 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
       e[k] = k < A.W ? A.ell[(int64_t)k * A.n_pad + ic] : (kPadBit | ic);
 #pragma unroll
     for (int k = 0; k < kMaxEll; ++k) {
-      const int c = ell_col(e[k]);
-      nr[k] = A.r_in[c];
-      ns[k] = A.s_in[c];
-      nq[k] = A.q_in[c];
-      nd[k] = A.dinv[c];
+      const Quad<T> qn = A.rq_in[ell_col(e[k])];
+      nr[k] = qn.r;
+      ns[k] = qn.s;
+      nq[k] = qn.q;
+      nd[k] = qn.d;
       nw[k] = ell_weight<T>(e[k]);
     }
   }
@@ -275,14 +290,16 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
     const double itol = P.mixed != 0.0 ? fmax(P.inner_rtol, want) : fmax(want, 1e-15);
     const double scale = 1.0 / rnorm;
     if (live) {
+      // D^-1 from the matrix (the per-row records may not hold it yet)
+      const T di = A.dinv[i];
       const T ri = (T)(A.r64[i] * scale);
-      const T zi = d0 * ri;
+      const T zi = di * ri;
       T acc = ri;  // diagonal term: K_ii z_i = r_i
       if constexpr (ELL) {
 #pragma unroll
         for (int k = 0; k < kMaxEll; ++k) {
-          const T rc = (T)(A.r64[ell_col(e[k])] * scale);
-          acc = fmaT(nw[k], nd[k] * rc, acc);
+          const int c = ell_col(e[k]);
+          acc = fmaT(nw[k], A.dinv[c] * (T)(A.r64[c] * scale), acc);
         }
       } else {
         for (int j = A.rowptr[i]; j < A.rowptr[i + 1]; ++j) {
@@ -292,9 +309,7 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
       }
       A.x[i] = T(0);
       A.p[i] = T(0);
-      A.q_out[i] = T(0);
-      A.r_out[i] = ri;
-      A.s_out[i] = acc;
+      A.rq_out[i] = Quad<T>{ri, acc, T(0), di};
       v[0] = (double)ri * (double)zi;
       v[1] = (double)zi * (double)acc;
       v[2] = (double)ri * (double)ri;
@@ -377,14 +392,12 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
     } else {
       const int j1 = A.rowptr[i + 1];
       for (int j = A.rowptr[i]; j < j1; ++j) {
-        const int c = A.col[j];
-        const T rc = next_r(A.r_in[c], A.s_in[c], A.q_in[c], a, b);
-        acc = fmaT(A.val[j], A.dinv[c] * rc, acc);
+        const Quad<T> qc = A.rq_in[A.col[j]];
+        const T rc = next_r(qc.r, qc.s, qc.q, a, b);
+        acc = fmaT(A.val[j], qc.d * rc, acc);
       }
     }
-    A.r_out[i] = ri;
-    A.q_out[i] = qi;
-    A.s_out[i] = acc;
+    A.rq_out[i] = Quad<T>{ri, acc, qi, d0};
     v[0] = (double)ri * (double)zi;
     v[1] = (double)zi * (double)acc;
     v[2] = (double)ri * (double)ri;
@@ -484,12 +497,8 @@ StepArgs<T> make_args(fi_mesh* M, int par, int force) {
   A.diag64 = M->d_diag64;
   A.x = (T*)S.x;
   A.p = (T*)S.p;
-  A.r_in = (const T*)S.r[a];
-  A.s_in = (const T*)S.s[a];
-  A.q_in = (const T*)S.q[a];
-  A.r_out = (T*)S.r[b];
-  A.s_out = (T*)S.s[b];
-  A.q_out = (T*)S.q[b];
+  A.rq_in = (const Quad<T>*)S.rq[a];
+  A.rq_out = (Quad<T>*)S.rq[b];
   if (M->large_mode) {
     A.part_in = M->d_red4;
     A.nparts_in = 1;
@@ -682,7 +691,8 @@ int solver_setup(fi_mesh* M) {
     if (bs != 256 && bs != 512) bs = 512;  // 1024 would spill the ELL kernel
     M->cg_bs = bs;
   }
-  const int64_t blocks = (n + M->cg_bs - 1) / M->cg_bs;
+  // grid rounded up to a multiple of 8 (the XCD-aware block mapping)
+  const int64_t blocks = ((n + M->cg_bs - 1) / M->cg_bs + 7) / 8 * 8;
   if (first) {
     // FI_CG_LARGE=1 forces the separate-reduction launch shape (tests use it
     // to check that path on systems small enough for the oracle).
