@@ -233,3 +233,28 @@ def serving_trace(seed: int = 4, n: int = 256, rate_hz: float = 4.0,
         dens = float(rng.uniform(dens_lo, dens_hi))
         out.append(ServingRequest(i, t, side, dens, 1000 + i))
     return out
+
+
+def busiest_block(img: np.ndarray, block: int) -> tuple[int, int]:
+    """(row, col) origin of the block-aligned square with the most pixels
+    strictly between 0 and 255 (ties: the first in row-major order)."""
+    H, W = img.shape
+    best, arg = -1, (0, 0)
+    for r in range(0, H - block + 1, block):
+        for c in range(0, W - block + 1, block):
+            t = img[r:r + block, c:c + block]
+            cnt = int(np.count_nonzero((t > 0) & (t < 255)))
+            if cnt > best:
+                best, arg = cnt, (r, c)
+    return arg
+
+
+def crop(img: np.ndarray, mask_idx: np.ndarray, r0: int, c0: int, side: int):
+    """The side x side crop at (r0, c0) of an image and of its mask (mask
+    indices re-numbered within the crop, ascending)."""
+    W = img.shape[1]
+    rows = np.asarray(mask_idx, dtype=np.int64) // W
+    cols = np.asarray(mask_idx, dtype=np.int64) % W
+    sel = (rows >= r0) & (rows < r0 + side) & (cols >= c0) & (cols < c0 + side)
+    m = ((rows[sel] - r0) * side + (cols[sel] - c0)).astype(np.int32)
+    return np.ascontiguousarray(img[r0:r0 + side, c0:c0 + side]), np.sort(m)
