@@ -71,8 +71,8 @@ typedef struct fi_solve_opts {
   double inner_rtol; /* each inner solve reduces its residual by this factor */
   int max_inner;     /* iteration cap of one inner solve */
   int max_refine;    /* cap on refinement steps (outer FP64 residual checks) */
-  int check_every;   /* host reads the device convergence flag every this
-                        many iterations (>= 1) */
+  int check_every;   /* unused (the host reads the solver state once per
+                        chunk of launches); kept for the layout */
 } fi_solve_opts;
 
 typedef struct fi_solve_stats {
@@ -84,7 +84,9 @@ typedef struct fi_solve_stats {
 
 typedef struct fi_tonal_opts {
   fi_solve_opts inner; /* options of every inner solve */
-  double rtol;         /* stop when ||B^T(f - B g)|| <= rtol ||B^T(f - B g0)|| */
+  double rtol;         /* stop when ||B^T(f - B g)|| <= rtol ||B^T(f - B g0)||;
+                          0: run max_outer iterations (then FI_OK);
+                          < 0: 1e-8 */
   int max_outer;       /* cap on outer CG iterations */
   int start_from_g;    /* 0: start from g0 = f on the mask; 1: from g_dev */
 } fi_tonal_opts;
@@ -109,6 +111,9 @@ typedef struct fi_mesh_info {
   int64_t nnz_ff; /* stored entries of K_FF, diagonal included */
   int64_t nnz_fd; /* stored entries of K_FD */
   int64_t device_bytes; /* device memory held by the mesh */
+  int64_t cg_blocks;    /* blocks of one CG step launch (0 before assembly) */
+  int64_t cg_block_size; /* threads per block of that launch */
+  int64_t large_mode;   /* 1: a separate launch sums the step's partial sums */
 } fi_mesh_info;
 
 /* Default solve options: FP32 inner PCG with FP64 refinement to 1e-10. */
@@ -255,6 +260,90 @@ int fi_time_cg_kernel(fi_mesh* mesh, int precision, int reps, double* ms_per_lau
 /* Algorithmic bytes one launch of the fused CG iteration kernel must move
  * (matrix, row pointers, and each vector read or written once). */
 int fi_cg_kernel_bytes(const fi_mesh* mesh, int precision, int64_t* bytes);
+
+/* ------------------------------------------------------------- serving --
+ * Batched serving of requests "inpaint, then run tonal_iters CGLS iterations
+ * of tonal optimisation" (Sections 2.2 and 4) for images of any power-of-two
+ * side and mask density. Builder threads build each request's mesh on the
+ * host and admit it when its device footprint (an upper bound computed from
+ * the mesh, see fi_server_footprint) fits in the server's memory budget;
+ * the engine keeps up to max_slots requests resident and advances all their
+ * FP32 solves together, one step launch per CG step for all of them, while
+ * requests arrive and leave (continuous batching). Each request computes the
+ * same values as fi_inpaint + fi_tonal_opt with max_outer = tonal_iters,
+ * bit for bit, whatever else is in the batch.
+ *
+ * With precision FI_PREC_FP64, or max_slots == 1, the server runs one
+ * request at a time with the single-mesh solver instead (the sequential
+ * comparator).
+ *
+ * Device memory: one allocation of hbm_budget bytes at creation (the arena);
+ * requests take and return parts of it without further device allocation.
+ * All request data is copied at submission, so the caller's buffers (except
+ * g_out) may be reused at once. */
+typedef struct fi_server fi_server;
+
+typedef struct fi_server_opts {
+  int max_slots;      /* requests resident at once, 1..64 (default 16) */
+  int precision;      /* FI_PREC_FP32_IR (batched) or FI_PREC_FP64 (sequential) */
+  size_t hbm_budget;  /* bytes of the arena (default 32 GiB) */
+  int build_threads;  /* host threads building meshes (default 4) */
+  int chunk;          /* step launches per submission, even (default 8) */
+} fi_server_opts;
+
+typedef struct fi_job_desc {
+  int side;              /* image side, a power of two, 2..16384 */
+  const uint8_t* f;      /* host uint8[side * side], row-major (copied) */
+  const int32_t* mask;   /* host int32[m], strictly ascending (copied) */
+  int64_t m;             /* mask pixels, >= 1 */
+  int tonal_iters;       /* CGLS iterations after the inpainting (0: none) */
+  double* g_out;         /* host float64[m] or NULL: the optimised g (f on
+                            the mask if tonal_iters == 0), written before the
+                            request reports done; must stay valid until then */
+  fi_solve_opts inner;   /* solve options; precision is the server's */
+} fi_job_desc;
+
+typedef struct fi_job_result {
+  int32_t done;           /* 0: still running (other fields unset) */
+  int32_t status;         /* FI_OK or the request's error code */
+  double mse_inpaint;     /* MSE of the inpainting with g = f on the mask */
+  double mse_tonal;       /* MSE after the tonal iterations */
+  int64_t inner_iterations; /* CG iterations of all the request's solves */
+  double t_submit, t_admit, t_start, t_done; /* seconds on the server clock:
+                            submitted, mesh uploaded, resident, finished */
+  int64_t device_bytes;   /* arena bytes the request held */
+  int64_t footprint_bound; /* its admission bound */
+  char error[128];        /* message when status != FI_OK */
+} fi_job_result;
+
+typedef struct fi_server_stats {
+  int64_t jobs_submitted, jobs_done, jobs_failed;
+  int64_t peak_resident;  /* most requests resident at once */
+  int64_t step_rounds;    /* batched step rounds launched */
+  int64_t slot_steps;     /* sum over rounds of the requests stepped */
+  int64_t arena_bytes, arena_used_bytes, arena_peak_bytes;
+  double clock;           /* server clock now, seconds */
+} fi_server_stats;
+
+void fi_server_opts_default(fi_server_opts* opts);
+/* Creates a server on ctx's device (its own streams; ctx is not kept).
+ * Errors: FI_E_INVALID (options), FI_E_NOMEM (arena), FI_E_HIP. */
+int fi_server_create(fi_ctx* ctx, const fi_server_opts* opts, fi_server** out);
+/* Queues a request; returns its ticket. Errors: FI_E_INVALID (side, mask,
+ * sizes), FI_E_EMPTY_MASK (m == 0). Thread-safe. */
+int fi_server_submit(fi_server* server, const fi_job_desc* job, uint64_t* ticket);
+/* Result of a request; wait != 0 blocks until it is done. A done result is
+ * returned once: the ticket is then released. A request that could not be
+ * admitted (its bound exceeds the budget) ends with FI_E_NOMEM. */
+int fi_server_poll(fi_server* server, uint64_t ticket, int wait, fi_job_result* result);
+int fi_server_stats_get(fi_server* server, fi_server_stats* stats);
+/* Seconds since the server was created (the clock of fi_job_result). */
+double fi_server_clock(fi_server* server);
+/* Finishes every queued request, then frees the server. */
+int fi_server_destroy(fi_server* server);
+/* Admission bound (bytes) of a request with this mask, computed on the host
+ * from its mesh; no device use. */
+int fi_server_footprint(int side, const int32_t* mask, int64_t m, int tonal_iters, int64_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,7 @@ import numpy as np
 __all__ = [
     "FIError", "NoConvergence", "library", "Context", "Mesh", "SolveOpts", "TonalOpts",
     "PREC_FP32_IR", "PREC_FP64", "lib_path", "EXPORTED_SYMBOLS", "host_mesh", "grow_mask",
+    "Server", "ServerOpts", "footprint_bound",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +40,9 @@ EXPORTED_SYMBOLS = (
     "fi_adjoint", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
     "fi_owner_map", "fi_topk_new_pixels", "fi_time_cg_kernel", "fi_cg_kernel_bytes",
     "fi_host_mesh_build", "fi_host_mesh_info", "fi_host_mesh_export", "fi_host_mesh_destroy",
-    "fi_mesh_upload", "fi_grow_mask",
+    "fi_mesh_upload", "fi_grow_mask", "fi_server_opts_default", "fi_server_create",
+    "fi_server_submit", "fi_server_poll", "fi_server_stats_get", "fi_server_clock",
+    "fi_server_destroy", "fi_server_footprint",
 )
 
 
@@ -77,10 +80,40 @@ class _TonalStats(ctypes.Structure):
 
 class _MeshInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
-                ("N", "P", "V", "T", "L", "n", "m", "nnz_ff", "nnz_fd", "device_bytes")]
+                ("N", "P", "V", "T", "L", "n", "m", "nnz_ff", "nnz_fd", "device_bytes",
+                 "cg_blocks", "cg_block_size", "large_mode")]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int), ("precision", ctypes.c_int),
+                ("hbm_budget", ctypes.c_size_t), ("build_threads", ctypes.c_int),
+                ("chunk", ctypes.c_int)]
+
+
+class _JobDesc(ctypes.Structure):
+    _fields_ = [("side", ctypes.c_int), ("f", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("tonal_iters", ctypes.c_int), ("g_out", ctypes.c_void_p),
+                ("inner", _SolveOpts)]
+
+
+class _JobResult(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("mse_inpaint", ctypes.c_double), ("mse_tonal", ctypes.c_double),
+                ("inner_iterations", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("footprint_bound", ctypes.c_int64), ("error", ctypes.c_char * 128)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("jobs_submitted", "jobs_done", "jobs_failed", "peak_resident", "step_rounds",
+                 "slot_steps", "arena_bytes", "arena_used_bytes", "arena_peak_bytes")] + \
+               [("clock", ctypes.c_double)]
 
 
 _lib = None
+_live_servers: "weakref.WeakSet" = weakref.WeakSet()
 _live_meshes: "weakref.WeakSet" = weakref.WeakSet()
 _live_contexts: "weakref.WeakSet" = weakref.WeakSet()
 
@@ -89,7 +122,7 @@ _live_contexts: "weakref.WeakSet" = weakref.WeakSet()
 def _close_all() -> None:
     # Meshes first (they borrow their context), before the HIP runtime's own
     # exit handlers run.
-    for obj in list(_live_meshes) + list(_live_contexts):
+    for obj in list(_live_servers) + list(_live_meshes) + list(_live_contexts):
         try:
             obj.close()
         except Exception:
@@ -142,6 +175,17 @@ def library() -> ctypes.CDLL:
         "fi_mesh_upload": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "fi_grow_mask": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_int, ctypes.POINTER(_SolveOpts), vp, vp, vp]),
+        "fi_server_opts_default": (None, [ctypes.POINTER(_ServerOpts)]),
+        "fi_server_create": (ctypes.c_int, [vp, ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]),
+        "fi_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(_JobDesc),
+                                            ctypes.POINTER(ctypes.c_uint64)]),
+        "fi_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.c_int,
+                                          ctypes.POINTER(_JobResult)]),
+        "fi_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(_ServerStats)]),
+        "fi_server_clock": (ctypes.c_double, [vp]),
+        "fi_server_destroy": (ctypes.c_int, [vp]),
+        "fi_server_footprint": (ctypes.c_int, [ctypes.c_int, vp, ctypes.c_int64, ctypes.c_int,
+                                               i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -300,6 +344,10 @@ class Mesh:
     @property
     def mask(self) -> np.ndarray:
         return self._mask
+
+    def large_mode(self) -> bool:
+        """True when a separate launch sums each CG step's partial sums."""
+        return bool(self.info["large_mode"])
 
     def close(self) -> None:
         if getattr(self, "_h", None):
@@ -463,3 +511,90 @@ def grow_mask(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
                                 c(out), c(mse), c(ms))
     _check(rc, "fi_grow_mask")
     return out, mse, ms
+
+
+# ------------------------------------------------------------------ serving --
+def footprint_bound(side: int, mask_idx, tonal_iters: int = 30) -> int:
+    """Device bytes the server reserves before it admits a request (host only)."""
+    m = np.ascontiguousarray(mask_idx, dtype=np.int32)
+    out = ctypes.c_int64()
+    _check(library().fi_server_footprint(int(side), m.ctypes.data_as(ctypes.c_void_p), m.size,
+                                         int(tonal_iters), ctypes.byref(out)),
+           "fi_server_footprint")
+    return out.value
+
+
+@dataclass
+class ServerOpts:
+    """Options of a serving engine (defaults as in the C library)."""
+    max_slots: int = 16
+    precision: int = PREC_FP32_IR
+    hbm_budget: int = 32 << 30
+    build_threads: int = 4
+    chunk: int = 8
+
+    def c(self) -> _ServerOpts:
+        return _ServerOpts(self.max_slots, self.precision, self.hbm_budget, self.build_threads,
+                           self.chunk)
+
+
+class Server:
+    """Continuous-batching server: submit (image, mask) requests, collect g
+    and the MSEs. Requests run ``inpaint`` then ``tonal_iters`` CGLS
+    iterations; see ``fi_server_*`` in include/fi.h."""
+
+    def __init__(self, ctx: Context, opts: ServerOpts | None = None):
+        self.opts = opts or ServerOpts()
+        h = ctypes.c_void_p()
+        _check(library().fi_server_create(ctx._h, ctypes.byref(self.opts.c()), ctypes.byref(h)),
+               "fi_server_create")
+        self._h = h
+        self._g = {}
+        _live_servers.add(self)
+
+    def submit(self, f, mask_idx, tonal_iters: int = 30, inner: SolveOpts | None = None) -> int:
+        f = np.ascontiguousarray(f, dtype=np.uint8)
+        side = int(round(f.size ** 0.5))
+        if side * side != f.size:
+            raise FIError(E_INVALID, "image must be square")
+        m = np.ascontiguousarray(mask_idx, dtype=np.int32)
+        g = np.empty(max(m.size, 1), np.float64)
+        d = _JobDesc(side, f.ctypes.data_as(ctypes.c_void_p), m.ctypes.data_as(ctypes.c_void_p),
+                     m.size, int(tonal_iters), g.ctypes.data_as(ctypes.c_void_p),
+                     (inner or SolveOpts()).c())
+        t = ctypes.c_uint64()
+        _check(library().fi_server_submit(self._h, ctypes.byref(d), ctypes.byref(t)),
+               "fi_server_submit")
+        self._g[t.value] = g[:m.size]
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True) -> dict | None:
+        """None while running; else a dict with g, the MSEs, timings, status."""
+        r = _JobResult()
+        _check(library().fi_server_poll(self._h, ticket, int(wait), ctypes.byref(r)),
+               "fi_server_poll")
+        if not r.done:
+            return None
+        out = {k: getattr(r, k) for k, _ in r._fields_ if k != "error"}
+        out["error"] = r.error.decode(errors="replace")
+        out["g"] = self._g.pop(ticket)
+        return out
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(library().fi_server_stats_get(self._h, ctypes.byref(s)), "fi_server_stats_get")
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def clock(self) -> float:
+        return library().fi_server_clock(self._h)
+
+    def close(self) -> None:
+        if self._h:
+            library().fi_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -23,6 +23,13 @@ int fail(int code, const std::string& msg) {
 int device_alloc(fi_mesh* M, void** p, size_t bytes) {
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~(size_t)255;
+  if (M->arena) {
+    *p = M->arena->alloc(bytes);
+    if (!*p) return fail(FI_E_NOMEM, "device arena exhausted");
+    M->allocations.push_back(*p);
+    M->device_bytes += (int64_t)bytes;
+    return FI_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -52,18 +59,28 @@ int upload(fi_mesh* M, T** p, const std::vector<T>& h) {
   return FI_OK;
 }
 
+}  // namespace
+
 void free_mesh(fi_mesh* M) {
   if (!M) return;
-  // hipFree waits for outstanding work on the device; the context (and its
-  // stream) may already be gone, so only the device id is used here.
   (void)hipSetDevice(M->device);
-  (void)hipDeviceSynchronize();
-  solver_release(M);
-  for (void* p : M->allocations) (void)hipFree(p);
+  if (M->arena) {
+    // arena meshes: the owner has waited for the mesh's last work
+    solver_release(M);
+    for (void* p : M->allocations) M->arena->free(p);
+  } else {
+    // hipFree waits for outstanding work on the device; the context (and its
+    // stream) may already be gone, so only the device id is used here.
+    (void)hipDeviceSynchronize();
+    solver_release(M);
+    for (void* p : M->allocations) (void)hipFree(p);
+  }
   if (M->h_red) (void)hipHostFree(M->h_red);
   if (M->h_ctl) (void)hipHostFree(M->h_ctl);
   delete M;
 }
+
+namespace {
 
 int alloc_workspace(fi_mesh* M) {
   int rc = 0;
@@ -305,12 +322,19 @@ int fi_mesh_build(fi_ctx* ctx, int width, int height, const int32_t* mask_idx, i
 }
 
 int fi_mesh_upload(fi_ctx* ctx, fi_host_mesh** host, fi_mesh** out) {
+  return mesh_upload(ctx, host, nullptr, out);
+}
+
+}  // extern "C"
+
+int fi::mesh_upload(fi_ctx* ctx, fi_host_mesh** host, Arena* arena, fi_mesh** out) {
   if (!ctx || !out || !host || !*host) return fail(FI_E_INVALID, "NULL argument");
   *out = nullptr;
   FI_HIP_TRY(hipSetDevice(ctx->device));
   fi_mesh* M = new fi_mesh();
   M->ctx = ctx;
   M->device = ctx->device;
+  M->arena = arena;
   M->host = std::move((*host)->mesh);
   int rc = FI_OK;
   const HostMesh& H = M->host;
@@ -340,6 +364,8 @@ int fi_mesh_upload(fi_ctx* ctx, fi_host_mesh** host, fi_mesh** out) {
   return FI_OK;
 }
 
+extern "C" {
+
 int fi_mesh_destroy(fi_mesh* M) {
   free_mesh(M);
   return FI_OK;
@@ -359,6 +385,9 @@ int fi_mesh_get_info(const fi_mesh* M, fi_mesh_info* info) {
   info->nnz_ff = M->nnz_off + M->n;
   info->nnz_fd = M->nnz_fd;
   info->device_bytes = M->device_bytes;
+  info->cg_blocks = M->cg_grid;
+  info->cg_block_size = M->cg_bs;
+  info->large_mode = M->large_mode ? 1 : 0;
   return FI_OK;
 }
 
@@ -463,88 +492,6 @@ int fi_adjoint(fi_mesh* M, const double* r_dev, double* s_dev, const fi_solve_op
   return FI_OK;
 }
 
-int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev, const fi_tonal_opts* opts,
-                 fi_tonal_stats* stats) {
-  int rc = check_mesh(M);
-  if (rc) return rc;
-  if (!f_dev || !g_dev) return fail(FI_E_INVALID, "f_dev and g_dev are required");
-  FI_HIP_TRY(hipSetDevice(M->ctx->device));
-  fi_tonal_opts o;
-  fi_tonal_opts_default(&o);
-  if (opts) {
-    o = *opts;
-    if (o.rtol <= 0) o.rtol = 1e-8;
-    if (o.max_outer <= 0) o.max_outer = 500;
-  }
-  const fi_solve_opts io = resolve_opts(opts ? &opts->inner : nullptr);
-  fi_tonal_stats ts{};
-  const int64_t m = M->m, P = M->P;
-  if (!M->d_tg) {
-    if ((rc = alloc_n(M, &M->d_tg, m)) || (rc = alloc_n(M, &M->d_ts, m)) ||
-        (rc = alloc_n(M, &M->d_tr, P)) || (rc = alloc_n(M, &M->d_tq, P)))
-      return rc;
-  }
-  double* p = M->d_tg;
-  double* s = M->d_ts;
-  double* r = M->d_tr;
-  double* q = M->d_tq;
-  fi_solve_stats st{};
-  auto acc = [&](const fi_solve_stats& x) -> int {
-    ts.inner_iterations += x.iterations;
-    if (x.status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");
-    return FI_OK;
-  };
-  if (!o.start_from_g) {
-    if ((rc = launch_gather_mask(M, f_dev, g_dev))) return rc;
-  }
-  // r = f - B g
-  if ((rc = apply_B(M, g_dev, q, &io, &st)) || (rc = acc(st))) return rc;
-  if ((rc = launch_pixel_residual(M, f_dev, q, r))) return rc;
-  double rr = 0;
-  if ((rc = dot_host(M, r, r, P, &rr))) return rc;
-  ts.mse_initial = rr / (double)P;
-  // s = B^T r, p = s
-  if ((rc = apply_BT(M, r, s, &io, &st)) || (rc = acc(st))) return rc;
-  FI_HIP_TRY(hipMemcpyAsync(p, s, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice,
-                            M->ctx->stream));
-  double gamma = 0;
-  if ((rc = dot_host(M, s, s, m, &gamma))) return rc;
-  const double s0 = std::sqrt(gamma);
-  if (!std::isfinite(s0)) return fail(FI_E_INVALID, "non-finite normal residual");
-  ts.rel_normal_residual = s0 > 0 ? 1.0 : 0.0;
-  ts.status = FI_OK;
-  int it = 0;
-  if (s0 > 0) {
-    ts.status = FI_E_NO_CONVERGENCE;
-    while (it < o.max_outer) {
-      if ((rc = apply_B(M, p, q, &io, &st)) || (rc = acc(st))) return rc;
-      double qq = 0;
-      if ((rc = dot_host(M, q, q, P, &qq))) return rc;
-      if (!(qq > 0)) break;
-      const double alpha = gamma / qq;
-      if ((rc = launch_axpy(M, m, alpha, p, g_dev))) return rc;
-      if ((rc = launch_axpy(M, P, -alpha, q, r))) return rc;
-      if ((rc = apply_BT(M, r, s, &io, &st)) || (rc = acc(st))) return rc;
-      double gnew = 0;
-      if ((rc = dot_host(M, s, s, m, &gnew))) return rc;
-      ++it;
-      ts.rel_normal_residual = std::sqrt(gnew) / s0;
-      if (ts.rel_normal_residual <= o.rtol) { ts.status = FI_OK; break; }
-      const double beta = gnew / gamma;
-      if ((rc = launch_xpby(M, m, s, beta, p))) return rc;
-      gamma = gnew;
-    }
-  }
-  ts.outer_iterations = it;
-  double mse = 0;
-  if ((rc = apply_B(M, g_dev, q, &io, &st)) || (rc = acc(st))) return rc;
-  if ((rc = mse_of(M, q, f_dev, &mse))) return rc;
-  ts.mse_final = mse;
-  if (stats) *stats = ts;
-  if (ts.status != FI_OK)
-    return fail(FI_E_NO_CONVERGENCE, "tonal optimisation reached the outer iteration cap");
-  return FI_OK;
-}
 
 int fi_mesh_export_geometry(const fi_mesh* M, int32_t* vxy, int32_t* tri, int32_t* leaves,
                             int32_t* free_vids, int32_t* mask_vids) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,6 +62,28 @@ struct DevBuf {
   int64_t n = 0;
 };
 
+// Device memory carved out of one allocation (the serving path): first fit
+// over a sorted free list, 256-byte granules, neighbours merged on free. The
+// bookkeeping is on the host; no call here touches the device except
+// init/release, so taking and returning memory never synchronises it.
+class Arena {
+ public:
+  int init(int device, size_t bytes);  // one hipMalloc of `bytes`
+  void release();                      // hipFree of the whole block
+  void* alloc(size_t bytes);           // nullptr when no free range fits
+  void free(void* p);
+  size_t capacity() const { return cap_; }
+  size_t used() const;
+  size_t peak() const;
+
+ private:
+  mutable std::mutex mu_;
+  char* base_ = nullptr;
+  size_t cap_ = 0, used_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;   // offset -> bytes
+  std::map<size_t, size_t> live_;   // offset -> bytes
+};
+
 struct CGState {  // state of one fused-CG inner solver in precision T
   void* x = nullptr;
   void* p = nullptr;
@@ -88,6 +112,7 @@ struct fi_mesh {
   int64_t nnz_df = 0;   // entries of K_DF
   int64_t device_bytes = 0;
   std::vector<void*> allocations;
+  fi::Arena* arena = nullptr;  // set: memory comes from (and returns to) it
 
   // geometry (device)
   int32_t* d_vxy = nullptr;
@@ -164,6 +189,7 @@ struct fi_mesh {
   double* d_ts = nullptr;  // m: s
   double* d_tr = nullptr;  // P: r
   double* d_tq = nullptr;  // P: q
+  double* d_tsc = nullptr; // CGLS scalars (see Cgls)
 
   // top-k workspace (device, allocated on first use)
   void* d_topk = nullptr;
@@ -176,6 +202,12 @@ constexpr int kBlock = 256;      // threads per block of the vector kernels
 constexpr int kMaxGrid = 1024;   // cap on blocks of the fused CG kernel
 
 int device_alloc(fi_mesh* M, void** p, size_t bytes);
+// Uploads a host mesh and assembles it; memory from `arena` when not NULL.
+// On success the host mesh is consumed (*host set to NULL).
+int mesh_upload(fi_ctx* ctx, fi_host_mesh** host, Arena* arena, fi_mesh** out);
+// Frees a mesh. A mesh without an arena waits for the device first; an arena
+// mesh returns its memory at once (its owner has waited for its last work).
+void free_mesh(fi_mesh* M);
 
 // Kernel launchers (kernels.hip). All stream-ordered, no host sync.
 int launch_assemble_count(fi_mesh* M, bool free_rows);
@@ -198,8 +230,12 @@ int launch_gather_vertex(fi_mesh* M, const double* tpart, double* tF, double* tD
 int launch_adjoint_tail(fi_mesh* M, const double* tD, const double* y, double* s);
 int launch_reduce(fi_mesh* M, const double* part, int nparts, int ncomp, double* out);
 int launch_dot(fi_mesh* M, const double* a, const double* b, int64_t n, double* out_dev);
-int launch_axpy(fi_mesh* M, int64_t n, double alpha, const double* x, double* y);
-int launch_xpby(fi_mesh* M, int64_t n, const double* x, double beta, double* y);
+// y += sign * (num / den) x and y = x + (num / den) y, the ratio read from
+// device scalars (0 when den <= 0).
+int launch_axpy_ratio(fi_mesh* M, int64_t n, const double* num, const double* den, double sign,
+                      const double* x, double* y);
+int launch_xpby_ratio(fi_mesh* M, int64_t n, const double* x, const double* num, const double* den,
+                      double* y);
 int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r);
 
 // Solver pieces (solver.hip).
@@ -209,6 +245,45 @@ void solver_release(fi_mesh* M);   // graphs and events
 int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats);
 int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms);
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision);
+
+// Batched stepping (solver.hip): the FP32 solves of several meshes advance
+// together, one step launch for all of them (for up to 20 meshes; more take
+// further launches per step).
+constexpr int kMaxSlots = 64;  // meshes a server keeps resident at once
+constexpr int kBatchBS = 512;  // the batched step needs this block size
+struct BatchSlot {
+  fi_mesh* M;
+};
+size_t solver_record_bytes();  // one mesh's pair of records
+// `count` (even) step launches over the meshes in `act`, parity 0 first.
+int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int count);
+// Start of an FP32 solve of K_FF x = b64 that the batch then steps.
+int solve_arm(fi_mesh* M, const fi_solve_opts* opts);
+// Reads a copy of the parity-0 record of a mesh: *done = 1 once the solve
+// has ended (stats filled, d_x64 set to the result).
+int solve_poll(fi_mesh* M, const void* rec_host, fi_solve_stats* stats, int* done);
+
+// CGLS on the normal equations B^T B g = B^T f (Section 4), split into
+// segments that each end in one solve with K_FF: the caller runs pre(),
+// then the solve of K_FF x = b64, then post(). All scalars of the method stay
+// on the device, so the same segments serve the host-driven call and the
+// batched server bit for bit.
+struct Cgls {
+  enum Seg : int { kInpaint = 0, kAdjoint = 1, kApplyP = 2, kFinal = 3, kDone = 4 };
+  // device scalar slots in d_tsc
+  enum : int { kScRR0 = 0, kScGamma = 1 /* and 2, by iteration parity */, kScQQ = 3, kScSSE = 4 };
+  fi_mesh* M = nullptr;
+  const uint8_t* f = nullptr;  // device image
+  double* g = nullptr;         // device, m: in the start (if start_from_g), out g
+  bool start_from_g = false;
+  int k = 0;                   // B p products applied
+  Seg seg = kInpaint;
+
+  int alloc();                 // tonal workspace (first use)
+  int pre();                   // right-hand side of the segment's solve into b64
+  int post();                  // consumes d_x64; does not advance seg
+  const double* scalar(int i) const { return M->d_tsc + i; }
+};
 
 // Top-k (topk.hip).
 int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out);

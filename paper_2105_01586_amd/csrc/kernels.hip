@@ -465,17 +465,29 @@ __global__ __launch_bounds__(kBlock) void k_dot_part(const double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, double alpha,
-                                                 const double* __restrict__ x,
-                                                 double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) y[i] += alpha * x[i];
+// Ratio of two device scalars, or 0 when the denominator is not positive
+// (a step of length zero where CG would divide by zero).
+__device__ __forceinline__ double ratio(const double* num, const double* den) {
+  const double d = *den;
+  return d > 0.0 ? *num / d : 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_xpby(int64_t n, const double* __restrict__ x,
-                                                 double beta, double* __restrict__ y) {
+// y += sign * (num / den) x
+__global__ __launch_bounds__(kBlock) void k_axpy_ratio(int64_t n, const double* __restrict__ num,
+                                                       const double* __restrict__ den, double sign,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) y[i] = x[i] + beta * y[i];
+  if (i < n) y[i] += sign * ratio(num, den) * x[i];
+}
+
+// y = x + (num / den) y
+__global__ __launch_bounds__(kBlock) void k_xpby_ratio(int64_t n, const double* __restrict__ x,
+                                                       const double* __restrict__ num,
+                                                       const double* __restrict__ den,
+                                                       double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = x[i] + ratio(num, den) * y[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_pixel_residual(int64_t P, const uint8_t* __restrict__ f,
@@ -606,16 +618,20 @@ int launch_dot(fi_mesh* M, const double* a, const double* b, int64_t n, double* 
   return launch_reduce(M, M->d_red, g, 1, out_dev);
 }
 
-int launch_axpy(fi_mesh* M, int64_t n, double alpha, const double* x, double* y) {
+int launch_axpy_ratio(fi_mesh* M, int64_t n, const double* num, const double* den, double sign,
+                      const double* x, double* y) {
   if (n == 0) return FI_OK;
-  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, alpha, x, y);
+  hipLaunchKernelGGL(k_axpy_ratio, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, num, den,
+                     sign, x, y);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }
 
-int launch_xpby(fi_mesh* M, int64_t n, const double* x, double beta, double* y) {
+int launch_xpby_ratio(fi_mesh* M, int64_t n, const double* x, const double* num, const double* den,
+                      double* y) {
   if (n == 0) return FI_OK;
-  hipLaunchKernelGGL(k_xpby, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, x, beta, y);
+  hipLaunchKernelGGL(k_xpby_ratio, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, x, num,
+                     den, y);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }

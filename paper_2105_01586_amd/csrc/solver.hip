@@ -177,13 +177,14 @@ __device__ __forceinline__ void put_rec(Rec* out, int phase, int iter, int total
   *out = r;
 }
 
-template <int BS>
-__device__ __forceinline__ void store_partials_bs(double* part_out, double (&v)[3]) {
+// Partial sums of block `lb` (the logical block: the index is what fixes the
+// order in which the next launch adds them up).
+__device__ __forceinline__ void store_partials(double* part_out, int lb, double (&v)[3]) {
   if (threadIdx.x == 0) {
-    part_out[4 * blockIdx.x] = v[0];
-    part_out[4 * blockIdx.x + 1] = v[1];
-    part_out[4 * blockIdx.x + 2] = v[2];
-    part_out[4 * blockIdx.x + 3] = 0.0;
+    part_out[4 * lb] = v[0];
+    part_out[4 * lb + 1] = v[1];
+    part_out[4 * lb + 2] = v[2];
+    part_out[4 * lb + 3] = 0.0;
   }
 }
 
@@ -192,7 +193,8 @@ template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, Params* prm_out) {
   __shared__ double lds[3 * (BS / 64)];
   double v[3] = {0.0, 0.0, 0.0};
-  const int i = logical_block() * BS + threadIdx.x;
+  const int lb = logical_block();
+  const int i = lb * BS + threadIdx.x;
   if (i < A.n) {
     const double bi = A.b64[i];
     A.x64a[i] = 0.0;
@@ -200,8 +202,8 @@ __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, P
     v[0] = bi * bi;
   }
   block_sum_w<3, BS / 64>(v, lds);
-  store_partials_bs<BS>(A.part_out, v);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  store_partials(A.part_out, lb, v);
+  if (lb == 0 && threadIdx.x == 0) {
     *prm_out = prm;
     Rec r{};
     r.phase = kInit;
@@ -209,11 +211,10 @@ __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, P
   }
 }
 
-// One step of the solve (see the file comment). One thread per row, BS
-// threads per block.
+// One step of the solve (see the file comment) for the rows of logical block
+// lb. One thread per row, BS threads per block.
 template <typename T, bool ELL, int BS>
-__global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
-  __shared__ double lds[3 * (BS / 64)];
+__device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, double* lds) {
   // The record slot read here is written only by the next launch, so every
   // thread reads it directly: uniform scalar loads, values kept read-only.
   const Rec Rin = *A.rec_in;
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
     red[1] += in ? a1 : 0.0;
     red[2] += in ? a2 : 0.0;
   }
-  const int i = logical_block() * BS + threadIdx.x;
+  const int i = lb * BS + threadIdx.x;
   const bool live = i < A.n;
   const int ic = live ? i : A.n - 1;  // the tail loads a valid row, stores nothing
   const Quad<T> own = A.rq_in[ic];
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
     }
   }
   block_sum_w<3, BS / 64>(red, lds);
-  const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool writer = lb == 0 && threadIdx.x == 0;
   const int phase = A.force ? (int)kIter : Rin.phase;
   double v[3] = {0.0, 0.0, 0.0};
 
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
       v[2] = (double)ri * (double)ri;
     }
     block_sum_w<3, BS / 64>(v, lds);
-    store_partials_bs<BS>(A.part_out, v);
+    store_partials(A.part_out, lb, v);
     if (writer)
       put_rec(A.rec_out, kIter, 0, Rin.total, Rin.ninner + 1, stagnant, Rin.xp, 0.0, 0.0, 0.0,
               itol * itol, rnorm, bnorm);
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
       v[0] = ri * ri;
     }
     block_sum_w<3, BS / 64>(v, lds);
-    store_partials_bs<BS>(A.part_out, v);
+    store_partials(A.part_out, lb, v);
     if (writer)
       put_rec(A.rec_out, kInit, iter, Rin.total + iter, Rin.ninner, Rin.stagnant, Rin.xp ^ 1,
               gamma, alpha, rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
@@ -403,16 +404,21 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
     v[2] = (double)ri * (double)ri;
   }
   block_sum_w<3, BS / 64>(v, lds);
-  store_partials_bs<BS>(A.part_out, v);
+  store_partials(A.part_out, lb, v);
   if (writer)
     put_rec(A.rec_out, kIter, iter + 1, Rin.total, Rin.ninner, Rin.stagnant, Rin.xp, gamma, alpha,
             rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
 }
 
+template <typename T, bool ELL, int BS>
+__global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
+  __shared__ double lds[3 * (BS / 64)];
+  step_body<T, ELL, BS>(A, logical_block(), lds);
+}
+
 // Large systems: one block sums the per-block partials between steps.
-__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __restrict__ part,
-                                                            int nparts, double* __restrict__ out) {
-  __shared__ double lds[12];
+__device__ __forceinline__ void reduce_partials_body(const double* __restrict__ part, int nparts,
+                                                     double* __restrict__ out, double* lds) {
   double v[3] = {0.0, 0.0, 0.0};
   for (int j = threadIdx.x; j < nparts; j += kBlock) {
     v[0] += part[4 * j];
@@ -426,6 +432,61 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
     out[2] = v[2];
     out[3] = 0.0;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __restrict__ part,
+                                                            int nparts, double* __restrict__ out) {
+  __shared__ double lds[12];
+  reduce_partials_body(part, nparts, out, lds);
+}
+
+// ---------------------------------------------------------- batched steps --
+// Several meshes' FP32 solves advance in one launch. The grid is the
+// concatenation of every slot's own grid (each a multiple of 8); a block finds
+// its slot from the start offsets, then runs exactly the code of the
+// single-mesh step on that slot's arguments with its slot-local logical block,
+// so a solve gives the same bits alone or in any batch. The arguments travel
+// by value (pointers in by-value kernel arguments are known to be global, so
+// the step keeps its SGPR-based addressing), which caps a launch at
+// kArgSlots slots.
+constexpr int kArgSlots = 20;
+
+struct BatchArgs {
+  int n;                         // slots in this launch
+  int32_t start[kArgSlots + 1];  // first logical block of each slot; start[n] = grid
+  StepArgs<float> a[kArgSlots];
+};
+
+static_assert(sizeof(BatchArgs) <= 4096, "kernel arguments of a batched step");
+
+struct ReduceArgs {
+  int n;
+  int32_t nparts[kArgSlots];
+  const double* part[kArgSlots];
+  double* out[kArgSlots];
+};
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_step_batch(BatchArgs B) {
+  __shared__ double lds[3 * (BS / 64)];
+  const int lb = logical_block();
+  int j = 0;  // slot of this block (uniform: scalar registers)
+#pragma unroll
+  for (int k = 1; k < kArgSlots; ++k) j += (k < B.n && B.start[k] <= lb) ? 1 : 0;
+  const StepArgs<float>& A = B.a[j];
+  const int lblk = lb - B.start[j];
+  if (A.rec_in->phase >= kDoneOk) {  // idle slot: keep its record, skip the work
+    if (lblk == 0 && threadIdx.x == 0) *A.rec_out = *A.rec_in;
+    return;
+  }
+  step_body<float, true, BS>(A, lblk, lds);
+}
+
+// One block per large-mode slot: the same sums as k_reduce_partials.
+__global__ __launch_bounds__(kBlock) void k_reduce_batch(ReduceArgs R) {
+  __shared__ double lds[12];
+  const int b = blockIdx.x;
+  reduce_partials_body(R.part[b], R.nparts[b], R.out[b], lds);
 }
 
 // ELL packing of the CSR off-diagonal part; flags values other than -1/2, -1.
@@ -664,6 +725,86 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
 }
 
 }  // namespace
+
+size_t solver_record_bytes() { return 2 * sizeof(Rec); }
+
+int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int count) {
+  if (act.empty() || count <= 0) return FI_OK;
+  for (const BatchSlot& s : act)
+    if (s.M->ell_w <= 0 || s.M->cg_bs != kBatchBS || s.M->n <= 0)
+      return fail(FI_E_INVALID, "mesh cannot take part in a batched solve");
+  // launches of at most kArgSlots slots each, both parities prepared
+  struct Launch {
+    BatchArgs b[2];
+    ReduceArgs r[2];
+    int64_t grid;
+  };
+  std::vector<Launch> L;
+  for (size_t j0 = 0; j0 < act.size(); j0 += kArgSlots) {
+    Launch l{};
+    const size_t j1 = std::min(act.size(), j0 + kArgSlots);
+    int64_t total = 0;
+    for (int par = 0; par < 2; ++par) {
+      l.b[par].n = (int)(j1 - j0);
+      l.r[par].n = 0;
+    }
+    for (size_t j = j0; j < j1; ++j) {
+      fi_mesh* M = act[j].M;
+      const int q = (int)(j - j0);
+      for (int par = 0; par < 2; ++par) {
+        l.b[par].start[q] = (int32_t)total;
+        l.b[par].a[q] = make_args<float>(M, par, 0);
+        if (M->large_mode) {
+          ReduceArgs& r = l.r[par];
+          // after the step of parity par: its partials (slot par ^ 1) -> d_red4
+          r.part[r.n] = M->d_part + (size_t)(par ^ 1) * 4 * M->cg_grid;
+          r.nparts[r.n] = M->cg_grid;
+          r.out[r.n] = M->d_red4;
+          ++r.n;
+        }
+      }
+      total += M->cg_grid;
+    }
+    if (total >= (int64_t)1 << 30) return fail(FI_E_INVALID, "batch grid too large");
+    for (int par = 0; par < 2; ++par) l.b[par].start[j1 - j0] = (int32_t)total;
+    l.grid = total;
+    L.push_back(l);
+  }
+  for (int k = 0; k < count; ++k) {
+    const int par = k & 1;
+    for (Launch& l : L) {
+      void* args[1] = {&l.b[par]};
+      FI_HIP_TRY(hipLaunchKernel((void*)k_step_batch<kBatchBS>, dim3((unsigned)l.grid),
+                                 dim3(kBatchBS), args, 0, st));
+    }
+    for (Launch& l : L) {
+      if (l.r[par].n == 0) continue;
+      void* rargs[1] = {&l.r[par]};
+      FI_HIP_TRY(hipLaunchKernel((void*)k_reduce_batch, dim3(l.r[par].n), dim3(kBlock), rargs, 0,
+                                 st));
+    }
+  }
+  return FI_OK;
+}
+
+int solve_arm(fi_mesh* M, const fi_solve_opts* o) {
+  if (M->n <= 0) return fail(FI_E_INVALID, "nothing to solve");
+  return launch_start<float>(M, o);
+}
+
+int solve_poll(fi_mesh* M, const void* rec_host, fi_solve_stats* stats, int* done) {
+  const Rec& R = *(const Rec*)rec_host;
+  *done = 0;
+  if (R.phase < kDoneOk) return FI_OK;
+  *done = 1;
+  stats->iterations = R.total;
+  stats->refinements = R.ninner;
+  stats->rel_residual = R.bnorm > 0 ? R.rnorm / R.bnorm : 0.0;
+  stats->status = R.phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
+  M->d_x64 = M->d_x64buf[R.xp];
+  if (R.phase == kDoneBad) return fail(FI_E_INVALID, "right-hand side or residual not finite");
+  return FI_OK;
+}
 
 void solver_release(fi_mesh* M) {
   for (int k = 0; k < 2; ++k) {

@@ -1,0 +1,198 @@
+// Tonal optimisation (Section 4): the least-squares problem min ||B g - f||^2
+// over the values g stored at the mask, with B = interpolation after the
+// harmonic solve, solved by CG on the normal equations B^T B g = B^T f in the
+// least-squares (CGLS) form. B^T B is never formed: each iteration applies B
+// once (a solve with K_FF) and B^T once (transposed interpolation, then the
+// same solve).
+//
+// The iteration is split into segments that each end with one solve, so the
+// same code runs host-driven here (fi_tonal_opt) and batched in the server.
+// Every scalar of the method (gamma = ||s||^2, ||q||^2, the step lengths) is
+// computed and consumed on the device.
+#include <cmath>
+
+#include "internal.h"
+
+namespace fi {
+
+int Cgls::alloc() {
+  if (M->d_tsc) return FI_OK;
+  const int64_t m = M->m, P = M->P;
+  int rc = 0;
+  if ((rc = device_alloc(M, (void**)&M->d_tg, (size_t)std::max<int64_t>(m, 1) * 8)) ||
+      (rc = device_alloc(M, (void**)&M->d_ts, (size_t)std::max<int64_t>(m, 1) * 8)) ||
+      (rc = device_alloc(M, (void**)&M->d_tr, (size_t)P * 8)) ||
+      (rc = device_alloc(M, (void**)&M->d_tq, (size_t)P * 8)) ||
+      (rc = device_alloc(M, (void**)&M->d_tsc, 8 * sizeof(double))))
+    return rc;
+  return FI_OK;
+}
+
+namespace {
+double* gamma_slot(fi_mesh* M, int k) { return M->d_tsc + Cgls::kScGamma + (k & 1); }
+}  // namespace
+
+int Cgls::pre() {
+  int rc = FI_OK;
+  switch (seg) {
+    case kInpaint:  // B g0: g0 = f on the mask unless given
+      if (!start_from_g && (rc = launch_gather_mask(M, f, g))) return rc;
+      return launch_lift(M, g, M->d_b64);
+    case kAdjoint:  // B^T r: t = R^T r, solve with t_F
+      if ((rc = launch_raster_transpose(M, M->d_tr, M->d_tpart))) return rc;
+      if ((rc = launch_gather_vertex(M, M->d_tpart, M->d_tF, M->d_tD))) return rc;
+      FI_HIP_TRY(hipMemcpyAsync(M->d_b64, M->d_tF, (size_t)M->n * sizeof(double),
+                                hipMemcpyDeviceToDevice, M->ctx->stream));
+      return FI_OK;
+    case kApplyP:  // q = B p
+      return launch_lift(M, M->d_tg, M->d_b64);
+    case kFinal:   // B g for the final error
+      return launch_lift(M, g, M->d_b64);
+    default:
+      return fail(FI_E_INVALID, "CGLS: no solve in this segment");
+  }
+}
+
+int Cgls::post() {
+  int rc = FI_OK;
+  double* p = M->d_tg;
+  double* s = M->d_ts;
+  double* r = M->d_tr;
+  double* q = M->d_tq;
+  double* sc = M->d_tsc;
+  const int64_t m = M->m, P = M->P;
+  switch (seg) {
+    case kInpaint:  // r = f - B g0, ||r||^2
+      if ((rc = launch_vertex_values(M, M->d_x64, g, M->d_uvert)) ||
+          (rc = launch_raster(M, M->d_uvert, nullptr, nullptr, q, nullptr, nullptr, nullptr,
+                              nullptr)) ||
+          (rc = launch_pixel_residual(M, f, q, r)))
+        return rc;
+      return launch_dot(M, r, r, P, sc + kScRR0);
+    case kAdjoint:  // s = t_D - K_DF y; first: p = s; later: p = s + (gamma_k / gamma_k-1) p
+      if ((rc = launch_adjoint_tail(M, M->d_tD, M->d_x64, s))) return rc;
+      if ((rc = launch_dot(M, s, s, m, gamma_slot(M, k)))) return rc;
+      if (k == 0) {
+        FI_HIP_TRY(hipMemcpyAsync(p, s, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice,
+                                  M->ctx->stream));
+        return FI_OK;
+      }
+      return launch_xpby_ratio(M, m, s, gamma_slot(M, k), gamma_slot(M, k - 1), p);
+    case kApplyP: {  // alpha = gamma / ||q||^2; g += alpha p; r -= alpha q
+      if ((rc = launch_vertex_values(M, M->d_x64, p, M->d_uvert)) ||
+          (rc = launch_raster(M, M->d_uvert, nullptr, nullptr, q, nullptr, nullptr, nullptr,
+                              nullptr)) ||
+          (rc = launch_dot(M, q, q, P, sc + kScQQ)))
+        return rc;
+      const double* gam = gamma_slot(M, k);
+      if ((rc = launch_axpy_ratio(M, m, gam, sc + kScQQ, 1.0, p, g)) ||
+          (rc = launch_axpy_ratio(M, P, gam, sc + kScQQ, -1.0, q, r)))
+        return rc;
+      ++k;
+      return FI_OK;
+    }
+    case kFinal:  // sum of squared errors of B g
+      if ((rc = launch_vertex_values(M, M->d_x64, g, M->d_uvert)) ||
+          (rc = launch_raster(M, M->d_uvert, nullptr, nullptr, q, nullptr, nullptr, nullptr,
+                              nullptr)) ||
+          (rc = launch_raster(M, nullptr, q, f, nullptr, nullptr, nullptr, nullptr, M->d_rpart)))
+        return rc;
+      return launch_reduce(M, M->d_rpart, raster_blocks(M), 1, sc + kScSSE);
+    default:
+      return fail(FI_E_INVALID, "CGLS: nothing to do after the last segment");
+  }
+}
+
+namespace {
+
+int read_scalars(fi_mesh* M, double* out, int count) {
+  FI_HIP_TRY(hipMemcpyAsync(M->h_red, M->d_tsc, (size_t)count * sizeof(double),
+                            hipMemcpyDeviceToHost, M->ctx->stream));
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  for (int i = 0; i < count; ++i) out[i] = M->h_red[i];
+  return FI_OK;
+}
+
+}  // namespace
+}  // namespace fi
+
+using namespace fi;
+
+extern "C" int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
+                            const fi_tonal_opts* opts, fi_tonal_stats* stats) {
+  if (!M || !M->ctx) return fail(FI_E_INVALID, "mesh is NULL");
+  if (!f_dev || !g_dev) return fail(FI_E_INVALID, "f_dev and g_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  fi_tonal_opts o;
+  fi_tonal_opts_default(&o);
+  if (opts) {
+    o = *opts;
+    if (o.rtol < 0) o.rtol = 1e-8;
+    if (o.max_outer <= 0) o.max_outer = 500;
+  }
+  fi_solve_opts io;
+  fi_solve_opts_default(&io);
+  if (opts) {
+    io = opts->inner;
+    fi_solve_opts d;
+    fi_solve_opts_default(&d);
+    if (io.rtol <= 0) io.rtol = d.rtol;
+    if (io.inner_rtol <= 0 || io.inner_rtol >= 1) io.inner_rtol = d.inner_rtol;
+    if (io.max_inner <= 0) io.max_inner = d.max_inner;
+    if (io.max_refine <= 0) io.max_refine = d.max_refine;
+    if (io.check_every <= 0) io.check_every = d.check_every;
+  }
+  fi_tonal_stats ts{};
+  Cgls c;
+  c.M = M;
+  c.f = f_dev;
+  c.g = g_dev;
+  c.start_from_g = o.start_from_g != 0;
+  int rc = c.alloc();
+  if (rc) return rc;
+  auto run = [&](Cgls::Seg seg) -> int {
+    c.seg = seg;
+    int r = c.pre();
+    if (r) return r;
+    fi_solve_stats st{};
+    r = solve_free(M, &io, &st);
+    ts.inner_iterations += st.iterations;
+    if (r) return r;
+    if (st.status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");
+    return c.post();
+  };
+  double sc[8] = {0};
+  if ((rc = run(Cgls::kInpaint)) || (rc = run(Cgls::kAdjoint))) return rc;
+  if ((rc = read_scalars(M, sc, 8))) return rc;
+  const double s0 = std::sqrt(sc[Cgls::kScGamma]);
+  if (!std::isfinite(s0)) return fail(FI_E_INVALID, "non-finite normal residual");
+  ts.mse_initial = sc[Cgls::kScRR0] / (double)M->P;
+  ts.rel_normal_residual = s0 > 0 ? 1.0 : 0.0;
+  ts.status = FI_OK;
+  int it = 0;
+  if (s0 > 0) {
+    ts.status = FI_E_NO_CONVERGENCE;
+    while (it < o.max_outer) {
+      if ((rc = run(Cgls::kApplyP))) return rc;
+      if ((rc = read_scalars(M, sc, 8))) return rc;
+      if (!(sc[Cgls::kScQQ] > 0)) break;  // B p = 0: no further progress
+      if ((rc = run(Cgls::kAdjoint))) return rc;
+      ++it;
+      if ((rc = read_scalars(M, sc, 8))) return rc;
+      ts.rel_normal_residual = std::sqrt(sc[Cgls::kScGamma + (c.k & 1)]) / s0;
+      if (ts.rel_normal_residual <= o.rtol) {
+        ts.status = FI_OK;
+        break;
+      }
+    }
+  }
+  ts.outer_iterations = it;
+  if (o.rtol == 0.0) ts.status = FI_OK;  // a fixed number of iterations was asked for
+  if ((rc = run(Cgls::kFinal))) return rc;
+  if ((rc = read_scalars(M, sc, 8))) return rc;
+  ts.mse_final = sc[Cgls::kScSSE] / (double)M->P;
+  if (stats) *stats = ts;
+  if (ts.status != FI_OK)
+    return fail(FI_E_NO_CONVERGENCE, "tonal optimisation reached the outer iteration cap");
+  return FI_OK;
+}

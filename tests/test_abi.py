@@ -93,3 +93,20 @@ def test_host_mesh_errors(side, mask, code):
     with pytest.raises(fi.FIError) as ei:
         fi.host_mesh(side, mask)
     assert ei.value.code == code
+
+
+def test_footprint_bound_host_only():
+    """The server's admission bound is computed on the host from the mesh:
+    positive, growing with the mesh, and rejecting bad masks."""
+    side = 128
+    small = synth.make_mask(7, side * side, 0.02)
+    large = synth.make_mask(7, side * side, 0.10)
+    b_small = fi.footprint_bound(side, small)
+    b_large = fi.footprint_bound(side, large)
+    P = side * side
+    assert b_small > 2 * 8 * P + P      # at least r, q (float64) and f per pixel
+    assert b_large > b_small
+    with pytest.raises(fi.FIError):
+        fi.footprint_bound(side, small[::-1].copy())
+    with pytest.raises(fi.FIError):
+        fi.footprint_bound(100, small)
