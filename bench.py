@@ -2,7 +2,8 @@
 
 One step = one pass of the hot path over the 512 x 512 synthetic image with a
 4% random mask (the mixed-precision + tonal-optimisation workload; the
-default; ``--workload large8192`` runs the 8192 x 8192 / 2% image instead):
+default; ``--workload large8192`` runs the 8192 x 8192 / 2% image instead,
+``--workload serving`` the batched-serving trace, see ``serving_main``):
   assembly of the stiffness matrix, inpainting u = B g with FP32 Jacobi-PCG +
   FP64 iterative refinement to relative residual 1e-10, interpolation to
   pixels and MSE (the "inpainting" phase), then tonal optimisation by CGLS to
@@ -39,7 +40,16 @@ def parse():
                     help="timed steps (default 5; 1 for the 8192^2 workload)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps (default 2; 0 for the 8192^2 workload)")
-    ap.add_argument("--workload", default="tonal512")
+    ap.add_argument("--workload", default="tonal512",
+                    help="tonal512 (default), large8192 or serving")
+    ap.add_argument("--requests", type=int, default=256, help="serving: requests in the trace")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving: arrivals per second (default 0.7 x FP64 capacity)")
+    ap.add_argument("--capacity-sample", type=int, default=64,
+                    help="serving: requests timed to measure the FP64 capacity")
+    ap.add_argument("--max-slots", type=int, default=16)
+    ap.add_argument("--build-threads", type=int, default=8)
+    ap.add_argument("--hbm-budget-gb", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--skip-fp64", action="store_true")
@@ -71,12 +81,151 @@ def cpu_baseline(side, f_np, mask, u_gpu, what):
                       f"solve, interpolation, MSE), {el:.1f} s"}, err
 
 
+def _gen(req):
+    return req.image().ravel(), req.mask()
+
+
+def serving_main(args):
+    """The batched-serving workload: a Poisson trace of requests (side
+    uniform over 128..2048, mask density U[2%, 10%]), each one inpainting +
+    30 CGLS iterations (FP32 inner solves, FP64 residuals).
+
+    1. Plain FP64 GPU server, one request at a time, all requests of the first
+       ``--capacity-sample`` queued at once: its capacity mu (requests/s).
+    2. The arrival rate is 0.7 mu (a load the sequential FP64 server can
+       sustain); the trace is drawn at that rate.
+    3. The batched FP32 server on the whole trace queued at once (throughput:
+       ``value``), then replayed at the trace's arrival times and at twice the
+       rate (p50 / p99 latency), and the FP64 server replayed at the trace's
+       arrival times (its p50 / p99)."""
+    import concurrent.futures as cf
+    import torch
+    import paper_2105_01586_amd as fi
+    from paper_2105_01586_amd import serving
+    import synth
+
+    iters = 30
+    trace = synth.serving_trace(seed=4, n=args.requests)
+    t = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        reqs = list(ex.map(_gen, trace, chunksize=4))
+    print(f"generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr,
+          flush=True)
+    ctx = fi.Context(0)
+    budget = args.hbm_budget_gb << 30
+    base = dict(hbm_budget=budget, build_threads=args.build_threads)
+    # 1. FP64 sequential capacity
+    k = min(args.capacity_sample, len(reqs))
+    with fi.Server(ctx, fi.ServerOpts(max_slots=1, precision=fi.PREC_FP64, **base)) as S:
+        cap = serving.summarize(serving.replay(S, reqs[:k], np.zeros(k), iters))
+    mu = cap["requests_per_s"]
+    rate = args.rate if args.rate else 0.7 * mu
+    print(f"FP64 sequential capacity {mu:.2f} req/s; rate {rate:.2f} req/s", file=sys.stderr,
+          flush=True)
+    # the same trace drawn at that rate: identical sides, densities and
+    # images; the exponential gaps scale with 1 / rate
+    arr = np.array([r.arrival_s for r in synth.serving_trace(seed=4, n=len(reqs), rate_hz=rate)])
+    out = {}
+    bopts = fi.ServerOpts(max_slots=args.max_slots, **base)
+    with fi.Server(ctx, bopts) as S:
+        closed = serving.summarize(serving.replay(S, reqs, np.zeros(len(reqs)), iters))
+        st_closed = S.stats()
+    print(f"batched closed loop {closed['mpixel_per_s']:.1f} Mpixel/s", file=sys.stderr,
+          flush=True)
+    with fi.Server(ctx, bopts) as S:
+        at1 = serving.summarize(serving.replay(S, reqs, arr, iters))
+        st1 = S.stats()
+    print(f"batched at rate: p50 {at1['p50_ms']:.0f} ms p99 {at1['p99_ms']:.0f} ms",
+          file=sys.stderr, flush=True)
+    with fi.Server(ctx, bopts) as S:
+        at2 = serving.summarize(serving.replay(S, reqs, arr / 2.0, iters))
+    print(f"batched at 2x rate: p50 {at2['p50_ms']:.0f} ms p99 {at2['p99_ms']:.0f} ms",
+          file=sys.stderr, flush=True)
+    fp64 = None
+    if not args.skip_fp64:
+        with fi.Server(ctx, fi.ServerOpts(max_slots=1, precision=fi.PREC_FP64, **base)) as S:
+            fp64 = serving.summarize(serving.replay(S, reqs, arr, iters))
+        print(f"FP64 sequential at rate: p50 {fp64['p50_ms']:.0f} ms p99 {fp64['p99_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+    # dominant kernel: the CG step on the largest request class (2048^2, 10%)
+    big = max(range(len(trace)), key=lambda i: (trace[i].side, trace[i].density))
+    f_big, m_big = reqs[big]
+    M = fi.Mesh(ctx, trace[big].side, m_big)
+    fd = torch.from_numpy(f_big.copy()).cuda()
+    M.inpaint(f=fd)
+    kms = M.time_cg_kernel(fi.PREC_FP32_IR, args.kernel_reps)
+    kbytes = M.cg_kernel_bytes(fi.PREC_FP32_IR)
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    M.close()
+    pix = sum(f.size for f, _ in reqs)
+    out = {
+        "metric": "inpainted Mpixel/s + tonal-opt solves/s at <=1e-6 err vs FP64; p50/p99 latency",
+        "value": closed["mpixel_per_s"],
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": closed["makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (CG) + f64 (residual, refinement, CGLS)",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {len(reqs)} requests, side U{{128..2048}}, mask "
+                               f"U[2%,10%], inpainting + {iters} CGLS iterations each",
+                   "requests": len(reqs), "total_pixels": pix, "rate_req_s": rate,
+                   "max_slots": args.max_slots, "hbm_budget_gb": args.hbm_budget_gb},
+        "batched_closed_loop": closed,
+        "batched_at_rate": at1,
+        "batched_at_2x_rate": at2,
+        "fp64_sequential_at_rate": fp64,
+        "fp64_sequential_capacity": cap,
+        "speedup_throughput_vs_fp64": closed["mpixel_per_s"] / cap["mpixel_per_s"],
+        "server_stats": {"closed_loop": st_closed, "at_rate": st1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_step<float, ELL, 512> on the {trace[big].side}^2 / "
+                               f"{trace[big].density:.1%} request",
+                     "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = serving_cpu_baseline(trace, reqs, iters)
+    print(json.dumps(out))
+    ctx.close()
+
+
+def serving_cpu_baseline(trace, reqs, iters):
+    """The oracle on the first requests of side <= 256 until about 15 s:
+    inpainting plus the same CGLS iterations with exact Cholesky solves."""
+    from oracle import tonal
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    pix, n = 0, 0
+    for r, (f, m) in zip(trace, reqs):
+        if r.side > 256:
+            continue
+        pr = tonal.Problem(r.side, m)
+        pr.mse(pr.inpaint(f), f)
+        pr.tonal_cgls(f.astype(np.float64), rtol=0.0, maxit=iters)
+        pix += f.size
+        n += 1
+        if time.perf_counter() - t0 > 15.0:
+            break
+    el = time.perf_counter() - t0
+    return {"value": pix / el / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} requests of side <= 256 from the trace (inpainting + {iters} CGLS "
+                      f"iterations, direct Cholesky), {el:.1f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not "
                                    "supported (see DESIGN.md for how the path would shard)"}))
         sys.exit(2)
+    if args.workload == "serving":
+        serving_main(args)
+        return
     import torch
     import paper_2105_01586_amd as fi
     import synth
