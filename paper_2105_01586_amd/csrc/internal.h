@@ -169,6 +169,7 @@ struct fi_mesh {
   int64_t n_pad = 0;
   bool large_mode = false;    // n too large for in-kernel partial re-reduction
   double* d_red4 = nullptr;   // reduced partial sums (large mode)
+  double* d_lvl1 = nullptr;   // first-level sums of that reduction
   double* d_prm = nullptr;    // inner-solve parameters read by the CG kernels
   int32_t* d_flag = nullptr;  // packing flags
   hipEvent_t ring_ev[2] = {nullptr, nullptr};

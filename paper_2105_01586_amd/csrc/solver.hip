@@ -213,7 +213,14 @@ __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, P
 
 // One step of the solve (see the file comment) for the rows of logical block
 // lb. One thread per row, BS threads per block.
-template <typename T, bool ELL, int BS>
+// W: ELL width (4, 6 or 8 slots per row), 0 for the CSR path.
+// SUMMED: the previous launch's dots arrive already summed by a separate
+// launch (large systems): they are uniform loads, alpha and beta are known
+// before the neighbour values arrive, and each neighbour is folded into the
+// product as its load returns (few registers, more waves in flight). Else
+// every block re-reduces the per-block partials, and the neighbour loads
+// are issued before that reduction to overlap with it.
+template <typename T, int W, bool SUMMED, int BS>
 __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, double* lds) {
   // The record slot read here is written only by the next launch, so every
   // thread reads it directly: uniform scalar loads, values kept read-only.
@@ -221,16 +228,19 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
   const Params P = *A.prm;
   // ---- loads that do not depend on the phase or on alpha, beta --------
   double red[3] = {0.0, 0.0, 0.0};
-  constexpr int kPer = (kMaxGrid + BS - 1) / BS;
+  if constexpr (!SUMMED) {
+    constexpr int kPer = (kMaxGrid + BS - 1) / BS;
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int j = threadIdx.x + u * BS;
-    const bool in = j < A.nparts_in;
-    const int jc = in ? j : 0;  // unconditional loads; out-of-range slots add 0
-    const double a0 = A.part_in[4 * jc], a1 = A.part_in[4 * jc + 1], a2 = A.part_in[4 * jc + 2];
-    red[0] += in ? a0 : 0.0;
-    red[1] += in ? a1 : 0.0;
-    red[2] += in ? a2 : 0.0;
+    for (int u = 0; u < kPer; ++u) {
+      const int j = threadIdx.x + u * BS;
+      const bool in = j < A.nparts_in;
+      const int jc = in ? j : 0;  // unconditional loads; out-of-range slots add 0
+      const double a0 = A.part_in[4 * jc], a1 = A.part_in[4 * jc + 1],
+                   a2 = A.part_in[4 * jc + 2];
+      red[0] += in ? a0 : 0.0;
+      red[1] += in ? a1 : 0.0;
+      red[2] += in ? a2 : 0.0;
+    }
   }
   const int i = lb * BS + threadIdx.x;
   const bool live = i < A.n;
@@ -238,23 +248,32 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
   const Quad<T> own = A.rq_in[ic];
   const T r0 = own.r, s0 = own.s, q0 = own.q, d0 = own.d;
   const T p0 = A.p[ic], x0 = A.x[ic];
-  T nr[kMaxEll], ns[kMaxEll], nq[kMaxEll], nd[kMaxEll], nw[kMaxEll];
-  int32_t e[kMaxEll];
-  if constexpr (ELL) {
+  constexpr int WA = W > 0 ? W : 1;
+  T nr[WA], ns[WA], nq[WA], nd[WA], nw[WA];
+  int32_t e[WA];
+  if constexpr (W > 0) {
+    const int32_t* ell = A.ell + ic;
 #pragma unroll
-    for (int k = 0; k < kMaxEll; ++k)
-      e[k] = k < A.W ? A.ell[(int64_t)k * A.n_pad + ic] : (kPadBit | ic);
+    for (int k = 0; k < W; ++k) e[k] = ell[(size_t)k * A.n_pad];
+    if constexpr (!SUMMED) {
 #pragma unroll
-    for (int k = 0; k < kMaxEll; ++k) {
-      const Quad<T> qn = A.rq_in[ell_col(e[k])];
-      nr[k] = qn.r;
-      ns[k] = qn.s;
-      nq[k] = qn.q;
-      nd[k] = qn.d;
-      nw[k] = ell_weight<T>(e[k]);
+      for (int k = 0; k < W; ++k) {
+        const Quad<T> qn = A.rq_in[ell_col(e[k])];
+        nr[k] = qn.r;
+        ns[k] = qn.s;
+        nq[k] = qn.q;
+        nd[k] = qn.d;
+        nw[k] = ell_weight<T>(e[k]);
+      }
     }
   }
-  block_sum_w<3, BS / 64>(red, lds);
+  if constexpr (SUMMED) {
+    red[0] = A.part_in[0];
+    red[1] = A.part_in[1];
+    red[2] = A.part_in[2];
+  } else {
+    block_sum_w<3, BS / 64>(red, lds);
+  }
   const bool writer = lb == 0 && threadIdx.x == 0;
   const int phase = A.force ? (int)kIter : Rin.phase;
   double v[3] = {0.0, 0.0, 0.0};
@@ -296,11 +315,11 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
       const T ri = (T)(A.r64[i] * scale);
       const T zi = di * ri;
       T acc = ri;  // diagonal term: K_ii z_i = r_i
-      if constexpr (ELL) {
+      if constexpr (W > 0) {
 #pragma unroll
-        for (int k = 0; k < kMaxEll; ++k) {
+        for (int k = 0; k < W; ++k) {
           const int c = ell_col(e[k]);
-          acc = fmaT(nw[k], A.dinv[c] * (T)(A.r64[c] * scale), acc);
+          acc = fmaT(ell_weight<T>(e[k]), A.dinv[c] * (T)(A.r64[c] * scale), acc);
         }
       } else {
         for (int j = A.rowptr[i]; j < A.rowptr[i + 1]; ++j) {
@@ -351,9 +370,9 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     if (live) {
       const double xi = xo[i] + sc * (double)x0;
       double acc = A.diag64[i] * xi;
-      if constexpr (ELL) {
+      if constexpr (W > 0) {
 #pragma unroll
-        for (int k = 0; k < kMaxEll; ++k) {
+        for (int k = 0; k < W; ++k) {
           const int c = ell_col(e[k]);
           acc += ell_weight<double>(e[k]) * (xo[c] + sc * (double)A.x[c]);
         }
@@ -384,9 +403,16 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     const T ri = next_r(r0, s0, q0, a, b);
     const T zi = d0 * ri;
     T acc = ri;  // diagonal term: K_ii z_i = r_i
-    if constexpr (ELL) {
+    if constexpr (W > 0 && SUMMED) {
 #pragma unroll
-      for (int k = 0; k < kMaxEll; ++k) {
+      for (int k = 0; k < W; ++k) {
+        const Quad<T> qn = A.rq_in[ell_col(e[k])];
+        const T rc = next_r(qn.r, qn.s, qn.q, a, b);
+        acc = fmaT(ell_weight<T>(e[k]), qn.d * rc, acc);
+      }
+    } else if constexpr (W > 0) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
         const T rc = next_r(nr[k], ns[k], nq[k], a, b);
         acc = fmaT(nw[k], nd[k] * rc, acc);
       }
@@ -410,34 +436,85 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
             rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
 }
 
-template <typename T, bool ELL, int BS>
+template <typename T, int W, bool SUMMED, int BS>
 __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
   __shared__ double lds[3 * (BS / 64)];
-  step_body<T, ELL, BS>(A, logical_block(), lds);
+  step_body<T, W, SUMMED, BS>(A, logical_block(), lds);
 }
 
-// Large systems: one block sums the per-block partials between steps.
-__device__ __forceinline__ void reduce_partials_body(const double* __restrict__ part, int nparts,
-                                                     double* __restrict__ out, double* lds) {
+// Systems handled by one batched launch (bounded by the kernel-argument size).
+constexpr int kArgSlots = 20;
+
+// Large systems: a separate launch sums the per-block partials between
+// steps, in two levels. Block b of that launch adds partials
+// [b * kRedChunk, (b + 1) * kRedChunk) in a fixed order; the block that ends
+// last (an integer counter tells) adds the block sums in a fixed order and
+// writes the total. Which block ends last does not change any bit. The block
+// sums travel through device-scope atomic stores and loads, so they are
+// coherent across the XCDs' L2 caches.
+constexpr int kRedChunk = 1024;   // partials per block of the reduction launch
+constexpr int kRedMaxBlocks = 256;
+
+struct ReduceArgs {
+  int n;                               // systems summed by this launch
+  int32_t start[kArgSlots + 1];     // first block of each system; start[n] = grid
+  int32_t nparts[kArgSlots];
+  const double* part[kArgSlots];    // per-block partials (4 doubles each)
+  double* level1[kArgSlots];        // block sums (4 doubles each)
+  int32_t* counter[kArgSlots];      // blocks done (0 between launches)
+  double* out[kArgSlots];           // total: 3 doubles (+ one 0)
+};
+
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(ReduceArgs R) {
+  __shared__ double lds[12];
+  __shared__ int last;
+  const int g = blockIdx.x;
+  int j = 0;  // system of this block (uniform)
+#pragma unroll
+  for (int k = 1; k < kArgSlots; ++k) j += (k < R.n && R.start[k] <= g) ? 1 : 0;
+  const int b = g - R.start[j], nb = R.start[j + 1] - R.start[j];
+  const double* part = R.part[j];
+  const int j0 = b * kRedChunk, j1 = min(R.nparts[j], j0 + kRedChunk);
   double v[3] = {0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < nparts; j += kBlock) {
-    v[0] += part[4 * j];
-    v[1] += part[4 * j + 1];
-    v[2] += part[4 * j + 2];
+  for (int q = j0 + threadIdx.x; q < j1; q += kBlock) {
+    v[0] += part[4 * q];
+    v[1] += part[4 * q + 1];
+    v[2] += part[4 * q + 2];
   }
   block_sum<3>(v, lds);
-  if (threadIdx.x == 0) {
-    out[0] = v[0];
-    out[1] = v[1];
-    out[2] = v[2];
-    out[3] = 0.0;
+  double* out = R.out[j];
+  if (nb == 1) {
+    if (threadIdx.x == 0) {
+      out[0] = v[0];
+      out[1] = v[1];
+      out[2] = v[2];
+      out[3] = 0.0;
+    }
+    return;
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __restrict__ part,
-                                                            int nparts, double* __restrict__ out) {
-  __shared__ double lds[12];
-  reduce_partials_body(part, nparts, out, lds);
+  double* l1 = R.level1[j];
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 3; ++c)
+      __hip_atomic_store(&l1[4 * b + c], v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const int t = atomicAdd(R.counter[j], 1);
+    last = t == nb - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double w[3] = {0.0, 0.0, 0.0};
+  for (int q = threadIdx.x; q < nb; q += kBlock)
+    for (int c = 0; c < 3; ++c)
+      w[c] += __hip_atomic_load(&l1[4 * q + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  block_sum<3>(w, lds);
+  if (threadIdx.x == 0) {
+    out[0] = w[0];
+    out[1] = w[1];
+    out[2] = w[2];
+    out[3] = 0.0;
+    __hip_atomic_store(R.counter[j], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ---------------------------------------------------------- batched steps --
@@ -449,7 +526,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
 // by value (pointers in by-value kernel arguments are known to be global, so
 // the step keeps its SGPR-based addressing), which caps a launch at
 // kArgSlots slots.
-constexpr int kArgSlots = 20;
 
 struct BatchArgs {
   int n;                         // slots in this launch
@@ -459,14 +535,7 @@ struct BatchArgs {
 
 static_assert(sizeof(BatchArgs) <= 4096, "kernel arguments of a batched step");
 
-struct ReduceArgs {
-  int n;
-  int32_t nparts[kArgSlots];
-  const double* part[kArgSlots];
-  double* out[kArgSlots];
-};
-
-template <int BS>
+template <int W, bool SUMMED, int BS>
 __global__ __launch_bounds__(BS) void k_step_batch(BatchArgs B) {
   __shared__ double lds[3 * (BS / 64)];
   const int lb = logical_block();
@@ -479,14 +548,7 @@ __global__ __launch_bounds__(BS) void k_step_batch(BatchArgs B) {
     if (lblk == 0 && threadIdx.x == 0) *A.rec_out = *A.rec_in;
     return;
   }
-  step_body<float, true, BS>(A, lblk, lds);
-}
-
-// One block per large-mode slot: the same sums as k_reduce_partials.
-__global__ __launch_bounds__(kBlock) void k_reduce_batch(ReduceArgs R) {
-  __shared__ double lds[12];
-  const int b = blockIdx.x;
-  reduce_partials_body(R.part[b], R.nparts[b], R.out[b], lds);
+  step_body<float, W, SUMMED, BS>(A, lblk, lds);
 }
 
 // ELL packing of the CSR off-diagonal part; flags values other than -1/2, -1.
@@ -518,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_max_rowlen(int n, const int32_t* __r
   if (i < n) atomicMax(out, rowptr[i + 1] - rowptr[i]);
 }
 
-__global__ void k_zero_flag(int32_t* f) { f[0] = 0; f[1] = 0; }
+__global__ void k_zero_flag(int32_t* f) { f[0] = 0; f[1] = 0; f[2] = 0; f[3] = 0; }
 
 // ---------------------------------------------------------------- host ----
 template <typename T>
@@ -579,18 +641,45 @@ StepArgs<T> make_args(fi_mesh* M, int par, int force) {
   return A;
 }
 
-template <typename T, bool ELL>
+template <typename T, int W, bool SUMMED>
 void* step_ptr(int bs) {
   switch (bs) {
-    case 256: return (void*)k_step<T, ELL, 256>;
-    default: return (void*)k_step<T, ELL, 512>;
+    case 256: return (void*)k_step<T, W, SUMMED, 256>;
+    default: return (void*)k_step<T, W, SUMMED, 512>;
+  }
+}
+
+template <typename T, bool SUMMED>
+void* step_ptr_w(int w, int bs) {
+  switch (w) {
+    case 4: return step_ptr<T, 4, SUMMED>(bs);
+    case 6: return step_ptr<T, 6, SUMMED>(bs);
+    case 8: return step_ptr<T, 8, SUMMED>(bs);
+    default: return step_ptr<T, 0, SUMMED>(bs);
   }
 }
 
 template <typename T>
 void* step_kernel(fi_mesh* M) {
-  return M->ell_w > 0 ? step_ptr<T, true>(M->cg_bs) : step_ptr<T, false>(M->cg_bs);
+  return M->large_mode ? step_ptr_w<T, true>(M->ell_w, M->cg_bs)
+                       : step_ptr_w<T, false>(M->ell_w, M->cg_bs);
 }
+
+template <bool SUMMED>
+void* batch_kernel_w(int w) {
+  switch (w) {
+    case 4: return (void*)k_step_batch<4, SUMMED, kBatchBS>;
+    case 6: return (void*)k_step_batch<6, SUMMED, kBatchBS>;
+    default: return (void*)k_step_batch<8, SUMMED, kBatchBS>;
+  }
+}
+
+void* batch_kernel(int w, bool large) {
+  return large ? batch_kernel_w<true>(w) : batch_kernel_w<false>(w);
+}
+
+// ELL width used for a widest row of w entries (0: too wide, CSR).
+int ell_width_for(int w) { return w <= 4 ? 4 : w <= 6 ? 6 : w <= kMaxEll ? 8 : 0; }
 
 template <typename T>
 void* start_kernel(fi_mesh* M) {
@@ -600,11 +689,26 @@ void* start_kernel(fi_mesh* M) {
   }
 }
 
+// Adds a large system's reduction after the step of parity `par` (which
+// wrote partial slot par ^ 1) to R, whose grid grows by the system's blocks.
+void add_reduce(ReduceArgs& R, fi_mesh* M, int par) {
+  const int q = R.n;
+  const int nb = (M->cg_grid + kRedChunk - 1) / kRedChunk;
+  R.start[q + 1] = R.start[q] + nb;
+  R.nparts[q] = M->cg_grid;
+  R.part[q] = M->d_part + (size_t)(par ^ 1) * 4 * M->cg_grid;
+  R.level1[q] = M->d_lvl1;
+  R.counter[q] = M->d_flag + 2;
+  R.out[q] = M->d_red4;
+  R.n = q + 1;
+}
+
 int launch_reduce_after(fi_mesh* M, int par) {
-  // the step of parity `par` wrote partial slot par^1
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, M->ctx->stream,
-                     M->d_part + (size_t)(par ^ 1) * 4 * M->cg_grid, M->cg_grid, M->d_red4);
-  FI_HIP_TRY(hipGetLastError());
+  ReduceArgs R{};
+  add_reduce(R, M, par);
+  void* args[1] = {&R};
+  FI_HIP_TRY(hipLaunchKernel((void*)k_reduce_partials, dim3(R.start[1]), dim3(kBlock), args, 0,
+                             M->ctx->stream));
   return FI_OK;
 }
 
@@ -662,13 +766,12 @@ int get_graph(fi_mesh* M, hipGraphExec_t* out) {
     FI_HIP_TRY(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
     prev = node;
     if (M->large_mode) {
-      const double* pin = M->d_part + (size_t)(par ^ 1) * 4 * M->cg_grid;
-      int np = M->cg_grid;
-      double* pout = M->d_red4;
-      void* rp[3] = {&pin, &np, &pout};
+      ReduceArgs R{};
+      add_reduce(R, M, par);
+      void* rp[1] = {&R};
       hipKernelNodeParams rk{};
       rk.func = (void*)k_reduce_partials;
-      rk.gridDim = dim3(1);
+      rk.gridDim = dim3(R.start[1]);
       rk.blockDim = dim3(kBlock);
       rk.sharedMemBytes = 0;
       rk.kernelParams = rp;
@@ -733,35 +836,38 @@ int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int co
   for (const BatchSlot& s : act)
     if (s.M->ell_w <= 0 || s.M->cg_bs != kBatchBS || s.M->n <= 0)
       return fail(FI_E_INVALID, "mesh cannot take part in a batched solve");
-  // launches of at most kArgSlots slots each, both parities prepared
+  // one launch per ELL width and per kArgSlots slots, both parities prepared
   struct Launch {
     BatchArgs b[2];
     ReduceArgs r[2];
     int64_t grid;
+    int w;
+    bool large;
   };
+  std::vector<BatchSlot> order(act);
+  auto key = [](const BatchSlot& a) { return a.M->ell_w * 2 + (a.M->large_mode ? 1 : 0); };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](const BatchSlot& a, const BatchSlot& b) { return key(a) < key(b); });
   std::vector<Launch> L;
-  for (size_t j0 = 0; j0 < act.size(); j0 += kArgSlots) {
+  for (size_t j0 = 0; j0 < order.size();) {
     Launch l{};
-    const size_t j1 = std::min(act.size(), j0 + kArgSlots);
+    size_t j1 = j0;
+    while (j1 < order.size() && j1 - j0 < (size_t)kArgSlots && key(order[j1]) == key(order[j0]))
+      ++j1;
+    l.w = order[j0].M->ell_w;
+    l.large = order[j0].M->large_mode;
     int64_t total = 0;
     for (int par = 0; par < 2; ++par) {
       l.b[par].n = (int)(j1 - j0);
       l.r[par].n = 0;
     }
     for (size_t j = j0; j < j1; ++j) {
-      fi_mesh* M = act[j].M;
+      fi_mesh* M = order[j].M;
       const int q = (int)(j - j0);
       for (int par = 0; par < 2; ++par) {
         l.b[par].start[q] = (int32_t)total;
         l.b[par].a[q] = make_args<float>(M, par, 0);
-        if (M->large_mode) {
-          ReduceArgs& r = l.r[par];
-          // after the step of parity par: its partials (slot par ^ 1) -> d_red4
-          r.part[r.n] = M->d_part + (size_t)(par ^ 1) * 4 * M->cg_grid;
-          r.nparts[r.n] = M->cg_grid;
-          r.out[r.n] = M->d_red4;
-          ++r.n;
-        }
+        if (M->large_mode) add_reduce(l.r[par], M, par);
       }
       total += M->cg_grid;
     }
@@ -769,19 +875,20 @@ int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int co
     for (int par = 0; par < 2; ++par) l.b[par].start[j1 - j0] = (int32_t)total;
     l.grid = total;
     L.push_back(l);
+    j0 = j1;
   }
   for (int k = 0; k < count; ++k) {
     const int par = k & 1;
     for (Launch& l : L) {
       void* args[1] = {&l.b[par]};
-      FI_HIP_TRY(hipLaunchKernel((void*)k_step_batch<kBatchBS>, dim3((unsigned)l.grid),
+      FI_HIP_TRY(hipLaunchKernel(batch_kernel(l.w, l.large), dim3((unsigned)l.grid),
                                  dim3(kBatchBS), args, 0, st));
     }
     for (Launch& l : L) {
       if (l.r[par].n == 0) continue;
       void* rargs[1] = {&l.r[par]};
-      FI_HIP_TRY(hipLaunchKernel((void*)k_reduce_batch, dim3(l.r[par].n), dim3(kBlock), rargs, 0,
-                                 st));
+      FI_HIP_TRY(hipLaunchKernel((void*)k_reduce_partials, dim3(l.r[par].start[l.r[par].n]),
+                                 dim3(kBlock), rargs, 0, st));
     }
   }
   return FI_OK;
@@ -844,6 +951,9 @@ int solver_setup(fi_mesh* M) {
     int rc = 0;
     if ((rc = device_alloc(M, (void**)&M->d_flag, 4 * sizeof(int32_t)))) return rc;
     if ((rc = device_alloc(M, (void**)&M->d_red4, 4 * sizeof(double)))) return rc;
+    if ((rc = device_alloc(M, (void**)&M->d_lvl1, 4 * kRedMaxBlocks * sizeof(double)))) return rc;
+    if (M->large_mode && (M->cg_grid + kRedChunk - 1) / kRedChunk > kRedMaxBlocks)
+      return fail(FI_E_INVALID, "system too large for the partial-sum reduction");
     if ((rc = device_alloc(M, (void**)&M->d_prm, sizeof(Params)))) return rc;
     if ((rc = device_alloc(M, &M->d_rec, 2 * sizeof(Rec)))) return rc;
     if ((rc = device_alloc(M, (void**)&M->d_part, (size_t)2 * 4 * M->cg_grid * sizeof(double))))
@@ -860,7 +970,7 @@ int solver_setup(fi_mesh* M) {
     FI_HIP_TRY(hipMemcpyAsync(M->h_ctl, M->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FI_HIP_TRY(hipStreamSynchronize(st));
     const int32_t w = M->h_ctl[0];
-    M->ell_w = (w <= kMaxEll) ? std::max(w, 1) : 0;
+    M->ell_w = ell_width_for(w);
     if (M->ell_w > 0) {
       if ((rc = device_alloc(M, (void**)&M->d_ell, (size_t)M->ell_w * M->n_pad * sizeof(int32_t))))
         return rc;
