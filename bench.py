@@ -20,6 +20,7 @@ times the FP64 CPU oracle on the same workload (one inpainting).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +32,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("solver.hip", "reduce.h", "internal.h")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources of the CG step kernel."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2105_01586_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the counter runs in
+    profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, scaled by a plain
+    copy), or None when they were taken on other kernel sources."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            rec = json.load(fh)[workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def parse():
@@ -183,8 +208,8 @@ def serving_main(args):
         "speedup_throughput_vs_fp64": closed["mpixel_per_s"] / cap["mpixel_per_s"],
         "server_stats": {"closed_loop": st_closed, "at_rate": st1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_step<float, ELL, 512> on the {trace[big].side}^2 / "
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("serving"),
+                     "kernel": f"k_step<float> on the {trace[big].side}^2 / "
                                f"{trace[big].density:.1%} request",
                      "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
     }
@@ -345,9 +370,10 @@ def main():
         "mse_tonal": ts["mse_final"],
         "fp64_gpu": fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step<float, ELL, 512>", "bytes_per_launch": kbytes,
-                     "us_per_launch": kms * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.workload),
+                     "kernel": f"k_step<float, {mesh.info['large_mode'] and 'summed' or 'block re-reduce'}, "
+                               f"ELL width from the mesh, {mesh.info['cg_block_size']}>",
+                     "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
     }
     out["device_memory_gb"] = {"mesh_and_solver": mesh.info["device_bytes"] / 1e9,
                                "torch_peak": torch.cuda.max_memory_allocated() / 1e9,
