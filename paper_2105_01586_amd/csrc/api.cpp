@@ -398,10 +398,12 @@ int fi_assemble(fi_mesh* M) {
   const int64_t n = M->n, m = M->m;
   int32_t* cnt_ff = M->d_cnt;
   int32_t* cnt_fd = M->d_cnt + (n + 1);
-  if ((rc = launch_assemble_count(M, true))) return rc;
-  if ((rc = scan_counts(M, cnt_ff, M->d_ff_rowptr, n + 1))) return rc;
-  if ((rc = scan_counts(M, cnt_fd, M->d_fd_rowptr, n + 1))) return rc;
+  // The sparsity pattern depends on the mesh only: counted and scanned on the
+  // first assembly, reused after (only the values are recomputed).
   if (!M->assembled_once) {
+    if ((rc = launch_assemble_count(M, true))) return rc;
+    if ((rc = scan_counts(M, cnt_ff, M->d_ff_rowptr, n + 1))) return rc;
+    if ((rc = scan_counts(M, cnt_fd, M->d_fd_rowptr, n + 1))) return rc;
     if ((rc = read_total(M, M->d_ff_rowptr + n, &M->nnz_off))) return rc;
     if ((rc = read_total(M, M->d_fd_rowptr + n, &M->nnz_fd))) return rc;
     if ((rc = alloc_n(M, &M->d_ff_col, M->nnz_off)) || (rc = alloc_n(M, &M->d_ff_val64, M->nnz_off)) ||
@@ -411,9 +413,9 @@ int fi_assemble(fi_mesh* M) {
   }
   if ((rc = launch_assemble_fill(M, true))) return rc;
   // mask rows: K_DF (reuses the count scratch after the fill above is queued)
-  if ((rc = launch_assemble_count(M, false))) return rc;
-  if ((rc = scan_counts(M, M->d_cnt, M->d_df_rowptr, m + 1))) return rc;
   if (!M->assembled_once) {
+    if ((rc = launch_assemble_count(M, false))) return rc;
+    if ((rc = scan_counts(M, M->d_cnt, M->d_df_rowptr, m + 1))) return rc;
     if ((rc = read_total(M, M->d_df_rowptr + m, &M->nnz_df))) return rc;
     if ((rc = alloc_n(M, &M->d_df_col, M->nnz_df)) || (rc = alloc_n(M, &M->d_df_val, M->nnz_df)))
       return rc;

@@ -149,7 +149,10 @@ struct fi_mesh {
   double* d_x64buf[2] = {nullptr, nullptr};
   double* d_r64 = nullptr;
   void* d_rec = nullptr;          // solver state records, two by launch parity
-  void* h_rec = nullptr;          // pinned ring of two record copies
+  void* h_mirror = nullptr;       // pinned host copy of the solver state (host pointer)
+  void* d_mirror = nullptr;       // the same memory as the device addresses it
+  int epoch = 0;                  // id of the latest solve started on this mesh
+  hipEvent_t chunk_ev[4] = {};    // one after each queued chunk of step launches
   fi::CGState cg32, cg64;
   double* d_part = nullptr;   // 2 x kMaxGrid x 4 partial sums
   double* d_scal = nullptr;   // scalar slots of the fused CG kernel
@@ -172,7 +175,6 @@ struct fi_mesh {
   double* d_lvl1 = nullptr;   // first-level sums of that reduction
   double* d_prm = nullptr;    // inner-solve parameters read by the CG kernels
   int32_t* d_flag = nullptr;  // packing flags
-  hipEvent_t ring_ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // [0] FP32, [1] FP64
   hipGraph_t graph[2] = {nullptr, nullptr};
   int graph_chunk = 0;
@@ -200,6 +202,7 @@ struct fi_mesh {
 namespace fi {
 
 constexpr int kBlock = 256;      // threads per block of the vector kernels
+constexpr int kChunkEvents = 4;  // events per mesh for pacing queued step launches
 constexpr int kMaxGrid = 1024;   // cap on blocks of the fused CG kernel
 
 int device_alloc(fi_mesh* M, void** p, size_t bytes);
@@ -255,14 +258,14 @@ constexpr int kBatchBS = 512;  // the batched step needs this block size
 struct BatchSlot {
   fi_mesh* M;
 };
-size_t solver_record_bytes();  // one mesh's pair of records
 // `count` (even) step launches over the meshes in `act`, parity 0 first.
 int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int count);
-// Start of an FP32 solve of K_FF x = b64 that the batch then steps.
-int solve_arm(fi_mesh* M, const fi_solve_opts* opts);
-// Reads a copy of the parity-0 record of a mesh: *done = 1 once the solve
-// has ended (stats filled, d_x64 set to the result).
-int solve_poll(fi_mesh* M, const void* rec_host, fi_solve_stats* stats, int* done);
+// Start of an FP32 solve of K_FF x = b64 that the batch then steps; *epoch
+// identifies it in the host mirror.
+int solve_arm(fi_mesh* M, const fi_solve_opts* opts, int* epoch);
+// Reads the host mirror of the solve `epoch`: *done = 1 once it has ended
+// (stats filled, d_x64 set to the result). Never blocks.
+int solve_poll(fi_mesh* M, int epoch, fi_solve_stats* stats, int* done);
 
 // CGLS on the normal equations B^T B g = B^T f (Section 4), split into
 // segments that each end in one solve with K_FF: the caller runs pre(),

@@ -18,8 +18,8 @@
 //                    the others keep stepping. Requests join and leave
 //                    between chunks of step launches.
 //
-// The host never waits on the GPU inside a chunk: it submits chunk c, then
-// reads the solver records that chunk c - 1 left in pinned memory. Each
+// The host stays two chunks ahead of the device and learns that a solve has
+// ended from the state each step launch writes to pinned host memory. Each
 // request's arithmetic is the same as that of the single-request calls
 // (fi_inpaint, fi_tonal_opt), so a result does not depend on what else was
 // in the batch.
@@ -190,6 +190,7 @@ struct Job {
   bool solving = false, advance = false, finished = false, done = false;
   bool collected = false, reaped = false;  // deleted once both hold
   int64_t armed_at = -1, finish_at = -1;
+  int epoch = 0;  // the running solve's id in the mesh's host mirror
   int status = FI_OK;
   std::string error;
   int64_t inner_iterations = 0;
@@ -227,10 +228,8 @@ struct fi_server {
   // engine state
   std::vector<fi::Job*> active;
   std::vector<int> free_slots;
-  char* d_recs = nullptr;            // record pairs of the slots (device)
-  char* h_ring = nullptr;            // pinned: two copies of d_recs
-  size_t rec_bytes = 0;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  static constexpr int kRing = 4;
+  hipEvent_t ev[kRing] = {};         // one per engine iteration, reused in turn
   fi_server_stats st{};
   std::string engine_error;
 };
@@ -423,7 +422,7 @@ int run_sequential(fi_server* S, Job* J) {
 int start_segment(fi_server* S, Job* J, int64_t it) {
   int rc = J->c.pre();
   if (rc) return rc;
-  if ((rc = solve_arm(J->M, &J->io))) return rc;
+  if ((rc = solve_arm(J->M, &J->io, &J->epoch))) return rc;
   J->solving = true;
   J->armed_at = it;
   (void)S;
@@ -469,7 +468,6 @@ void engine_batched(fi_server* S) {
         J->slot = S->free_slots.back();
         S->free_slots.pop_back();
         J->M->ctx = &S->ctx_run;
-        J->M->d_rec = S->d_recs + (size_t)J->slot * S->rec_bytes;
         J->t_start = since(S);
         J->c.seg = Cgls::kInpaint;
         J->advance = false;
@@ -500,11 +498,7 @@ void engine_batched(fi_server* S) {
       S->st.slot_steps += (int64_t)chunk * (int64_t)act.size();
     }
     hipError_t e = hipSuccess;
-    if (!rc) {
-      e = hipMemcpyAsync(S->h_ring + (size_t)(it & 1) * kMaxSlots * S->rec_bytes, S->d_recs,
-                         (size_t)kMaxSlots * S->rec_bytes, hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipEventRecord(S->ev[it & 1], st);
-    }
+    if (!rc) e = hipEventRecord(S->ev[it % fi_server::kRing], st);
     if (rc || e != hipSuccess) {  // the stream is unusable: fail everything resident
       S->engine_error = rc ? fi_last_error() : hipGetErrorString(e);
       (void)hipStreamSynchronize(st);
@@ -522,15 +516,18 @@ void engine_batched(fi_server* S) {
       ++it;
       continue;
     }
-    // the chunk before this one has ended: read its records
-    if (it > 0) {
-      const int64_t pv = it - 1;
-      (void)hipEventSynchronize(S->ev[pv & 1]);
-      const char* ring = S->h_ring + (size_t)(pv & 1) * kMaxSlots * S->rec_bytes;
+    // Pace the host two iterations ahead of the device; everything queued up
+    // to iteration `done_it` has then finished.
+    int64_t done_it = -1;
+    if (it >= 2) {
+      (void)hipEventSynchronize(S->ev[(it - 2) % fi_server::kRing]);
+      done_it = it - 2;
+    }
+    {
       std::vector<Job*> keep;
       bool freed = false;
       for (Job* J : S->active) {
-        if (J->finished && J->finish_at <= pv) {
+        if (J->finished && J->finish_at <= done_it) {
           collect_results(S, J);
           std::lock_guard<std::mutex> lk(S->mu);
           S->free_slots.push_back(J->slot);
@@ -539,10 +536,10 @@ void engine_batched(fi_server* S) {
           freed = true;
           continue;
         }
-        if (J->solving && J->armed_at <= pv) {
+        if (J->solving) {  // the solve reports its end through the host mirror
           fi_solve_stats ss{};
           int done = 0;
-          int prc = solve_poll(J->M, ring + (size_t)J->slot * S->rec_bytes, &ss, &done);
+          int prc = solve_poll(J->M, J->epoch, &ss, &done);
           if (done) {
             J->solving = false;
             J->inner_iterations += ss.iterations;
@@ -617,10 +614,8 @@ void destroy_server(fi_server* S) {
   for (auto& kv : S->jobs) delete kv.second;
   S->jobs.clear();
   if (S->ctx_run.stream) (void)hipStreamSynchronize(S->ctx_run.stream);
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < fi_server::kRing; ++k)
     if (S->ev[k]) (void)hipEventDestroy(S->ev[k]);
-  if (S->h_ring) (void)hipHostFree(S->h_ring);
-  if (S->d_recs) (void)hipFree(S->d_recs);
   S->arena.release();
   if (S->ctx_run.stream) (void)hipStreamDestroy(S->ctx_run.stream);
   if (S->ctx_build.stream) (void)hipStreamDestroy(S->ctx_build.stream);
@@ -671,13 +666,8 @@ int fi_server_create(fi_ctx* ctx, const fi_server_opts* opts, fi_server** out) {
   };
   hipError_t e = hipStreamCreateWithFlags(&S->ctx_run.stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->ctx_build.stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming);
-  S->rec_bytes = solver_record_bytes();
-  if (e == hipSuccess) e = hipMalloc((void**)&S->d_recs, (size_t)kMaxSlots * S->rec_bytes);
-  if (e == hipSuccess) e = hipMemset(S->d_recs, 0, (size_t)kMaxSlots * S->rec_bytes);
-  if (e == hipSuccess)
-    e = hipHostMalloc((void**)&S->h_ring, 2 * (size_t)kMaxSlots * S->rec_bytes, hipHostMallocDefault);
+  for (int k = 0; k < fi_server::kRing && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&S->ev[k], hipEventDisableTiming);
   if (e != hipSuccess) return bail(fail(FI_E_HIP, hipGetErrorString(e)));
   int rc = S->arena.init(ctx->device, o.hbm_budget);
   if (rc) return bail(rc);

@@ -19,8 +19,9 @@
 // Every per-launch quantity (state record, partial sums, r, s, q) is double
 // buffered by launch parity: launch k reads slot k % 2 and writes the other,
 // so blocks of one launch never see each other's writes. The host only
-// replays a recorded HIP graph of step launches and polls a copy of the
-// record one chunk behind; it makes no decision between refinements.
+// replays a recorded HIP graph of step launches, a couple of chunks ahead of
+// the device, until the launch that ends the solve reports the outcome in
+// pinned host memory; it makes no decision between refinements.
 //
 // Matrix layout: the off-diagonal part of K_FF in column-major ELL (slot k of
 // row i at ell[k * n_pad + i], coalesced across a wavefront); on the
@@ -46,6 +47,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstring>
+#include <string>
 
 #include "internal.h"
 #include "reduce.h"
@@ -69,7 +72,8 @@ struct Rec {
   int32_t ninner;     // inner solves started
   int32_t stagnant;   // consecutive refinements that did not halve ||r||
   int32_t xp;         // x64 buffer holding the iterate
-  int32_t pad0, pad1;
+  int32_t epoch;      // solve this record belongs to (set by the start launch)
+  int32_t seq;        // launches since the start
   double gamma_prev, alpha_prev, rho_ref;
   double tol2;        // inner tolerance, squared
   double rnorm;       // FP64 residual norm at the start of this inner solve
@@ -78,9 +82,25 @@ struct Rec {
 };
 static_assert(sizeof(Rec) == 96, "record layout");
 
+// What the host sees of a solve: the launch that ends it writes the outcome
+// into pinned host memory with system-scope stores (they go through to host
+// memory; nobody waits for them). Other launches do not write here: a store
+// to host memory costs a working launch several microseconds. `word` holds,
+// in one 64-bit store,
+//   bits  0-3   phase            bits 4-30  epoch (the solve)
+//   bits 32-55  iterations       bits 56-62 inner solves     bit 63 x64 buffer,
+// so the host reads phase, epoch and counts consistently; the residual norms
+// are stored first, to the same cache line.
+struct Mirror {
+  uint64_t word;
+  int64_t pad;
+  double rnorm, bnorm;
+};
+constexpr int kEpochMask = (1 << 27) - 1;
+
 // Constant parameters of a solve (written by the start launch).
 struct Params {
-  double rtol, inner_rtol, max_inner, max_refine, mixed, pad[3];
+  double rtol, inner_rtol, max_inner, max_refine, mixed, epoch, pad[2];
 };
 
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -148,15 +168,17 @@ struct StepArgs {
   double* r64;
   double* x64a;           // x64 buffers; rec.xp selects the current one
   double* x64b;
+  Mirror* mirror;         // pinned host memory (device-visible), or NULL
   int force;              // timing only: always iterate, ignore stop tests
 };
 
 // Builds a record from explicit fields (no copy of an input record, whose
-// unused bytes the compiler would otherwise carry through the kernel).
-__device__ __forceinline__ void put_rec(Rec* out, int phase, int iter, int total, int ninner,
-                                        int stagnant, int xp, double gamma_prev,
-                                        double alpha_prev, double rho_ref, double tol2,
-                                        double rnorm, double bnorm) {
+// unused bytes the compiler would otherwise carry through the kernel), and
+// reports it to the host mirror.
+__device__ __forceinline__ void put_rec(Rec* out, Mirror* mirror, int epoch, int seq, int phase,
+                                        int iter, int total, int ninner, int stagnant, int xp,
+                                        double gamma_prev, double alpha_prev, double rho_ref,
+                                        double tol2, double rnorm, double bnorm) {
   Rec r;
   r.phase = phase;
   r.iter = iter;
@@ -164,8 +186,8 @@ __device__ __forceinline__ void put_rec(Rec* out, int phase, int iter, int total
   r.ninner = ninner;
   r.stagnant = stagnant;
   r.xp = xp;
-  r.pad0 = 0;
-  r.pad1 = 0;
+  r.epoch = epoch;
+  r.seq = seq;
   r.gamma_prev = gamma_prev;
   r.alpha_prev = alpha_prev;
   r.rho_ref = rho_ref;
@@ -175,6 +197,14 @@ __device__ __forceinline__ void put_rec(Rec* out, int phase, int iter, int total
   r.pad2 = 0.0;
   r.pad3 = 0.0;
   *out = r;
+  if (mirror && phase >= kDoneOk) {
+    __hip_atomic_store(&mirror->rnorm, rnorm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mirror->bnorm, bnorm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint64_t w = (uint64_t)(uint32_t)((epoch << 4) | phase) |
+                       ((uint64_t)((uint32_t)total & 0xFFFFFFu) << 32) |
+                       ((uint64_t)((uint32_t)ninner & 0x7Fu) << 56) | ((uint64_t)(xp & 1) << 63);
+    __hip_atomic_store(&mirror->word, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Partial sums of block `lb` (the logical block: the index is what fixes the
@@ -204,10 +234,14 @@ __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, P
   block_sum_w<3, BS / 64>(v, lds);
   store_partials(A.part_out, lb, v);
   if (lb == 0 && threadIdx.x == 0) {
-    *prm_out = prm;
-    Rec r{};
-    r.phase = kInit;
-    *A.rec_out = r;
+    prm_out->rtol = prm.rtol;  // field by field, as for the record
+    prm_out->inner_rtol = prm.inner_rtol;
+    prm_out->max_inner = prm.max_inner;
+    prm_out->max_refine = prm.max_refine;
+    prm_out->mixed = prm.mixed;
+    prm_out->epoch = prm.epoch;
+    put_rec(A.rec_out, nullptr, (int)prm.epoch, 0, kInit, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0,
+            0.0);
   }
 }
 
@@ -279,9 +313,12 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
   double v[3] = {0.0, 0.0, 0.0};
 
   if (phase >= kDoneOk) {  // finished: carry the record forward
+    // carry the record forward field by field (a whole-struct copy of the
+    // local record would put it in LDS); the host mirror already shows the end
     if (writer)
-      put_rec(A.rec_out, Rin.phase, Rin.iter, Rin.total, Rin.ninner, Rin.stagnant, Rin.xp,
-              Rin.gamma_prev, Rin.alpha_prev, Rin.rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
+      put_rec(A.rec_out, nullptr, Rin.epoch, Rin.seq, Rin.phase, Rin.iter, Rin.total, Rin.ninner,
+              Rin.stagnant, Rin.xp, Rin.gamma_prev, Rin.alpha_prev, Rin.rho_ref, Rin.tol2,
+              Rin.rnorm, Rin.bnorm);
     return;
   }
 
@@ -300,7 +337,8 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     }
     if (next) {
       if (writer)
-        put_rec(A.rec_out, next, Rin.iter, Rin.total, Rin.ninner, stagnant, Rin.xp,
+        put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, next, Rin.iter, Rin.total,
+                Rin.ninner, stagnant, Rin.xp,
                 Rin.gamma_prev, Rin.alpha_prev, Rin.rho_ref, Rin.tol2, rnorm, bnorm);
       return;
     }
@@ -337,7 +375,8 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     block_sum_w<3, BS / 64>(v, lds);
     store_partials(A.part_out, lb, v);
     if (writer)
-      put_rec(A.rec_out, kIter, 0, Rin.total, Rin.ninner + 1, stagnant, Rin.xp, 0.0, 0.0, 0.0,
+      put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kIter, 0, Rin.total, Rin.ninner + 1,
+              stagnant, Rin.xp, 0.0, 0.0, 0.0,
               itol * itol, rnorm, bnorm);
     return;
   }
@@ -390,7 +429,8 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     block_sum_w<3, BS / 64>(v, lds);
     store_partials(A.part_out, lb, v);
     if (writer)
-      put_rec(A.rec_out, kInit, iter, Rin.total + iter, Rin.ninner, Rin.stagnant, Rin.xp ^ 1,
+      put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kInit, iter, Rin.total + iter,
+              Rin.ninner, Rin.stagnant, Rin.xp ^ 1,
               gamma, alpha, rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
     return;
   }
@@ -432,7 +472,8 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
   block_sum_w<3, BS / 64>(v, lds);
   store_partials(A.part_out, lb, v);
   if (writer)
-    put_rec(A.rec_out, kIter, iter + 1, Rin.total, Rin.ninner, Rin.stagnant, Rin.xp, gamma, alpha,
+    put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kIter, iter + 1, Rin.total, Rin.ninner,
+            Rin.stagnant, Rin.xp, gamma, alpha,
             rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
 }
 
@@ -637,6 +678,7 @@ StepArgs<T> make_args(fi_mesh* M, int par, int force) {
   A.r64 = M->d_r64;
   A.x64a = M->d_x64buf[0];
   A.x64b = M->d_x64buf[1];
+  A.mirror = (Mirror*)M->d_mirror;
   A.force = force;
   return A;
 }
@@ -723,7 +765,7 @@ int launch_step(fi_mesh* M, int par, int force) {
 }
 
 template <typename T>
-int launch_start(fi_mesh* M, const fi_solve_opts* o) {
+int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch) {
   StepArgs<T> A = make_args<T>(M, 1, 0);  // writes record and partials of slot 0
   Params prm{};
   prm.rtol = o->rtol;
@@ -731,6 +773,7 @@ int launch_start(fi_mesh* M, const fi_solve_opts* o) {
   prm.max_inner = o->max_inner;
   prm.max_refine = o->max_refine;
   prm.mixed = sizeof(T) == sizeof(float) ? 1.0 : 0.0;
+  prm.epoch = epoch;
   Params* pout = (Params*)M->d_prm;
   void* args[3] = {&A, &prm, &pout};
   FI_HIP_TRY(hipLaunchKernel(start_kernel<T>(M), dim3(M->cg_grid), dim3(M->cg_bs), args, 0,
@@ -789,10 +832,44 @@ int get_graph(fi_mesh* M, hipGraphExec_t* out) {
   return FI_OK;
 }
 
+int next_epoch(fi_mesh* M) {
+  M->epoch = (M->epoch + 1) & kEpochMask;
+  if (M->epoch == 0) M->epoch = 1;  // 0 never names a solve
+  return M->epoch;
+}
+
+// Reads the host mirror: 1 with stats filled when solve `epoch` has ended,
+// 0 while it runs.
+int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
+  Mirror* m = (Mirror*)M->h_mirror;
+  const uint64_t w = __atomic_load_n(&m->word, __ATOMIC_ACQUIRE);
+  *rc = FI_OK;
+  if ((int)((w & 0x7FFFFFFFu) >> 4) != epoch) return 0;
+  const int phase = (int)(w & 15);
+  if (phase < kDoneOk) return 0;
+  stats->iterations = (int64_t)((w >> 32) & 0xFFFFFFu);
+  stats->refinements = (int32_t)((w >> 56) & 0x7Fu);
+  double rn, bn;
+  __atomic_load(&m->rnorm, &rn, __ATOMIC_RELAXED);
+  __atomic_load(&m->bnorm, &bn, __ATOMIC_RELAXED);
+  stats->rel_residual = bn > 0 ? rn / bn : 0.0;
+  stats->status = phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
+  M->d_x64 = M->d_x64buf[(w >> 63) & 1];
+  if (phase == kDoneBad) *rc = fail(FI_E_INVALID, "right-hand side or residual not finite");
+  return 1;
+}
+
+// The host replays graphs of kChunk step launches, each followed by an event,
+// keeps at most kAhead chunks queued, and stops as soon as the mirror shows
+// the end of this solve. Chunks still queued then run as idle launches;
+// later work on the stream is ordered after them.
+constexpr int kAhead = 2;
+
 template <typename T>
 int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
   hipStream_t st = M->ctx->stream;
-  int rc = launch_start<T>(M, o);
+  const int epoch = next_epoch(M);
+  int rc = launch_start<T>(M, o, epoch);
   if (rc) return rc;
   hipGraphExec_t ex = nullptr;
   rc = get_graph<T>(M, &ex);
@@ -800,36 +877,33 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
   // Upper bound on launches: every inner solve takes at most max_inner + 2.
   const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
   const int64_t max_chunks = max_launch / kChunk + 2;
-  Rec* ring = (Rec*)M->h_rec;
-  // Chunk c: replay, copy the record it ends with (slot 0) to ring c % 2 and
-  // record an event; the host checks chunk c - 1 while chunk c runs.
-  for (int64_t c = 0;; ++c) {
-    if (c < max_chunks) {
+  int64_t launched = 0, completed = 0;
+  for (;;) {
+    int drc = FI_OK;
+    if (read_mirror(M, epoch, stats, &drc)) return drc;
+    if (launched < max_chunks && launched - completed < kAhead) {
       FI_HIP_TRY(hipGraphLaunch(ex, st));
-      FI_HIP_TRY(hipMemcpyAsync(ring + (c & 1), rec_slot(M, 0), sizeof(Rec), hipMemcpyDeviceToHost,
-                                st));
-      FI_HIP_TRY(hipEventRecord(M->ring_ev[c & 1], st));
+      FI_HIP_TRY(hipEventRecord(M->chunk_ev[launched % kChunkEvents], st));
+      ++launched;
+      continue;
     }
-    const int64_t prev = c - 1;
-    if (prev < 0) continue;
-    FI_HIP_TRY(hipEventSynchronize(M->ring_ev[prev & 1]));
-    const Rec R = ring[prev & 1];
-    if (R.phase >= kDoneOk) {
-      stats->iterations = R.total;
-      stats->refinements = R.ninner;
-      stats->rel_residual = R.bnorm > 0 ? R.rnorm / R.bnorm : 0.0;
-      stats->status = R.phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
-      M->d_x64 = M->d_x64buf[R.xp];
-      if (R.phase == kDoneBad) return fail(FI_E_INVALID, "right-hand side or residual not finite");
-      return FI_OK;
+    if (completed < launched) {
+      const hipError_t q = hipEventQuery(M->chunk_ev[completed % kChunkEvents]);
+      if (q == hipSuccess) {
+        ++completed;
+        continue;
+      }
+      if (q != hipErrorNotReady)
+        return fail(FI_E_HIP, std::string("stream failed: ") + hipGetErrorString(q));
+    } else {  // everything launched has run and the solve never ended
+      if (read_mirror(M, epoch, stats, &drc)) return drc;
+      return fail(FI_E_HIP, "solver did not report termination");
     }
-    if (prev >= max_chunks - 1) return fail(FI_E_HIP, "solver did not report termination");
+    __builtin_ia32_pause();
   }
 }
 
 }  // namespace
-
-size_t solver_record_bytes() { return 2 * sizeof(Rec); }
 
 int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int count) {
   if (act.empty() || count <= 0) return FI_OK;
@@ -894,23 +968,16 @@ int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int co
   return FI_OK;
 }
 
-int solve_arm(fi_mesh* M, const fi_solve_opts* o) {
+int solve_arm(fi_mesh* M, const fi_solve_opts* o, int* epoch) {
   if (M->n <= 0) return fail(FI_E_INVALID, "nothing to solve");
-  return launch_start<float>(M, o);
+  *epoch = next_epoch(M);
+  return launch_start<float>(M, o, *epoch);
 }
 
-int solve_poll(fi_mesh* M, const void* rec_host, fi_solve_stats* stats, int* done) {
-  const Rec& R = *(const Rec*)rec_host;
-  *done = 0;
-  if (R.phase < kDoneOk) return FI_OK;
-  *done = 1;
-  stats->iterations = R.total;
-  stats->refinements = R.ninner;
-  stats->rel_residual = R.bnorm > 0 ? R.rnorm / R.bnorm : 0.0;
-  stats->status = R.phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
-  M->d_x64 = M->d_x64buf[R.xp];
-  if (R.phase == kDoneBad) return fail(FI_E_INVALID, "right-hand side or residual not finite");
-  return FI_OK;
+int solve_poll(fi_mesh* M, int epoch, fi_solve_stats* stats, int* done) {
+  int rc = FI_OK;
+  *done = read_mirror(M, epoch, stats, &rc);
+  return rc;
 }
 
 void solver_release(fi_mesh* M) {
@@ -919,11 +986,14 @@ void solver_release(fi_mesh* M) {
     if (M->graph[k]) (void)hipGraphDestroy(M->graph[k]);
     M->graph_exec[k] = nullptr;
     M->graph[k] = nullptr;
-    if (M->ring_ev[k]) (void)hipEventDestroy(M->ring_ev[k]);
-    M->ring_ev[k] = nullptr;
   }
-  if (M->h_rec) (void)hipHostFree(M->h_rec);
-  M->h_rec = nullptr;
+  for (int k = 0; k < kChunkEvents; ++k) {
+    if (M->chunk_ev[k]) (void)hipEventDestroy(M->chunk_ev[k]);
+    M->chunk_ev[k] = nullptr;
+  }
+  if (M->h_mirror) (void)hipHostFree(M->h_mirror);
+  M->h_mirror = nullptr;
+  M->d_mirror = nullptr;
 }
 
 // Called after every assembly: picks the launch shape and packs the ELL copy.
@@ -958,9 +1028,13 @@ int solver_setup(fi_mesh* M) {
     if ((rc = device_alloc(M, &M->d_rec, 2 * sizeof(Rec)))) return rc;
     if ((rc = device_alloc(M, (void**)&M->d_part, (size_t)2 * 4 * M->cg_grid * sizeof(double))))
       return rc;
-    FI_HIP_TRY(hipHostMalloc(&M->h_rec, 2 * sizeof(Rec), hipHostMallocDefault));
-    for (int k = 0; k < 2; ++k)
-      FI_HIP_TRY(hipEventCreateWithFlags(&M->ring_ev[k], hipEventDisableTiming));
+    // the host mirror: fine-grained pinned memory the kernels write through to
+    FI_HIP_TRY(hipHostMalloc(&M->h_mirror, sizeof(Mirror),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(M->h_mirror, 0, sizeof(Mirror));
+    FI_HIP_TRY(hipHostGetDevicePointer(&M->d_mirror, M->h_mirror, 0));
+    for (int k = 0; k < kChunkEvents; ++k)
+      FI_HIP_TRY(hipEventCreateWithFlags(&M->chunk_ev[k], hipEventDisableTiming));
     // widest row decides the ELL width
     hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, st, M->d_flag);
     if (n > 0)
@@ -1011,7 +1085,8 @@ int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
   fi_solve_opts o;
   fi_solve_opts_default(&o);
   // a start launch plus one init step give a valid state to iterate from
-  int rc = d ? launch_start<double>(M, &o) : launch_start<float>(M, &o);
+  const int epoch = next_epoch(M);
+  int rc = d ? launch_start<double>(M, &o, epoch) : launch_start<float>(M, &o, epoch);
   if (rc) return rc;
   rc = d ? launch_step<double>(M, 0, 0) : launch_step<float>(M, 0, 0);
   if (rc) return rc;

@@ -172,11 +172,9 @@ extern "C" int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
   int it = 0;
   if (s0 > 0) {
     ts.status = FI_E_NO_CONVERGENCE;
+    // one host read per iteration: ||q||^2 and the new gamma together
     while (it < o.max_outer) {
-      if ((rc = run(Cgls::kApplyP))) return rc;
-      if ((rc = read_scalars(M, sc, 8))) return rc;
-      if (!(sc[Cgls::kScQQ] > 0)) break;  // B p = 0: no further progress
-      if ((rc = run(Cgls::kAdjoint))) return rc;
+      if ((rc = run(Cgls::kApplyP)) || (rc = run(Cgls::kAdjoint))) return rc;
       ++it;
       if ((rc = read_scalars(M, sc, 8))) return rc;
       ts.rel_normal_residual = std::sqrt(sc[Cgls::kScGamma + (c.k & 1)]) / s0;
@@ -184,6 +182,7 @@ extern "C" int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
         ts.status = FI_OK;
         break;
       }
+      if (!(sc[Cgls::kScQQ] > 0)) break;  // B p = 0: the step had length 0, no progress
     }
   }
   ts.outer_iterations = it;
