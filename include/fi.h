@@ -250,6 +250,32 @@ int fi_grow_mask(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mas
                  int64_t k_add, int rounds, const fi_solve_opts* opts, int32_t* mask_out,
                  double* mse_out, double* gpu_ms_out);
 
+/* Section 3's densification step, as the paper states it: the total squared
+ * error E_T of every triangle (its pixels' e, added in ascending pixel
+ * order); triangles taken in descending E_T (ties: lower triangle index),
+ * skipping those that own no pixel outside the mask; from each, its non-mask
+ * pixel of largest e (ties: lower index); k pixels in all, or every
+ * candidate triangle's if there are fewer.
+ *   e_dev:   float64[P] device, the pointwise error (fi_error's pix_err);
+ *   out_dev: int32[k] device, the chosen pixels in ascending order;
+ *   added:   host, how many were chosen (<= k).
+ * Synchronous. */
+int fi_paper_densify_step(fi_mesh* mesh, const double* e_dev, int64_t k, int32_t* out_dev,
+                          int64_t* added);
+
+/* Mask-growth rules of fi_densify. */
+enum fi_densify_rule {
+  FI_DENSIFY_TOPK = 0,      /* the k_add non-mask pixels of largest e (fi_grow_mask) */
+  FI_DENSIFY_TRIANGLES = 1  /* Section 3's per-triangle step (fi_paper_densify_step) */
+};
+
+/* fi_grow_mask with a choice of rule. With FI_DENSIFY_TRIANGLES a round may
+ * add fewer than k_add pixels; mask_out is sized for m0 + rounds * k_add and
+ * *mask_size_out (host, may be NULL) receives how many were written. */
+int fi_densify(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0, int64_t m0,
+               int64_t k_add, int rounds, int rule, const fi_solve_opts* opts, int32_t* mask_out,
+               double* mse_out, double* gpu_ms_out, int64_t* mask_size_out);
+
 /* Timing helper: runs `reps` iterations of the fused FP32 (precision =
  * FI_PREC_FP32_IR) or FP64 (FI_PREC_FP64) CG iteration kernel on this mesh's
  * current solver state between two HIP events recorded on the context

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "FIError", "NoConvergence", "library", "Context", "Mesh", "SolveOpts", "TonalOpts",
     "PREC_FP32_IR", "PREC_FP64", "lib_path", "EXPORTED_SYMBOLS", "host_mesh", "grow_mask",
-    "Server", "ServerOpts", "footprint_bound",
+    "Server", "ServerOpts", "footprint_bound", "densify", "DENSIFY_TOPK", "DENSIFY_TRIANGLES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,6 +32,7 @@ lib_path = os.path.join(_HERE, "libfi.so")
 
 OK, E_INVALID, E_EMPTY_MASK, E_NO_CONVERGENCE, E_NOMEM, E_HIP = range(6)
 PREC_FP32_IR, PREC_FP64 = 0, 1
+DENSIFY_TOPK, DENSIFY_TRIANGLES = 0, 1
 
 EXPORTED_SYMBOLS = (
     "fi_solve_opts_default", "fi_tonal_opts_default", "fi_last_error", "fi_version",
@@ -42,7 +43,7 @@ EXPORTED_SYMBOLS = (
     "fi_host_mesh_build", "fi_host_mesh_info", "fi_host_mesh_export", "fi_host_mesh_destroy",
     "fi_mesh_upload", "fi_grow_mask", "fi_server_opts_default", "fi_server_create",
     "fi_server_submit", "fi_server_poll", "fi_server_stats_get", "fi_server_clock",
-    "fi_server_destroy", "fi_server_footprint",
+    "fi_server_destroy", "fi_server_footprint", "fi_paper_densify_step", "fi_densify",
 )
 
 
@@ -175,6 +176,10 @@ def library() -> ctypes.CDLL:
         "fi_mesh_upload": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "fi_grow_mask": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_int, ctypes.POINTER(_SolveOpts), vp, vp, vp]),
+        "fi_paper_densify_step": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, i64p]),
+        "fi_densify": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int, ctypes.c_int, ctypes.POINTER(_SolveOpts), vp,
+                                      vp, vp, i64p]),
         "fi_server_opts_default": (None, [ctypes.POINTER(_ServerOpts)]),
         "fi_server_create": (ctypes.c_int, [vp, ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]),
         "fi_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(_JobDesc),
@@ -475,6 +480,18 @@ class Mesh:
         _check(rc, "fi_topk_new_pixels")
         return out[:int(k)]
 
+    def paper_densify_step(self, e, k: int):
+        """Section 3's per-triangle step: up to k new pixels (ascending)."""
+        torch = _torch()
+        out = self._empty(max(int(k), 1), torch.int32)
+        added = ctypes.c_int64()
+        rc = library().fi_paper_densify_step(self._h, _ptr(e, torch.float64, self.P, "e",
+                                                           self._dev()),
+                                             int(k), ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.byref(added))
+        _check(rc, "fi_paper_densify_step")
+        return out[:added.value]
+
     # -- measurement ---------------------------------------------------------
     def time_cg_kernel(self, precision: int = PREC_FP32_IR, reps: int = 200) -> float:
         ms = ctypes.c_double()
@@ -511,6 +528,26 @@ def grow_mask(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
                                 c(out), c(mse), c(ms))
     _check(rc, "fi_grow_mask")
     return out, mse, ms
+
+
+def densify(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
+            rule: int = DENSIFY_TRIANGLES, opts: SolveOpts | None = None):
+    """Mask growth by a chosen rule (fi_densify); returns (mask_order, mse,
+    gpu_ms) like grow_mask, mask_order holding only the pixels added."""
+    torch = _torch()
+    mask0 = np.ascontiguousarray(np.asarray(mask0, dtype=np.int32).ravel())
+    P = int(side) * int(side)
+    out = np.empty(mask0.size + int(rounds) * int(k_add), np.int32)
+    mse = np.empty(int(rounds) + 1, np.float64)
+    ms = np.empty(int(rounds) + 1, np.float64)
+    total = ctypes.c_int64()
+    o = (opts or SolveOpts()).c()
+    c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    rc = library().fi_densify(ctx._h, int(side), _ptr(f, torch.uint8, P, "f", ctx.device),
+                              c(mask0), mask0.size, int(k_add), int(rounds), int(rule),
+                              ctypes.byref(o), c(out), c(mse), c(ms), ctypes.byref(total))
+    _check(rc, "fi_densify")
+    return out[:total.value], mse, ms
 
 
 # ------------------------------------------------------------------ serving --

@@ -194,9 +194,12 @@ struct fi_mesh {
   double* d_tq = nullptr;  // P: q
   double* d_tsc = nullptr; // CGLS scalars (see Cgls)
 
-  // top-k workspace (device, allocated on first use)
+  // mask-growth workspace (device, allocated on first use)
   void* d_topk = nullptr;
   int64_t topk_bytes = 0;
+  double* d_tri_err = nullptr;   // T: per-triangle error
+  int32_t* d_tri_best = nullptr; // T: empty pixel of largest error
+  int32_t* d_sel_tri = nullptr;  // selected triangles
 };
 
 namespace fi {
@@ -230,6 +233,10 @@ int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uin
                   double* partial_out);
 int raster_blocks(const fi_mesh* M);
 int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart);
+// Per triangle: total error of its pixels, and its empty pixel of largest
+// error (-1 if none); in_mask holds one byte per pixel.
+int launch_tri_best(fi_mesh* M, const double* e, const uint8_t* in_mask, double* tri_err,
+                    int32_t* tri_best);
 int launch_gather_vertex(fi_mesh* M, const double* tpart, double* tF, double* tD);
 int launch_adjoint_tail(fi_mesh* M, const double* tD, const double* y, double* s);
 int launch_reduce(fi_mesh* M, const double* part, int nparts, int ncomp, double* out);
@@ -289,7 +296,9 @@ struct Cgls {
   const double* scalar(int i) const { return M->d_tsc + i; }
 };
 
-// Top-k (topk.hip).
+// Mask growth (topk.hip).
 int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out);
+// Section 3's step: up to k new pixels (ascending) into out; *added of them.
+int paper_densify_step(fi_mesh* M, const double* e, int64_t k, int32_t* out, int64_t* added);
 
 }  // namespace fi

@@ -367,6 +367,62 @@ __global__ __launch_bounds__(kBlock) void k_raster(
   if (partial && threadIdx.x == 0) partial[blockIdx.x] = acc[0];
 }
 
+// Per triangle: the total squared error of the pixels it owns (added in
+// ascending pixel order), and its pixel of largest error that is not in the
+// mask (ties: the lower index; -1 if it owns none). Section 3's inputs to the
+// densification step.
+__global__ __launch_bounds__(kBlock) void k_tri_best(int64_t nleaves, int N,
+                                                     const int32_t* __restrict__ leaves,
+                                                     const int32_t* __restrict__ tri,
+                                                     const int32_t* __restrict__ vxy,
+                                                     const double* __restrict__ e,
+                                                     const uint8_t* __restrict__ in_mask,
+                                                     double* __restrict__ tri_err,
+                                                     int32_t* __restrict__ tri_best) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nleaves) return;
+  LeafTris L;
+  load_leaf(leaves, i, tri, vxy, L);
+  double E[kMaxLeafTri], bestv[kMaxLeafTri];
+  int32_t best[kMaxLeafTri];
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) {
+    E[k] = 0.0;
+    bestv[k] = 0.0;
+    best[k] = -1;
+  }
+  const int x0 = leaves[4 * i], y0 = leaves[4 * i + 1];
+  const int s = 1 << leaves[4 * i + 2];
+  for (int dy = 0; dy < s; ++dy) {
+    for (int dx = 0; dx < s; ++dx) {
+      const int x = x0 + dx, y = y0 + dy;
+      int oa = 0, ob = 0, oc = 0;
+      const int own = locate(L, x, y, oa, ob, oc);
+      const int64_t pix = (int64_t)y * N + x;
+      const double ev = e[pix];
+      const bool empty = !in_mask[pix];
+#pragma unroll
+      for (int k = 0; k < kMaxLeafTri; ++k) {
+        if (k == own) {
+          E[k] += ev;
+          // pixels come in ascending order, so a strictly larger error wins
+          if (empty && (best[k] < 0 || ev > bestv[k])) {
+            best[k] = (int32_t)pix;
+            bestv[k] = ev;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) {
+    if (k < L.nt) {
+      tri_err[L.t0 + k] = E[k];
+      tri_best[L.t0 + k] = best[k];
+    }
+  }
+}
+
 // Transposed interpolation: per triangle and corner, sum over the pixels the
 // triangle owns of weight * r (t = R^T r before the per-vertex gather).
 __global__ __launch_bounds__(kBlock) void k_raster_T(int64_t nleaves, int N,
@@ -579,6 +635,14 @@ int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uin
   hipLaunchKernelGGL(k_raster, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L, M->N,
                      M->d_leaves, M->d_tri, M->d_vxy, uvert, u_in, f, u_out, e_out, tri_err_out,
                      owner_out, partial_out);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_tri_best(fi_mesh* M, const double* e, const uint8_t* in_mask, double* tri_err,
+                    int32_t* tri_best) {
+  hipLaunchKernelGGL(k_tri_best, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L,
+                     M->N, M->d_leaves, M->d_tri, M->d_vxy, e, in_mask, tri_err, tri_best);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }

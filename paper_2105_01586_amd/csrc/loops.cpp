@@ -1,5 +1,6 @@
 // Multi-call procedures built on the single-mesh calls: error-driven mask
-// growth (Section 3).
+// growth (Section 3), by the global top-k rule or the paper's per-triangle
+// step.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -28,14 +29,20 @@ struct Event {
 
 using namespace fi;
 
-extern "C" int fi_grow_mask(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0,
-                            int64_t m0, int64_t k_add, int rounds, const fi_solve_opts* opts,
-                            int32_t* mask_out, double* mse_out, double* gpu_ms_out) {
+namespace {
+
+// Shared loop of fi_grow_mask and fi_densify: rule 0 adds the global top-k
+// (exactly k_add per round), rule 1 the per-triangle step (up to k_add).
+int densify_loop(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0, int64_t m0,
+                 int64_t k_add, int rounds, int rule, const fi_solve_opts* opts, int32_t* mask_out,
+                 double* mse_out, double* gpu_ms_out, int64_t* total_out) {
   if (!ctx || !f_dev || !mask0 || !mask_out || !mse_out)
-    return fail(FI_E_INVALID, "fi_grow_mask: NULL argument");
-  if (side < 2 || k_add < 0 || rounds < 0) return fail(FI_E_INVALID, "fi_grow_mask: bad sizes");
+    return fail(FI_E_INVALID, "densify: NULL argument");
+  if (side < 2 || k_add < 0 || rounds < 0) return fail(FI_E_INVALID, "densify: bad sizes");
+  if (rule != FI_DENSIFY_TOPK && rule != FI_DENSIFY_TRIANGLES)
+    return fail(FI_E_INVALID, "densify: unknown rule");
   const int64_t P = (int64_t)side * side;
-  if (m0 + (int64_t)rounds * k_add > P) return fail(FI_E_INVALID, "fi_grow_mask: mask would exceed the image");
+  if (m0 + (int64_t)rounds * k_add > P) return fail(FI_E_INVALID, "densify: mask would exceed the image");
   FI_HIP_TRY(hipSetDevice(ctx->device));
   DevMem u, e, sel;
   FI_HIP_TRY(hipMalloc(&u.p, (size_t)P * sizeof(double)));
@@ -67,23 +74,56 @@ extern "C" int fi_grow_mask(fi_ctx* ctx, int side, const uint8_t* f_dev, const i
       gpu_ms_out[r] = ms;
     }
     if (rc == FI_OK) mse_out[r] = mse;
+    int64_t got = 0;
     if (rc == FI_OK && r < rounds && k_add > 0) {
-      rc = fi_topk_new_pixels(M, (double*)e.p, k_add, (int32_t*)sel.p);
-      if (rc == FI_OK) {
-        hipError_t he = hipMemcpy(add.data(), sel.p, (size_t)k_add * sizeof(int32_t),
+      if (rule == FI_DENSIFY_TOPK) {
+        rc = fi_topk_new_pixels(M, (double*)e.p, k_add, (int32_t*)sel.p);
+        got = k_add;
+      } else {
+        rc = paper_densify_step(M, (double*)e.p, k_add, (int32_t*)sel.p, &got);
+      }
+      if (rc == FI_OK && got > 0) {
+        hipError_t he = hipMemcpy(add.data(), sel.p, (size_t)got * sizeof(int32_t),
                                   hipMemcpyDeviceToHost);
         if (he != hipSuccess) rc = fail(FI_E_HIP, hipGetErrorString(he));
       }
     }
     fi_mesh_destroy(M);
     if (rc) return rc;
-    if (r < rounds && k_add > 0) {
-      std::memcpy(mask_out + written, add.data(), (size_t)k_add * sizeof(int32_t));
-      written += k_add;
-      std::vector<int32_t> merged(mask.size() + (size_t)k_add);
-      std::merge(mask.begin(), mask.end(), add.begin(), add.begin() + k_add, merged.begin());
+    if (got > 0) {
+      std::memcpy(mask_out + written, add.data(), (size_t)got * sizeof(int32_t));
+      written += got;
+      std::vector<int32_t> merged(mask.size() + (size_t)got);
+      std::merge(mask.begin(), mask.end(), add.begin(), add.begin() + got, merged.begin());
       mask.swap(merged);
     }
   }
+  if (total_out) *total_out = written;
   return FI_OK;
+}
+
+}  // namespace
+
+extern "C" int fi_grow_mask(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0,
+                            int64_t m0, int64_t k_add, int rounds, const fi_solve_opts* opts,
+                            int32_t* mask_out, double* mse_out, double* gpu_ms_out) {
+  return densify_loop(ctx, side, f_dev, mask0, m0, k_add, rounds, FI_DENSIFY_TOPK, opts, mask_out,
+                      mse_out, gpu_ms_out, nullptr);
+}
+
+extern "C" int fi_densify(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0,
+                          int64_t m0, int64_t k_add, int rounds, int rule,
+                          const fi_solve_opts* opts, int32_t* mask_out, double* mse_out,
+                          double* gpu_ms_out, int64_t* mask_size_out) {
+  return densify_loop(ctx, side, f_dev, mask0, m0, k_add, rounds, rule, opts, mask_out, mse_out,
+                      gpu_ms_out, mask_size_out);
+}
+
+extern "C" int fi_paper_densify_step(fi_mesh* M, const double* e_dev, int64_t k, int32_t* out_dev,
+                                     int64_t* added) {
+  if (!M || !M->ctx || !e_dev || !added || (k > 0 && !out_dev))
+    return fail(FI_E_INVALID, "fi_paper_densify_step: NULL argument");
+  if (k < 0) return fail(FI_E_INVALID, "fi_paper_densify_step: k < 0");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  return paper_densify_step(M, e_dev, k, out_dev, added);
 }

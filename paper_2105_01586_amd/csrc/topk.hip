@@ -1,6 +1,9 @@
-// Global top-k mask growth: choose the k non-mask pixels with the largest
-// pointwise error e_i = (u_i - f_i)^2 (Section 3's error map), ties broken by
-// the lower linear index, returned in ascending index order.
+// Error-driven mask growth (Section 3's error map e_i = (u_i - f_i)^2):
+// - global top-k: the k non-mask pixels with the largest e_i, ties broken by
+//   the lower linear index, returned in ascending index order;
+// - the paper's per-triangle step: the k triangles of largest total error
+//   (ties: lower triangle index) that still own an empty pixel, each giving
+//   its empty pixel of largest e_i (ties: lower index).
 //
 // Radix select finds the k-th largest key in four passes of 16-bit digits
 // (integer histograms, so counts are exact); pixels above that key are all
@@ -87,17 +90,29 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int64_t P, const int32_t* __
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-}  // namespace
+__global__ void k_excl_no_best(int64_t T, const int32_t* __restrict__ best,
+                               uint8_t* __restrict__ excl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < T) excl[t] = best[t] < 0;
+}
 
-int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out) {
-  if (k == 0) return FI_OK;
-  hipStream_t st = M->ctx->stream;
-  const int64_t P = M->P;
-  // workspace: is_mask (P bytes, rounded), hist, gt, eq, rank, sel, pos
-  const size_t mask_bytes = ((size_t)P + 255) & ~(size_t)255;
-  const size_t tmp_ints = (size_t)scan_tmp_ints(P + 1);
+__global__ void k_flag_best(int64_t k, const int32_t* __restrict__ sel_tri,
+                            const int32_t* __restrict__ best, int32_t* __restrict__ flag) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) flag[best[sel_tri[j]]] = 1;
+}
+
+// Workspace of a selection over n keys (device, from the mesh).
+struct SelectSpace {
+  uint8_t* excl;  // n bytes (rounded to 256)
+  int32_t *hist, *gt, *eq, *rank, *sel, *pos, *scan_tmp;
+};
+
+int select_space(fi_mesh* M, int64_t n, SelectSpace& W) {
+  const size_t excl_bytes = ((size_t)n + 255) & ~(size_t)255;
+  const size_t tmp_ints = (size_t)scan_tmp_ints(n + 1);
   const size_t need =
-      mask_bytes + sizeof(int32_t) * ((size_t)kBins + 5 * (size_t)(P + 1) + tmp_ints);
+      excl_bytes + sizeof(int32_t) * ((size_t)kBins + 5 * (size_t)(n + 1) + tmp_ints);
   if ((int64_t)need > M->topk_bytes) {
     void* p = nullptr;
     int rc = device_alloc(M, &p, need);
@@ -105,57 +120,137 @@ int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out) {
     M->d_topk = p;
     M->topk_bytes = (int64_t)need;
   }
-  uint8_t* is_mask = (uint8_t*)M->d_topk;
-  int32_t* hist = (int32_t*)((char*)M->d_topk + mask_bytes);
-  int32_t* gt = hist + kBins;
-  int32_t* eq = gt + (P + 1);
-  int32_t* rank = eq + (P + 1);
-  int32_t* sel = rank + (P + 1);
-  int32_t* pos = sel + (P + 1);
-  int32_t* scan_tmp = pos + (P + 1);
+  W.excl = (uint8_t*)M->d_topk;
+  W.hist = (int32_t*)((char*)M->d_topk + excl_bytes);
+  W.gt = W.hist + kBins;
+  W.eq = W.gt + (n + 1);
+  W.rank = W.eq + (n + 1);
+  W.sel = W.rank + (n + 1);
+  W.pos = W.sel + (n + 1);
+  W.scan_tmp = W.pos + (n + 1);
+  return FI_OK;
+}
 
-  hipLaunchKernelGGL(k_zero_u8, dim3(blocks(P)), dim3(kBlock), 0, st, P, is_mask);
-  hipLaunchKernelGGL(k_mark_mask, dim3(blocks(M->m)), dim3(kBlock), 0, st, (int)M->m,
-                     M->d_mask_pix, is_mask);
-  FI_HIP_TRY(hipGetLastError());
-
+// The k entries of largest key among those not excluded (ties: lower index),
+// written in ascending index order to out. With fewer than k candidates,
+// *taken < k of them (all) are written.
+int select_topk(hipStream_t st, int64_t n, const double* key, SelectSpace& W, int64_t k,
+                int32_t* out, int64_t* taken) {
+  *taken = 0;
+  if (k == 0 || n == 0) return FI_OK;
   std::vector<int32_t> h(kBins);
   uint64_t prefix = 0, hi_mask = 0;
+  // candidates in total: a histogram of the top digit counts them all
   int64_t remaining = k;  // rank (1-based, from the top) still to locate
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 64 - kDigitBits * (pass + 1);
-    hipLaunchKernelGGL(k_zero_i32, dim3(blocks(kBins)), dim3(kBlock), 0, st, (int64_t)kBins, hist);
-    int g = (int)std::min<int64_t>(blocks(P), 2048);
-    hipLaunchKernelGGL(k_hist, dim3(g), dim3(kBlock), 0, st, P, e, is_mask, shift, prefix, hi_mask,
-                       hist);
+    hipLaunchKernelGGL(k_zero_i32, dim3(blocks(kBins)), dim3(kBlock), 0, st, (int64_t)kBins,
+                       W.hist);
+    int g = (int)std::min<int64_t>(blocks(n), 2048);
+    hipLaunchKernelGGL(k_hist, dim3(g), dim3(kBlock), 0, st, n, key, W.excl, shift, prefix,
+                       hi_mask, W.hist);
     FI_HIP_TRY(hipGetLastError());
-    FI_HIP_TRY(hipMemcpyAsync(h.data(), hist, sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
+    FI_HIP_TRY(hipMemcpyAsync(h.data(), W.hist, sizeof(int32_t) * kBins, hipMemcpyDeviceToHost,
+                              st));
     FI_HIP_TRY(hipStreamSynchronize(st));
+    if (pass == 0) {
+      int64_t total = 0;
+      for (int d = 0; d < kBins; ++d) total += h[d];
+      if (total == 0) return FI_OK;
+      if (total < remaining) remaining = total;
+      *taken = remaining;
+    }
     int64_t acc = 0;
     int d = kBins - 1;
     for (; d >= 0; --d) {
       if (acc + h[d] >= remaining) break;
       acc += h[d];
     }
-    if (d < 0) return fail(FI_E_INVALID, "top-k: fewer candidates than requested");
     remaining -= acc;
     prefix |= (uint64_t)d << shift;
     hi_mask |= (uint64_t)(kBins - 1) << shift;
   }
   const uint64_t tau = prefix;  // the k-th largest key; `remaining` ties are needed
-  hipLaunchKernelGGL(k_flags, dim3(blocks(P + 1)), dim3(kBlock), 0, st, P, e, is_mask, tau, gt, eq);
+  hipLaunchKernelGGL(k_flags, dim3(blocks(n + 1)), dim3(kBlock), 0, st, n, key, W.excl, tau, W.gt,
+                     W.eq);
   FI_HIP_TRY(hipGetLastError());
-  int rc = scan_exclusive(st, eq, rank, P + 1, scan_tmp);
+  int rc = scan_exclusive(st, W.eq, W.rank, n + 1, W.scan_tmp);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_select, dim3(blocks(P + 1)), dim3(kBlock), 0, st, P, gt, eq, rank,
-                     (int32_t)remaining, sel);
+  hipLaunchKernelGGL(k_select, dim3(blocks(n + 1)), dim3(kBlock), 0, st, n, W.gt, W.eq, W.rank,
+                     (int32_t)remaining, W.sel);
   FI_HIP_TRY(hipGetLastError());
-  rc = scan_exclusive(st, sel, pos, P + 1, scan_tmp);
+  rc = scan_exclusive(st, W.sel, W.pos, n + 1, W.scan_tmp);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks(P)), dim3(kBlock), 0, st, P, sel, pos, out);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kBlock), 0, st, n, W.sel, W.pos, out);
   FI_HIP_TRY(hipGetLastError());
+  return FI_OK;
+}
+
+}  // namespace
+
+int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out) {
+  if (k == 0) return FI_OK;
+  hipStream_t st = M->ctx->stream;
+  const int64_t P = M->P;
+  SelectSpace W;
+  int rc = select_space(M, P, W);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_zero_u8, dim3(blocks(P)), dim3(kBlock), 0, st, P, W.excl);
+  hipLaunchKernelGGL(k_mark_mask, dim3(blocks(M->m)), dim3(kBlock), 0, st, (int)M->m,
+                     M->d_mask_pix, W.excl);
+  FI_HIP_TRY(hipGetLastError());
+  int64_t taken = 0;
+  rc = select_topk(st, P, e, W, k, out, &taken);
+  if (rc) return rc;
+  if (taken < k) return fail(FI_E_INVALID, "top-k: fewer candidates than requested");
   FI_HIP_TRY(hipStreamSynchronize(st));
   return FI_OK;
 }
 
+// Section 3's densification step: triangles in descending order of their
+// total squared error, one new mask pixel in each (its empty pixel of
+// largest error), k pixels in all.
+int paper_densify_step(fi_mesh* M, const double* e, int64_t k, int32_t* out, int64_t* added) {
+  *added = 0;
+  if (k == 0) return FI_OK;
+  hipStream_t st = M->ctx->stream;
+  const int64_t T = M->T, P = M->P;
+  // per-triangle error and best empty pixel (the pixel mask travels in the
+  // selection workspace's byte array, sized for max(P, T))
+  const int64_t n = std::max(P, T);
+  SelectSpace W;
+  int rc = select_space(M, n, W);
+  if (rc) return rc;
+  if (!M->d_tri_err) {
+    if ((rc = device_alloc(M, (void**)&M->d_tri_err, (size_t)T * sizeof(double))) ||
+        (rc = device_alloc(M, (void**)&M->d_tri_best, (size_t)T * sizeof(int32_t))) ||
+        (rc = device_alloc(M, (void**)&M->d_sel_tri, (size_t)std::max<int64_t>(T, 1) *
+                                                         sizeof(int32_t))))
+      return rc;
+  }
+  hipLaunchKernelGGL(k_zero_u8, dim3(blocks(P)), dim3(kBlock), 0, st, P, W.excl);
+  hipLaunchKernelGGL(k_mark_mask, dim3(blocks(M->m)), dim3(kBlock), 0, st, (int)M->m,
+                     M->d_mask_pix, W.excl);
+  FI_HIP_TRY(hipGetLastError());
+  if ((rc = launch_tri_best(M, e, W.excl, M->d_tri_err, M->d_tri_best))) return rc;
+  // exclusion over triangles: those without an empty pixel
+  hipLaunchKernelGGL(k_excl_no_best, dim3(blocks(T)), dim3(kBlock), 0, st, T, M->d_tri_best,
+                     W.excl);
+  FI_HIP_TRY(hipGetLastError());
+  int64_t taken = 0;
+  if ((rc = select_topk(st, T, M->d_tri_err, W, k, M->d_sel_tri, &taken))) return rc;
+  // their pixels, in ascending pixel order: flag, scan, scatter over P
+  int32_t* flag = W.gt;  // reuse (n + 1 ints each)
+  hipLaunchKernelGGL(k_zero_i32, dim3(blocks(P + 1)), dim3(kBlock), 0, st, P + 1, flag);
+  if (taken > 0)
+    hipLaunchKernelGGL(k_flag_best, dim3(blocks(taken)), dim3(kBlock), 0, st, taken,
+                       M->d_sel_tri, M->d_tri_best, flag);
+  FI_HIP_TRY(hipGetLastError());
+  if ((rc = scan_exclusive(st, flag, W.pos, P + 1, W.scan_tmp))) return rc;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks(P)), dim3(kBlock), 0, st, P, flag, W.pos, out);
+  FI_HIP_TRY(hipGetLastError());
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  *added = taken;
+  return FI_OK;
+}
 }  // namespace fi
