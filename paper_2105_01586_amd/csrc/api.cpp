@@ -87,7 +87,7 @@ int alloc_workspace(fi_mesh* M) {
   const int64_t n = M->n, m = M->m, V = M->V, T = M->T;
 #define TRY(x) do { rc = (x); if (rc) return rc; } while (0)
   TRY(alloc_n(M, &M->d_cnt, std::max(2 * (n + 1), m + 1)));
-  TRY(alloc_n(M, &M->d_scan_tmp, scan_tmp_ints(std::max(n, m) + 1)));
+  TRY(alloc_n(M, &M->d_scan_tmp, scan_tmp_ints(std::max(std::max(n, m), T) + 1)));
   TRY(alloc_n(M, &M->d_ff_rowptr, n + 1));
   TRY(alloc_n(M, &M->d_fd_rowptr, n + 1));
   TRY(alloc_n(M, &M->d_df_rowptr, m + 1));
@@ -118,6 +118,9 @@ int alloc_workspace(fi_mesh* M) {
   TRY(alloc_n(M, &M->d_tF, n));
   TRY(alloc_n(M, &M->d_tD, m));
   TRY(alloc_n(M, &M->d_rpart, raster_blocks(M)));
+  TRY(alloc_n(M, &M->d_owner, M->P));
+  TRY(alloc_n(M, &M->d_tri_px, M->P));
+  TRY(alloc_n(M, &M->d_tri_px_ptr, T + 1));
 #undef TRY
   FI_HIP_TRY(hipHostMalloc((void**)&M->h_red, 8 * sizeof(double), hipHostMallocDefault));
   FI_HIP_TRY(hipHostMalloc((void**)&M->h_ctl, 4 * sizeof(int32_t), hipHostMallocDefault));
@@ -351,7 +354,7 @@ int fi::mesh_upload(fi_ctx* ctx, fi_host_mesh** host, Arena* arena, fi_mesh** ou
       (rc = upload(M, &M->d_mask_vids, H.mask_vids)) ||
       (rc = upload(M, &M->d_mask_pix, H.mask_pix)) || (rc = upload(M, &M->d_vt_ptr, H.vt_ptr)) ||
       (rc = upload(M, &M->d_vt_idx, H.vt_idx)) || (rc = alloc_workspace(M)) ||
-      (rc = fi_assemble(M))) {
+      (rc = build_pixel_maps(M)) || (rc = fi_assemble(M))) {
     std::string keep = g_last_error;
     (*host)->mesh = std::move(M->host);
     free_mesh(M);
@@ -559,8 +562,9 @@ int fi_owner_map(fi_mesh* M, int32_t* owner_dev) {
   if (rc) return rc;
   if (!owner_dev) return fail(FI_E_INVALID, "owner_dev is NULL");
   FI_HIP_TRY(hipSetDevice(M->ctx->device));
-  rc = launch_raster(M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, owner_dev, nullptr);
-  if (rc) return rc;
+  // the map the interpolation kernels use (built once with the mesh)
+  FI_HIP_TRY(hipMemcpyAsync(owner_dev, M->d_owner, (size_t)M->P * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, M->ctx->stream));
   FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
   return FI_OK;
 }

@@ -186,6 +186,9 @@ struct fi_mesh {
   double* d_tF = nullptr;     // n
   double* d_tD = nullptr;     // m
   double* d_rpart = nullptr;  // raster partial sums (one per leaf block)
+  int32_t* d_owner = nullptr;      // P: owner triangle of every pixel
+  int32_t* d_tri_px_ptr = nullptr; // T + 1: pixel list of each triangle (CSR)
+  int32_t* d_tri_px = nullptr;     // P: pixels by owner triangle, ascending within one
 
   // tonal workspace (device, allocated on first use)
   double* d_tg = nullptr;  // m: p
@@ -232,6 +235,8 @@ int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uin
                   double* u_out, double* e_out, double* tri_err_out, int32_t* owner_out,
                   double* partial_out);
 int raster_blocks(const fi_mesh* M);
+// Owner map and per-triangle pixel lists (geometry only; once per mesh).
+int build_pixel_maps(fi_mesh* M);
 int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart);
 // Per triangle: total error of its pixels, and its empty pixel of largest
 // error (-1 if none); in_mask holds one byte per pixel.

@@ -367,6 +367,152 @@ __global__ __launch_bounds__(kBlock) void k_raster(
   if (partial && threadIdx.x == 0) partial[blockIdx.x] = acc[0];
 }
 
+// ------------------------------------------------- pixel-major passes ----
+// The leaf-major kernels above give one thread a whole leaf; the passes below
+// give one thread a pixel (interpolation, error) or a triangle's pixel list
+// (the transposed interpolation), with the owner of every pixel found once
+// per mesh by the leaf-major rule.
+
+// Per leaf: how many pixels each of its triangles owns.
+__global__ __launch_bounds__(kBlock) void k_tri_count(int64_t nleaves,
+                                                      const int32_t* __restrict__ leaves,
+                                                      const int32_t* __restrict__ tri,
+                                                      const int32_t* __restrict__ vxy,
+                                                      int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nleaves) return;
+  LeafTris L;
+  load_leaf(leaves, i, tri, vxy, L);
+  int c[kMaxLeafTri];
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) c[k] = 0;
+  const int x0 = leaves[4 * i], y0 = leaves[4 * i + 1];
+  const int s = 1 << leaves[4 * i + 2];
+  for (int dy = 0; dy < s; ++dy) {
+    for (int dx = 0; dx < s; ++dx) {
+      int oa, ob, oc;
+      const int own = max(0, locate(L, x0 + dx, y0 + dy, oa, ob, oc));  // (always >= 0)
+#pragma unroll
+      for (int k = 0; k < kMaxLeafTri; ++k) c[k] += k == own;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k)
+    if (k < L.nt) cnt[L.t0 + k] = c[k];
+}
+
+// Per leaf: its pixels into their owners' lists, ascending, and the owner map.
+__global__ __launch_bounds__(kBlock) void k_tri_fill(int64_t nleaves, int N,
+                                                     const int32_t* __restrict__ leaves,
+                                                     const int32_t* __restrict__ tri,
+                                                     const int32_t* __restrict__ vxy,
+                                                     const int32_t* __restrict__ ptr,
+                                                     int32_t* __restrict__ px,
+                                                     int32_t* __restrict__ owner) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nleaves) return;
+  LeafTris L;
+  load_leaf(leaves, i, tri, vxy, L);
+  int cur[kMaxLeafTri];
+#pragma unroll
+  for (int k = 0; k < kMaxLeafTri; ++k) cur[k] = k < L.nt ? ptr[L.t0 + k] : 0;
+  const int x0 = leaves[4 * i], y0 = leaves[4 * i + 1];
+  const int s = 1 << leaves[4 * i + 2];
+  for (int dy = 0; dy < s; ++dy) {
+    for (int dx = 0; dx < s; ++dx) {
+      int oa, ob, oc;
+      const int own = max(0, locate(L, x0 + dx, y0 + dy, oa, ob, oc));  // (always >= 0)
+      const int32_t pix = (y0 + dy) * N + (x0 + dx);
+      owner[pix] = L.t0 + own;
+#pragma unroll
+      for (int k = 0; k < kMaxLeafTri; ++k) {
+        if (k == own) {
+          px[cur[k]] = pix;
+          ++cur[k];
+        }
+      }
+    }
+  }
+}
+
+// u at every pixel from the vertex values (one thread per pixel; the weights
+// are formed exactly as in the leaf-major pass).
+__global__ __launch_bounds__(kBlock) void k_interp_px(int64_t P, int logN,
+                                                      const int32_t* __restrict__ owner,
+                                                      const int32_t* __restrict__ tri,
+                                                      const int32_t* __restrict__ vxy,
+                                                      const double* __restrict__ uv,
+                                                      double* __restrict__ u_out) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= P) return;
+  const int t = owner[p];
+  const int x = (int)(p & ((1 << logN) - 1)), y = (int)(p >> logN);
+  const int va = tri[3 * t], vb = tri[3 * t + 1], vc = tri[3 * t + 2];
+  const int ax = vxy[2 * va], ay = vxy[2 * va + 1];
+  const int bx = vxy[2 * vb], by = vxy[2 * vb + 1];
+  const int cx = vxy[2 * vc], cy = vxy[2 * vc + 1];
+  const int den = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+  const double ia = 1.0 / (double)den;
+  const int oa = (bx - x) * (cy - y) - (by - y) * (cx - x);
+  const int ob = (cx - x) * (ay - y) - (cy - y) * (ax - x);
+  const int oc = (ax - x) * (by - y) - (ay - y) * (bx - x);
+  u_out[p] = ((double)oa * ia) * uv[va] + ((double)ob * ia) * uv[vb] + ((double)oc * ia) * uv[vc];
+}
+
+// e = (u - f)^2 per pixel and per-block partial sums; `nblocks` blocks cover
+// the pixels grid-stride, so the number of partial sums is fixed by the mesh.
+__global__ __launch_bounds__(kBlock) void k_err_px(int64_t P, const double* __restrict__ u,
+                                                   const uint8_t* __restrict__ f,
+                                                   double* __restrict__ e_out,
+                                                   double* __restrict__ partial) {
+  __shared__ double lds[4];
+  double acc[1] = {0.0};
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * kBlock) {
+    const double d = u[p] - (double)f[p];
+    const double e = d * d;
+    if (e_out) e_out[p] = e;
+    acc[0] += e;
+  }
+  block_sum<1>(acc, lds);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+}
+
+// Transposed interpolation, one thread per triangle over its pixel list (in
+// ascending pixel order, as the leaf-major pass adds them).
+__global__ __launch_bounds__(kBlock) void k_interp_T_tri(int64_t T, int logN,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ px,
+                                                         const int32_t* __restrict__ tri,
+                                                         const int32_t* __restrict__ vxy,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ tpart) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= T) return;
+  const int va = tri[3 * t], vb = tri[3 * t + 1], vc = tri[3 * t + 2];
+  const int ax = vxy[2 * va], ay = vxy[2 * va + 1];
+  const int bx = vxy[2 * vb], by = vxy[2 * vb + 1];
+  const int cx = vxy[2 * vc], cy = vxy[2 * vc + 1];
+  const int den = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+  const double ia = 1.0 / (double)den;
+  double Sa = 0.0, Sb = 0.0, Sc = 0.0;
+  const int j1 = ptr[t + 1];
+  for (int j = ptr[t]; j < j1; ++j) {
+    const int p = px[j];
+    const int x = p & ((1 << logN) - 1), y = p >> logN;
+    const int oa = (bx - x) * (cy - y) - (by - y) * (cx - x);
+    const int ob = (cx - x) * (ay - y) - (cy - y) * (ax - x);
+    const int oc = (ax - x) * (by - y) - (ay - y) * (bx - x);
+    const double rv = r[p];
+    Sa += ((double)oa * ia) * rv;
+    Sb += ((double)ob * ia) * rv;
+    Sc += ((double)oc * ia) * rv;
+  }
+  tpart[3 * t] = Sa;
+  tpart[3 * t + 1] = Sb;
+  tpart[3 * t + 2] = Sc;
+}
+
 // Per triangle: the total squared error of the pixels it owns (added in
 // ascending pixel order), and its pixel of largest error that is not in the
 // mask (ties: the lower index; -1 if it owns none). Section 3's inputs to the
@@ -632,9 +778,43 @@ int launch_vertex_values(fi_mesh* M, const double* xF, const double* g, double* 
 int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uint8_t* f,
                   double* u_out, double* e_out, double* tri_err_out, int32_t* owner_out,
                   double* partial_out) {
-  hipLaunchKernelGGL(k_raster, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L, M->N,
-                     M->d_leaves, M->d_tri, M->d_vxy, uvert, u_in, f, u_out, e_out, tri_err_out,
-                     owner_out, partial_out);
+  hipStream_t st = M->ctx->stream;
+  if (tri_err_out || owner_out || !M->d_owner || (u_in && u_out)) {
+    // per-triangle sums and the owner map need the leaf-major pass
+    hipLaunchKernelGGL(k_raster, dim3(grid_for(M->L)), dim3(kBlock), 0, st, M->L, M->N,
+                       M->d_leaves, M->d_tri, M->d_vxy, uvert, u_in, f, u_out, e_out,
+                       tri_err_out, owner_out, partial_out);
+    FI_LAUNCH_CHECK();
+    return FI_OK;
+  }
+  const double* u = u_in;
+  if (!u_in && u_out) {
+    if (!uvert) return fail(FI_E_INVALID, "interpolation without vertex values");
+    hipLaunchKernelGGL(k_interp_px, dim3(grid_for(M->P)), dim3(kBlock), 0, st, M->P,
+                       M->host.levels, M->d_owner, M->d_tri, M->d_vxy, uvert, u_out);
+    FI_LAUNCH_CHECK();
+    u = u_out;
+  }
+  if (f) {
+    if (!u) return fail(FI_E_INVALID, "error without pixel values");
+    hipLaunchKernelGGL(k_err_px, dim3(raster_blocks(M)), dim3(kBlock), 0, st, M->P, u, f, e_out,
+                       partial_out);
+    FI_LAUNCH_CHECK();
+  }
+  return FI_OK;
+}
+
+int build_pixel_maps(fi_mesh* M) {
+  hipStream_t st = M->ctx->stream;
+  int32_t* cnt = (int32_t*)M->d_tpart;  // scratch: 3T doubles hold T + 1 counts
+  hipLaunchKernelGGL(k_tri_count, dim3(grid_for(M->L)), dim3(kBlock), 0, st, M->L, M->d_leaves,
+                     M->d_tri, M->d_vxy, cnt);
+  FI_LAUNCH_CHECK();
+  FI_HIP_TRY(hipMemsetAsync(cnt + M->T, 0, sizeof(int32_t), st));
+  int rc = scan_exclusive(st, cnt, M->d_tri_px_ptr, M->T + 1, M->d_scan_tmp);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_tri_fill, dim3(grid_for(M->L)), dim3(kBlock), 0, st, M->L, M->N,
+                     M->d_leaves, M->d_tri, M->d_vxy, M->d_tri_px_ptr, M->d_tri_px, M->d_owner);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }
@@ -648,6 +828,13 @@ int launch_tri_best(fi_mesh* M, const double* e, const uint8_t* in_mask, double*
 }
 
 int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart) {
+  if (M->d_tri_px) {
+    hipLaunchKernelGGL(k_interp_T_tri, dim3(grid_for(M->T)), dim3(kBlock), 0, M->ctx->stream,
+                       M->T, M->host.levels, M->d_tri_px_ptr, M->d_tri_px, M->d_tri, M->d_vxy, r,
+                       tpart);
+    FI_LAUNCH_CHECK();
+    return FI_OK;
+  }
   hipLaunchKernelGGL(k_raster_T, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L,
                      M->N, M->d_leaves, M->d_tri, M->d_vxy, r, tpart);
   FI_LAUNCH_CHECK();

@@ -143,13 +143,14 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   add(2 * V, 4); add(3 * T, 4); add(4 * (L + 1), 4); add(V, 4); add(n, 4); add(m, 4); add(m, 4);
   add(V + 1, 4); add(3 * T, 4);
   // workspace
-  add(std::max(2 * (n + 1), m + 1), 4); add(scan_tmp_ints(std::max(n, m) + 1), 4);
+  add(std::max(2 * (n + 1), m + 1), 4); add(scan_tmp_ints(std::max(std::max(n, m), T) + 1), 4);
   add(n + 1, 4); add(n + 1, 4); add(m + 1, 4);
   add(n, 8); add(n, 8); add(n, 4); add(n, 8); add(n, 8); add(n, 8); add(n, 8);
   add(n, 4); add(n, 4); add(4 * n, 4); add(4 * n, 4);
   add(n, 8); add(n, 8); add(4 * n, 8); add(4 * n, 8);
   add(2 * 4 * kMaxGrid, 8); add(8, 8); add(4, 4); add(kMaxGrid, 8); add(8, 8);
   add(V, 8); add(m, 8); add(3 * T, 8); add(n, 8); add(m, 8); add((L + kBlock - 1) / kBlock, 8);
+  add(P, 4); add(P, 4); add(T + 1, 4);  // owner map and per-triangle pixel lists
   // matrices
   add(deg_free, 4); add(deg_free, 8); add(deg_free, 4); add(deg_free, 4); add(deg_free, 8);
   add(deg_mask, 4); add(deg_mask, 8);
