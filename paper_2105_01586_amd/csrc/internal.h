@@ -175,9 +175,6 @@ struct fi_mesh {
   double* d_lvl1 = nullptr;   // first-level sums of that reduction
   double* d_prm = nullptr;    // inner-solve parameters read by the CG kernels
   int32_t* d_flag = nullptr;  // packing flags
-  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // [0] FP32, [1] FP64
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  int graph_chunk = 0;
 
   // pixel / vertex work vectors (device)
   double* d_uvert = nullptr;  // V
@@ -256,8 +253,8 @@ int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double*
 
 // Solver pieces (solver.hip).
 constexpr int kMaxEll = 8;
-int solver_setup(fi_mesh* M);      // after assembly: ELL packing, mode, graphs reset
-void solver_release(fi_mesh* M);   // graphs and events
+int solver_setup(fi_mesh* M);      // after assembly: ELL packing, launch shape
+void solver_release(fi_mesh* M);   // events and the host mirror
 int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats);
 int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms);
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision);

@@ -19,9 +19,9 @@
 // Every per-launch quantity (state record, partial sums, r, s, q) is double
 // buffered by launch parity: launch k reads slot k % 2 and writes the other,
 // so blocks of one launch never see each other's writes. The host only
-// replays a recorded HIP graph of step launches, a couple of chunks ahead of
-// the device, until the launch that ends the solve reports the outcome in
-// pinned host memory; it makes no decision between refinements.
+// queues step launches, a couple of chunks ahead of the device, until the
+// launch that ends the solve reports the outcome in pinned host memory; it
+// makes no decision between refinements.
 //
 // Matrix layout: the off-diagonal part of K_FF in column-major ELL (slot k of
 // row i at ell[k * n_pad + i], coalesced across a wavefront); on the
@@ -301,6 +301,8 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
       }
     }
   }
+  const bool writer = lb == 0 && threadIdx.x == 0;
+  const int phase = A.force ? (int)kIter : Rin.phase;
   if constexpr (SUMMED) {
     red[0] = A.part_in[0];
     red[1] = A.part_in[1];
@@ -308,11 +310,10 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
   } else {
     block_sum_w<3, BS / 64>(red, lds);
   }
-  const bool writer = lb == 0 && threadIdx.x == 0;
-  const int phase = A.force ? (int)kIter : Rin.phase;
-  double v[3] = {0.0, 0.0, 0.0};
-
-  if (phase >= kDoneOk) {  // finished: carry the record forward
+  // A launch queued after the solve has ended leaves here (the phase is
+  // uniform). Testing it before the reduction above would put the record
+  // load on every working launch's critical path.
+  if (phase >= kDoneOk) {
     // carry the record forward field by field (a whole-struct copy of the
     // local record would put it in LDS); the host mirror already shows the end
     if (writer)
@@ -321,6 +322,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
               Rin.rnorm, Rin.bnorm);
     return;
   }
+  double v[3] = {0.0, 0.0, 0.0};
 
   if (phase == kInit) {
     // red[0] = ||r64||^2 from the start or refinement launch
@@ -782,55 +784,8 @@ int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch) {
   return FI_OK;
 }
 
-constexpr int kChunk = 8;  // step launches per recorded graph (even)
+constexpr int kChunk = 8;  // step launches per paced chunk (even)
 
-template <typename T>
-int get_graph(fi_mesh* M, hipGraphExec_t* out) {
-  const int pi = Prec<T>::idx;
-  if (M->graph_exec[pi]) {
-    *out = M->graph_exec[pi];
-    return FI_OK;
-  }
-  hipGraph_t g = nullptr;
-  FI_HIP_TRY(hipGraphCreate(&g, 0));
-  hipGraphNode_t prev = nullptr;
-  for (int k = 0; k < kChunk; ++k) {
-    const int par = k & 1;  // chunks start on parity 0: the start launch wrote slot 0
-    StepArgs<T> A = make_args<T>(M, par, 0);
-    void* params[1] = {&A};
-    hipKernelNodeParams kp{};
-    kp.func = step_kernel<T>(M);
-    kp.gridDim = dim3(M->cg_grid);
-    kp.blockDim = dim3(M->cg_bs);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = params;
-    kp.extra = nullptr;
-    hipGraphNode_t node;
-    FI_HIP_TRY(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-    prev = node;
-    if (M->large_mode) {
-      ReduceArgs R{};
-      add_reduce(R, M, par);
-      void* rp[1] = {&R};
-      hipKernelNodeParams rk{};
-      rk.func = (void*)k_reduce_partials;
-      rk.gridDim = dim3(R.start[1]);
-      rk.blockDim = dim3(kBlock);
-      rk.sharedMemBytes = 0;
-      rk.kernelParams = rp;
-      rk.extra = nullptr;
-      hipGraphNode_t rnode;
-      FI_HIP_TRY(hipGraphAddKernelNode(&rnode, g, &prev, 1, &rk));
-      prev = rnode;
-    }
-  }
-  hipGraphExec_t ex = nullptr;
-  FI_HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-  M->graph[pi] = g;
-  M->graph_exec[pi] = ex;
-  *out = ex;
-  return FI_OK;
-}
 
 int next_epoch(fi_mesh* M) {
   M->epoch = (M->epoch + 1) & kEpochMask;
@@ -859,7 +814,8 @@ int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
   return 1;
 }
 
-// The host replays graphs of kChunk step launches, each followed by an event,
+// The host queues chunks of kChunk step launches, each followed by an event
+// (plain launches: measured faster here than replaying a recorded graph),
 // keeps at most kAhead chunks queued, and stops as soon as the mirror shows
 // the end of this solve. Chunks still queued then run as idle launches;
 // later work on the stream is ordered after them.
@@ -871,9 +827,6 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
   const int epoch = next_epoch(M);
   int rc = launch_start<T>(M, o, epoch);
   if (rc) return rc;
-  hipGraphExec_t ex = nullptr;
-  rc = get_graph<T>(M, &ex);
-  if (rc) return rc;
   // Upper bound on launches: every inner solve takes at most max_inner + 2.
   const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
   const int64_t max_chunks = max_launch / kChunk + 2;
@@ -882,7 +835,10 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
     int drc = FI_OK;
     if (read_mirror(M, epoch, stats, &drc)) return drc;
     if (launched < max_chunks && launched - completed < kAhead) {
-      FI_HIP_TRY(hipGraphLaunch(ex, st));
+      for (int q = 0; q < kChunk; ++q) {
+        rc = launch_step<T>(M, q & 1, 0);
+        if (rc) return rc;
+      }
       FI_HIP_TRY(hipEventRecord(M->chunk_ev[launched % kChunkEvents], st));
       ++launched;
       continue;
@@ -981,12 +937,6 @@ int solve_poll(fi_mesh* M, int epoch, fi_solve_stats* stats, int* done) {
 }
 
 void solver_release(fi_mesh* M) {
-  for (int k = 0; k < 2; ++k) {
-    if (M->graph_exec[k]) (void)hipGraphExecDestroy(M->graph_exec[k]);
-    if (M->graph[k]) (void)hipGraphDestroy(M->graph[k]);
-    M->graph_exec[k] = nullptr;
-    M->graph[k] = nullptr;
-  }
   for (int k = 0; k < kChunkEvents; ++k) {
     if (M->chunk_ev[k]) (void)hipEventDestroy(M->chunk_ev[k]);
     M->chunk_ev[k] = nullptr;
