@@ -29,4 +29,5 @@ that it follows:
   through the normal equations B^T B g = B^T f (Section 4, eqs. (4), (5)).
 * ``densify``: global top-k error-driven mask growth, and the paper's
   per-triangle densification (Section 3).
+* ``colour``: the method channel by channel on one shared mesh (Section 6).
 """

@@ -26,6 +26,14 @@ Pixel (r, c) has x = c and y = r. Images are row-major, index r * W + c.
 
 Masks draw ``k = count_from_density(density, P)`` distinct pixels uniformly
 without replacement from ``default_rng([seed, 1])`` and return them sorted.
+
+Colour images (``make_image_rgb``) share one luminance layout across their
+three channels, as natural photographs do: the grey image of the same seed
+(before its noise and quantisation) is the common part; channel c adds, from
+``default_rng([seed, 3, c])``, ``max(1, bumps // 4)`` broad chroma bumps
+(A ~ U[-50, 50], sigma ~ U[4 sigma_lo, 4 sigma_hi], same window rule) and its
+own N(0, noise_std) noise, then is clipped and rounded like the grey image.
+The result is planar: shape (3, H, W), channel c at [c].
 """
 from __future__ import annotations
 
@@ -37,6 +45,7 @@ import numpy as np
 __all__ = [
     "count_from_density",
     "make_image",
+    "make_image_rgb",
     "make_mask",
     "Workload",
     "WORKLOADS",
@@ -107,18 +116,13 @@ def _halfplane_direct(img: np.ndarray, px: float, py: float, theta: float, amoun
     img[((x - px) * math.cos(theta) + (y - py) * math.sin(theta)) > 0] += amount
 
 
-def make_image(seed: int, W: int, H: int | None = None, bumps: int = 8, edges: int = 3,
-               sigma_lo: float = 3.0, sigma_hi: float = 15.0, noise_std: float = 2.0,
-               _direct_edges: bool = False) -> np.ndarray:
-    """Synthetic 8-bit greyscale image, shape (H, W), dtype uint8 (recipe above)."""
-    if H is None:
-        H = W
-    rng = np.random.default_rng([seed, 0])
-    img = np.full((H, W), 128.0, dtype=np.float64)
+def _add_bumps(img: np.ndarray, rng, bumps: int, amp: float, sigma_lo: float,
+               sigma_hi: float) -> None:
+    H, W = img.shape
     for _ in range(bumps):
         cx = rng.uniform(0.0, W)
         cy = rng.uniform(0.0, H)
-        A = rng.uniform(-80.0, 80.0)
+        A = rng.uniform(-amp, amp)
         sig = rng.uniform(sigma_lo, sigma_hi)
         rad = 6.0 * sig
         x0 = max(0, int(math.ceil(cx - rad)))
@@ -132,6 +136,18 @@ def make_image(seed: int, W: int, H: int | None = None, bumps: int = 8, edges: i
         gx = np.exp(-((xs - cx) ** 2) / (2.0 * sig * sig))
         gy = np.exp(-((ys - cy) ** 2) / (2.0 * sig * sig))
         img[y0:y1 + 1, x0:x1 + 1] += A * np.outer(gy, gx)
+
+
+def make_image(seed: int, W: int, H: int | None = None, bumps: int = 8, edges: int = 3,
+               sigma_lo: float = 3.0, sigma_hi: float = 15.0, noise_std: float = 2.0,
+               _direct_edges: bool = False, _field: bool = False) -> np.ndarray:
+    """Synthetic 8-bit greyscale image, shape (H, W), dtype uint8 (recipe above).
+    ``_field``: return the float64 image before noise, clipping and rounding."""
+    if H is None:
+        H = W
+    rng = np.random.default_rng([seed, 0])
+    img = np.full((H, W), 128.0, dtype=np.float64)
+    _add_bumps(img, rng, bumps, 80.0, sigma_lo, sigma_hi)
     for _ in range(edges):
         px = rng.uniform(0.0, W)
         py = rng.uniform(0.0, H)
@@ -141,10 +157,32 @@ def make_image(seed: int, W: int, H: int | None = None, bumps: int = 8, edges: i
             _halfplane_direct(img, px, py, theta, 40.0 * sign)
         else:
             _halfplane_add(img, px, py, theta, 40.0 * sign)
+    if _field:
+        return img
     if noise_std > 0:
         img += rng.normal(0.0, noise_std, size=(H, W))
     np.clip(img, 0.0, 255.0, out=img)
     return np.rint(img).astype(np.uint8)
+
+
+def make_image_rgb(seed: int, W: int, H: int | None = None, bumps: int = 8, edges: int = 3,
+                   sigma_lo: float = 3.0, sigma_hi: float = 15.0,
+                   noise_std: float = 2.0) -> np.ndarray:
+    """Synthetic 8-bit colour image, planar shape (3, H, W), dtype uint8
+    (recipe above)."""
+    if H is None:
+        H = W
+    base = make_image(seed, W, H, bumps, edges, sigma_lo, sigma_hi, _field=True)
+    out = np.empty((3, H, W), dtype=np.uint8)
+    for c in range(3):
+        rng = np.random.default_rng([seed, 3, c])
+        img = base.copy()
+        _add_bumps(img, rng, max(1, bumps // 4), 50.0, 4.0 * sigma_lo, 4.0 * sigma_hi)
+        if noise_std > 0:
+            img += rng.normal(0.0, noise_std, size=(H, W))
+        np.clip(img, 0.0, 255.0, out=img)
+        out[c] = np.rint(img).astype(np.uint8)
+    return out
 
 
 def make_mask(seed: int, P: int, density: float | None = None, k: int | None = None) -> np.ndarray:

@@ -39,3 +39,16 @@ def test_serving_trace():
     assert {r.side for r in tr} <= {128, 256, 512, 1024, 2048}
     assert all(0.02 <= r.density <= 0.10 for r in tr)
     assert tr[5].image_seed == 1005
+
+
+def test_colour_image():
+    a = synth.make_image_rgb(7, 64, 48, bumps=8, edges=3)
+    b = synth.make_image_rgb(7, 64, 48, bumps=8, edges=3)
+    assert a.dtype == np.uint8 and a.shape == (3, 48, 64)
+    assert np.array_equal(a, b)
+    # the channels share the luminance layout but are not copies of each other
+    x = a.reshape(3, -1).astype(np.float64)
+    for i in range(3):
+        for j in range(i + 1, 3):
+            assert not np.array_equal(a[i], a[j])
+            assert np.corrcoef(x[i], x[j])[0, 1] > 0.3
