@@ -21,6 +21,7 @@ import math
 
 import numpy as np
 
+from . import delaunay
 from . import error as err
 from . import fem, mesh as mesh_mod, raster, solve
 
@@ -28,12 +29,18 @@ from . import fem, mesh as mesh_mod, raster, solve
 class Problem:
     """Everything the oracle derives from one (image side, mask) pair."""
 
-    def __init__(self, N: int, mask_idx, factor_method: str = "auto"):
-        self.mesh = mesh_mod.build_mesh(N, mask_idx)
+    def __init__(self, N: int, mask_idx, factor_method: str = "auto", unknown_idx=None):
+        """unknown_idx: None for the quadtree mesh; else the unknown vertices
+        (pixel indices) of the paper's Delaunay mesh (``delaunay``)."""
+        if unknown_idx is None:
+            self.mesh = mesh_mod.build_mesh(N, mask_idx)
+        else:
+            self.mesh = delaunay.build_mesh(N, mask_idx, unknown_idx)
         if self.mesh.m == 0:
             raise ValueError("empty mask: the system is singular (Section 2.2 needs a mask pixel)")
         self.sys = fem.assemble(self.mesh)
-        self.rast = raster.rasteriser(self.mesh)
+        self.rast = (raster.rasteriser(self.mesh) if unknown_idx is None
+                     else delaunay.rasteriser(self.mesh))
         R = self.rast.R.tocsc()
         self.R_F = R[:, self.mesh.free_vids].tocsr()
         self.R_D = R[:, self.mesh.mask_vids].tocsr()

@@ -27,6 +27,9 @@ Pixel (r, c) has x = c and y = r. Images are row-major, index r * W + c.
 Masks draw ``k = count_from_density(density, P)`` distinct pixels uniformly
 without replacement from ``default_rng([seed, 1])`` and return them sorted.
 
+Unknown vertices of the Delaunay mesh (``make_unknowns``) are non-mask
+pixels drawn uniformly without replacement from ``default_rng([seed, 4])``.
+
 Colour images (``make_image_rgb``) share one luminance layout across their
 three channels, as natural photographs do: the grey image of the same seed
 (before its noise and quantisation) is the common part; channel c adds, from
@@ -47,6 +50,7 @@ __all__ = [
     "make_image",
     "make_image_rgb",
     "make_mask",
+    "make_unknowns",
     "Workload",
     "WORKLOADS",
     "serving_trace",
@@ -196,6 +200,18 @@ def make_mask(seed: int, P: int, density: float | None = None, k: int | None = N
     rng = np.random.default_rng([seed, 1])
     idx = rng.choice(P, size=k, replace=False)
     return np.sort(idx).astype(np.int32)
+
+
+def make_unknowns(seed: int, P: int, mask_idx, count: int) -> np.ndarray:
+    """Unknown vertices of the paper's Delaunay mesh: ``count`` distinct
+    non-mask pixels drawn uniformly without replacement from
+    ``default_rng([seed, 4])``, sorted int32."""
+    mask = np.asarray(mask_idx, dtype=np.int64)
+    free = np.setdiff1d(np.arange(P, dtype=np.int64), mask, assume_unique=False)
+    if not 0 <= count <= free.size:
+        raise ValueError("unknown-vertex count out of range")
+    rng = np.random.default_rng([seed, 4])
+    return np.sort(rng.choice(free, size=count, replace=False)).astype(np.int32)
 
 
 @dataclass(frozen=True)
