@@ -30,4 +30,9 @@ that it follows:
 * ``densify``: global top-k error-driven mask growth, and the paper's
   per-triangle densification (Section 3).
 * ``colour``: the method channel by channel on one shared mesh (Section 6).
+* ``delaunay``: the paper's own mesh, a Delaunay triangulation of the mask
+  pixels and the unknown vertices (Section 2.2), made unique by symbolic
+  perturbation where vertices are cocircular.
+* ``l1``: tonal optimisation for the L1 error by iteratively reweighted least
+  squares (the paper's large colour example; it states no method).
 """
