@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps (default 2; 0 for the 8192^2 workload)")
     ap.add_argument("--workload", default="tonal512",
-                    help="tonal512 (default), large8192, serving or densify")
+                    help="tonal512 (default), large8192, serving, densify or rgb512")
     ap.add_argument("--requests", type=int, default=256, help="serving: requests in the trace")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving: arrivals per second (default 0.7 x FP64 capacity)")
@@ -251,7 +251,9 @@ def densify_main(args):
       +0.1% (21 inpaintings);
     * the paper's own per-triangle rule at 512^2 and 1024^2: final density
       4% introduced in n = 10 inpaintings, m/n pixels each (first m/n at
-      random), as in its Table 2 (context only: the paper's CPU and image).
+      random), as in its Table 2 (context only: the paper's CPU and image);
+    * the same at 512^2 on the paper's own Delaunay mesh, with m unknown
+      vertices drawn once.
 
     ``value`` is inpainted Mpixel/s over all the loops (pixels of every
     inpainting / wall time, mesh builds included)."""
@@ -262,13 +264,15 @@ def densify_main(args):
     ctx = fi.Context(0)
     runs = {}
 
-    def run(name, side, f_np, mask0, k, rounds, rule):
+    def run(name, side, f_np, mask0, k, rounds, rule, unknowns=None):
         f = torch.from_numpy(f_np.ravel().copy()).cuda()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        order, mse, ms = fi.densify(ctx, side, f, mask0, k, rounds, rule=rule)
+        order, mse, ms = fi.densify(ctx, side, f, mask0, k, rounds, rule=rule, unknowns=unknowns)
         wall = time.perf_counter() - t0
         runs[name] = {"side": side, "rule": "top-k" if rule == fi.DENSIFY_TOPK else "per-triangle",
+                      "mesh": "quadtree" if unknowns is None else
+                              f"Delaunay, {len(unknowns)} unknown vertices",
                       "inpaintings": rounds + 1, "final_mask": int(order.size),
                       "wall_s": wall, "gpu_ms_total": float(np.sum(ms)),
                       "mse_first": float(mse[0]), "mse_last": float(mse[-1]),
@@ -290,6 +294,13 @@ def densify_main(args):
                     fi.DENSIFY_TRIANGLES)
         if side == 1024:
             last_mask = np.sort(order)
+    # the paper's whole method: its own Delaunay mesh, unknown vertices drawn
+    # once (as many as the final mask), the per-triangle rule, 4% in n = 10
+    Pn = 512 * 512
+    m = synth.count_from_density(0.04, Pn)
+    mask0 = synth.make_mask(2, Pn, k=m // 10)
+    run("paper_delaunay_512", 512, f512, mask0, m // 10, 9, fi.DENSIFY_TRIANGLES,
+        unknowns=synth.make_unknowns(2, Pn, mask0, m))
     total_pix = sum(r["inpaintings"] * r["side"] ** 2 for r in runs.values())
     total_wall = sum(r["wall_s"] for r in runs.values())
     # dominant kernel on the final 1024^2 mesh of the per-triangle run
@@ -308,7 +319,8 @@ def densify_main(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (CG) + f64 (residual, refinement, error)", "data": "synthetic",
         "config": {"workload": "densify: 1024^2 top-k 1%->3% x20 rounds; paper per-triangle "
-                               "rule at 512^2 and 1024^2, 4% in n=10 inpaintings"},
+                               "rule at 512^2 and 1024^2, 4% in n=10 inpaintings; the same "
+                               "at 512^2 on the Delaunay mesh"},
         "runs": runs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("densify"),
@@ -349,28 +361,158 @@ def densify_cpu_baseline(f512):
                       f"inpainting, error, selection), {el:.1f} s"}
 
 
+def colour_main(args):
+    """Colour (Section 6: the method per channel on one shared mesh): the
+    512^2 image of the tonal512 recipe in three correlated channels
+    (synth.make_image_rgb), 4% mask. One step = assembly, inpainting of all
+    three channels (one multi-right-hand-side solve), colour MSE, then tonal
+    optimisation of every channel to relative normal residual 1e-8.
+
+    ``value`` is inpainted colour Mpixel/s (P / inpainting-phase time, three
+    channels per pixel). The same work done channel after channel with the
+    grey calls is timed beside it (``grey_by_channel``)."""
+    import torch
+    import paper_2105_01586_amd as fi
+    import synth
+
+    w = synth.WORKLOADS["tonal512"]
+    side = w.side
+    P = side * side
+    f_np = synth.make_image_rgb(w.seed, side, side, w.bumps, w.edges, w.sigma_lo,
+                                w.sigma_hi).reshape(3, -1)
+    mask = w.mask()
+    steps = args.steps or 5
+    warmup = 2 if args.warmup is None else args.warmup
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(0)
+    ctx = fi.Context(0, stream)
+    mesh = fi.Mesh(ctx, side, mask)
+    f = torch.from_numpy(f_np.ravel().copy()).to(dev)
+    fch = [torch.from_numpy(f_np[c].copy()).to(dev) for c in range(3)]
+    u = torch.empty(3 * P, dtype=torch.float64, device=dev)
+    g = torch.empty(3 * mesh.m, dtype=torch.float64, device=dev)
+    inner = fi.SolveOpts(precision=fi.PREC_FP32_IR)
+    topts = fi.TonalOpts(inner=inner, rtol=1e-8)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step_rgb(rec):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        mesh.assemble()
+        _, st = mesh.inpaint_rgb(f=f, u=u, opts=inner)
+        mse, _ = mesh.error_rgb(u, f)
+        e1.record(stream)
+        _, ts = mesh.tonal_opt_rgb(f, g=g, opts=topts)
+        e2.record(stream)
+        rec.append((e0, e1, e2, st, ts, mse))
+
+    def step_grey(rec):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        mesh.assemble()
+        for c in range(3):
+            mesh.inpaint(f=fch[c], u=u[c * P:(c + 1) * P], opts=inner)
+            mesh.error(u[c * P:(c + 1) * P], fch[c])
+        e1.record(stream)
+        for c in range(3):
+            mesh.tonal_opt(fch[c], g=g[c * mesh.m:(c + 1) * mesh.m], opts=topts)
+        e2.record(stream)
+        rec.append((e0, e1, e2))
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn([])
+        torch.cuda.synchronize()
+        rec = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn(rec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        inp = float(np.mean([r[0].elapsed_time(r[1]) for r in rec]))
+        ton = float(np.mean([r[1].elapsed_time(r[2]) for r in rec]))
+        return rec, wall, inp, ton
+
+    rec, wall, inp, ton = timed(step_rgb)
+    st, ts, mse = rec[-1][3], rec[-1][4], rec[-1][5]
+    _, wall_g, inp_g, ton_g = timed(step_grey)
+    _, st = mesh.inpaint_rgb(f=f, u=u, opts=inner)  # leave the colour result in u
+    kms = mesh.time_cg_multi_kernel(3, fi.PREC_FP32_IR, args.kernel_reps)
+    kbytes = mesh.cg_multi_kernel_bytes(3, fi.PREC_FP32_IR)
+    k1 = mesh.time_cg_kernel(fi.PREC_FP32_IR, args.kernel_reps)
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    out = {
+        "metric": "inpainted Mpixel/s + tonal-opt solves/s at <=1e-6 err vs FP64; p50/p99 latency",
+        "value": P / (inp * 1e3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (CG) + f64 (residual, refinement, tonal)", "data": "synthetic",
+        "config": {"workload": f"rgb512: 512x512 colour (3 channels), {w.bumps} bumps, "
+                               f"{w.edges} edges, 4% random mask (m={mesh.m})",
+                   "side": side, "channels": 3, "mask_pixels": mesh.m, "unknowns": mesh.n},
+        "inpaint_ms": inp, "tonal_ms": ton, "tonal_solves_per_s": 1000.0 / ton,
+        "cg_iterations_inpaint": [x["iterations"] for x in st],
+        "tonal_outer_iterations": [x["outer_iterations"] for x in ts],
+        "tonal_inner_iterations": [x["inner_iterations"] for x in ts],
+        "mse_inpaint": mse, "mse_tonal": float(np.mean([x["mse_final"] for x in ts])),
+        "grey_by_channel": {"inpaint_ms": inp_g, "tonal_ms": ton_g,
+                            "ms_per_step": wall_g * 1e3 / steps,
+                            "inpaint_speedup": inp_g / inp, "tonal_speedup": ton_g / ton},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("rgb512"),
+                     "kernel": "k_step_multi<float, 3 right-hand sides, block re-reduce, 512>",
+                     "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3,
+                     "one_rhs_step_us": k1 * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import colour, tonal
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        pr = tonal.Problem(side, mask)
+        u_ref = colour.inpaint(pr, f_np)
+        colour.mse(u_ref, f_np)
+        el = time.perf_counter() - t0
+        out["max_abs_err_vs_fp64_oracle"] = float(np.max(np.abs(u.cpu().numpy().reshape(3, -1)
+                                                                - u_ref)))
+        out["cpu_baseline"] = {"value": P / el / 1e6, "unit": "Mpixel/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"1 colour inpainting of the 512^2 image (mesh, "
+                                         f"assembly, one direct Cholesky, three solves, "
+                                         f"interpolation, MSE), {el:.1f} s"}
+    print(json.dumps(out))
+    mesh.close()
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not "
                                    "supported (see DESIGN.md for how the path would shard)"}))
         sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        # a 256 MiB device copy whose counter readings scale FETCH_SIZE and
+        # WRITE_SIZE in profiles
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.workload == "serving":
         serving_main(args)
         return
     if args.workload == "densify":
         densify_main(args)
         return
-    import torch
+    if args.workload == "rgb512":
+        colour_main(args)
+        return
     import paper_2105_01586_amd as fi
     import synth
 
-    if args.copy_calibration:
-        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     w = synth.WORKLOADS[args.workload]
     big = w.side > 2048
     if args.steps is None:

@@ -158,6 +158,30 @@ int fi_host_mesh_export(const fi_host_mesh* host, int32_t* vxy, int32_t* tri, in
 int fi_host_mesh_destroy(fi_host_mesh* host);
 int fi_mesh_upload(fi_ctx* ctx, fi_host_mesh** host, fi_mesh** out);
 
+/* The paper's own mesh (Section 2.2): every mask pixel is a vertex, the
+ * unknown_idx pixels are the "unknown vertices" (Section 3 draws them at
+ * random; here they are an input), and the point set, with the four corner
+ * pixels always included, is triangulated by Delaunay. Pixel (r, c) is the
+ * point (x = c, y = r); vertex ids follow the pixel index. Where four or more
+ * vertices are cocircular the triangulation is made unique by symbolic
+ * perturbation of the lifted heights (lower vertex ids perturbed more), and
+ * triangles are listed counter-clockwise from their lowest vertex id in
+ * lexicographic order. A pixel's owner triangle is the lowest-index triangle
+ * holding it. Everything else (assembly, solves, interpolation, error,
+ * adjoint, tonal, colour, the per-triangle densification step) works on it
+ * as on the quadtree mesh; its stiffness entries are general cotangent
+ * weights, so the solver uses the CSR layout. The batched server takes
+ * quadtree meshes only.
+ *   side: power of two in [2, 8192]; mask_idx, unknown_idx: host int32,
+ *   each strictly ascending and in range, disjoint.
+ * Errors: FI_E_INVALID (shape, ordering, range, overlap, a vertex with more
+ * than 31 incident triangles), FI_E_EMPTY_MASK (m == 0). The host variant
+ * builds without a device (for checking). */
+int fi_mesh_build_delaunay(fi_ctx* ctx, int side, const int32_t* mask_idx, int64_t m,
+                           const int32_t* unknown_idx, int64_t nu, fi_mesh** out);
+int fi_host_mesh_build_delaunay(int side, const int32_t* mask_idx, int64_t m,
+                                const int32_t* unknown_idx, int64_t nu, fi_host_mesh** out);
+
 /* (Re)assembles the P1 stiffness matrix on the device: element matrices
  * K^e_ij = (b_i b_j + c_i c_j) / (4A) summed per vertex row, split into the
  * free block K_FF, the coupling K_FD and its transpose K_DF; exact zeros are
@@ -276,6 +300,18 @@ int fi_densify(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0
                int64_t k_add, int rounds, int rule, const fi_solve_opts* opts, int32_t* mask_out,
                double* mse_out, double* gpu_ms_out, int64_t* mask_size_out);
 
+/* Section 3's spatial optimisation on the paper's own mesh: fi_densify with
+ * FI_DENSIFY_TRIANGLES, where every round triangulates (Delaunay, as
+ * fi_mesh_build_delaunay) the current mask and the unknown vertices. The
+ * unknown vertices are drawn once, before the first round (an input here:
+ * unknowns, host int32[nu], strictly ascending, none in mask0); a pixel the
+ * step adds that was an unknown vertex becomes a mask vertex. Arguments,
+ * outputs and errors otherwise as fi_densify. */
+int fi_densify_delaunay(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0,
+                        int64_t m0, const int32_t* unknowns, int64_t nu, int64_t k_add,
+                        int rounds, const fi_solve_opts* opts, int32_t* mask_out,
+                        double* mse_out, double* gpu_ms_out, int64_t* mask_size_out);
+
 /* Timing helper: runs `reps` iterations of the fused FP32 (precision =
  * FI_PREC_FP32_IR) or FP64 (FI_PREC_FP64) CG iteration kernel on this mesh's
  * current solver state between two HIP events recorded on the context
@@ -286,6 +322,71 @@ int fi_time_cg_kernel(fi_mesh* mesh, int precision, int reps, double* ms_per_lau
 /* Algorithmic bytes one launch of the fused CG iteration kernel must move
  * (matrix, row pointers, and each vector read or written once). */
 int fi_cg_kernel_bytes(const fi_mesh* mesh, int precision, int64_t* bytes);
+
+/* ------------------------------------------------------------- colour --
+ * Section 6 extends the method to colour images channel by channel. The
+ * three channels share the mask, so they share the mesh, K_FF, K_FD and the
+ * interpolation; each channel is the grey problem with its own data. Arrays
+ * are planar: channel c of a per-pixel array occupies [c * P, (c + 1) * P),
+ * of the mask values [c * m, (c + 1) * m).
+ *
+ * The three solves of every step run in ONE multi-right-hand-side launch
+ * whose blocks for the same rows of the three channels run side by side on
+ * one XCD, so the rows' matrix entries come from HBM once and from that
+ * XCD's L2 for the other channels. Every channel keeps its own solver state
+ * and runs the grey step on its own data, so each channel's result is bit
+ * for bit what the grey call returns for that channel (also its iteration
+ * counts). A channel whose solve has ended leaves the launches.
+ * The first colour call on a mesh allocates the data-dependent state of
+ * channels 1 and 2 (solver vectors and work vectors, about twice the
+ * per-image part of the mesh's memory); fi_mesh_get_info's device_bytes
+ * includes it from then on. Colour calls are synchronous like the grey ones. */
+
+/* u_c = B g_c for c = 0, 1, 2 (Section 4's B, Section 6).
+ *   f_dev: uint8[3P] device, planar; used only when g_dev is NULL (then
+ *          g_c = f_c on the mask). May be NULL when g_dev is given.
+ *   g_dev: float64[3m] device, planar, or NULL.
+ *   u_dev: float64[3P] device output, planar.
+ *   opts:  NULL for defaults. stats: host array of 3 (one per channel) or NULL.
+ * Errors: FI_E_INVALID (NULL u_dev, or both f_dev and g_dev NULL);
+ * FI_E_NO_CONVERGENCE when a channel's solve missed the tolerance (u_dev is
+ * written all the same); FI_E_NOMEM / FI_E_HIP. */
+int fi_inpaint_rgb(fi_mesh* mesh, const uint8_t* f_dev, const double* g_dev, double* u_dev,
+                   const fi_solve_opts* opts, fi_solve_stats* stats);
+
+/* Colour MSE: the mean over all 3P values of (u - f)^2, i.e. the mean of
+ * the three channel MSEs (the paper defines no colour error; this reading
+ * weights the channels equally).
+ *   u_dev: float64[3P], f_dev: uint8[3P], both device, planar;
+ *   mse_host: output scalar (may be NULL); mse_ch_host: host float64[3],
+ *   the channel MSEs (may be NULL). Synchronous. */
+int fi_error_rgb(fi_mesh* mesh, const double* u_dev, const uint8_t* f_dev, double* mse_host,
+                 double* mse_ch_host);
+
+/* Tonal optimisation of a colour image (Section 4 per channel, Section 6):
+ * three independent least-squares problems, each solved by the CGLS of
+ * fi_tonal_opt, whose solves share the multi-right-hand-side launches.
+ * A channel stops at its own relative normal residual opts->rtol (rtol 0:
+ * every channel runs opts->max_outer iterations); the others go on.
+ *   f_dev: uint8[3P] device, planar; g_dev: float64[3m] device, planar
+ *   (start values if opts->start_from_g; the result on return);
+ *   stats: host array of 3 or NULL. Channel c's g and stats equal
+ *   fi_tonal_opt's on channel c's data, bit for bit.
+ * Errors: as fi_tonal_opt; FI_E_NO_CONVERGENCE if any channel missed rtol. */
+int fi_tonal_opt_rgb(fi_mesh* mesh, const uint8_t* f_dev, double* g_dev,
+                     const fi_tonal_opts* opts, fi_tonal_stats* stats);
+
+/* Timing helper for the multi-right-hand-side step: `reps` launches with
+ * nrhs (1..3) channels all in the iteration phase, as fi_time_cg_kernel;
+ * returns mean milliseconds per launch (with the large-system reduction
+ * launch when the mesh uses one). Channel states are left undefined. */
+int fi_time_cg_multi_kernel(fi_mesh* mesh, int nrhs, int precision, int reps,
+                            double* ms_per_launch);
+
+/* Algorithmic bytes of one multi-right-hand-side step launch over nrhs
+ * channels: the encoded matrix once, and per channel each vector read or
+ * written once (as fi_cg_kernel_bytes). */
+int fi_cg_multi_kernel_bytes(const fi_mesh* mesh, int nrhs, int precision, int64_t* bytes);
 
 /* ------------------------------------------------------------- serving --
  * Batched serving of requests "inpaint, then run tonal_iters CGLS iterations

@@ -44,6 +44,9 @@ EXPORTED_SYMBOLS = (
     "fi_mesh_upload", "fi_grow_mask", "fi_server_opts_default", "fi_server_create",
     "fi_server_submit", "fi_server_poll", "fi_server_stats_get", "fi_server_clock",
     "fi_server_destroy", "fi_server_footprint", "fi_paper_densify_step", "fi_densify",
+    "fi_inpaint_rgb", "fi_error_rgb", "fi_tonal_opt_rgb", "fi_time_cg_multi_kernel",
+    "fi_cg_multi_kernel_bytes", "fi_mesh_build_delaunay", "fi_host_mesh_build_delaunay",
+    "fi_densify_delaunay",
 )
 
 
@@ -180,6 +183,21 @@ def library() -> ctypes.CDLL:
         "fi_densify": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(_SolveOpts), vp,
                                       vp, vp, i64p]),
+        "fi_inpaint_rgb": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                          ctypes.POINTER(_SolveStats)]),
+        "fi_error_rgb": (ctypes.c_int, [vp, vp, vp, dp, dp]),
+        "fi_tonal_opt_rgb": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_TonalOpts),
+                                            ctypes.POINTER(_TonalStats)]),
+        "fi_time_cg_multi_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                   dp]),
+        "fi_cg_multi_kernel_bytes": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, i64p]),
+        "fi_mesh_build_delaunay": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_int64, vp,
+                                                  ctypes.c_int64, ctypes.POINTER(vp)]),
+        "fi_host_mesh_build_delaunay": (ctypes.c_int, [ctypes.c_int, vp, ctypes.c_int64, vp,
+                                                       ctypes.c_int64, ctypes.POINTER(vp)]),
+        "fi_densify_delaunay": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp,
+                                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                               ctypes.POINTER(_SolveOpts), vp, vp, vp, i64p]),
         "fi_server_opts_default": (None, [ctypes.POINTER(_ServerOpts)]),
         "fi_server_create": (ctypes.c_int, [vp, ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]),
         "fi_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(_JobDesc),
@@ -245,8 +263,9 @@ def _torch():
     return torch
 
 
-def host_mesh(side: int, mask_idx) -> dict:
-    """Builds the quadtree mesh on the host only (no GPU) and exports it.
+def host_mesh(side: int, mask_idx, unknowns=None) -> dict:
+    """Builds the mesh on the host only (no GPU) and exports it: the quadtree
+    mesh, or with ``unknowns`` (pixel indices) the paper's Delaunay mesh.
 
     Returns numpy arrays: vxy (V, 2), tri (T, 3), leaves (L, 3), free_vids,
     mask_vids, plus the counts.
@@ -254,8 +273,15 @@ def host_mesh(side: int, mask_idx) -> dict:
     L = library()
     mask = np.ascontiguousarray(np.asarray(mask_idx, dtype=np.int32).ravel())
     h = ctypes.c_void_p()
-    _check(L.fi_host_mesh_build(int(side), int(side), mask.ctypes.data_as(ctypes.c_void_p),
-                                mask.size, ctypes.byref(h)), "fi_host_mesh_build")
+    if unknowns is None:
+        _check(L.fi_host_mesh_build(int(side), int(side), mask.ctypes.data_as(ctypes.c_void_p),
+                                    mask.size, ctypes.byref(h)), "fi_host_mesh_build")
+    else:
+        unk = np.ascontiguousarray(np.asarray(unknowns, dtype=np.int32).ravel())
+        _check(L.fi_host_mesh_build_delaunay(int(side), mask.ctypes.data_as(ctypes.c_void_p),
+                                             mask.size, unk.ctypes.data_as(ctypes.c_void_p),
+                                             unk.size, ctypes.byref(h)),
+               "fi_host_mesh_build_delaunay")
     try:
         info = _MeshInfo()
         _check(L.fi_host_mesh_info(h, ctypes.byref(info)), "fi_host_mesh_info")
@@ -329,14 +355,24 @@ def _ptr(t, dtype, numel, name, device):
 class Mesh:
     """Quadtree FEM mesh for one (image side, mask) pair, with its device matrices."""
 
-    def __init__(self, ctx: Context, side: int, mask_idx):
+    def __init__(self, ctx: Context, side: int, mask_idx, unknowns=None):
+        """``unknowns``: None for the quadtree mesh; else the unknown vertices
+        (pixel indices) of the paper's Delaunay mesh."""
         self.ctx = ctx
         mask = np.ascontiguousarray(np.asarray(mask_idx, dtype=np.int32).ravel())
         self._mask = mask
         h = ctypes.c_void_p()
-        _check(library().fi_mesh_build(ctx._h, int(side), int(side),
-                                       mask.ctypes.data_as(ctypes.c_void_p), mask.size,
-                                       ctypes.byref(h)), "fi_mesh_build")
+        if unknowns is None:
+            _check(library().fi_mesh_build(ctx._h, int(side), int(side),
+                                           mask.ctypes.data_as(ctypes.c_void_p), mask.size,
+                                           ctypes.byref(h)), "fi_mesh_build")
+        else:
+            unk = np.ascontiguousarray(np.asarray(unknowns, dtype=np.int32).ravel())
+            _check(library().fi_mesh_build_delaunay(ctx._h, int(side),
+                                                    mask.ctypes.data_as(ctypes.c_void_p),
+                                                    mask.size, unk.ctypes.data_as(ctypes.c_void_p),
+                                                    unk.size, ctypes.byref(h)),
+                   "fi_mesh_build_delaunay")
         self._h = h
         ctx._meshes.add(self)
         _live_meshes.add(self)
@@ -442,6 +478,57 @@ class Mesh:
         _check(rc, "fi_tonal_opt")
         return g, _stats(st)
 
+    # -- colour (planar: channel c at [c * P, (c + 1) * P)) ------------------
+    def inpaint_rgb(self, f=None, g=None, u=None, opts: SolveOpts | None = None):
+        """u_c = B g_c for the three channels (g defaults to f on the mask).
+        f: uint8[3P], g: float64[3m], u: float64[3P]. Returns (u, [stats] * 3)."""
+        torch = _torch()
+        d = self._dev()
+        if u is None:
+            u = self._empty(3 * self.P, torch.float64)
+        st = (_SolveStats * 3)()
+        o = (opts or SolveOpts()).c()
+        rc = library().fi_inpaint_rgb(self._h, _ptr(f, torch.uint8, 3 * self.P, "f", d),
+                                      _ptr(g, torch.float64, 3 * self.m, "g", d),
+                                      _ptr(u, torch.float64, 3 * self.P, "u", d), ctypes.byref(o),
+                                      st)
+        _check(rc, "fi_inpaint_rgb")
+        return u, [_stats(x) for x in st]
+
+    def error_rgb(self, u, f):
+        """Returns (colour MSE over all 3P values, [MSE of each channel])."""
+        torch = _torch()
+        d = self._dev()
+        mse = ctypes.c_double()
+        ch = (ctypes.c_double * 3)()
+        rc = library().fi_error_rgb(self._h, _ptr(u, torch.float64, 3 * self.P, "u", d),
+                                    _ptr(f, torch.uint8, 3 * self.P, "f", d), ctypes.byref(mse),
+                                    ch)
+        _check(rc, "fi_error_rgb")
+        return mse.value, list(ch)
+
+    def tonal_opt_rgb(self, f, g=None, opts: TonalOpts | None = None):
+        """Per-channel CGLS with shared solve launches. Returns (g[3m], [stats] * 3)."""
+        torch = _torch()
+        d = self._dev()
+        o = opts or TonalOpts()
+        if g is None:
+            g = self._empty(3 * self.m, torch.float64)
+            o = TonalOpts(o.inner, o.rtol, o.max_outer, False)
+        co = o.c()
+        st = (_TonalStats * 3)()
+        rc = library().fi_tonal_opt_rgb(self._h, _ptr(f, torch.uint8, 3 * self.P, "f", d),
+                                        _ptr(g, torch.float64, 3 * self.m, "g", d),
+                                        ctypes.byref(co), st)
+        _check(rc, "fi_tonal_opt_rgb")
+        return g, [_stats(x) for x in st]
+
+    def device_bytes(self) -> int:
+        """Device memory the mesh holds now (channel state included once created)."""
+        info = _MeshInfo()
+        _check(library().fi_mesh_get_info(self._h, ctypes.byref(info)), "fi_mesh_get_info")
+        return int(info.device_bytes)
+
     # -- exports for checking --------------------------------------------
     def export_geometry(self) -> dict:
         vxy = np.empty((self.V, 2), np.int32)
@@ -505,6 +592,19 @@ class Mesh:
                "fi_cg_kernel_bytes")
         return b.value
 
+    def time_cg_multi_kernel(self, nrhs: int = 3, precision: int = PREC_FP32_IR,
+                             reps: int = 200) -> float:
+        ms = ctypes.c_double()
+        _check(library().fi_time_cg_multi_kernel(self._h, int(nrhs), int(precision), int(reps),
+                                                 ctypes.byref(ms)), "fi_time_cg_multi_kernel")
+        return ms.value
+
+    def cg_multi_kernel_bytes(self, nrhs: int = 3, precision: int = PREC_FP32_IR) -> int:
+        b = ctypes.c_int64()
+        _check(library().fi_cg_multi_kernel_bytes(self._h, int(nrhs), int(precision),
+                                                  ctypes.byref(b)), "fi_cg_multi_kernel_bytes")
+        return b.value
+
 
 def grow_mask(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
               opts: SolveOpts | None = None):
@@ -531,9 +631,11 @@ def grow_mask(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
 
 
 def densify(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
-            rule: int = DENSIFY_TRIANGLES, opts: SolveOpts | None = None):
+            rule: int = DENSIFY_TRIANGLES, opts: SolveOpts | None = None, unknowns=None):
     """Mask growth by a chosen rule (fi_densify); returns (mask_order, mse,
-    gpu_ms) like grow_mask, mask_order holding only the pixels added."""
+    gpu_ms) like grow_mask, mask_order holding mask0 then the pixels added.
+    With ``unknowns`` the rounds run on the paper's Delaunay mesh with those
+    unknown vertices (fi_densify_delaunay, per-triangle rule)."""
     torch = _torch()
     mask0 = np.ascontiguousarray(np.asarray(mask0, dtype=np.int32).ravel())
     P = int(side) * int(side)
@@ -543,10 +645,20 @@ def densify(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,
     total = ctypes.c_int64()
     o = (opts or SolveOpts()).c()
     c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
-    rc = library().fi_densify(ctx._h, int(side), _ptr(f, torch.uint8, P, "f", ctx.device),
-                              c(mask0), mask0.size, int(k_add), int(rounds), int(rule),
-                              ctypes.byref(o), c(out), c(mse), c(ms), ctypes.byref(total))
-    _check(rc, "fi_densify")
+    fp = _ptr(f, torch.uint8, P, "f", ctx.device)
+    if unknowns is None:
+        rc = library().fi_densify(ctx._h, int(side), fp, c(mask0), mask0.size, int(k_add),
+                                  int(rounds), int(rule), ctypes.byref(o), c(out), c(mse), c(ms),
+                                  ctypes.byref(total))
+        _check(rc, "fi_densify")
+    else:
+        if rule != DENSIFY_TRIANGLES:
+            raise ValueError("the Delaunay loop uses the per-triangle rule")
+        unk = np.ascontiguousarray(np.asarray(unknowns, dtype=np.int32).ravel())
+        rc = library().fi_densify_delaunay(ctx._h, int(side), fp, c(mask0), mask0.size, c(unk),
+                                           unk.size, int(k_add), int(rounds), ctypes.byref(o),
+                                           c(out), c(mse), c(ms), ctypes.byref(total))
+        _check(rc, "fi_densify_delaunay")
     return out[:total.value], mse, ms
 
 

@@ -63,6 +63,10 @@ int upload(fi_mesh* M, T** p, const std::vector<T>& h) {
 
 void free_mesh(fi_mesh* M) {
   if (!M) return;
+  for (fi_mesh*& c : M->chan) {
+    free_mesh(c);
+    c = nullptr;
+  }
   (void)hipSetDevice(M->device);
   if (M->arena) {
     // arena meshes: the owner has waited for the mesh's last work
@@ -82,18 +86,13 @@ void free_mesh(fi_mesh* M) {
 
 namespace {
 
-int alloc_workspace(fi_mesh* M) {
+#define TRY(x) do { rc = (x); if (rc) return rc; } while (0)
+
+// Vectors of one right-hand side: the solve's b, iterate and residual, the
+// CG vectors of both precisions, and the per-pixel / per-vertex work vectors.
+int alloc_rhs_space(fi_mesh* M) {
   int rc = 0;
   const int64_t n = M->n, m = M->m, V = M->V, T = M->T;
-#define TRY(x) do { rc = (x); if (rc) return rc; } while (0)
-  TRY(alloc_n(M, &M->d_cnt, std::max(2 * (n + 1), m + 1)));
-  TRY(alloc_n(M, &M->d_scan_tmp, scan_tmp_ints(std::max(std::max(n, m), T) + 1)));
-  TRY(alloc_n(M, &M->d_ff_rowptr, n + 1));
-  TRY(alloc_n(M, &M->d_fd_rowptr, n + 1));
-  TRY(alloc_n(M, &M->d_df_rowptr, m + 1));
-  TRY(alloc_n(M, &M->d_diag64, n));
-  TRY(alloc_n(M, &M->d_dinv64, n));
-  TRY(alloc_n(M, &M->d_dinv32, n));
   TRY(alloc_n(M, &M->d_b64, n));
   TRY(alloc_n(M, &M->d_x64buf[0], n));
   TRY(alloc_n(M, &M->d_x64buf[1], n));
@@ -107,9 +106,6 @@ int alloc_workspace(fi_mesh* M) {
   for (int k = 2; k < 4; ++k) TRY(alloc_n(M, &f64[k], 4 * n));
   M->cg32 = CGState{f32[0], f32[1], {f32[2], f32[3]}};
   M->cg64 = CGState{f64[0], f64[1], {f64[2], f64[3]}};
-  TRY(alloc_n(M, &M->d_part, 2 * 4 * kMaxGrid));
-  TRY(alloc_n(M, &M->d_scal, 8));
-  TRY(alloc_n(M, &M->d_ctl, 4));
   TRY(alloc_n(M, &M->d_red, kMaxGrid));
   TRY(alloc_n(M, &M->d_red_out, 8));
   TRY(alloc_n(M, &M->d_uvert, V));
@@ -118,16 +114,89 @@ int alloc_workspace(fi_mesh* M) {
   TRY(alloc_n(M, &M->d_tF, n));
   TRY(alloc_n(M, &M->d_tD, m));
   TRY(alloc_n(M, &M->d_rpart, raster_blocks(M)));
+  FI_HIP_TRY(hipHostMalloc((void**)&M->h_red, 8 * sizeof(double), hipHostMallocDefault));
+  FI_HIP_TRY(hipHostMalloc((void**)&M->h_ctl, 4 * sizeof(int32_t), hipHostMallocDefault));
+  return FI_OK;
+}
+
+int alloc_workspace(fi_mesh* M) {
+  int rc = 0;
+  const int64_t n = M->n, m = M->m, T = M->T;
+  TRY(alloc_n(M, &M->d_cnt, std::max(2 * (n + 1), m + 1)));
+  TRY(alloc_n(M, &M->d_scan_tmp, scan_tmp_ints(std::max(std::max(n, m), T) + 1)));
+  TRY(alloc_n(M, &M->d_ff_rowptr, n + 1));
+  TRY(alloc_n(M, &M->d_fd_rowptr, n + 1));
+  TRY(alloc_n(M, &M->d_df_rowptr, m + 1));
+  TRY(alloc_n(M, &M->d_diag64, n));
+  TRY(alloc_n(M, &M->d_dinv64, n));
+  TRY(alloc_n(M, &M->d_dinv32, n));
+  TRY(alloc_rhs_space(M));
   TRY(alloc_n(M, &M->d_owner, M->P));
   TRY(alloc_n(M, &M->d_tri_px, M->P));
   TRY(alloc_n(M, &M->d_tri_px_ptr, T + 1));
-#undef TRY
-  FI_HIP_TRY(hipHostMalloc((void**)&M->h_red, 8 * sizeof(double), hipHostMallocDefault));
-  FI_HIP_TRY(hipHostMalloc((void**)&M->h_ctl, 4 * sizeof(int32_t), hipHostMallocDefault));
-  int64_t g = (n + kBlock - 1) / kBlock;
-  M->cg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxGrid));
   return FI_OK;
 }
+
+// Channel c of a colour image: shares everything that depends on the mesh
+// alone (geometry, matrices, ELL copy, pixel maps) with M and owns what
+// depends on the data.
+int make_channel(fi_mesh* M, fi_mesh** out) {
+  *out = nullptr;
+  fi_mesh* S = new fi_mesh();
+  S->ctx = M->ctx;
+  S->device = M->device;
+  S->arena = M->arena;
+  S->is_channel = true;
+  S->host.N = M->host.N;
+  S->host.levels = M->host.levels;
+  S->N = M->N;
+  S->P = M->P;
+  S->V = M->V;
+  S->T = M->T;
+  S->L = M->L;
+  S->n = M->n;
+  S->m = M->m;
+  S->nnz_off = M->nnz_off;
+  S->nnz_fd = M->nnz_fd;
+  S->nnz_df = M->nnz_df;
+  S->d_vxy = M->d_vxy;
+  S->d_tri = M->d_tri;
+  S->d_leaves = M->d_leaves;
+  S->d_vmap = M->d_vmap;
+  S->d_free_vids = M->d_free_vids;
+  S->d_mask_vids = M->d_mask_vids;
+  S->d_mask_pix = M->d_mask_pix;
+  S->d_vt_ptr = M->d_vt_ptr;
+  S->d_vt_idx = M->d_vt_idx;
+  S->assembled_once = true;
+  S->d_ff_rowptr = M->d_ff_rowptr;
+  S->d_ff_col = M->d_ff_col;
+  S->d_ff_val64 = M->d_ff_val64;
+  S->d_ff_val32 = M->d_ff_val32;
+  S->d_diag64 = M->d_diag64;
+  S->d_dinv64 = M->d_dinv64;
+  S->d_dinv32 = M->d_dinv32;
+  S->d_fd_rowptr = M->d_fd_rowptr;
+  S->d_fd_col = M->d_fd_col;
+  S->d_fd_val = M->d_fd_val;
+  S->d_df_rowptr = M->d_df_rowptr;
+  S->d_df_col = M->d_df_col;
+  S->d_df_val = M->d_df_val;
+  S->d_owner = M->d_owner;
+  S->d_tri_px_ptr = M->d_tri_px_ptr;
+  S->d_tri_px = M->d_tri_px;
+  int rc = alloc_rhs_space(S);
+  if (!rc) rc = solver_channel_setup(S, M);
+  if (rc) {
+    std::string keep = g_last_error;
+    free_mesh(S);
+    g_last_error = keep;
+    return rc;
+  }
+  *out = S;
+  return FI_OK;
+}
+#undef TRY
 
 int read_total(fi_mesh* M, const int32_t* dptr, int64_t* out) {
   int32_t v = 0;
@@ -197,19 +266,30 @@ int dot_host(fi_mesh* M, const double* a, const double* b, int64_t n, double* ou
   return sync_read_scalar(M, M->d_red_out, out);
 }
 
-int mse_of(fi_mesh* M, const double* u, const uint8_t* f, double* mse) {
+// Sum of squared errors of u against f, left on the device in *out_dev.
+int sse_dev(fi_mesh* M, const double* u, const uint8_t* f, double* out_dev) {
   int rc = launch_raster(M, nullptr, u, f, nullptr, nullptr, nullptr, nullptr, M->d_rpart);
   if (rc) return rc;
-  rc = launch_reduce(M, M->d_rpart, raster_blocks(M), 1, M->d_red_out);
-  if (rc) return rc;
-  double s = 0;
-  rc = sync_read_scalar(M, M->d_red_out, &s);
-  if (rc) return rc;
-  *mse = s / (double)M->P;
+  return launch_reduce(M, M->d_rpart, raster_blocks(M), 1, out_dev);
+}
+
+
+}  // namespace
+
+int channel_views(fi_mesh* M, int nc, fi_mesh** ch) {
+  if (M->is_channel) return fail(FI_E_INVALID, "a channel view has no channels");
+  if (nc < 1 || nc > kMaxRhs) return fail(FI_E_INVALID, "1 to 3 channels");
+  ch[0] = M;
+  for (int c = 1; c < nc; ++c) {
+    if (!M->chan[c - 1]) {
+      int rc = make_channel(M, &M->chan[c - 1]);
+      if (rc) return rc;
+    }
+    ch[c] = M->chan[c - 1];
+  }
   return FI_OK;
 }
 
-}  // namespace
 }  // namespace fi
 
 using namespace fi;
@@ -273,6 +353,30 @@ int fi_host_mesh_build(int width, int height, const int32_t* mask_idx, int64_t m
   if (rc) { delete h; return rc; }
   *out = h;
   return FI_OK;
+}
+
+int fi_host_mesh_build_delaunay(int side, const int32_t* mask_idx, int64_t m,
+                                const int32_t* unknown_idx, int64_t nu, fi_host_mesh** out) {
+  if (!out) return fail(FI_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (m < 1) return fail(FI_E_EMPTY_MASK, "the mask is empty");
+  fi_host_mesh* h = new fi_host_mesh();
+  int rc = build_delaunay_mesh(side, mask_idx, m, unknown_idx, nu, h->mesh);
+  if (rc) { delete h; return rc; }
+  *out = h;
+  return FI_OK;
+}
+
+int fi_mesh_build_delaunay(fi_ctx* ctx, int side, const int32_t* mask_idx, int64_t m,
+                           const int32_t* unknown_idx, int64_t nu, fi_mesh** out) {
+  if (!ctx || !out) return fail(FI_E_INVALID, "ctx or out is NULL");
+  *out = nullptr;
+  fi_host_mesh* h = nullptr;
+  int rc = fi_host_mesh_build_delaunay(side, mask_idx, m, unknown_idx, nu, &h);
+  if (rc) return rc;
+  rc = fi_mesh_upload(ctx, &h, out);
+  if (h) fi_host_mesh_destroy(h);
+  return rc;
 }
 
 int fi_host_mesh_info(const fi_host_mesh* h, fi_mesh_info* info) {
@@ -388,6 +492,8 @@ int fi_mesh_get_info(const fi_mesh* M, fi_mesh_info* info) {
   info->nnz_ff = M->nnz_off + M->n;
   info->nnz_fd = M->nnz_fd;
   info->device_bytes = M->device_bytes;
+  for (const fi_mesh* c : M->chan)
+    if (c) info->device_bytes += c->device_bytes;
   info->cg_blocks = M->cg_grid;
   info->cg_block_size = M->cg_bs;
   info->large_mode = M->large_mode ? 1 : 0;
@@ -584,6 +690,82 @@ int fi_time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms_per_launch
   if (!ms_per_launch) return fail(FI_E_INVALID, "output is NULL");
   FI_HIP_TRY(hipSetDevice(M->ctx->device));
   return time_cg_kernel(M, precision, reps, ms_per_launch);
+}
+
+int fi_inpaint_rgb(fi_mesh* M, const uint8_t* f_dev, const double* g_dev, double* u_dev,
+                   const fi_solve_opts* opts, fi_solve_stats* stats) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_dev) return fail(FI_E_INVALID, "u_dev is NULL");
+  if (!g_dev && !f_dev) return fail(FI_E_INVALID, "need f_dev or g_dev");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  fi_mesh* ch[kMaxRhs];
+  if ((rc = channel_views(M, kMaxRhs, ch))) return rc;
+  const fi_solve_opts o = resolve_opts(opts);
+  const double* g[kMaxRhs];
+  for (int c = 0; c < kMaxRhs; ++c) {
+    if (g_dev) {
+      g[c] = g_dev + (size_t)c * M->m;
+    } else {
+      if ((rc = launch_gather_mask(ch[c], f_dev + (size_t)c * M->P, ch[c]->d_g))) return rc;
+      g[c] = ch[c]->d_g;
+    }
+    if ((rc = launch_lift(ch[c], g[c], ch[c]->d_b64))) return rc;
+  }
+  fi_solve_stats st[kMaxRhs] = {};
+  rc = solve_multi(ch, kMaxRhs, &o, st);
+  if (stats)
+    for (int c = 0; c < kMaxRhs; ++c) stats[c] = st[c];
+  if (rc) return rc;
+  for (int c = 0; c < kMaxRhs; ++c) {
+    if ((rc = launch_vertex_values(ch[c], ch[c]->d_x64, g[c], ch[c]->d_uvert)) ||
+        (rc = launch_raster(ch[c], ch[c]->d_uvert, nullptr, nullptr, u_dev + (size_t)c * M->P,
+                            nullptr, nullptr, nullptr, nullptr)))
+      return rc;
+  }
+  for (int c = 0; c < kMaxRhs; ++c)
+    if (st[c].status != FI_OK)
+      return fail(FI_E_NO_CONVERGENCE, "inpainting solve of a channel did not reach the tolerance");
+  return FI_OK;
+}
+
+int fi_error_rgb(fi_mesh* M, const double* u_dev, const uint8_t* f_dev, double* mse_host,
+                 double* mse_ch_host) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_dev || !f_dev) return fail(FI_E_INVALID, "u_dev and f_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  for (int c = 0; c < kMaxRhs; ++c)
+    if ((rc = sse_dev(M, u_dev + (size_t)c * M->P, f_dev + (size_t)c * M->P, M->d_red_out + c)))
+      return rc;
+  FI_HIP_TRY(hipMemcpyAsync(M->h_red, M->d_red_out, kMaxRhs * sizeof(double),
+                            hipMemcpyDeviceToHost, M->ctx->stream));
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  double total = 0.0;
+  for (int c = 0; c < kMaxRhs; ++c) {
+    total += M->h_red[c];
+    if (mse_ch_host) mse_ch_host[c] = M->h_red[c] / (double)M->P;
+  }
+  if (mse_host) *mse_host = total / (double)(kMaxRhs * M->P);
+  return FI_OK;
+}
+
+int fi_time_cg_multi_kernel(fi_mesh* M, int nrhs, int precision, int reps, double* ms) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!ms) return fail(FI_E_INVALID, "output is NULL");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  fi_mesh* ch[kMaxRhs];
+  if ((rc = channel_views(M, nrhs, ch))) return rc;
+  return time_multi_kernel(ch, nrhs, precision, reps, ms);
+}
+
+int fi_cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision, int64_t* bytes) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!bytes || nrhs < 1 || nrhs > kMaxRhs) return fail(FI_E_INVALID, "bad argument");
+  *bytes = cg_multi_kernel_bytes(M, nrhs, precision);
+  return FI_OK;
 }
 
 int fi_cg_kernel_bytes(const fi_mesh* M, int precision, int64_t* bytes) {

@@ -41,6 +41,7 @@ struct HostMesh {
   std::vector<int32_t> vt_ptr;     // V+1: incident (triangle, corner) lists
   std::vector<int32_t> vt_idx;     // 3T: 3 * triangle + corner, ascending
   int max_incident = 0;            // largest incident-triangle count
+  bool delaunay = false;           // the Delaunay mesh (no quadtree leaves)
 
   int64_t L() const { return (int64_t)leaves.size() / 4 - 1; }
   int64_t V() const { return (int64_t)vxy.size() / 2; }
@@ -54,6 +55,16 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& out);
 // Incident triangles per vertex never exceed this on a 2:1 balanced quadtree
 // with centre fans (four leaves meet at a point, each gives at most two).
 constexpr int kMaxIncident = 8;
+// Cap on incident triangles per vertex of a Delaunay mesh (the assembly's
+// per-row neighbour list).
+constexpr int kMaxIncidentGeneral = 31;
+
+// Builds the paper's Delaunay mesh of the mask pixels, the unknown vertices
+// and the four corner pixels (delaunay.cpp). Checks: N power of two in
+// [2, 8192], both lists strictly ascending in range, no unknown on a mask
+// pixel.
+int build_delaunay_mesh(int N, const int32_t* mask, int64_t m, const int32_t* unknown, int64_t nu,
+                        HostMesh& out);
 
 // ----------------------------------------------------------- device mesh --
 template <typename T>
@@ -200,6 +211,12 @@ struct fi_mesh {
   double* d_tri_err = nullptr;   // T: per-triangle error
   int32_t* d_tri_best = nullptr; // T: empty pixel of largest error
   int32_t* d_sel_tri = nullptr;  // selected triangles
+
+  // channels 1 and 2 of a colour image (created on first use): views that
+  // share this mesh's geometry, matrices and pixel maps and own their solver
+  // state and work vectors
+  fi_mesh* chan[2] = {nullptr, nullptr};
+  bool is_channel = false;
 };
 
 namespace fi {
@@ -207,6 +224,8 @@ namespace fi {
 constexpr int kBlock = 256;      // threads per block of the vector kernels
 constexpr int kChunkEvents = 4;  // events per mesh for pacing queued step launches
 constexpr int kMaxGrid = 1024;   // cap on blocks of the fused CG kernel
+constexpr int kRedMaxBlocks = 256;  // blocks of the large-system partial-sum reduction
+constexpr int kMaxRhs = 3;       // right-hand sides one multi-RHS step advances
 
 int device_alloc(fi_mesh* M, void** p, size_t bytes);
 // Uploads a host mesh and assembles it; memory from `arena` when not NULL.
@@ -258,6 +277,21 @@ void solver_release(fi_mesh* M);   // events and the host mirror
 int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats);
 int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms);
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision);
+int64_t cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision);
+// Solver state of one solve (records, partials, mirror, events); solver_setup
+// calls it, and a channel view gets its own with the parent's launch shape.
+int alloc_solver_state(fi_mesh* M);
+int solver_channel_setup(fi_mesh* S, const fi_mesh* M);
+
+// Multi-RHS solves (solver.hip): K_FF x_c = b64 of channel view c, for the nc
+// views in ch (ch[0] the mesh itself), advanced together by one step launch
+// per iteration whose blocks for the same rows share an XCD (and so the
+// matrix in its L2); each channel's result and stats are those of its own
+// solve_free, bit for bit.
+int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats);
+int time_multi_kernel(fi_mesh* const* ch, int nc, int precision, int reps, double* ms);
+// The mesh and its channel views 1..nc-1 (created on first use) into ch.
+int channel_views(fi_mesh* M, int nc, fi_mesh** ch);
 
 // Batched stepping (solver.hip): the FP32 solves of several meshes advance
 // together, one step launch for all of them (for up to 20 meshes; more take

@@ -6,6 +6,7 @@
 // the result is bitwise reproducible. Rasterisation is leaf-centric: one
 // thread owns one quadtree leaf, whose half-open box holds exactly its own
 // pixels, so per-triangle sums are private to the thread.
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.h"
@@ -25,12 +26,13 @@ inline int grid_for(int64_t n, int per_block = kBlock) {
 // v and w of (b_v b_w + c_v c_w) / (4A), with b_i = y_j - y_k, c_i = x_k - x_j
 // for (i, j, k) cyclic (Section 2.2, P1 elements). Returns the distinct
 // neighbours with non-zero weight, sorted by vertex id, and the diagonal.
+// NB: capacity of the neighbour list (at least the incident triangles + 1).
+template <int NB>
 __device__ __forceinline__ int stiffness_row(int v, const int32_t* __restrict__ vxy,
                                              const int32_t* __restrict__ tri,
                                              const int32_t* __restrict__ vt_ptr,
                                              const int32_t* __restrict__ vt_idx,
-                                             int32_t (&nb)[2 * kMaxIncident],
-                                             double (&w)[2 * kMaxIncident], double& diag) {
+                                             int32_t (&nb)[NB], double (&w)[NB], double& diag) {
   int cnt = 0;
   double d = 0.0;
   const int64_t xa = vxy[2 * v], ya = vxy[2 * v + 1];
@@ -77,6 +79,7 @@ __device__ __forceinline__ int stiffness_row(int v, const int32_t* __restrict__ 
 }
 
 // Rows of the free vertices: count entries of K_FF (off-diagonal) and K_FD.
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_asm_free_count(
     int n, const int32_t* __restrict__ free_vids, const int32_t* __restrict__ vxy,
     const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
@@ -85,10 +88,10 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_count(
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == n) { cnt_ff[n] = 0; cnt_fd[n] = 0; }
   if (i >= n) return;
-  int32_t nb[2 * kMaxIncident];
-  double w[2 * kMaxIncident];
+  int32_t nb[NB];
+  double w[NB];
   double d;
-  const int k = stiffness_row(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  const int k = stiffness_row<NB>(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int cf = 0, cd = 0;
   for (int q = 0; q < k; ++q) {
     if (vmap[nb[q]] >= 0) ++cf; else ++cd;
@@ -97,6 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_count(
   cnt_fd[i] = cd;
 }
 
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_asm_free_fill(
     int n, const int32_t* __restrict__ free_vids, const int32_t* __restrict__ vxy,
     const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
@@ -108,10 +112,10 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_fill(
     float* __restrict__ dinv32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int32_t nb[2 * kMaxIncident];
-  double w[2 * kMaxIncident];
+  int32_t nb[NB];
+  double w[NB];
   double d;
-  const int k = stiffness_row(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  const int k = stiffness_row<NB>(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int pf = ff_ptr[i], pd = fd_ptr[i];
   for (int q = 0; q < k; ++q) {
     const int32_t mv = vmap[nb[q]];
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_fill(
 }
 
 // Rows of the mask vertices: K_DF (free columns only).
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_asm_mask_count(
     int m, const int32_t* __restrict__ mask_vids, const int32_t* __restrict__ vxy,
     const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
@@ -140,15 +145,16 @@ __global__ __launch_bounds__(kBlock) void k_asm_mask_count(
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j == m) cnt_df[m] = 0;
   if (j >= m) return;
-  int32_t nb[2 * kMaxIncident];
-  double w[2 * kMaxIncident];
+  int32_t nb[NB];
+  double w[NB];
   double d;
-  const int k = stiffness_row(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  const int k = stiffness_row<NB>(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int cf = 0;
   for (int q = 0; q < k; ++q) cf += vmap[nb[q]] >= 0;
   cnt_df[j] = cf;
 }
 
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_asm_mask_fill(
     int m, const int32_t* __restrict__ mask_vids, const int32_t* __restrict__ vxy,
     const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
@@ -157,10 +163,10 @@ __global__ __launch_bounds__(kBlock) void k_asm_mask_fill(
     double* __restrict__ df_val) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
-  int32_t nb[2 * kMaxIncident];
-  double w[2 * kMaxIncident];
+  int32_t nb[NB];
+  double w[NB];
   double d;
-  const int k = stiffness_row(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  const int k = stiffness_row<NB>(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int p = df_ptr[j];
   for (int q = 0; q < k; ++q) {
     const int32_t mv = vmap[nb[q]];
@@ -435,6 +441,163 @@ __global__ __launch_bounds__(kBlock) void k_tri_fill(int64_t nleaves, int N,
   }
 }
 
+// ------------------------------------------- Delaunay-mesh pixel maps ----
+// Without leaves, a pixel's owner is the lowest-index triangle that holds it
+// (boundary included). Work is split into (triangle, bounding-box row)
+// items, so a large triangle does not serialise one thread: item g belongs
+// to the triangle t with rowstart[t] <= g < rowstart[t + 1] and covers row
+// y0(t) + g - rowstart[t] of its box.
+
+struct TriBox {
+  int ax, ay, bx, by, cx, cy, x0, x1;
+};
+
+__device__ __forceinline__ int item_triangle(const int32_t* __restrict__ rowstart, int T,
+                                             int64_t g) {
+  int lo = 0, hi = T - 1;  // last t with rowstart[t] <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rowstart[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ TriBox tri_box(const int32_t* __restrict__ tri,
+                                          const int32_t* __restrict__ vxy, int t) {
+  TriBox B;
+  const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+  B.ax = vxy[2 * a]; B.ay = vxy[2 * a + 1];
+  B.bx = vxy[2 * b]; B.by = vxy[2 * b + 1];
+  B.cx = vxy[2 * c]; B.cy = vxy[2 * c + 1];
+  B.x0 = min(B.ax, min(B.bx, B.cx));
+  B.x1 = max(B.ax, max(B.bx, B.cx));
+  return B;
+}
+
+__device__ __forceinline__ bool tri_holds(const TriBox& B, int x, int y) {
+  const int64_t o1 = (int64_t)(B.bx - B.ax) * (y - B.ay) - (int64_t)(B.by - B.ay) * (x - B.ax);
+  const int64_t o2 = (int64_t)(B.cx - B.bx) * (y - B.by) - (int64_t)(B.cy - B.by) * (x - B.bx);
+  const int64_t o3 = (int64_t)(B.ax - B.cx) * (y - B.cy) - (int64_t)(B.ay - B.cy) * (x - B.cx);
+  return o1 >= 0 && o2 >= 0 && o3 >= 0;
+}
+
+// Rows of each triangle's bounding box (the item counts).
+__global__ __launch_bounds__(kBlock) void k_dt_rows(int T, const int32_t* __restrict__ tri,
+                                                    const int32_t* __restrict__ vxy,
+                                                    int32_t* __restrict__ rows) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t > T) return;
+  if (t == T) { rows[T] = 0; return; }
+  const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+  const int ya = vxy[2 * a + 1], yb = vxy[2 * b + 1], yc = vxy[2 * c + 1];
+  rows[t] = max(ya, max(yb, yc)) - min(ya, min(yb, yc)) + 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int64_t n, int32_t v, int32_t* __restrict__ a) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// owner[p] = min over triangles holding p (integer minimum: any order).
+__global__ __launch_bounds__(kBlock) void k_dt_owner(int64_t items, int T, int N,
+                                                     const int32_t* __restrict__ rowstart,
+                                                     const int32_t* __restrict__ tri,
+                                                     const int32_t* __restrict__ vxy,
+                                                     int32_t* __restrict__ owner) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= items) return;
+  const int t = item_triangle(rowstart, T, g);
+  const TriBox B = tri_box(tri, vxy, t);
+  const int y = min(B.ay, min(B.by, B.cy)) + (int)(g - rowstart[t]);
+  for (int x = B.x0; x <= B.x1; ++x)
+    if (tri_holds(B, x, y)) atomicMin(&owner[(int64_t)y * N + x], t);
+}
+
+// Pixels of row item g that its triangle owns.
+__global__ __launch_bounds__(kBlock) void k_dt_count(int64_t items, int T, int N,
+                                                     const int32_t* __restrict__ rowstart,
+                                                     const int32_t* __restrict__ tri,
+                                                     const int32_t* __restrict__ vxy,
+                                                     const int32_t* __restrict__ owner,
+                                                     int32_t* __restrict__ cnt) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g > items) return;
+  if (g == items) { cnt[items] = 0; return; }
+  const int t = item_triangle(rowstart, T, g);
+  const TriBox B = tri_box(tri, vxy, t);
+  const int y = min(B.ay, min(B.by, B.cy)) + (int)(g - rowstart[t]);
+  int c = 0;
+  for (int x = B.x0; x <= B.x1; ++x) c += owner[(int64_t)y * N + x] == t;
+  cnt[g] = c;
+}
+
+// The owned pixels of row item g at their offset: rows ascend within a
+// triangle and x within a row, so every list is in ascending pixel order.
+__global__ __launch_bounds__(kBlock) void k_dt_fill(int64_t items, int T, int N,
+                                                    const int32_t* __restrict__ rowstart,
+                                                    const int32_t* __restrict__ tri,
+                                                    const int32_t* __restrict__ vxy,
+                                                    const int32_t* __restrict__ owner,
+                                                    const int32_t* __restrict__ off,
+                                                    int32_t* __restrict__ px) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= items) return;
+  const int t = item_triangle(rowstart, T, g);
+  const TriBox B = tri_box(tri, vxy, t);
+  const int y = min(B.ay, min(B.by, B.cy)) + (int)(g - rowstart[t]);
+  int pos = off[g];
+  for (int x = B.x0; x <= B.x1; ++x) {
+    const int64_t p = (int64_t)y * N + x;
+    if (owner[p] == t) px[pos++] = (int32_t)p;
+  }
+}
+
+// Start of each triangle's list: the offset of its first row item.
+__global__ __launch_bounds__(kBlock) void k_dt_ptr(int T, int64_t items,
+                                                   const int32_t* __restrict__ rowstart,
+                                                   const int32_t* __restrict__ off,
+                                                   int32_t* __restrict__ ptr) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t > T) return;
+  ptr[t] = off[t < T ? rowstart[t] : items];
+}
+
+// Per triangle over its pixel list (ascending): the total squared error
+// (from e, or from u and f), and, when in_mask is given, its pixel of
+// largest e outside the mask (ties: lower index; -1 if none).
+__global__ __launch_bounds__(kBlock) void k_tri_err_list(int64_t T,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ px,
+                                                         const double* __restrict__ e,
+                                                         const double* __restrict__ u,
+                                                         const uint8_t* __restrict__ f,
+                                                         const uint8_t* __restrict__ in_mask,
+                                                         double* __restrict__ tri_err,
+                                                         int32_t* __restrict__ tri_best) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= T) return;
+  double E = 0.0, bv = -1.0;
+  int32_t best = -1;
+  const int j1 = ptr[t + 1];
+  for (int j = ptr[t]; j < j1; ++j) {
+    const int p = px[j];
+    double ep;
+    if (e) {
+      ep = e[p];
+    } else {
+      const double d = u[p] - (double)f[p];
+      ep = d * d;
+    }
+    E += ep;
+    if (in_mask && !in_mask[p] && ep > bv) {
+      bv = ep;
+      best = p;
+    }
+  }
+  tri_err[t] = E;
+  if (tri_best) tri_best[t] = best;
+}
+
 // u at every pixel from the vertex values (one thread per pixel; the weights
 // are formed exactly as in the leaf-major pass).
 __global__ __launch_bounds__(kBlock) void k_interp_px(int64_t P, int logN,
@@ -569,51 +732,6 @@ __global__ __launch_bounds__(kBlock) void k_tri_best(int64_t nleaves, int N,
   }
 }
 
-// Transposed interpolation: per triangle and corner, sum over the pixels the
-// triangle owns of weight * r (t = R^T r before the per-vertex gather).
-__global__ __launch_bounds__(kBlock) void k_raster_T(int64_t nleaves, int N,
-                                                     const int32_t* __restrict__ leaves,
-                                                     const int32_t* __restrict__ tri,
-                                                     const int32_t* __restrict__ vxy,
-                                                     const double* __restrict__ r,
-                                                     double* __restrict__ tpart) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nleaves) return;
-  LeafTris L;
-  load_leaf(leaves, i, tri, vxy, L);
-  double Sa[kMaxLeafTri], Sb[kMaxLeafTri], Sc[kMaxLeafTri];
-#pragma unroll
-  for (int k = 0; k < kMaxLeafTri; ++k) Sa[k] = Sb[k] = Sc[k] = 0.0;
-  const int x0 = leaves[4 * i], y0 = leaves[4 * i + 1];
-  const int s = 1 << leaves[4 * i + 2];
-  for (int dy = 0; dy < s; ++dy) {
-    for (int dx = 0; dx < s; ++dx) {
-      const int x = x0 + dx, y = y0 + dy;
-      int oa = 0, ob = 0, oc = 0;
-      const int own = locate(L, x, y, oa, ob, oc);
-      const double rv = r[(int64_t)y * N + x];
-#pragma unroll
-      for (int k = 0; k < kMaxLeafTri; ++k) {
-        if (k == own) {
-          const double ia = L.inv[k];
-          Sa[k] += ((double)oa * ia) * rv;
-          Sb[k] += ((double)ob * ia) * rv;
-          Sc[k] += ((double)oc * ia) * rv;
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < kMaxLeafTri; ++k) {
-    if (k < L.nt) {
-      const int64_t t = L.t0 + k;
-      tpart[3 * t] = Sa[k];
-      tpart[3 * t + 1] = Sb[k];
-      tpart[3 * t + 2] = Sc[k];
-    }
-  }
-}
-
 // t_v = sum over (triangle, corner) pairs at v of the partial sums, in the
 // fixed ascending order of the adjacency list; split into free and mask parts.
 __global__ __launch_bounds__(kBlock) void k_gather_vertex(int V, const int32_t* __restrict__ vt_ptr,
@@ -704,35 +822,48 @@ __global__ __launch_bounds__(kBlock) void k_pixel_residual(int64_t P, const uint
 // ------------------------------------------------------------ launchers ----
 #define FI_LAUNCH_CHECK() FI_HIP_TRY(hipGetLastError())
 
-int launch_assemble_count(fi_mesh* M, bool free_rows) {
+template <int NB>
+int assemble_count(fi_mesh* M, bool free_rows) {
   hipStream_t st = M->ctx->stream;
   if (free_rows) {
-    hipLaunchKernelGGL(k_asm_free_count, dim3(grid_for(M->n + 1)), dim3(kBlock), 0, st, (int)M->n,
-                       M->d_free_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
-                       M->d_cnt, M->d_cnt + (M->n + 1));
+    hipLaunchKernelGGL(k_asm_free_count<NB>, dim3(grid_for(M->n + 1)), dim3(kBlock), 0, st,
+                       (int)M->n, M->d_free_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx,
+                       M->d_vmap, M->d_cnt, M->d_cnt + (M->n + 1));
   } else {
-    hipLaunchKernelGGL(k_asm_mask_count, dim3(grid_for(M->m + 1)), dim3(kBlock), 0, st, (int)M->m,
-                       M->d_mask_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
-                       M->d_cnt);
+    hipLaunchKernelGGL(k_asm_mask_count<NB>, dim3(grid_for(M->m + 1)), dim3(kBlock), 0, st,
+                       (int)M->m, M->d_mask_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx,
+                       M->d_vmap, M->d_cnt);
   }
   FI_LAUNCH_CHECK();
   return FI_OK;
 }
 
-int launch_assemble_fill(fi_mesh* M, bool free_rows) {
+template <int NB>
+int assemble_fill(fi_mesh* M, bool free_rows) {
   hipStream_t st = M->ctx->stream;
   if (free_rows) {
-    hipLaunchKernelGGL(k_asm_free_fill, dim3(grid_for(M->n)), dim3(kBlock), 0, st, (int)M->n,
+    hipLaunchKernelGGL(k_asm_free_fill<NB>, dim3(grid_for(M->n)), dim3(kBlock), 0, st, (int)M->n,
                        M->d_free_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
                        M->d_ff_rowptr, M->d_ff_col, M->d_ff_val64, M->d_ff_val32, M->d_fd_rowptr,
                        M->d_fd_col, M->d_fd_val, M->d_diag64, M->d_dinv64, M->d_dinv32);
   } else {
-    hipLaunchKernelGGL(k_asm_mask_fill, dim3(grid_for(M->m)), dim3(kBlock), 0, st, (int)M->m,
+    hipLaunchKernelGGL(k_asm_mask_fill<NB>, dim3(grid_for(M->m)), dim3(kBlock), 0, st, (int)M->m,
                        M->d_mask_vids, M->d_vxy, M->d_tri, M->d_vt_ptr, M->d_vt_idx, M->d_vmap,
                        M->d_df_rowptr, M->d_df_col, M->d_df_val);
   }
   FI_LAUNCH_CHECK();
   return FI_OK;
+}
+
+// A row has at most (incident triangles + 1) neighbours.
+int launch_assemble_count(fi_mesh* M, bool free_rows) {
+  return M->host.delaunay ? assemble_count<kMaxIncidentGeneral + 1>(M, free_rows)
+                          : assemble_count<2 * kMaxIncident>(M, free_rows);
+}
+
+int launch_assemble_fill(fi_mesh* M, bool free_rows) {
+  return M->host.delaunay ? assemble_fill<kMaxIncidentGeneral + 1>(M, free_rows)
+                          : assemble_fill<2 * kMaxIncident>(M, free_rows);
 }
 
 int scan_counts(fi_mesh* M, const int32_t* cnt, int32_t* rowptr, int64_t n_plus_1) {
@@ -775,10 +906,47 @@ int launch_vertex_values(fi_mesh* M, const double* xF, const double* g, double* 
   return FI_OK;
 }
 
+// Interpolation and error passes on a mesh without leaves: pixel-major,
+// then the per-triangle sums over the pixel lists and a copy of the owner map.
+int raster_general(fi_mesh* M, const double* uvert, const double* u_in, const uint8_t* f,
+                   double* u_out, double* e_out, double* tri_err_out, int32_t* owner_out,
+                   double* partial_out) {
+  hipStream_t st = M->ctx->stream;
+  const double* u = u_in;
+  if (!u_in && (u_out || f)) {
+    if (!uvert) return fail(FI_E_INVALID, "interpolation without vertex values");
+    if (!u_out) return fail(FI_E_INVALID, "error of interpolated values needs an output");
+    hipLaunchKernelGGL(k_interp_px, dim3(grid_for(M->P)), dim3(kBlock), 0, st, M->P,
+                       M->host.levels, M->d_owner, M->d_tri, M->d_vxy, uvert, u_out);
+    FI_LAUNCH_CHECK();
+    u = u_out;
+  } else if (u_in && u_out && u_out != u_in) {
+    FI_HIP_TRY(hipMemcpyAsync(u_out, u_in, (size_t)M->P * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+  }
+  if (f) {
+    hipLaunchKernelGGL(k_err_px, dim3(raster_blocks(M)), dim3(kBlock), 0, st, M->P, u, f, e_out,
+                       partial_out);
+    FI_LAUNCH_CHECK();
+    if (tri_err_out) {
+      hipLaunchKernelGGL(k_tri_err_list, dim3(grid_for(M->T)), dim3(kBlock), 0, st, M->T,
+                         M->d_tri_px_ptr, M->d_tri_px, (const double*)nullptr, u, f,
+                         (const uint8_t*)nullptr, tri_err_out, (int32_t*)nullptr);
+      FI_LAUNCH_CHECK();
+    }
+  }
+  if (owner_out)
+    FI_HIP_TRY(hipMemcpyAsync(owner_out, M->d_owner, (size_t)M->P * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, st));
+  return FI_OK;
+}
+
 int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uint8_t* f,
                   double* u_out, double* e_out, double* tri_err_out, int32_t* owner_out,
                   double* partial_out) {
   hipStream_t st = M->ctx->stream;
+  if (M->host.delaunay) return raster_general(M, uvert, u_in, f, u_out, e_out, tri_err_out,
+                                              owner_out, partial_out);
   if (tri_err_out || owner_out || !M->d_owner || (u_in && u_out)) {
     // per-triangle sums and the owner map need the leaf-major pass
     hipLaunchKernelGGL(k_raster, dim3(grid_for(M->L)), dim3(kBlock), 0, st, M->L, M->N,
@@ -804,7 +972,64 @@ int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uin
   return FI_OK;
 }
 
+// Temporary device memory of one call (freed on every return path).
+struct DevTmp {
+  int32_t* p = nullptr;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Owner map and pixel lists of a mesh without leaves (see k_dt_owner).
+int build_pixel_maps_general(fi_mesh* M) {
+  hipStream_t st = M->ctx->stream;
+  const int T = (int)M->T;
+  DevTmp rows, tmp, off;
+  // item counts and their starts (kept in the list-start array until the end)
+  FI_HIP_TRY(hipMalloc(&rows.p, (size_t)(T + 1) * sizeof(int32_t)));
+  FI_HIP_TRY(hipMalloc(&tmp.p, (size_t)scan_tmp_ints(T + 1) * sizeof(int32_t)));
+  int32_t* rowstart = M->d_tri_px_ptr;
+  hipLaunchKernelGGL(k_dt_rows, dim3(grid_for(T + 1)), dim3(kBlock), 0, st, T, M->d_tri,
+                     M->d_vxy, rows.p);
+  FI_LAUNCH_CHECK();
+  int rc = scan_exclusive(st, rows.p, rowstart, T + 1, tmp.p);
+  if (rc) return rc;
+  int32_t items32 = 0;
+  FI_HIP_TRY(hipMemcpyAsync(&items32, rowstart + T, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  const int64_t items = items32;
+  FI_HIP_TRY(hipFree(tmp.p));
+  tmp.p = nullptr;
+  FI_HIP_TRY(hipMalloc(&off.p, (size_t)(items + 1) * sizeof(int32_t) * 2));
+  FI_HIP_TRY(hipMalloc(&tmp.p, (size_t)scan_tmp_ints(items + 1) * sizeof(int32_t)));
+  int32_t* cnt = off.p + (items + 1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(M->P)), dim3(kBlock), 0, st, M->P,
+                     (int32_t)0x7fffffff, M->d_owner);
+  hipLaunchKernelGGL(k_dt_owner, dim3(grid_for(items)), dim3(kBlock), 0, st, items, T, M->N,
+                     rowstart, M->d_tri, M->d_vxy, M->d_owner);
+  hipLaunchKernelGGL(k_dt_count, dim3(grid_for(items + 1)), dim3(kBlock), 0, st, items, T, M->N,
+                     rowstart, M->d_tri, M->d_vxy, M->d_owner, cnt);
+  FI_LAUNCH_CHECK();
+  if ((rc = scan_exclusive(st, cnt, off.p, items + 1, tmp.p))) return rc;
+  // every pixel must have an owner (the triangles tile the square)
+  int32_t owned = 0;
+  FI_HIP_TRY(hipMemcpyAsync(&owned, off.p + items, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  if (owned != M->P) return fail(FI_E_INVALID, "the triangles do not cover every pixel");
+  hipLaunchKernelGGL(k_dt_fill, dim3(grid_for(items)), dim3(kBlock), 0, st, items, T, M->N,
+                     rowstart, M->d_tri, M->d_vxy, M->d_owner, off.p, M->d_tri_px);
+  // the list starts replace the item starts (same array): staged through rows
+  hipLaunchKernelGGL(k_dt_ptr, dim3(grid_for(T + 1)), dim3(kBlock), 0, st, T, items, rowstart,
+                     off.p, rows.p);
+  FI_LAUNCH_CHECK();
+  FI_HIP_TRY(hipMemcpyAsync(M->d_tri_px_ptr, rows.p, (size_t)(T + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, st));
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  return FI_OK;
+}
+
 int build_pixel_maps(fi_mesh* M) {
+  if (M->host.delaunay) return build_pixel_maps_general(M);
   hipStream_t st = M->ctx->stream;
   int32_t* cnt = (int32_t*)M->d_tpart;  // scratch: 3T doubles hold T + 1 counts
   hipLaunchKernelGGL(k_tri_count, dim3(grid_for(M->L)), dim3(kBlock), 0, st, M->L, M->d_leaves,
@@ -821,6 +1046,13 @@ int build_pixel_maps(fi_mesh* M) {
 
 int launch_tri_best(fi_mesh* M, const double* e, const uint8_t* in_mask, double* tri_err,
                     int32_t* tri_best) {
+  if (M->host.delaunay) {
+    hipLaunchKernelGGL(k_tri_err_list, dim3(grid_for(M->T)), dim3(kBlock), 0, M->ctx->stream,
+                       M->T, M->d_tri_px_ptr, M->d_tri_px, e, (const double*)nullptr,
+                       (const uint8_t*)nullptr, in_mask, tri_err, tri_best);
+    FI_LAUNCH_CHECK();
+    return FI_OK;
+  }
   hipLaunchKernelGGL(k_tri_best, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L,
                      M->N, M->d_leaves, M->d_tri, M->d_vxy, e, in_mask, tri_err, tri_best);
   FI_LAUNCH_CHECK();
@@ -828,15 +1060,8 @@ int launch_tri_best(fi_mesh* M, const double* e, const uint8_t* in_mask, double*
 }
 
 int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart) {
-  if (M->d_tri_px) {
-    hipLaunchKernelGGL(k_interp_T_tri, dim3(grid_for(M->T)), dim3(kBlock), 0, M->ctx->stream,
-                       M->T, M->host.levels, M->d_tri_px_ptr, M->d_tri_px, M->d_tri, M->d_vxy, r,
-                       tpart);
-    FI_LAUNCH_CHECK();
-    return FI_OK;
-  }
-  hipLaunchKernelGGL(k_raster_T, dim3(grid_for(M->L)), dim3(kBlock), 0, M->ctx->stream, M->L,
-                     M->N, M->d_leaves, M->d_tri, M->d_vxy, r, tpart);
+  hipLaunchKernelGGL(k_interp_T_tri, dim3(grid_for(M->T)), dim3(kBlock), 0, M->ctx->stream, M->T,
+                     M->host.levels, M->d_tri_px_ptr, M->d_tri_px, M->d_tri, M->d_vxy, r, tpart);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }
@@ -898,7 +1123,9 @@ int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double*
 
 namespace fi {
 int raster_blocks(const fi_mesh* M) {
-  const int64_t g = (M->L + kBlock - 1) / kBlock;
+  // one partial sum per leaf block; a mesh without leaves: per 2048 pixels
+  const int64_t g = M->host.delaunay ? std::min<int64_t>((M->P + 2047) / 2048, 1024)
+                                     : (M->L + kBlock - 1) / kBlock;
   return (int)(g < 1 ? 1 : g);
 }
 }  // namespace fi

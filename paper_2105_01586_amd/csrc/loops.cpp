@@ -3,6 +3,7 @@
 // step.
 #include <algorithm>
 #include <cstring>
+#include <iterator>
 #include <vector>
 
 #include "internal.h"
@@ -33,9 +34,13 @@ namespace {
 
 // Shared loop of fi_grow_mask and fi_densify: rule 0 adds the global top-k
 // (exactly k_add per round), rule 1 the per-triangle step (up to k_add).
+// With `unknowns` (the Delaunay mesh), every round triangulates the current
+// mask and the unknown vertices that are not mask pixels yet: a chosen pixel
+// that was an unknown vertex becomes a mask vertex.
 int densify_loop(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mask0, int64_t m0,
                  int64_t k_add, int rounds, int rule, const fi_solve_opts* opts, int32_t* mask_out,
-                 double* mse_out, double* gpu_ms_out, int64_t* total_out) {
+                 double* mse_out, double* gpu_ms_out, int64_t* total_out,
+                 const std::vector<int32_t>* unknowns = nullptr) {
   if (!ctx || !f_dev || !mask0 || !mask_out || !mse_out)
     return fail(FI_E_INVALID, "densify: NULL argument");
   if (side < 2 || k_add < 0 || rounds < 0) return fail(FI_E_INVALID, "densify: bad sizes");
@@ -57,9 +62,19 @@ int densify_loop(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32_t* mas
   std::memcpy(mask_out, mask0, (size_t)m0 * sizeof(int32_t));
   int64_t written = m0;
   std::vector<int32_t> add((size_t)std::max<int64_t>(k_add, 1));
+  std::vector<int32_t> unk;
   for (int r = 0; r <= rounds; ++r) {
     fi_mesh* M = nullptr;
-    int rc = fi_mesh_build(ctx, side, side, mask.data(), (int64_t)mask.size(), &M);
+    int rc;
+    if (unknowns) {
+      unk.clear();
+      std::set_difference(unknowns->begin(), unknowns->end(), mask.begin(), mask.end(),
+                          std::back_inserter(unk));
+      rc = fi_mesh_build_delaunay(ctx, side, mask.data(), (int64_t)mask.size(), unk.data(),
+                                  (int64_t)unk.size(), &M);
+    } else {
+      rc = fi_mesh_build(ctx, side, side, mask.data(), (int64_t)mask.size(), &M);
+    }
     if (rc) return rc;
     if (gpu_ms_out) FI_HIP_TRY(hipEventRecord(t0.e, ctx->stream));
     fi_solve_stats st{};
@@ -117,6 +132,20 @@ extern "C" int fi_densify(fi_ctx* ctx, int side, const uint8_t* f_dev, const int
                           double* gpu_ms_out, int64_t* mask_size_out) {
   return densify_loop(ctx, side, f_dev, mask0, m0, k_add, rounds, rule, opts, mask_out, mse_out,
                       gpu_ms_out, mask_size_out);
+}
+
+extern "C" int fi_densify_delaunay(fi_ctx* ctx, int side, const uint8_t* f_dev,
+                                   const int32_t* mask0, int64_t m0, const int32_t* unknowns,
+                                   int64_t nu, int64_t k_add, int rounds,
+                                   const fi_solve_opts* opts, int32_t* mask_out, double* mse_out,
+                                   double* gpu_ms_out, int64_t* mask_size_out) {
+  if (nu > 0 && !unknowns) return fail(FI_E_INVALID, "densify: unknown vertices are NULL");
+  std::vector<int32_t> unk(unknowns, unknowns + std::max<int64_t>(nu, 0));
+  for (size_t i = 1; i < unk.size(); ++i)
+    if (unk[i] <= unk[i - 1])
+      return fail(FI_E_INVALID, "densify: unknown vertices must be strictly ascending");
+  return densify_loop(ctx, side, f_dev, mask0, m0, k_add, rounds, FI_DENSIFY_TRIANGLES, opts,
+                      mask_out, mse_out, gpu_ms_out, mask_size_out, &unk);
 }
 
 extern "C" int fi_paper_densify_step(fi_mesh* M, const double* e_dev, int64_t k, int32_t* out_dev,

@@ -148,7 +148,7 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   add(n, 8); add(n, 8); add(n, 4); add(n, 8); add(n, 8); add(n, 8); add(n, 8);
   add(n, 4); add(n, 4); add(4 * n, 4); add(4 * n, 4);
   add(n, 8); add(n, 8); add(4 * n, 8); add(4 * n, 8);
-  add(2 * 4 * kMaxGrid, 8); add(8, 8); add(4, 4); add(kMaxGrid, 8); add(8, 8);
+  add(kMaxGrid, 8); add(8, 8);
   add(V, 8); add(m, 8); add(3 * T, 8); add(n, 8); add(m, 8); add((L + kBlock - 1) / kBlock, 8);
   add(P, 4); add(P, 4); add(T + 1, 4);  // owner map and per-triangle pixel lists
   // matrices
@@ -156,7 +156,7 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   add(deg_mask, 4); add(deg_mask, 8);
   // solver set-up
   const int64_t grid = ((n + kBatchBS - 1) / kBatchBS + 7) / 8 * 8;
-  add(4, 4); add(4, 8); add(8, 8); add(2, 96); add(2 * 4 * grid, 8);
+  add(4, 4); add(4, 8); add(4 * kRedMaxBlocks, 8); add(8, 8); add(2, 96); add(2 * 4 * grid, 8);
   add((int64_t)kMaxEll * ((n + 63) / 64 * 64), 4);
   // CGLS workspace and the request's buffers
   add(m, 8); add(m, 8); add(P, 8); add(P, 8); add(8, 8);

@@ -254,8 +254,12 @@ __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, P
 // product as its load returns (few registers, more waves in flight). Else
 // every block re-reduces the per-block partials, and the neighbour loads
 // are issued before that reduction to overlap with it.
-template <typename T, int W, bool SUMMED, int BS>
+// LATE: gather the neighbours after the reduction even when the block
+// re-reduces the partials itself (fewer registers: more blocks per CU when
+// one launch carries several solves).
+template <typename T, int W, bool SUMMED, int BS, bool LATE = false>
 __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, double* lds) {
+  constexpr bool PRE = !SUMMED && !LATE;  // neighbour values loaded before the reduction
   // The record slot read here is written only by the next launch, so every
   // thread reads it directly: uniform scalar loads, values kept read-only.
   const Rec Rin = *A.rec_in;
@@ -289,7 +293,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     const int32_t* ell = A.ell + ic;
 #pragma unroll
     for (int k = 0; k < W; ++k) e[k] = ell[(size_t)k * A.n_pad];
-    if constexpr (!SUMMED) {
+    if constexpr (PRE) {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         const Quad<T> qn = A.rq_in[ell_col(e[k])];
@@ -445,7 +449,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     const T ri = next_r(r0, s0, q0, a, b);
     const T zi = d0 * ri;
     T acc = ri;  // diagonal term: K_ii z_i = r_i
-    if constexpr (W > 0 && SUMMED) {
+    if constexpr (W > 0 && !PRE) {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         const Quad<T> qn = A.rq_in[ell_col(e[k])];
@@ -496,7 +500,6 @@ constexpr int kArgSlots = 20;
 // sums travel through device-scope atomic stores and loads, so they are
 // coherent across the XCDs' L2 caches.
 constexpr int kRedChunk = 1024;   // partials per block of the reduction launch
-constexpr int kRedMaxBlocks = 256;
 
 struct ReduceArgs {
   int n;                               // systems summed by this launch
@@ -592,6 +595,33 @@ __global__ __launch_bounds__(BS) void k_step_batch(BatchArgs B) {
     return;
   }
   step_body<float, W, SUMMED, BS>(A, lblk, lds);
+}
+
+// ------------------------------------------------------ multi-RHS steps --
+// The channels of a colour image share the mask, hence K_FF: one launch
+// advances up to kMaxRhs solves with the same matrix. Hardware block b runs
+// on XCD b % 8; the k-th block of an XCD takes solve k % nrhs and row block
+// (b % 8) * (G / 8) + k / nrhs (G row blocks per solve), so the solves'
+// blocks for the same rows run side by side on one XCD: the rows' matrix
+// entries and D^-1, fetched from HBM by the first of them, are L2 hits for
+// the others. Every block runs the single-solve step on its solve's
+// arguments and the row block the single-solve launch would give it, so
+// each solve gets the bits of its own single solve (records, partial sums
+// and vectors are per solve; the solves may be in different phases).
+template <typename T>
+struct MultiArgs {
+  int nrhs;  // solves in this launch, 1..kMaxRhs; the grid is nrhs * G
+  StepArgs<T> a[kMaxRhs];
+};
+
+template <typename T, int W, bool SUMMED, int BS>
+__global__ __launch_bounds__(BS) void k_step_multi(MultiArgs<T> B) {
+  __shared__ double lds[3 * (BS / 64)];
+  const int nr = B.nrhs;
+  const int per = (int)(gridDim.x / nr) >> 3;  // row blocks per XCD slab
+  const int k = blockIdx.x >> 3;
+  const int c = k % nr;
+  step_body<T, W, SUMMED, BS, true>(B.a[c], (blockIdx.x & 7) * per + k / nr, lds);
 }
 
 // ELL packing of the CSR off-diagonal part; flags values other than -1/2, -1.
@@ -859,7 +889,190 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
   }
 }
 
+template <typename T, int W, bool SUMMED>
+void* multi_ptr(int bs) {
+  return bs == 256 ? (void*)k_step_multi<T, W, SUMMED, 256> : (void*)k_step_multi<T, W, SUMMED, 512>;
+}
+
+template <typename T, bool SUMMED>
+void* multi_kernel_w(int w, int bs) {
+  switch (w) {
+    case 4: return multi_ptr<T, 4, SUMMED>(bs);
+    case 6: return multi_ptr<T, 6, SUMMED>(bs);
+    case 8: return multi_ptr<T, 8, SUMMED>(bs);
+    default: return multi_ptr<T, 0, SUMMED>(bs);
+  }
+}
+
+template <typename T>
+void* multi_kernel(const fi_mesh* M) {
+  return M->large_mode ? multi_kernel_w<T, true>(M->ell_w, M->cg_bs)
+                       : multi_kernel_w<T, false>(M->ell_w, M->cg_bs);
+}
+
+// Launch arguments of a multi-RHS step for both parities (and, for large
+// systems, of the reduction that follows it: one launch sums every solve's
+// partials).
+template <typename T>
+struct MultiLaunch {
+  MultiArgs<T> a[2];
+  ReduceArgs r[2];
+};
+
+template <typename T>
+void multi_prepare(fi_mesh* const* ch, int nc, int force, MultiLaunch<T>& L) {
+  for (int par = 0; par < 2; ++par) {
+    L.a[par] = MultiArgs<T>{};
+    L.a[par].nrhs = nc;
+    L.r[par] = ReduceArgs{};
+    for (int c = 0; c < nc; ++c) {
+      L.a[par].a[c] = make_args<T>(ch[c], par, force);
+      if (ch[0]->large_mode) add_reduce(L.r[par], ch[c], par);
+    }
+  }
+}
+
+template <typename T>
+int multi_launch(fi_mesh* M0, MultiLaunch<T>& L, int par) {
+  void* args[1] = {&L.a[par]};
+  const unsigned grid = (unsigned)L.a[par].nrhs * (unsigned)M0->cg_grid;
+  FI_HIP_TRY(hipLaunchKernel(multi_kernel<T>(M0), dim3(grid), dim3(M0->cg_bs), args, 0,
+                             M0->ctx->stream));
+  if (!M0->large_mode) return FI_OK;
+  void* rargs[1] = {&L.r[par]};
+  FI_HIP_TRY(hipLaunchKernel((void*)k_reduce_partials, dim3(L.r[par].start[L.r[par].n]),
+                             dim3(kBlock), rargs, 0, M0->ctx->stream));
+  return FI_OK;
+}
+
+// The solves of all channels advance together, one launch per step, paced
+// like solve_dev (events of channel 0), until every channel's mirror shows
+// its end.
+template <typename T>
+int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve_stats* stats) {
+  fi_mesh* M0 = ch[0];
+  hipStream_t st = M0->ctx->stream;
+  int epoch[kMaxRhs];
+  bool done[kMaxRhs] = {};
+  int rc = FI_OK, first_rc = FI_OK;
+  for (int c = 0; c < nc; ++c) {
+    epoch[c] = next_epoch(ch[c]);
+    if ((rc = launch_start<T>(ch[c], o, epoch[c]))) return rc;
+  }
+  // Launch arguments for the solves still running; a solve that has ended
+  // leaves the launches from the next chunk on (chunks start at parity 0).
+  MultiLaunch<T> L;
+  fi_mesh* run[kMaxRhs];
+  int nrun = nc;
+  for (int c = 0; c < nc; ++c) run[c] = ch[c];
+  multi_prepare<T>(run, nrun, 0, L);
+  const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
+  const int64_t max_chunks = max_launch / kChunk + 2;
+  int64_t launched = 0, completed = 0;
+  auto all_done = [&]() {
+    bool all = true;
+    for (int c = 0; c < nc; ++c) {
+      if (!done[c]) {
+        int drc = FI_OK;
+        done[c] = read_mirror(ch[c], epoch[c], &stats[c], &drc) != 0;
+        if (done[c] && drc && !first_rc) first_rc = drc;
+      }
+      all = all && done[c];
+    }
+    return all;
+  };
+  for (;;) {
+    if (all_done()) return first_rc;
+    int left = 0;
+    for (int c = 0; c < nc; ++c)
+      if (!done[c]) run[left++] = ch[c];
+    if (left < nrun) {
+      nrun = left;
+      multi_prepare<T>(run, nrun, 0, L);
+    }
+    if (launched < max_chunks && launched - completed < kAhead) {
+      for (int q = 0; q < kChunk; ++q)
+        if ((rc = multi_launch<T>(M0, L, q & 1))) return rc;
+      FI_HIP_TRY(hipEventRecord(M0->chunk_ev[launched % kChunkEvents], st));
+      ++launched;
+      continue;
+    }
+    if (completed < launched) {
+      const hipError_t q = hipEventQuery(M0->chunk_ev[completed % kChunkEvents]);
+      if (q == hipSuccess) {
+        ++completed;
+        continue;
+      }
+      if (q != hipErrorNotReady)
+        return fail(FI_E_HIP, std::string("stream failed: ") + hipGetErrorString(q));
+    } else {
+      if (all_done()) return first_rc;
+      return fail(FI_E_HIP, "solver did not report termination");
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 }  // namespace
+
+int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats) {
+  if (nc < 1 || nc > kMaxRhs) return fail(FI_E_INVALID, "1 to 3 right-hand sides per solve");
+  for (int c = 0; c < nc; ++c) {
+    stats[c].iterations = 0;
+    stats[c].refinements = 0;
+    stats[c].status = FI_OK;
+    stats[c].rel_residual = 0.0;
+  }
+  if (ch[0]->n == 0) return FI_OK;
+  if (opts->precision == FI_PREC_FP64) return solve_multi_dev<double>(ch, nc, opts, stats);
+  return solve_multi_dev<float>(ch, nc, opts, stats);
+}
+
+// Times `reps` multi-RHS steps over nc channels forced into the iteration
+// phase (every channel iterating), between two HIP events on the stream.
+int time_multi_kernel(fi_mesh* const* ch, int nc, int precision, int reps, double* ms) {
+  fi_mesh* M0 = ch[0];
+  if (M0->n == 0 || reps < 1 || nc < 1 || nc > kMaxRhs)
+    return fail(FI_E_INVALID, "nothing to time");
+  hipStream_t st = M0->ctx->stream;
+  const bool d = precision == FI_PREC_FP64;
+  fi_solve_opts o;
+  fi_solve_opts_default(&o);
+  int rc = FI_OK;
+  for (int c = 0; c < nc; ++c) {
+    const int epoch = next_epoch(ch[c]);
+    rc = d ? launch_start<double>(ch[c], &o, epoch) : launch_start<float>(ch[c], &o, epoch);
+    if (rc) return rc;
+  }
+  MultiLaunch<float> Lf;
+  MultiLaunch<double> Ld;
+  if (d) {
+    multi_prepare<double>(ch, nc, 0, Ld);
+    if ((rc = multi_launch<double>(M0, Ld, 0))) return rc;
+    multi_prepare<double>(ch, nc, 1, Ld);
+  } else {
+    multi_prepare<float>(ch, nc, 0, Lf);
+    if ((rc = multi_launch<float>(M0, Lf, 0))) return rc;
+    multi_prepare<float>(ch, nc, 1, Lf);
+  }
+  hipEvent_t e0, e1;
+  FI_HIP_TRY(hipEventCreate(&e0));
+  FI_HIP_TRY(hipEventCreate(&e1));
+  auto step = [&](int k) { return d ? multi_launch<double>(M0, Ld, k & 1) : multi_launch<float>(M0, Lf, k & 1); };
+  for (int k = 0; k < 4; ++k)
+    if ((rc = step(k + 1))) return rc;
+  FI_HIP_TRY(hipEventRecord(e0, st));
+  for (int k = 0; k < reps; ++k)
+    if ((rc = step(k + 1))) return rc;
+  FI_HIP_TRY(hipEventRecord(e1, st));
+  FI_HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  FI_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  return FI_OK;
+}
 
 int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int count) {
   if (act.empty() || count <= 0) return FI_OK;
@@ -946,6 +1159,41 @@ void solver_release(fi_mesh* M) {
   M->d_mirror = nullptr;
 }
 
+// The state of one solve: flags and reduction counter, reduced and
+// first-level sums, parameters, the two records, the per-block partial sums
+// of both parities, the host mirror and the pacing events. Needs cg_grid.
+int alloc_solver_state(fi_mesh* M) {
+  int rc = 0;
+  if ((rc = device_alloc(M, (void**)&M->d_flag, 4 * sizeof(int32_t)))) return rc;
+  if ((rc = device_alloc(M, (void**)&M->d_red4, 4 * sizeof(double)))) return rc;
+  if ((rc = device_alloc(M, (void**)&M->d_lvl1, 4 * kRedMaxBlocks * sizeof(double)))) return rc;
+  if ((rc = device_alloc(M, (void**)&M->d_prm, sizeof(Params)))) return rc;
+  if ((rc = device_alloc(M, &M->d_rec, 2 * sizeof(Rec)))) return rc;
+  if ((rc = device_alloc(M, (void**)&M->d_part, (size_t)2 * 4 * M->cg_grid * sizeof(double))))
+    return rc;
+  // the host mirror: fine-grained pinned memory the kernels write through to
+  FI_HIP_TRY(hipHostMalloc(&M->h_mirror, sizeof(Mirror),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(M->h_mirror, 0, sizeof(Mirror));
+  FI_HIP_TRY(hipHostGetDevicePointer(&M->d_mirror, M->h_mirror, 0));
+  for (int k = 0; k < kChunkEvents; ++k)
+    FI_HIP_TRY(hipEventCreateWithFlags(&M->chunk_ev[k], hipEventDisableTiming));
+  // the reduction counter starts at zero (the flag words are cleared too)
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, M->ctx->stream, M->d_flag);
+  FI_HIP_TRY(hipGetLastError());
+  return FI_OK;
+}
+
+int solver_channel_setup(fi_mesh* S, const fi_mesh* M) {
+  S->cg_bs = M->cg_bs;
+  S->cg_grid = M->cg_grid;
+  S->large_mode = M->large_mode;
+  S->n_pad = M->n_pad;
+  S->ell_w = M->ell_w;
+  S->d_ell = M->d_ell;
+  return alloc_solver_state(S);
+}
+
 // Called after every assembly: picks the launch shape and packs the ELL copy.
 int solver_setup(fi_mesh* M) {
   hipStream_t st = M->ctx->stream;
@@ -968,23 +1216,10 @@ int solver_setup(fi_mesh* M) {
     M->large_mode = blocks > kMaxGrid || (force_large && std::atoi(force_large) == 1);
     M->cg_grid = (int)std::max<int64_t>(1, blocks);
     M->n_pad = (n + 63) / 64 * 64;
-    int rc = 0;
-    if ((rc = device_alloc(M, (void**)&M->d_flag, 4 * sizeof(int32_t)))) return rc;
-    if ((rc = device_alloc(M, (void**)&M->d_red4, 4 * sizeof(double)))) return rc;
-    if ((rc = device_alloc(M, (void**)&M->d_lvl1, 4 * kRedMaxBlocks * sizeof(double)))) return rc;
     if (M->large_mode && (M->cg_grid + kRedChunk - 1) / kRedChunk > kRedMaxBlocks)
       return fail(FI_E_INVALID, "system too large for the partial-sum reduction");
-    if ((rc = device_alloc(M, (void**)&M->d_prm, sizeof(Params)))) return rc;
-    if ((rc = device_alloc(M, &M->d_rec, 2 * sizeof(Rec)))) return rc;
-    if ((rc = device_alloc(M, (void**)&M->d_part, (size_t)2 * 4 * M->cg_grid * sizeof(double))))
-      return rc;
-    // the host mirror: fine-grained pinned memory the kernels write through to
-    FI_HIP_TRY(hipHostMalloc(&M->h_mirror, sizeof(Mirror),
-                             hipHostMallocMapped | hipHostMallocCoherent));
-    std::memset(M->h_mirror, 0, sizeof(Mirror));
-    FI_HIP_TRY(hipHostGetDevicePointer(&M->d_mirror, M->h_mirror, 0));
-    for (int k = 0; k < kChunkEvents; ++k)
-      FI_HIP_TRY(hipEventCreateWithFlags(&M->chunk_ev[k], hipEventDisableTiming));
+    int rc = alloc_solver_state(M);
+    if (rc) return rc;
     // widest row decides the ELL width
     hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, st, M->d_flag);
     if (n > 0)
@@ -1067,10 +1302,15 @@ int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
 // plus row pointers), and per row the reads of r, s, q, D^-1, x, p and the
 // writes of x, p, r, s, q.
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision) {
+  return cg_multi_kernel_bytes(M, 1, precision);
+}
+
+// With nrhs solves per launch the matrix counts once.
+int64_t cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision) {
   const int64_t w = precision == FI_PREC_FP64 ? 8 : 4;
   const int64_t mat = M->ell_w > 0 ? M->nnz_off * 4  // encoded entries; padding not counted
                                    : M->nnz_off * (4 + w) + (M->n + 1) * 4;
-  return mat + M->n * w * 11;
+  return mat + (int64_t)nrhs * M->n * w * 11;
 }
 
 }  // namespace fi

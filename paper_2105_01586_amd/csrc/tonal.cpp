@@ -195,3 +195,113 @@ extern "C" int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
     return fail(FI_E_NO_CONVERGENCE, "tonal optimisation reached the outer iteration cap");
   return FI_OK;
 }
+
+extern "C" int fi_tonal_opt_rgb(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
+                                const fi_tonal_opts* opts, fi_tonal_stats* stats) {
+  if (!M || !M->ctx) return fail(FI_E_INVALID, "mesh is NULL");
+  if (!f_dev || !g_dev) return fail(FI_E_INVALID, "f_dev and g_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  fi_tonal_opts o;
+  fi_tonal_opts_default(&o);
+  if (opts) {
+    o = *opts;
+    if (o.rtol < 0) o.rtol = 1e-8;
+    if (o.max_outer <= 0) o.max_outer = 500;
+  }
+  fi_solve_opts io;
+  fi_solve_opts_default(&io);
+  if (opts) {
+    io = opts->inner;
+    fi_solve_opts d;
+    fi_solve_opts_default(&d);
+    if (io.rtol <= 0) io.rtol = d.rtol;
+    if (io.inner_rtol <= 0 || io.inner_rtol >= 1) io.inner_rtol = d.inner_rtol;
+    if (io.max_inner <= 0) io.max_inner = d.max_inner;
+    if (io.max_refine <= 0) io.max_refine = d.max_refine;
+    if (io.check_every <= 0) io.check_every = d.check_every;
+  }
+  constexpr int C = kMaxRhs;
+  fi_mesh* ch[C];
+  int rc = channel_views(M, C, ch);
+  if (rc) return rc;
+  Cgls cg[C];
+  fi_tonal_stats ts[C] = {};
+  bool active[C];
+  for (int c = 0; c < C; ++c) {
+    cg[c].M = ch[c];
+    cg[c].f = f_dev + (size_t)c * M->P;
+    cg[c].g = g_dev + (size_t)c * M->m;
+    cg[c].start_from_g = o.start_from_g != 0;
+    if ((rc = cg[c].alloc())) return rc;
+    active[c] = true;
+  }
+  // One segment for the active channels: their right-hand sides, one
+  // multi-right-hand-side solve, then each channel's own update.
+  auto run = [&](Cgls::Seg seg) -> int {
+    fi_mesh* act[C];
+    int idx[C], na = 0;
+    for (int c = 0; c < C; ++c) {
+      if (!active[c]) continue;
+      cg[c].seg = seg;
+      int r = cg[c].pre();
+      if (r) return r;
+      act[na] = ch[c];
+      idx[na++] = c;
+    }
+    if (na == 0) return FI_OK;
+    fi_solve_stats st[C] = {};
+    int r = solve_multi(act, na, &io, st);
+    for (int q = 0; q < na; ++q) ts[idx[q]].inner_iterations += st[q].iterations;
+    if (r) return r;
+    for (int q = 0; q < na; ++q)
+      if (st[q].status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");
+    for (int q = 0; q < na; ++q)
+      if ((r = cg[idx[q]].post())) return r;
+    return FI_OK;
+  };
+  double sc[8] = {0};
+  double s0[C];
+  if ((rc = run(Cgls::kInpaint)) || (rc = run(Cgls::kAdjoint))) return rc;
+  for (int c = 0; c < C; ++c) {
+    if ((rc = read_scalars(ch[c], sc, 8))) return rc;
+    s0[c] = std::sqrt(sc[Cgls::kScGamma]);
+    if (!std::isfinite(s0[c])) return fail(FI_E_INVALID, "non-finite normal residual");
+    ts[c].mse_initial = sc[Cgls::kScRR0] / (double)M->P;
+    ts[c].rel_normal_residual = s0[c] > 0 ? 1.0 : 0.0;
+    ts[c].status = s0[c] > 0 ? FI_E_NO_CONVERGENCE : FI_OK;
+    active[c] = s0[c] > 0;
+  }
+  for (int it = 0; it < o.max_outer; ++it) {
+    bool any = false;
+    for (int c = 0; c < C; ++c) any = any || active[c];
+    if (!any) break;
+    if ((rc = run(Cgls::kApplyP)) || (rc = run(Cgls::kAdjoint))) return rc;
+    for (int c = 0; c < C; ++c) {
+      if (!active[c]) continue;
+      ++ts[c].outer_iterations;
+      if ((rc = read_scalars(ch[c], sc, 8))) return rc;
+      ts[c].rel_normal_residual = std::sqrt(sc[Cgls::kScGamma + (cg[c].k & 1)]) / s0[c];
+      if (ts[c].rel_normal_residual <= o.rtol) {
+        ts[c].status = FI_OK;
+        active[c] = false;
+      } else if (!(sc[Cgls::kScQQ] > 0)) {
+        active[c] = false;  // B p = 0: no progress possible
+      }
+    }
+  }
+  for (int c = 0; c < C; ++c) {
+    if (o.rtol == 0.0) ts[c].status = FI_OK;  // a fixed number of iterations was asked for
+    active[c] = true;
+  }
+  if ((rc = run(Cgls::kFinal))) return rc;
+  bool ok = true;
+  for (int c = 0; c < C; ++c) {
+    if ((rc = read_scalars(ch[c], sc, 8))) return rc;
+    ts[c].mse_final = sc[Cgls::kScSSE] / (double)M->P;
+    ok = ok && ts[c].status == FI_OK;
+  }
+  if (stats)
+    for (int c = 0; c < C; ++c) stats[c] = ts[c];
+  if (!ok) return fail(FI_E_NO_CONVERGENCE, "tonal optimisation of a channel reached the cap");
+  return FI_OK;
+}

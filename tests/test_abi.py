@@ -110,3 +110,46 @@ def test_footprint_bound_host_only():
         fi.footprint_bound(side, small[::-1].copy())
     with pytest.raises(fi.FIError):
         fi.footprint_bound(100, small)
+
+
+@pytest.mark.parametrize("N,dens,seed", [(2, 0.5, 1), (8, 0.2, 2), (64, 0.05, 3), (256, 0.03, 4),
+                                         (512, 0.04, 2)])
+def test_host_delaunay_mesh_bit_exact(N, dens, seed):
+    """The library's Delaunay builder (host C++) against the oracle's: the
+    same canonical triangles, vertices and free / mask split."""
+    from oracle import delaunay
+    P = N * N
+    mask = synth.make_mask(seed, P, dens)
+    unk = synth.make_unknowns(seed, P, mask, min(mask.size, P - mask.size))
+    h = fi.host_mesh(N, mask, unk)
+    o = delaunay.build_mesh(N, mask, unk)
+    assert np.array_equal(h["vxy"], o.vxy)
+    assert np.array_equal(h["tri"], o.tri)
+    assert np.array_equal(h["free_vids"], o.free_vids)
+    assert np.array_equal(h["mask_vids"], o.mask_vids)
+    assert h["L"] == 0
+
+
+def test_host_delaunay_full_grid():
+    """Every pixel a vertex: each unit square is cocircular, the diagonal is
+    the perturbation's choice on both sides."""
+    from oracle import delaunay
+    N = 32
+    pix = np.arange(N * N, dtype=np.int32)
+    mask, unk = pix[::5], np.setdiff1d(pix, pix[::5])
+    h = fi.host_mesh(N, mask, unk)
+    assert np.array_equal(h["tri"], delaunay.build_mesh(N, mask, unk).tri)
+    assert h["T"] == 2 * (N - 1) ** 2
+
+
+@pytest.mark.parametrize("side,mask,unk,code", [
+    (16, [], [3], fi.E_EMPTY_MASK),
+    (16, [3], [3], fi.E_INVALID),
+    (16, [3], [9, 5], fi.E_INVALID),
+    (16, [3], [256], fi.E_INVALID),
+    (12, [1], [2], fi.E_INVALID),
+])
+def test_host_delaunay_errors(side, mask, unk, code):
+    with pytest.raises(fi.FIError) as ei:
+        fi.host_mesh(side, mask, unk)
+    assert ei.value.code == code
