@@ -100,6 +100,25 @@ typedef struct fi_tonal_stats {
   double mse_final;       /* MSE of B g against f */
 } fi_tonal_stats;
 
+/* L1 tonal optimisation by iteratively reweighted least squares (see
+ * fi_tonal_opt_l1). */
+typedef struct fi_l1_opts {
+  fi_solve_opts inner; /* every solve with K_FF */
+  double eps;          /* floor of |r| in the weights 1 / max(|r|, eps) (grey levels) */
+  int irls_iters;      /* K: reweighting steps */
+  int cgls_iters;      /* J: CGLS iterations per step (from the current g) */
+  int start_from_g;    /* nonzero: g_dev holds the start values */
+} fi_l1_opts;
+
+typedef struct fi_l1_stats {
+  int32_t irls_iters;
+  int32_t status;
+  int64_t inner_iterations; /* CG iterations over all solves */
+  double mae_initial;       /* mean |B g0 - f| */
+  double mae_final;         /* mean |B g - f| */
+  double mse_final;         /* MSE of B g */
+} fi_l1_stats;
+
 typedef struct fi_mesh_info {
   int64_t N;      /* image side */
   int64_t P;      /* pixels, N * N */
@@ -200,6 +219,15 @@ int fi_assemble(fi_mesh* mesh);
 int fi_inpaint(fi_mesh* mesh, const uint8_t* f_dev, const double* g_dev, double* u_dev,
                const fi_solve_opts* opts, fi_solve_stats* stats);
 
+/* One-shot inpainting of an image given as a mask bitmap: builds the
+ * quadtree mesh of the pixels where mask_u8_host is nonzero (host
+ * uint8[width * height], row-major), inpaints as fi_inpaint, and frees the
+ * mesh. For repeated calls on one mask, build the mesh once instead.
+ * Errors as fi_mesh_build and fi_inpaint. */
+int fi_inpaint_image(fi_ctx* ctx, int width, int height, const uint8_t* f_dev,
+                     const uint8_t* mask_u8_host, const double* g_dev, double* u_dev,
+                     const fi_solve_opts* opts, fi_solve_stats* stats);
+
 /* The vertex values of the last fi_inpaint on this mesh, float64[V] in
  * vertex order, copied to a device buffer. */
 int fi_vertex_values(fi_mesh* mesh, double* u_vertex_dev);
@@ -228,6 +256,24 @@ int fi_adjoint(fi_mesh* mesh, const double* r_dev, double* s_dev, const fi_solve
  *   result on return. opts: NULL for defaults. */
 int fi_tonal_opt(fi_mesh* mesh, const uint8_t* f_dev, double* g_dev, const fi_tonal_opts* opts,
                  fi_tonal_stats* stats);
+
+/* Defaults: eps = 0.5, irls_iters = 8, cgls_iters = 20, inner as
+ * fi_solve_opts_default, start_from_g = 0. */
+void fi_l1_opts_default(fi_l1_opts* opts);
+
+/* Tonal optimisation for the L1 error E1(g) = sum_i |(B g)_i - f_i| (the
+ * paper optimises its large colour result for it and states no method; this
+ * is iteratively reweighted least squares). From g0 = f on the mask (or the
+ * given g), each of irls_iters steps computes r = f - B g, the weights
+ * w = 1 / max(|r|, eps), and runs cgls_iters iterations of the CGLS of
+ * fi_tonal_opt on W^(1/2) B with right side W^(1/2) f, started from g. The
+ * Huber function of the residual (|r| above eps, r^2 / (2 eps) + eps / 2
+ * below) never increases from step to step.
+ *   f_dev: uint8[P]; g_dev: float64[m] (start if start_from_g; result);
+ *   mae_hist: host float64[irls_iters + 1] or NULL, the mean |B g - f| at
+ *   the start and after each step. Synchronous (one host read per step). */
+int fi_tonal_opt_l1(fi_mesh* mesh, const uint8_t* f_dev, double* g_dev, const fi_l1_opts* opts,
+                    fi_l1_stats* stats, double* mae_hist);
 
 /* Export of the mesh for checking (host buffers of the stated sizes, each may
  * be NULL): vertex lattice coordinates int32[V][2] (x, y); triangles

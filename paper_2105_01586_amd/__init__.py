@@ -46,7 +46,7 @@ EXPORTED_SYMBOLS = (
     "fi_server_destroy", "fi_server_footprint", "fi_paper_densify_step", "fi_densify",
     "fi_inpaint_rgb", "fi_error_rgb", "fi_tonal_opt_rgb", "fi_time_cg_multi_kernel",
     "fi_cg_multi_kernel_bytes", "fi_mesh_build_delaunay", "fi_host_mesh_build_delaunay",
-    "fi_densify_delaunay",
+    "fi_densify_delaunay", "fi_l1_opts_default", "fi_tonal_opt_l1", "fi_inpaint_image",
 )
 
 
@@ -80,6 +80,17 @@ class _TonalStats(ctypes.Structure):
     _fields_ = [("outer_iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("inner_iterations", ctypes.c_int64), ("rel_normal_residual", ctypes.c_double),
                 ("mse_initial", ctypes.c_double), ("mse_final", ctypes.c_double)]
+
+
+class _L1Opts(ctypes.Structure):
+    _fields_ = [("inner", _SolveOpts), ("eps", ctypes.c_double), ("irls_iters", ctypes.c_int),
+                ("cgls_iters", ctypes.c_int), ("start_from_g", ctypes.c_int)]
+
+
+class _L1Stats(ctypes.Structure):
+    _fields_ = [("irls_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("inner_iterations", ctypes.c_int64), ("mae_initial", ctypes.c_double),
+                ("mae_final", ctypes.c_double), ("mse_final", ctypes.c_double)]
 
 
 class _MeshInfo(ctypes.Structure):
@@ -198,6 +209,12 @@ def library() -> ctypes.CDLL:
         "fi_densify_delaunay": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp,
                                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                                ctypes.POINTER(_SolveOpts), vp, vp, vp, i64p]),
+        "fi_inpaint_image": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp,
+                                            ctypes.POINTER(_SolveOpts),
+                                            ctypes.POINTER(_SolveStats)]),
+        "fi_l1_opts_default": (None, [ctypes.POINTER(_L1Opts)]),
+        "fi_tonal_opt_l1": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_L1Opts),
+                                           ctypes.POINTER(_L1Stats), vp]),
         "fi_server_opts_default": (None, [ctypes.POINTER(_ServerOpts)]),
         "fi_server_create": (ctypes.c_int, [vp, ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]),
         "fi_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(_JobDesc),
@@ -478,6 +495,25 @@ class Mesh:
         _check(rc, "fi_tonal_opt")
         return g, _stats(st)
 
+    def tonal_opt_l1(self, f, g=None, eps: float = 0.5, irls_iters: int = 8,
+                     cgls_iters: int = 20, inner: SolveOpts | None = None):
+        """L1 tonal optimisation by IRLS (fi_tonal_opt_l1). Returns (g, stats,
+        MAE at the start and after each step)."""
+        torch = _torch()
+        d = self._dev()
+        start = g is not None
+        if g is None:
+            g = self._empty(self.m, torch.float64)
+        o = _L1Opts((inner or SolveOpts()).c(), float(eps), int(irls_iters), int(cgls_iters),
+                    int(start))
+        st = _L1Stats()
+        hist = np.empty(int(irls_iters) + 1, np.float64)
+        rc = library().fi_tonal_opt_l1(self._h, _ptr(f, torch.uint8, self.P, "f", d),
+                                       _ptr(g, torch.float64, self.m, "g", d), ctypes.byref(o),
+                                       ctypes.byref(st), hist.ctypes.data_as(ctypes.c_void_p))
+        _check(rc, "fi_tonal_opt_l1")
+        return g, _stats(st), hist
+
     # -- colour (planar: channel c at [c * P, (c + 1) * P)) ------------------
     def inpaint_rgb(self, f=None, g=None, u=None, opts: SolveOpts | None = None):
         """u_c = B g_c for the three channels (g defaults to f on the mask).
@@ -604,6 +640,30 @@ class Mesh:
         _check(library().fi_cg_multi_kernel_bytes(self._h, int(nrhs), int(precision),
                                                   ctypes.byref(b)), "fi_cg_multi_kernel_bytes")
         return b.value
+
+
+def inpaint_image(ctx: Context, f, mask_u8, g=None, opts: SolveOpts | None = None):
+    """One-shot inpainting (fi_inpaint_image): f uint8 device tensor of
+    side * side pixels, mask_u8 a host array of the same size (nonzero =
+    mask pixel), g optional device values at the mask pixels in ascending
+    order. Returns (u, stats)."""
+    torch = _torch()
+    mask_u8 = np.ascontiguousarray(np.asarray(mask_u8, dtype=np.uint8).ravel())
+    side = int(round(mask_u8.size ** 0.5))
+    if side * side != mask_u8.size:
+        raise ValueError("square images only")
+    d = ctx.device
+    m = int(np.count_nonzero(mask_u8))
+    u = torch.empty(side * side, dtype=torch.float64, device=f"cuda:{d}")
+    st = _SolveStats()
+    o = (opts or SolveOpts()).c()
+    rc = library().fi_inpaint_image(ctx._h, side, side, _ptr(f, torch.uint8, side * side, "f", d),
+                                    mask_u8.ctypes.data_as(ctypes.c_void_p),
+                                    _ptr(g, torch.float64, m, "g", d),
+                                    ctypes.c_void_p(u.data_ptr()), ctypes.byref(o),
+                                    ctypes.byref(st))
+    _check(rc, "fi_inpaint_image")
+    return u, _stats(st)
 
 
 def grow_mask(ctx: Context, side: int, f, mask0, k_add: int, rounds: int,

@@ -558,6 +558,26 @@ int fi_inpaint(fi_mesh* M, const uint8_t* f_dev, const double* g_dev, double* u_
   return FI_OK;
 }
 
+int fi_inpaint_image(fi_ctx* ctx, int width, int height, const uint8_t* f_dev,
+                     const uint8_t* mask_u8_host, const double* g_dev, double* u_dev,
+                     const fi_solve_opts* opts, fi_solve_stats* stats) {
+  if (!ctx || !mask_u8_host) return fail(FI_E_INVALID, "ctx or mask is NULL");
+  if (width < 1 || height < 1) return fail(FI_E_INVALID, "bad image size");
+  std::vector<int32_t> idx;
+  const int64_t P = (int64_t)width * height;
+  for (int64_t p = 0; p < P; ++p)
+    if (mask_u8_host[p]) idx.push_back((int32_t)p);
+  fi_mesh* M = nullptr;
+  int rc = fi_mesh_build(ctx, width, height, idx.data(), (int64_t)idx.size(), &M);
+  if (rc) return rc;
+  rc = fi_inpaint(M, f_dev, g_dev, u_dev, opts, stats);
+  std::string keep = g_last_error;
+  if (rc == FI_OK || rc == FI_E_NO_CONVERGENCE) (void)hipStreamSynchronize(ctx->stream);
+  free_mesh(M);
+  g_last_error = keep;
+  return rc;
+}
+
 int fi_vertex_values(fi_mesh* M, double* u_vertex_dev) {
   int rc = check_mesh(M);
   if (rc) return rc;

@@ -204,6 +204,7 @@ struct fi_mesh {
   double* d_tr = nullptr;  // P: r
   double* d_tq = nullptr;  // P: q
   double* d_tsc = nullptr; // CGLS scalars (see Cgls)
+  double* d_wsqrt = nullptr; // P: IRLS weights^(1/2) (L1 tonal optimisation, first use)
 
   // mask-growth workspace (device, allocated on first use)
   void* d_topk = nullptr;
@@ -253,7 +254,9 @@ int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uin
 int raster_blocks(const fi_mesh* M);
 // Owner map and per-triangle pixel lists (geometry only; once per mesh).
 int build_pixel_maps(fi_mesh* M);
-int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart);
+// t = R^T r, or R^T (w r) when w is given (weighted least squares).
+int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart,
+                            const double* w = nullptr);
 // Per triangle: total error of its pixels, and its empty pixel of largest
 // error (-1 if none); in_mask holds one byte per pixel.
 int launch_tri_best(fi_mesh* M, const double* e, const uint8_t* in_mask, double* tri_err,
@@ -268,7 +271,15 @@ int launch_axpy_ratio(fi_mesh* M, int64_t n, const double* num, const double* de
                       const double* x, double* y);
 int launch_xpby_ratio(fi_mesh* M, int64_t n, const double* x, const double* num, const double* den,
                       double* y);
-int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r);
+// r = f - u, or w (f - u) when w is given.
+int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r,
+                          const double* w = nullptr);
+int launch_scale(fi_mesh* M, int64_t n, const double* w, double* x);  // x *= w
+// IRLS weights w^(1/2) = sqrt(1 / max(|f - u|, eps)) per pixel.
+int launch_irls_weights(fi_mesh* M, const uint8_t* f, const double* u, double eps,
+                        double* wsqrt);
+// sum |u - f| into *out_dev (fixed-order reduction).
+int launch_abs_err(fi_mesh* M, const double* u, const uint8_t* f, double* out_dev);
 
 // Solver pieces (solver.hip).
 constexpr int kMaxEll = 8;
@@ -318,10 +329,12 @@ int solve_poll(fi_mesh* M, int epoch, fi_solve_stats* stats, int* done);
 struct Cgls {
   enum Seg : int { kInpaint = 0, kAdjoint = 1, kApplyP = 2, kFinal = 3, kDone = 4 };
   // device scalar slots in d_tsc
-  enum : int { kScRR0 = 0, kScGamma = 1 /* and 2, by iteration parity */, kScQQ = 3, kScSSE = 4 };
+  enum : int { kScRR0 = 0, kScGamma = 1 /* and 2, by iteration parity */, kScQQ = 3, kScSSE = 4,
+               kScAbs = 5 /* sum |B g - f| (L1 optimisation) */ };
   fi_mesh* M = nullptr;
   const uint8_t* f = nullptr;  // device image
   double* g = nullptr;         // device, m: in the start (if start_from_g), out g
+  const double* wsqrt = nullptr;  // device, P: weights^(1/2) (weighted least squares), or none
   bool start_from_g = false;
   int k = 0;                   // B p products applied
   Seg seg = kInpaint;

@@ -643,12 +643,15 @@ __global__ __launch_bounds__(kBlock) void k_err_px(int64_t P, const double* __re
 
 // Transposed interpolation, one thread per triangle over its pixel list (in
 // ascending pixel order, as the leaf-major pass adds them).
+// WEIGHTED: the residual is scaled by w per pixel first (R^T (w r)).
+template <bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_interp_T_tri(int64_t T, int logN,
                                                          const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ px,
                                                          const int32_t* __restrict__ tri,
                                                          const int32_t* __restrict__ vxy,
                                                          const double* __restrict__ r,
+                                                         const double* __restrict__ w,
                                                          double* __restrict__ tpart) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= T) return;
@@ -666,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_T_tri(int64_t T, int logN,
     const int oa = (bx - x) * (cy - y) - (by - y) * (cx - x);
     const int ob = (cx - x) * (ay - y) - (cy - y) * (ax - x);
     const int oc = (ax - x) * (by - y) - (ay - y) * (bx - x);
-    const double rv = r[p];
+    const double rv = WEIGHTED ? r[p] * w[p] : r[p];
     Sa += ((double)oa * ia) * rv;
     Sb += ((double)ob * ia) * rv;
     Sc += ((double)oc * ia) * rv;
@@ -815,6 +818,45 @@ __global__ __launch_bounds__(kBlock) void k_pixel_residual(int64_t P, const uint
                                                            double* __restrict__ r) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < P) r[i] = (double)f[i] - u[i];
+}
+
+// Weighted residual r = w (f - u).
+__global__ __launch_bounds__(kBlock) void k_pixel_residual_w(int64_t P,
+                                                             const uint8_t* __restrict__ f,
+                                                             const double* __restrict__ u,
+                                                             const double* __restrict__ w,
+                                                             double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < P) r[i] = w[i] * ((double)f[i] - u[i]);
+}
+
+// x *= w elementwise.
+__global__ __launch_bounds__(kBlock) void k_scale(int64_t n, const double* __restrict__ w,
+                                                  double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = w[i] * x[i];
+}
+
+// IRLS weights: w^(1/2) = sqrt(1 / max(|f - u|, eps)).
+__global__ __launch_bounds__(kBlock) void k_irls_weights(int64_t P, const uint8_t* __restrict__ f,
+                                                         const double* __restrict__ u,
+                                                         double eps,
+                                                         double* __restrict__ wsqrt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < P) wsqrt[i] = sqrt(1.0 / fmax(fabs((double)f[i] - u[i]), eps));
+}
+
+// Per-block partial sums of |u - f| (grid-stride, like k_err_px).
+__global__ __launch_bounds__(kBlock) void k_abs_err(int64_t P, const double* __restrict__ u,
+                                                    const uint8_t* __restrict__ f,
+                                                    double* __restrict__ partial) {
+  __shared__ double lds[4];
+  double acc[1] = {0.0};
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * kBlock)
+    acc[0] += fabs(u[p] - (double)f[p]);
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
 }
 
 }  // namespace
@@ -1059,9 +1101,15 @@ int launch_tri_best(fi_mesh* M, const double* e, const uint8_t* in_mask, double*
   return FI_OK;
 }
 
-int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart) {
-  hipLaunchKernelGGL(k_interp_T_tri, dim3(grid_for(M->T)), dim3(kBlock), 0, M->ctx->stream, M->T,
-                     M->host.levels, M->d_tri_px_ptr, M->d_tri_px, M->d_tri, M->d_vxy, r, tpart);
+int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart, const double* w) {
+  if (w)
+    hipLaunchKernelGGL(k_interp_T_tri<true>, dim3(grid_for(M->T)), dim3(kBlock), 0,
+                       M->ctx->stream, M->T, M->host.levels, M->d_tri_px_ptr, M->d_tri_px,
+                       M->d_tri, M->d_vxy, r, w, tpart);
+  else
+    hipLaunchKernelGGL(k_interp_T_tri<false>, dim3(grid_for(M->T)), dim3(kBlock), 0,
+                       M->ctx->stream, M->T, M->host.levels, M->d_tri_px_ptr, M->d_tri_px,
+                       M->d_tri, M->d_vxy, r, (const double*)nullptr, tpart);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }
@@ -1112,11 +1160,37 @@ int launch_xpby_ratio(fi_mesh* M, int64_t n, const double* x, const double* num,
   return FI_OK;
 }
 
-int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r) {
-  hipLaunchKernelGGL(k_pixel_residual, dim3(grid_for(M->P)), dim3(kBlock), 0, M->ctx->stream,
-                     M->P, f, u, r);
+int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double* r,
+                          const double* w) {
+  if (w)
+    hipLaunchKernelGGL(k_pixel_residual_w, dim3(grid_for(M->P)), dim3(kBlock), 0,
+                       M->ctx->stream, M->P, f, u, w, r);
+  else
+    hipLaunchKernelGGL(k_pixel_residual, dim3(grid_for(M->P)), dim3(kBlock), 0, M->ctx->stream,
+                       M->P, f, u, r);
   FI_LAUNCH_CHECK();
   return FI_OK;
+}
+
+int launch_scale(fi_mesh* M, int64_t n, const double* w, double* x) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n, w, x);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_irls_weights(fi_mesh* M, const uint8_t* f, const double* u, double eps,
+                        double* wsqrt) {
+  hipLaunchKernelGGL(k_irls_weights, dim3(grid_for(M->P)), dim3(kBlock), 0, M->ctx->stream, M->P,
+                     f, u, eps, wsqrt);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_abs_err(fi_mesh* M, const double* u, const uint8_t* f, double* out_dev) {
+  hipLaunchKernelGGL(k_abs_err, dim3(raster_blocks(M)), dim3(kBlock), 0, M->ctx->stream, M->P, u,
+                     f, M->d_rpart);
+  FI_LAUNCH_CHECK();
+  return launch_reduce(M, M->d_rpart, raster_blocks(M), 1, out_dev);
 }
 
 }  // namespace fi

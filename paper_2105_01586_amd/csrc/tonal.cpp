@@ -39,7 +39,7 @@ int Cgls::pre() {
       if (!start_from_g && (rc = launch_gather_mask(M, f, g))) return rc;
       return launch_lift(M, g, M->d_b64);
     case kAdjoint:  // B^T r: t = R^T r, solve with t_F
-      if ((rc = launch_raster_transpose(M, M->d_tr, M->d_tpart))) return rc;
+      if ((rc = launch_raster_transpose(M, M->d_tr, M->d_tpart, wsqrt))) return rc;
       if ((rc = launch_gather_vertex(M, M->d_tpart, M->d_tF, M->d_tD))) return rc;
       FI_HIP_TRY(hipMemcpyAsync(M->d_b64, M->d_tF, (size_t)M->n * sizeof(double),
                                 hipMemcpyDeviceToDevice, M->ctx->stream));
@@ -66,7 +66,7 @@ int Cgls::post() {
       if ((rc = launch_vertex_values(M, M->d_x64, g, M->d_uvert)) ||
           (rc = launch_raster(M, M->d_uvert, nullptr, nullptr, q, nullptr, nullptr, nullptr,
                               nullptr)) ||
-          (rc = launch_pixel_residual(M, f, q, r)))
+          (rc = launch_pixel_residual(M, f, q, r, wsqrt)))
         return rc;
       return launch_dot(M, r, r, P, sc + kScRR0);
     case kAdjoint:  // s = t_D - K_DF y; first: p = s; later: p = s + (gamma_k / gamma_k-1) p
@@ -82,6 +82,7 @@ int Cgls::post() {
       if ((rc = launch_vertex_values(M, M->d_x64, p, M->d_uvert)) ||
           (rc = launch_raster(M, M->d_uvert, nullptr, nullptr, q, nullptr, nullptr, nullptr,
                               nullptr)) ||
+          (wsqrt && (rc = launch_scale(M, P, wsqrt, q))) ||
           (rc = launch_dot(M, q, q, P, sc + kScQQ)))
         return rc;
       const double* gam = gamma_slot(M, k);
@@ -303,5 +304,89 @@ extern "C" int fi_tonal_opt_rgb(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
   if (stats)
     for (int c = 0; c < C; ++c) stats[c] = ts[c];
   if (!ok) return fail(FI_E_NO_CONVERGENCE, "tonal optimisation of a channel reached the cap");
+  return FI_OK;
+}
+
+extern "C" void fi_l1_opts_default(fi_l1_opts* o) {
+  if (!o) return;
+  fi_solve_opts_default(&o->inner);
+  o->eps = 0.5;
+  o->irls_iters = 8;
+  o->cgls_iters = 20;
+  o->start_from_g = 0;
+}
+
+extern "C" int fi_tonal_opt_l1(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
+                               const fi_l1_opts* opts, fi_l1_stats* stats, double* mae_hist) {
+  if (!M || !M->ctx) return fail(FI_E_INVALID, "mesh is NULL");
+  if (!f_dev || !g_dev) return fail(FI_E_INVALID, "f_dev and g_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  fi_l1_opts o;
+  fi_l1_opts_default(&o);
+  if (opts) {
+    o = *opts;
+    if (!(o.eps > 0)) return fail(FI_E_INVALID, "eps must be positive");
+    if (o.irls_iters < 0 || o.cgls_iters < 0) return fail(FI_E_INVALID, "negative iteration count");
+    fi_solve_opts d;
+    fi_solve_opts_default(&d);
+    if (o.inner.rtol <= 0) o.inner.rtol = d.rtol;
+    if (o.inner.inner_rtol <= 0 || o.inner.inner_rtol >= 1) o.inner.inner_rtol = d.inner_rtol;
+    if (o.inner.max_inner <= 0) o.inner.max_inner = d.max_inner;
+    if (o.inner.max_refine <= 0) o.inner.max_refine = d.max_refine;
+    if (o.inner.check_every <= 0) o.inner.check_every = d.check_every;
+  }
+  Cgls c;
+  c.M = M;
+  c.f = f_dev;
+  c.g = g_dev;
+  int rc = c.alloc();
+  if (rc) return rc;
+  if (!M->d_wsqrt && (rc = device_alloc(M, (void**)&M->d_wsqrt, (size_t)M->P * sizeof(double))))
+    return rc;
+  if (!o.start_from_g && (rc = launch_gather_mask(M, f_dev, g_dev))) return rc;
+  fi_l1_stats st{};
+  auto run = [&](Cgls::Seg seg) -> int {
+    c.seg = seg;
+    int r = c.pre();
+    if (r) return r;
+    fi_solve_stats ss{};
+    r = solve_free(M, &o.inner, &ss);
+    st.inner_iterations += ss.iterations;
+    if (r) return r;
+    if (ss.status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");
+    return c.post();
+  };
+  // B g and its errors (q = B g stays in the CGLS workspace for the weights)
+  auto evaluate = [&](double* mae, double* mse) -> int {
+    c.wsqrt = nullptr;
+    int r = run(Cgls::kFinal);
+    if (r) return r;
+    if ((r = launch_abs_err(M, M->d_tq, f_dev, M->d_tsc + Cgls::kScAbs))) return r;
+    double sc[8];
+    if ((r = read_scalars(M, sc, 8))) return r;
+    *mae = sc[Cgls::kScAbs] / (double)M->P;
+    *mse = sc[Cgls::kScSSE] / (double)M->P;
+    return FI_OK;
+  };
+  double mae = 0.0, mse = 0.0;
+  if ((rc = evaluate(&mae, &mse))) return rc;
+  st.mae_initial = mae;
+  if (mae_hist) mae_hist[0] = mae;
+  for (int k = 0; k < o.irls_iters; ++k) {
+    if ((rc = launch_irls_weights(M, f_dev, M->d_tq, o.eps, M->d_wsqrt))) return rc;
+    c.wsqrt = M->d_wsqrt;
+    c.start_from_g = true;
+    c.k = 0;
+    if ((rc = run(Cgls::kInpaint)) || (rc = run(Cgls::kAdjoint))) return rc;
+    for (int j = 0; j < o.cgls_iters; ++j)
+      if ((rc = run(Cgls::kApplyP)) || (rc = run(Cgls::kAdjoint))) return rc;
+    if ((rc = evaluate(&mae, &mse))) return rc;
+    if (mae_hist) mae_hist[k + 1] = mae;
+    ++st.irls_iters;
+  }
+  st.mae_final = mae;
+  st.mse_final = mse;
+  st.status = FI_OK;
+  if (stats) *stats = st;
   return FI_OK;
 }

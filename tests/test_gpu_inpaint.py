@@ -127,6 +127,18 @@ def test_given_g_and_constant(ctx):
     assert np.max(np.abs(u.cpu().numpy() - pr.B(gv))) <= PIX_TOL
 
 
+def test_inpaint_image_one_shot(ctx):
+    """fi_inpaint_image (mask as a bitmap, mesh built and freed inside) gives
+    the mesh path's bits."""
+    side, mask, f = case("n256_k2000")
+    bitmap = np.zeros(side * side, np.uint8)
+    bitmap[mask] = 1
+    u1, st1 = fi.inpaint_image(ctx, dev(f), bitmap)
+    M = gpu_mesh(ctx, "n256_k2000")
+    u2, st2 = M.inpaint(f=dev(f))
+    assert torch.equal(u1, u2) and st1["iterations"] == st2["iterations"]
+
+
 def test_reassemble_is_identical(ctx):
     M = gpu_mesh(ctx, "n128_k300")
     before = M.export_csr()
