@@ -33,7 +33,9 @@
 //
 // All loads of an iteration that do not depend on alpha and beta (the
 // previous partial sums, the thread's row, its neighbours' values) are
-// issued before the block reduction. When the rows fit in at most kMaxGrid
+// issued before the block reduction. Block sums use DPP within each wave and
+// one barrier (two per launch), with the two sums of a launch in separate LDS
+// regions. When the rows fit in at most kMaxGrid
 // blocks, every block re-reduces the previous launch's per-block partial sums
 // in a fixed order; larger systems put a one-block reduction launch between
 // steps. No atomics: results are reproducible bit for bit. Each row's r, s,
@@ -312,7 +314,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     red[1] = A.part_in[1];
     red[2] = A.part_in[2];
   } else {
-    block_sum_w<3, BS / 64>(red, lds);
+    block_sum_once<3, BS / 64>(red, lds);
   }
   // A launch queued after the solve has ended leaves here (the phase is
   // uniform). Testing it before the reduction above would put the record
@@ -378,7 +380,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
       v[1] = (double)zi * (double)acc;
       v[2] = (double)ri * (double)ri;
     }
-    block_sum_w<3, BS / 64>(v, lds);
+    block_sum_once<3, BS / 64>(v, lds + 3 * (BS / 64));
     store_partials(A.part_out, lb, v);
     if (writer)
       put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kIter, 0, Rin.total, Rin.ninner + 1,
@@ -432,7 +434,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
       A.r64[i] = ri;
       v[0] = ri * ri;
     }
-    block_sum_w<3, BS / 64>(v, lds);
+    block_sum_once<3, BS / 64>(v, lds + 3 * (BS / 64));
     store_partials(A.part_out, lb, v);
     if (writer)
       put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kInit, iter, Rin.total + iter,
@@ -475,7 +477,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     v[1] = (double)zi * (double)acc;
     v[2] = (double)ri * (double)ri;
   }
-  block_sum_w<3, BS / 64>(v, lds);
+  block_sum_once<3, BS / 64>(v, lds + 3 * (BS / 64));
   store_partials(A.part_out, lb, v);
   if (writer)
     put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kIter, iter + 1, Rin.total, Rin.ninner,
@@ -485,7 +487,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
 
 template <typename T, int W, bool SUMMED, int BS>
 __global__ __launch_bounds__(BS) void k_step(StepArgs<T> A) {
-  __shared__ double lds[3 * (BS / 64)];
+  __shared__ double lds[6 * (BS / 64)];
   step_body<T, W, SUMMED, BS>(A, logical_block(), lds);
 }
 
@@ -583,7 +585,7 @@ static_assert(sizeof(BatchArgs) <= 4096, "kernel arguments of a batched step");
 
 template <int W, bool SUMMED, int BS>
 __global__ __launch_bounds__(BS) void k_step_batch(BatchArgs B) {
-  __shared__ double lds[3 * (BS / 64)];
+  __shared__ double lds[6 * (BS / 64)];
   const int lb = logical_block();
   int j = 0;  // slot of this block (uniform: scalar registers)
 #pragma unroll
@@ -616,7 +618,7 @@ struct MultiArgs {
 
 template <typename T, int W, bool SUMMED, int BS>
 __global__ __launch_bounds__(BS) void k_step_multi(MultiArgs<T> B) {
-  __shared__ double lds[3 * (BS / 64)];
+  __shared__ double lds[6 * (BS / 64)];
   const int nr = B.nrhs;
   const int per = (int)(gridDim.x / nr) >> 3;  // row blocks per XCD slab
   const int k = blockIdx.x >> 3;
