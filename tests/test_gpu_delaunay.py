@@ -219,3 +219,24 @@ def test_paper_loop_on_delaunay(ctx):
         valid_choice(added, e, pr.rast.owner, pr.mesh.T, mask, k, delta)
         start += k
     assert mse[-1] < mse[0]
+
+
+def test_separate_reduction_on_delaunay(ctx, monkeypatch):
+    """The CSR step with the separate partial-sum reduction (the launch shape
+    of large systems), single and three-channel, on the Delaunay mesh."""
+    side, mask, unk, f = case("d256")
+    monkeypatch.setenv("FI_CG_LARGE", "1")
+    M = mesh(ctx, "d256")
+    monkeypatch.delenv("FI_CG_LARGE")
+    assert M.large_mode()
+    u, st = M.inpaint(f=torch.from_numpy(f.copy()).cuda())
+    want = problem("d256").inpaint(f)
+    assert np.max(np.abs(u.cpu().numpy() - want)) <= 1e-6
+    f3 = synth.make_image_rgb(25, side, side, 16, 4).reshape(3, -1)
+    u3, st3 = M.inpaint_rgb(f=torch.from_numpy(f3.ravel().copy()).cuda())
+    u3 = u3.cpu().numpy().reshape(3, -1)
+    for c in range(3):
+        uc, sc = M.inpaint(f=torch.from_numpy(f3[c].copy()).cuda())
+        assert np.array_equal(u3[c], uc.cpu().numpy())
+        assert st3[c]["iterations"] == sc["iterations"]
+    M.close()
