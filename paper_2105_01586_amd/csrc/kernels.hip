@@ -36,46 +36,150 @@ __device__ __forceinline__ int stiffness_row(int v, const int32_t* __restrict__ 
   int cnt = 0;
   double d = 0.0;
   const int64_t xa = vxy[2 * v], ya = vxy[2 * v + 1];
-  const int e1 = vt_ptr[v + 1];
-  for (int e = vt_ptr[v]; e < e1; ++e) {
-    const int code = vt_idx[e];
-    const int t = code / 3;
-    const int k = code - 3 * t;
-    const int b = tri[3 * t + (k + 1) % 3];
-    const int c = tri[3 * t + (k + 2) % 3];
-    const int64_t xb = vxy[2 * b], yb = vxy[2 * b + 1];
-    const int64_t xc = vxy[2 * c], yc = vxy[2 * c + 1];
-    const int64_t ba = yb - yc, ca = xc - xb;
-    const int64_t bb = yc - ya, cb = xa - xc;
-    const int64_t bc = ya - yb, cc = xb - xa;
-    const int64_t twoA = (xb - xa) * (yc - ya) - (yb - ya) * (xc - xa);
-    const double inv = 1.0 / (2.0 * (double)twoA);
-    d += (double)(ba * ba + ca * ca) * inv;
-    const double wb = (double)(ba * bb + ca * cb) * inv;
-    const double wc = (double)(ba * bc + ca * cc) * inv;
-    int fb = -1, fc = -1;
-    for (int q = 0; q < cnt; ++q) {
-      if (nb[q] == b) fb = q;
-      if (nb[q] == c) fc = q;
+  const int e0 = vt_ptr[v], e1 = vt_ptr[v + 1];
+  // Quadtree rows (at most kMaxIncident triangles): every index and
+  // coordinate is loaded before the arithmetic, three dependent rounds in
+  // all instead of three per triangle. Other meshes walk the list.
+  constexpr bool PRE = NB == 2 * kMaxIncident;
+  constexpr int MT = PRE ? kMaxIncident : 1;
+  int pb[MT], pc[MT];
+  int64_t pxb[MT], pyb[MT], pxc[MT], pyc[MT];
+  if constexpr (PRE) {
+    const int last = e1 - 1;  // every vertex has a triangle: clamped loads stay in the list
+    int code[MT];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) code[q] = vt_idx[min(e0 + q, last)];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      const int t = code[q] / 3;
+      const int k = code[q] - 3 * t;
+      pb[q] = tri[3 * t + (k + 1) % 3];
+      pc[q] = tri[3 * t + (k + 2) % 3];
     }
-    if (fb >= 0) w[fb] += wb; else { nb[cnt] = b; w[cnt] = wb; ++cnt; }
-    if (fc >= 0) w[fc] += wc; else { nb[cnt] = c; w[cnt] = wc; ++cnt; }
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      pxb[q] = vxy[2 * pb[q]];
+      pyb[q] = vxy[2 * pb[q] + 1];
+      pxc[q] = vxy[2 * pc[q]];
+      pyc[q] = vxy[2 * pc[q] + 1];
+    }
   }
-  // drop exact zeros (hypotenuse couplings), then insertion sort by id
-  int k2 = 0;
-  for (int q = 0; q < cnt; ++q) {
-    if (w[q] != 0.0) { nb[k2] = nb[q]; w[k2] = w[q]; ++k2; }
+  // One incident triangle (b, c its other two corners), in list order: the
+  // weights of b and c join their slots, or open new ones.
+  if constexpr (PRE) {
+    // Slots addressed only by compile-time indices (predicated updates), so
+    // no lane-dependent register indexing; then a sorting network.
+    int32_t id[NB];
+    double wv[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      id[q] = 0x7fffffff;
+      wv[q] = 0.0;
+    }
+    auto put = [&](int32_t u, double wu) {
+      bool found = false;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (id[q] == u) {
+          wv[q] += wu;
+          found = true;
+        }
+      }
+      if (!found) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (q == cnt) {
+            id[q] = u;
+            wv[q] = wu;
+          }
+        }
+        ++cnt;
+      }
+    };
+    const int ne = e1 - e0;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (t < ne) {
+        const int64_t xb = pxb[t], yb = pyb[t], xc = pxc[t], yc = pyc[t];
+        const int64_t ba = yb - yc, ca = xc - xb;
+        const int64_t bb = yc - ya, cb = xa - xc;
+        const int64_t bc = ya - yb, cc = xb - xa;
+        const int64_t twoA = (xb - xa) * (yc - ya) - (yb - ya) * (xc - xa);
+        const double inv = 1.0 / (2.0 * (double)twoA);
+        d += (double)(ba * ba + ca * ca) * inv;
+        put(pb[t], (double)(ba * bb + ca * cb) * inv);
+        put(pc[t], (double)(ba * bc + ca * cc) * inv);
+      }
+    }
+    // drop exact zeros (hypotenuse couplings), sort by id (odd-even
+    // transposition network; ids are distinct)
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (wv[q] == 0.0) id[q] = 0x7fffffff;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+#pragma unroll
+      for (int q = r & 1; q + 1 < NB; q += 2) {
+        const bool sw = id[q] > id[q + 1];
+        const int32_t i0 = sw ? id[q + 1] : id[q], i1 = sw ? id[q] : id[q + 1];
+        const double w0 = sw ? wv[q + 1] : wv[q], w1 = sw ? wv[q] : wv[q + 1];
+        id[q] = i0;
+        id[q + 1] = i1;
+        wv[q] = w0;
+        wv[q + 1] = w1;
+      }
+    }
+    int k2 = 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      nb[q] = id[q];
+      w[q] = wv[q];
+      k2 += id[q] != 0x7fffffff;
+    }
+    diag = d;
+    return k2;
+  } else {
+    auto add = [&](int b, int c, int64_t xb, int64_t yb, int64_t xc, int64_t yc) {
+      const int64_t ba = yb - yc, ca = xc - xb;
+      const int64_t bb = yc - ya, cb = xa - xc;
+      const int64_t bc = ya - yb, cc = xb - xa;
+      const int64_t twoA = (xb - xa) * (yc - ya) - (yb - ya) * (xc - xa);
+      const double inv = 1.0 / (2.0 * (double)twoA);
+      d += (double)(ba * ba + ca * ca) * inv;
+      const double wb = (double)(ba * bb + ca * cb) * inv;
+      const double wc = (double)(ba * bc + ca * cc) * inv;
+      int fb = -1, fc = -1;
+      for (int q = 0; q < cnt; ++q) {
+        if (nb[q] == b) fb = q;
+        if (nb[q] == c) fc = q;
+      }
+      if (fb >= 0) w[fb] += wb; else { nb[cnt] = b; w[cnt] = wb; ++cnt; }
+      if (fc >= 0) w[fc] += wc; else { nb[cnt] = c; w[cnt] = wc; ++cnt; }
+    };
+    for (int e = e0; e < e1; ++e) {
+      const int code = vt_idx[e];
+      const int t = code / 3;
+      const int k = code - 3 * t;
+      const int b = tri[3 * t + (k + 1) % 3];
+      const int c = tri[3 * t + (k + 2) % 3];
+      add(b, c, vxy[2 * b], vxy[2 * b + 1], vxy[2 * c], vxy[2 * c + 1]);
+    }
+    // drop exact zeros (hypotenuse couplings), then insertion sort by id
+    int k2 = 0;
+    for (int q = 0; q < cnt; ++q) {
+      if (w[q] != 0.0) { nb[k2] = nb[q]; w[k2] = w[q]; ++k2; }
+    }
+    for (int q = 1; q < k2; ++q) {
+      const int32_t kn = nb[q];
+      const double kw = w[q];
+      int r = q - 1;
+      while (r >= 0 && nb[r] > kn) { nb[r + 1] = nb[r]; w[r + 1] = w[r]; --r; }
+      nb[r + 1] = kn;
+      w[r + 1] = kw;
+    }
+    diag = d;
+    return k2;
   }
-  for (int q = 1; q < k2; ++q) {
-    const int32_t kn = nb[q];
-    const double kw = w[q];
-    int r = q - 1;
-    while (r >= 0 && nb[r] > kn) { nb[r + 1] = nb[r]; w[r + 1] = w[r]; --r; }
-    nb[r + 1] = kn;
-    w[r + 1] = kw;
-  }
-  diag = d;
-  return k2;
 }
 
 // Rows of the free vertices: count entries of K_FF (off-diagonal) and K_FD.
@@ -93,8 +197,11 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_count(
   double d;
   const int k = stiffness_row<NB>(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int cf = 0, cd = 0;
-  for (int q = 0; q < k; ++q) {
-    if (vmap[nb[q]] >= 0) ++cf; else ++cd;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (q < k) {
+      if (vmap[nb[q]] >= 0) ++cf; else ++cd;
+    }
   }
   cnt_ff[i] = cf;
   cnt_fd[i] = cd;
@@ -117,17 +224,20 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_fill(
   double d;
   const int k = stiffness_row<NB>(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int pf = ff_ptr[i], pd = fd_ptr[i];
-  for (int q = 0; q < k; ++q) {
-    const int32_t mv = vmap[nb[q]];
-    if (mv >= 0) {
-      ff_col[pf] = mv;
-      ff_val64[pf] = w[q];
-      ff_val32[pf] = (float)w[q];
-      ++pf;
-    } else {
-      fd_col[pd] = -mv - 1;
-      fd_val[pd] = w[q];
-      ++pd;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (q < k) {
+      const int32_t mv = vmap[nb[q]];
+      if (mv >= 0) {
+        ff_col[pf] = mv;
+        ff_val64[pf] = w[q];
+        ff_val32[pf] = (float)w[q];
+        ++pf;
+      } else {
+        fd_col[pd] = -mv - 1;
+        fd_val[pd] = w[q];
+        ++pd;
+      }
     }
   }
   diag64[i] = d;
@@ -150,7 +260,9 @@ __global__ __launch_bounds__(kBlock) void k_asm_mask_count(
   double d;
   const int k = stiffness_row<NB>(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int cf = 0;
-  for (int q = 0; q < k; ++q) cf += vmap[nb[q]] >= 0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    if (q < k) cf += vmap[nb[q]] >= 0;
   cnt_df[j] = cf;
 }
 
@@ -168,9 +280,12 @@ __global__ __launch_bounds__(kBlock) void k_asm_mask_fill(
   double d;
   const int k = stiffness_row<NB>(mask_vids[j], vxy, tri, vt_ptr, vt_idx, nb, w, d);
   int p = df_ptr[j];
-  for (int q = 0; q < k; ++q) {
-    const int32_t mv = vmap[nb[q]];
-    if (mv >= 0) { df_col[p] = mv; df_val[p] = w[q]; ++p; }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (q < k) {
+      const int32_t mv = vmap[nb[q]];
+      if (mv >= 0) { df_col[p] = mv; df_val[p] = w[q]; ++p; }
+    }
   }
 }
 
@@ -746,7 +861,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_vertex(int V, const int32_t* 
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   double acc = 0.0;
-  for (int e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) acc += tpart[vt_idx[e]];
+  const int e0 = vt_ptr[v], e1 = vt_ptr[v + 1];
+  if (e1 - e0 <= kMaxIncident) {
+    // all loads first (quadtree lists are this short), then the sum in order
+    double t[kMaxIncident];
+#pragma unroll
+    for (int q = 0; q < kMaxIncident; ++q) t[q] = tpart[vt_idx[min(e0 + q, e1 - 1)]];
+#pragma unroll
+    for (int q = 0; q < kMaxIncident; ++q)
+      if (e0 + q < e1) acc += t[q];
+  } else {
+    for (int e = e0; e < e1; ++e) acc += tpart[vt_idx[e]];
+  }
   const int32_t mv = vmap[v];
   if (mv >= 0) tF[mv] = acc; else tD[-mv - 1] = acc;
 }
