@@ -89,6 +89,9 @@ typedef struct fi_tonal_opts {
                           < 0: 1e-8 */
   int max_outer;       /* cap on outer CG iterations */
   int start_from_g;    /* 0: start from g0 = f on the mask; 1: from g_dev */
+  int cold_adjoint;    /* 0: each adjoint solve starts from the previous one's
+                          solution (same stopping test, fewer iterations);
+                          1: from 0 */
 } fi_tonal_opts;
 
 typedef struct fi_tonal_stats {

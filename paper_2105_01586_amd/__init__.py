@@ -73,7 +73,7 @@ class _SolveStats(ctypes.Structure):
 
 class _TonalOpts(ctypes.Structure):
     _fields_ = [("inner", _SolveOpts), ("rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("start_from_g", ctypes.c_int)]
+                ("start_from_g", ctypes.c_int), ("cold_adjoint", ctypes.c_int)]
 
 
 class _TonalStats(ctypes.Structure):
@@ -265,10 +265,12 @@ class TonalOpts:
     rtol: float = 1e-8
     max_outer: int = 500
     start_from_g: bool = False
+    cold_adjoint: bool = False
 
     def c(self) -> _TonalOpts:
         inner = (self.inner or SolveOpts()).c()
-        return _TonalOpts(inner, self.rtol, self.max_outer, int(self.start_from_g))
+        return _TonalOpts(inner, self.rtol, self.max_outer, int(self.start_from_g),
+                          int(self.cold_adjoint))
 
 
 def _stats(s) -> dict:
@@ -486,7 +488,7 @@ class Mesh:
         o = opts or TonalOpts()
         if g is None:
             g = self._empty(self.m, torch.float64)
-            o = TonalOpts(o.inner, o.rtol, o.max_outer, False)
+            o = TonalOpts(o.inner, o.rtol, o.max_outer, False, o.cold_adjoint)
         co = o.c()
         st = _TonalStats()
         rc = library().fi_tonal_opt(self._h, _ptr(f, torch.uint8, self.P, "f", d),
@@ -550,7 +552,7 @@ class Mesh:
         o = opts or TonalOpts()
         if g is None:
             g = self._empty(3 * self.m, torch.float64)
-            o = TonalOpts(o.inner, o.rtol, o.max_outer, False)
+            o = TonalOpts(o.inner, o.rtol, o.max_outer, False, o.cold_adjoint)
         co = o.c()
         st = (_TonalStats * 3)()
         rc = library().fi_tonal_opt_rgb(self._h, _ptr(f, torch.uint8, 3 * self.P, "f", d),

@@ -312,6 +312,7 @@ void fi_tonal_opts_default(fi_tonal_opts* o) {
   o->rtol = 1e-8;
   o->max_outer = 500;
   o->start_from_g = 0;
+  o->cold_adjoint = 0;
 }
 
 const char* fi_last_error(void) { return g_last_error.c_str(); }

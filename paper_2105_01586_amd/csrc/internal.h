@@ -204,6 +204,7 @@ struct fi_mesh {
   double* d_tr = nullptr;  // P: r
   double* d_tq = nullptr;  // P: q
   double* d_tsc = nullptr; // CGLS scalars (see Cgls)
+  double* d_ywarm = nullptr; // n: the last adjoint solve's solution (its next start)
   double* d_wsqrt = nullptr; // P: IRLS weights^(1/2) (L1 tonal optimisation, first use)
 
   // mask-growth workspace (device, allocated on first use)
@@ -285,7 +286,10 @@ int launch_abs_err(fi_mesh* M, const double* u, const uint8_t* f, double* out_de
 constexpr int kMaxEll = 8;
 int solver_setup(fi_mesh* M);      // after assembly: ELL packing, launch shape
 void solver_release(fi_mesh* M);   // events and the host mirror
-int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats);
+// Solves K_FF x = b64 from x0 (device, n doubles, not a buffer of the mesh's
+// solver; NULL: from 0), to the same relative residual ||b - K x|| / ||b||.
+int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats,
+               const double* x0 = nullptr);
 int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms);
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision);
 int64_t cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision);
@@ -299,7 +303,9 @@ int solver_channel_setup(fi_mesh* S, const fi_mesh* M);
 // per iteration whose blocks for the same rows share an XCD (and so the
 // matrix in its L2); each channel's result and stats are those of its own
 // solve_free, bit for bit.
-int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats);
+// x0: NULL, or a start for each channel (entries may be NULL).
+int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats,
+                const double* const* x0 = nullptr);
 int time_multi_kernel(fi_mesh* const* ch, int nc, int precision, int reps, double* ms);
 // The mesh and its channel views 1..nc-1 (created on first use) into ch.
 int channel_views(fi_mesh* M, int nc, fi_mesh** ch);
@@ -316,7 +322,7 @@ struct BatchSlot {
 int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int count);
 // Start of an FP32 solve of K_FF x = b64 that the batch then steps; *epoch
 // identifies it in the host mirror.
-int solve_arm(fi_mesh* M, const fi_solve_opts* opts, int* epoch);
+int solve_arm(fi_mesh* M, const fi_solve_opts* opts, int* epoch, const double* x0 = nullptr);
 // Reads the host mirror of the solve `epoch`: *done = 1 once it has ended
 // (stats filled, d_x64 set to the result). Never blocks.
 int solve_poll(fi_mesh* M, int epoch, fi_solve_stats* stats, int* done);
@@ -338,6 +344,12 @@ struct Cgls {
   bool start_from_g = false;
   int k = 0;                   // B p products applied
   Seg seg = kInpaint;
+  // Start of the segment's solve (set by pre()): the adjoint solve starts
+  // from the previous adjoint solution, since r, and with it R^T r, changes
+  // less and less from one iteration to the next; other solves start at 0.
+  const double* x0 = nullptr;
+  bool use_warm = true;        // keep adjoint solutions as starts
+  bool warm = false;           // d_ywarm holds an adjoint solution
 
   int alloc();                 // tonal workspace (first use)
   int pre();                   // right-hand side of the segment's solve into b64

@@ -159,7 +159,7 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   add(4, 4); add(4, 8); add(4 * kRedMaxBlocks, 8); add(8, 8); add(2, 96); add(2 * 4 * grid, 8);
   add((int64_t)kMaxEll * ((n + 63) / 64 * 64), 4);
   // CGLS workspace and the request's buffers
-  add(m, 8); add(m, 8); add(P, 8); add(P, 8); add(8, 8);
+  add(m, 8); add(m, 8); add(P, 8); add(P, 8); add(n, 8); add(8, 8);
   add(P, 1); add(m, 8);
   (void)iters;
   return total;
@@ -404,7 +404,7 @@ int run_sequential(fi_server* S, Job* J) {
     int rc = J->c.pre();
     if (rc) return rc;
     fi_solve_stats st{};
-    rc = solve_free(M, &J->io, &st);
+    rc = solve_free(M, &J->io, &st, J->c.x0);
     J->inner_iterations += st.iterations;
     if (rc) return rc;
     if (st.status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");
@@ -423,7 +423,7 @@ int run_sequential(fi_server* S, Job* J) {
 int start_segment(fi_server* S, Job* J, int64_t it) {
   int rc = J->c.pre();
   if (rc) return rc;
-  if ((rc = solve_arm(J->M, &J->io, &J->epoch))) return rc;
+  if ((rc = solve_arm(J->M, &J->io, &J->epoch, J->c.x0))) return rc;
   J->solving = true;
   J->armed_at = it;
   (void)S;

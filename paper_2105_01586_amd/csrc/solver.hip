@@ -220,18 +220,37 @@ __device__ __forceinline__ void store_partials(double* part_out, int lb, double 
   }
 }
 
-// Start of a solve: x64 = 0, r64 = b, partial ||b||^2, first record.
+// Start of a solve: x64 = x0 (0 when x0 is NULL), r64 = b - K_FF x0 in
+// FP64, partial sums ||r64||^2 and ||b||^2, first record. The stopping test
+// stays relative to ||b|| whatever the start: a good x0 only saves
+// iterations. x0 must not alias x64 buffer a, r64 or b64.
 template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, Params* prm_out) {
+__global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, Params* prm_out,
+                                                    const double* __restrict__ x0) {
   __shared__ double lds[3 * (BS / 64)];
   double v[3] = {0.0, 0.0, 0.0};
   const int lb = logical_block();
   const int i = lb * BS + threadIdx.x;
   if (i < A.n) {
     const double bi = A.b64[i];
-    A.x64a[i] = 0.0;
-    A.r64[i] = bi;
-    v[0] = bi * bi;
+    double ri = bi, xi = 0.0;
+    if (x0) {
+      xi = x0[i];
+      double acc = A.diag64[i] * xi;
+      if (A.W > 0) {
+        for (int k = 0; k < A.W; ++k) {
+          const int32_t e = A.ell[(size_t)k * A.n_pad + i];
+          acc += ell_weight<double>(e) * x0[ell_col(e)];
+        }
+      } else {
+        for (int j = A.rowptr[i]; j < A.rowptr[i + 1]; ++j) acc += A.val64[j] * x0[A.col[j]];
+      }
+      ri = bi - acc;
+    }
+    A.x64a[i] = xi;
+    A.r64[i] = ri;
+    v[0] = ri * ri;
+    v[1] = bi * bi;
   }
   block_sum_w<3, BS / 64>(v, lds);
   store_partials(A.part_out, lb, v);
@@ -331,13 +350,20 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
   double v[3] = {0.0, 0.0, 0.0};
 
   if (phase == kInit) {
-    // red[0] = ||r64||^2 from the start or refinement launch
-    const double rnorm = sqrt(red[0]);
-    const double bnorm = Rin.ninner == 0 ? rnorm : Rin.bnorm;
+    // red[0] = ||r64||^2 from the start or refinement launch; the start
+    // launch also sends red[1] = ||b||^2
+    double rnorm = sqrt(red[0]);
+    const double bnorm = Rin.ninner == 0 ? sqrt(red[1]) : Rin.bnorm;
     int stagnant = Rin.stagnant;
     int next = 0;
     if (!isfinite(rnorm)) next = kDoneBad;
     else if (rnorm <= P.rtol * bnorm) next = kDoneOk;
+    else if (bnorm == 0.0 && Rin.ninner == 0) {
+      // b = 0 with a non-zero start: the solution is x = 0
+      if (live) (Rin.xp ? A.x64b : A.x64a)[i] = 0.0;
+      rnorm = 0.0;
+      next = kDoneOk;
+    }
     else if ((double)Rin.ninner >= P.max_refine) next = kDoneNoConv;
     else if (Rin.ninner > 0) {
       stagnant = rnorm > 0.5 * Rin.rnorm ? stagnant + 1 : 0;
@@ -799,7 +825,7 @@ int launch_step(fi_mesh* M, int par, int force) {
 }
 
 template <typename T>
-int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch) {
+int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0 = nullptr) {
   StepArgs<T> A = make_args<T>(M, 1, 0);  // writes record and partials of slot 0
   Params prm{};
   prm.rtol = o->rtol;
@@ -809,7 +835,7 @@ int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch) {
   prm.mixed = sizeof(T) == sizeof(float) ? 1.0 : 0.0;
   prm.epoch = epoch;
   Params* pout = (Params*)M->d_prm;
-  void* args[3] = {&A, &prm, &pout};
+  void* args[4] = {&A, &prm, &pout, &x0};
   FI_HIP_TRY(hipLaunchKernel(start_kernel<T>(M), dim3(M->cg_grid), dim3(M->cg_bs), args, 0,
                              M->ctx->stream));
   if (M->large_mode) return launch_reduce_after(M, 1);
@@ -854,10 +880,10 @@ int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
 constexpr int kAhead = 2;
 
 template <typename T>
-int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats) {
+int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const double* x0) {
   hipStream_t st = M->ctx->stream;
   const int epoch = next_epoch(M);
-  int rc = launch_start<T>(M, o, epoch);
+  int rc = launch_start<T>(M, o, epoch, x0);
   if (rc) return rc;
   // Upper bound on launches: every inner solve takes at most max_inner + 2.
   const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
@@ -951,7 +977,8 @@ int multi_launch(fi_mesh* M0, MultiLaunch<T>& L, int par) {
 // like solve_dev (events of channel 0), until every channel's mirror shows
 // its end.
 template <typename T>
-int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve_stats* stats) {
+int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve_stats* stats,
+                    const double* const* x0) {
   fi_mesh* M0 = ch[0];
   hipStream_t st = M0->ctx->stream;
   int epoch[kMaxRhs];
@@ -959,7 +986,7 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
   int rc = FI_OK, first_rc = FI_OK;
   for (int c = 0; c < nc; ++c) {
     epoch[c] = next_epoch(ch[c]);
-    if ((rc = launch_start<T>(ch[c], o, epoch[c]))) return rc;
+    if ((rc = launch_start<T>(ch[c], o, epoch[c], x0 ? x0[c] : nullptr))) return rc;
   }
   // Launch arguments for the solves still running; a solve that has ended
   // leaves the launches from the next chunk on (chunks start at parity 0).
@@ -1017,7 +1044,8 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
 
 }  // namespace
 
-int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats) {
+int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats,
+                const double* const* x0) {
   if (nc < 1 || nc > kMaxRhs) return fail(FI_E_INVALID, "1 to 3 right-hand sides per solve");
   for (int c = 0; c < nc; ++c) {
     stats[c].iterations = 0;
@@ -1026,8 +1054,8 @@ int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_
     stats[c].rel_residual = 0.0;
   }
   if (ch[0]->n == 0) return FI_OK;
-  if (opts->precision == FI_PREC_FP64) return solve_multi_dev<double>(ch, nc, opts, stats);
-  return solve_multi_dev<float>(ch, nc, opts, stats);
+  if (opts->precision == FI_PREC_FP64) return solve_multi_dev<double>(ch, nc, opts, stats, x0);
+  return solve_multi_dev<float>(ch, nc, opts, stats, x0);
 }
 
 // Times `reps` multi-RHS steps over nc channels forced into the iteration
@@ -1139,10 +1167,10 @@ int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int co
   return FI_OK;
 }
 
-int solve_arm(fi_mesh* M, const fi_solve_opts* o, int* epoch) {
+int solve_arm(fi_mesh* M, const fi_solve_opts* o, int* epoch, const double* x0) {
   if (M->n <= 0) return fail(FI_E_INVALID, "nothing to solve");
   *epoch = next_epoch(M);
-  return launch_start<float>(M, o, *epoch);
+  return launch_start<float>(M, o, *epoch, x0);
 }
 
 int solve_poll(fi_mesh* M, int epoch, fi_solve_stats* stats, int* done) {
@@ -1252,15 +1280,16 @@ int solver_setup(fi_mesh* M) {
   return FI_OK;
 }
 
-// Solves K_FF x = b64 (both in the mesh workspace); the result is in d_x64.
-int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats) {
+// Solves K_FF x = b64 (both in the mesh workspace) from x0 (device, n; NULL
+// for 0); the result is in d_x64.
+int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats, const double* x0) {
   stats->iterations = 0;
   stats->refinements = 0;
   stats->status = FI_OK;
   stats->rel_residual = 0.0;
   if (M->n == 0) return FI_OK;
-  if (opts->precision == FI_PREC_FP64) return solve_dev<double>(M, opts, stats);
-  return solve_dev<float>(M, opts, stats);
+  if (opts->precision == FI_PREC_FP64) return solve_dev<double>(M, opts, stats, x0);
+  return solve_dev<float>(M, opts, stats, x0);
 }
 
 // Times `reps` CG iterations (step launches forced into the iteration

@@ -23,6 +23,7 @@ int Cgls::alloc() {
       (rc = device_alloc(M, (void**)&M->d_ts, (size_t)std::max<int64_t>(m, 1) * 8)) ||
       (rc = device_alloc(M, (void**)&M->d_tr, (size_t)P * 8)) ||
       (rc = device_alloc(M, (void**)&M->d_tq, (size_t)P * 8)) ||
+      (rc = device_alloc(M, (void**)&M->d_ywarm, (size_t)std::max<int64_t>(M->n, 1) * 8)) ||
       (rc = device_alloc(M, (void**)&M->d_tsc, 8 * sizeof(double))))
     return rc;
   return FI_OK;
@@ -34,6 +35,7 @@ double* gamma_slot(fi_mesh* M, int k) { return M->d_tsc + Cgls::kScGamma + (k & 
 
 int Cgls::pre() {
   int rc = FI_OK;
+  x0 = nullptr;
   switch (seg) {
     case kInpaint:  // B g0: g0 = f on the mask unless given
       if (!start_from_g && (rc = launch_gather_mask(M, f, g))) return rc;
@@ -43,6 +45,7 @@ int Cgls::pre() {
       if ((rc = launch_gather_vertex(M, M->d_tpart, M->d_tF, M->d_tD))) return rc;
       FI_HIP_TRY(hipMemcpyAsync(M->d_b64, M->d_tF, (size_t)M->n * sizeof(double),
                                 hipMemcpyDeviceToDevice, M->ctx->stream));
+      if (warm) x0 = M->d_ywarm;
       return FI_OK;
     case kApplyP:  // q = B p
       return launch_lift(M, M->d_tg, M->d_b64);
@@ -71,6 +74,11 @@ int Cgls::post() {
       return launch_dot(M, r, r, P, sc + kScRR0);
     case kAdjoint:  // s = t_D - K_DF y; first: p = s; later: p = s + (gamma_k / gamma_k-1) p
       if ((rc = launch_adjoint_tail(M, M->d_tD, M->d_x64, s))) return rc;
+      if (use_warm && M->n > 0) {
+        FI_HIP_TRY(hipMemcpyAsync(M->d_ywarm, M->d_x64, (size_t)M->n * sizeof(double),
+                                  hipMemcpyDeviceToDevice, M->ctx->stream));
+        warm = true;
+      }
       if ((rc = launch_dot(M, s, s, m, gamma_slot(M, k)))) return rc;
       if (k == 0) {
         FI_HIP_TRY(hipMemcpyAsync(p, s, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice,
@@ -149,6 +157,7 @@ extern "C" int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
   c.f = f_dev;
   c.g = g_dev;
   c.start_from_g = o.start_from_g != 0;
+  c.use_warm = o.cold_adjoint == 0;
   int rc = c.alloc();
   if (rc) return rc;
   auto run = [&](Cgls::Seg seg) -> int {
@@ -156,7 +165,7 @@ extern "C" int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
     int r = c.pre();
     if (r) return r;
     fi_solve_stats st{};
-    r = solve_free(M, &io, &st);
+    r = solve_free(M, &io, &st, c.x0);
     ts.inner_iterations += st.iterations;
     if (r) return r;
     if (st.status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");
@@ -233,6 +242,7 @@ extern "C" int fi_tonal_opt_rgb(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
     cg[c].f = f_dev + (size_t)c * M->P;
     cg[c].g = g_dev + (size_t)c * M->m;
     cg[c].start_from_g = o.start_from_g != 0;
+    cg[c].use_warm = o.cold_adjoint == 0;
     if ((rc = cg[c].alloc())) return rc;
     active[c] = true;
   }
@@ -240,6 +250,7 @@ extern "C" int fi_tonal_opt_rgb(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
   // multi-right-hand-side solve, then each channel's own update.
   auto run = [&](Cgls::Seg seg) -> int {
     fi_mesh* act[C];
+    const double* x0[C];
     int idx[C], na = 0;
     for (int c = 0; c < C; ++c) {
       if (!active[c]) continue;
@@ -247,11 +258,12 @@ extern "C" int fi_tonal_opt_rgb(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
       int r = cg[c].pre();
       if (r) return r;
       act[na] = ch[c];
+      x0[na] = cg[c].x0;
       idx[na++] = c;
     }
     if (na == 0) return FI_OK;
     fi_solve_stats st[C] = {};
-    int r = solve_multi(act, na, &io, st);
+    int r = solve_multi(act, na, &io, st, x0);
     for (int q = 0; q < na; ++q) ts[idx[q]].inner_iterations += st[q].iterations;
     if (r) return r;
     for (int q = 0; q < na; ++q)
@@ -350,7 +362,7 @@ extern "C" int fi_tonal_opt_l1(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
     int r = c.pre();
     if (r) return r;
     fi_solve_stats ss{};
-    r = solve_free(M, &o.inner, &ss);
+    r = solve_free(M, &o.inner, &ss, c.x0);
     st.inner_iterations += ss.iterations;
     if (r) return r;
     if (ss.status != FI_OK) return fail(FI_E_NO_CONVERGENCE, "inner solve did not converge");

@@ -42,6 +42,9 @@ def test_version_and_defaults():
     t = fi._TonalOpts()
     lib.fi_tonal_opts_default(t)
     assert t.rtol == 1e-8 and t.inner.rtol == 1e-10
+    t.cold_adjoint = 7
+    lib.fi_tonal_opts_default(t)
+    assert t.cold_adjoint == 0 and t.start_from_g == 0
 
 
 def rand_mask(N, k, seed):

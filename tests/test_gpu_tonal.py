@@ -119,3 +119,25 @@ def test_tonal_parity(ctx, name, precision):
     assert mse_ref <= mse0 + 1e-12 and st["mse_final"] <= st["mse_initial"]
     s0 = np.linalg.norm(pr.normal_residual(pr.default_g(f), f))
     assert np.linalg.norm(pr.normal_residual(g, f)) <= 1e-6 * s0
+
+
+@pytest.mark.parametrize("name", ["n256_k2000", "c2"])
+def test_adjoint_warm_start(ctx, name):
+    """Each adjoint solve of the CGLS loop starts from the previous one's
+    solution (the default) or from 0: the same stopping test, so the same
+    result to the parity bar, and fewer CG iterations warm."""
+    print(f"case {name}", flush=True)
+    M = gpu_mesh(ctx, name)
+    pr = oracle_problem(name)
+    _, _, f = case(name)
+    g_w, st_w = M.tonal_opt(dev(f), opts=fi.TonalOpts())
+    g_c, st_c = M.tonal_opt(dev(f), opts=fi.TonalOpts(cold_adjoint=True))
+    g_ref, _, _ = oracle_tonal(name)
+    mse_ref = pr.mse_of_g(g_ref, f)
+    print(f"  inner iterations warm {st_w['inner_iterations']} cold {st_c['inner_iterations']}, "
+          f"outer {st_w['outer_iterations']} / {st_c['outer_iterations']}", flush=True)
+    for st, g in ((st_w, g_w), (st_c, g_c)):
+        assert st["status"] == 0
+        assert abs(st["mse_final"] - mse_ref) <= 1e-6 * mse_ref
+        assert abs(pr.mse_of_g(g.cpu().numpy(), f) - mse_ref) <= 1e-6 * mse_ref
+    assert st_w["inner_iterations"] < st_c["inner_iterations"]
