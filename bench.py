@@ -85,7 +85,8 @@ def parse():
 
 
 def cpu_baseline(side, f_np, mask, u_gpu, what):
-    """The oracle, as it stands, on one to three inpaintings of ``what``."""
+    """The oracle, as it stands, on repeated inpaintings of ``what`` until
+    about 10 s of host time have passed (at least one)."""
     from oracle import tonal
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -97,7 +98,7 @@ def cpu_baseline(side, f_np, mask, u_gpu, what):
         pr.mse(u_ref, f_np.ravel())
         reps += 1
         el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 3:
+        if el > 10.0 or reps >= 100:
             break
     P = side * side
     err = float(np.max(np.abs(u_gpu - u_ref))) if u_gpu is not None else None
@@ -334,27 +335,30 @@ def densify_main(args):
 
 
 def densify_cpu_baseline(f512):
-    """The oracle running the paper's per-triangle loop at 512^2 (4%, n = 10)
-    for up to about 20 s: mesh, Cholesky, inpainting, error, selection."""
+    """The oracle running the paper's per-triangle loop at 512^2 (4%, n = 10),
+    started over until about 10 s have passed: mesh, Cholesky, inpainting,
+    error, selection."""
     from oracle import densify, tonal
     import synth
     cores = len(os.sched_getaffinity(0))
     side = 512
     P = side * side
     k = synth.count_from_density(0.04, P) // 10
-    mask = synth.make_mask(2, P, k=k)
+    mask0 = synth.make_mask(2, P, k=k)
     f = f512.ravel()
     t0 = time.perf_counter()
     n = 0
-    for _ in range(10):
-        pr = tonal.Problem(side, mask)
-        u = pr.inpaint(f)
-        e = (u - f.astype(np.float64)) ** 2
-        n += 1
-        if time.perf_counter() - t0 > 20.0:
-            break
-        add = densify.paper_densify_step(e, pr.rast.owner, pr.mesh.T, mask, k)
-        mask = np.sort(np.concatenate([mask, add]))
+    while time.perf_counter() - t0 <= 10.0 and n < 100:
+        mask = mask0
+        for r in range(10):
+            pr = tonal.Problem(side, mask)
+            u = pr.inpaint(f)
+            e = (u - f.astype(np.float64)) ** 2
+            n += 1
+            if r == 9 or time.perf_counter() - t0 > 10.0:
+                break
+            add = densify.paper_densify_step(e, pr.rast.owner, pr.mesh.T, mask, k)
+            mask = np.sort(np.concatenate([mask, add]))
     el = time.perf_counter() - t0
     return {"value": n * P / el / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} rounds of the per-triangle loop at 512^2 (mesh, direct Cholesky, "
@@ -470,15 +474,20 @@ def colour_main(args):
         from oracle import colour, tonal
         cores = len(os.sched_getaffinity(0))
         t0 = time.perf_counter()
-        pr = tonal.Problem(side, mask)
-        u_ref = colour.inpaint(pr, f_np)
-        colour.mse(u_ref, f_np)
-        el = time.perf_counter() - t0
+        reps = 0
+        while True:
+            pr = tonal.Problem(side, mask)
+            u_ref = colour.inpaint(pr, f_np)
+            colour.mse(u_ref, f_np)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > 10.0 or reps >= 100:
+                break
         out["max_abs_err_vs_fp64_oracle"] = float(np.max(np.abs(u.cpu().numpy().reshape(3, -1)
                                                                 - u_ref)))
-        out["cpu_baseline"] = {"value": P / el / 1e6, "unit": "Mpixel/s", "cores": cores,
+        out["cpu_baseline"] = {"value": reps * P / el / 1e6, "unit": "Mpixel/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"1 colour inpainting of the 512^2 image (mesh, "
+                               "sample": f"{reps} colour inpainting(s) of the 512^2 image (mesh, "
                                          f"assembly, one direct Cholesky, three solves, "
                                          f"interpolation, MSE), {el:.1f} s"}
     print(json.dumps(out))

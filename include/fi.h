@@ -245,6 +245,21 @@ int fi_vertex_values(fi_mesh* mesh, double* u_vertex_dev);
 int fi_error(fi_mesh* mesh, const double* u_dev, const uint8_t* f_dev, double* mse_host,
              double* pix_err_dev, double* tri_err_dev);
 
+/* The harmonic-extension system itself (Section 2.2: K_FF x = b, SPD, solved
+ * by CG; here Jacobi PCG, FP32 iterations with FP64 refinement, or FP64), for
+ * a caller's right-hand side, started from x0.
+ *   b_dev:  float64[n] right-hand side, free unknowns in ascending free-vertex
+ *           order (the order fi_mesh_export_geometry gives free_vids).
+ *   x0_dev: float64[n] start, or NULL for 0. The stopping test is
+ *           ||b - K_FF x|| <= opts->rtol ||b|| whatever the start, so a good
+ *           start only saves iterations; with b = 0 the result is x = 0.
+ *   x_dev:  float64[n] output (may be x0_dev or b_dev).
+ * Stream-ordered on the context's stream; returns after the solve has ended.
+ * Errors: FI_E_INVALID (NULL b_dev or x_dev while n > 0, non-finite values),
+ * FI_E_NO_CONVERGENCE (x_dev still written). */
+int fi_solve(fi_mesh* mesh, const double* b_dev, const double* x0_dev, double* x_dev,
+             const fi_solve_opts* opts, fi_solve_stats* stats);
+
 /* Adjoint of the inpainting map, s = B^T r = t_D - K_DF K_FF^{-1} t_F with
  * t = R^T r (R: interpolation to pixels). Section 4's nested CG applies it
  * through one more solve with the same symmetric matrix.

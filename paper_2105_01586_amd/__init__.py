@@ -38,7 +38,7 @@ EXPORTED_SYMBOLS = (
     "fi_solve_opts_default", "fi_tonal_opts_default", "fi_last_error", "fi_version",
     "fi_ctx_create", "fi_ctx_set_stream", "fi_ctx_destroy", "fi_mesh_build", "fi_mesh_destroy",
     "fi_mesh_get_info", "fi_assemble", "fi_inpaint", "fi_vertex_values", "fi_error",
-    "fi_adjoint", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
+    "fi_adjoint", "fi_solve", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
     "fi_owner_map", "fi_topk_new_pixels", "fi_time_cg_kernel", "fi_cg_kernel_bytes",
     "fi_host_mesh_build", "fi_host_mesh_info", "fi_host_mesh_export", "fi_host_mesh_destroy",
     "fi_mesh_upload", "fi_grow_mask", "fi_server_opts_default", "fi_server_create",
@@ -172,6 +172,8 @@ def library() -> ctypes.CDLL:
                                       ctypes.POINTER(_SolveStats)]),
         "fi_vertex_values": (ctypes.c_int, [vp, vp]),
         "fi_error": (ctypes.c_int, [vp, vp, vp, dp, vp, vp]),
+        "fi_solve": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                    ctypes.POINTER(_SolveStats)]),
         "fi_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                       ctypes.POINTER(_SolveStats)]),
         "fi_tonal_opt": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_TonalOpts),
@@ -480,6 +482,22 @@ class Mesh:
                                   ctypes.byref(st))
         _check(rc, "fi_adjoint")
         return s, _stats(st)
+
+    def solve(self, b, x0=None, x=None, opts: SolveOpts | None = None):
+        """x = K_FF^{-1} b (free unknowns in free-vertex order), started from
+        x0 (None: 0). Returns (x, stats)."""
+        torch = _torch()
+        d = self._dev()
+        if x is None:
+            x = self._empty(self.n, torch.float64)
+        st = _SolveStats()
+        o = (opts or SolveOpts()).c()
+        x0p = None if x0 is None else _ptr(x0, torch.float64, self.n, "x0", d)
+        rc = library().fi_solve(self._h, _ptr(b, torch.float64, self.n, "b", d), x0p,
+                                _ptr(x, torch.float64, self.n, "x", d), ctypes.byref(o),
+                                ctypes.byref(st))
+        _check(rc, "fi_solve")
+        return x, _stats(st)
 
     def tonal_opt(self, f, g=None, opts: TonalOpts | None = None):
         """g* = argmin ||B g - f||^2 by CGLS. Returns (g, stats)."""

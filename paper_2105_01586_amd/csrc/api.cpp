@@ -625,6 +625,30 @@ int fi_adjoint(fi_mesh* M, const double* r_dev, double* s_dev, const fi_solve_op
 }
 
 
+int fi_solve(fi_mesh* M, const double* b_dev, const double* x0_dev, double* x_dev,
+             const fi_solve_opts* opts, fi_solve_stats* stats) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (M->n > 0 && (!b_dev || !x_dev)) return fail(FI_E_INVALID, "b_dev and x_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  const fi_solve_opts o = resolve_opts(opts);
+  fi_solve_stats st{};
+  const size_t bytes = (size_t)M->n * sizeof(double);
+  if (M->n > 0) {
+    FI_HIP_TRY(hipMemcpyAsync(M->d_b64, b_dev, bytes, hipMemcpyDeviceToDevice, M->ctx->stream));
+    rc = solve_free(M, &o, &st, x0_dev);
+    if (stats) *stats = st;
+    if (rc) return rc;
+    FI_HIP_TRY(hipMemcpyAsync(x_dev, M->d_x64, bytes, hipMemcpyDeviceToDevice, M->ctx->stream));
+    FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  } else if (stats) {
+    *stats = st;
+  }
+  if (st.status != FI_OK)
+    return fail(FI_E_NO_CONVERGENCE, "solve did not reach the tolerance");
+  return FI_OK;
+}
+
 int fi_mesh_export_geometry(const fi_mesh* M, int32_t* vxy, int32_t* tri, int32_t* leaves,
                             int32_t* free_vids, int32_t* mask_vids) {
   int rc = check_mesh(M);
