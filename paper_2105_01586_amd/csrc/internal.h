@@ -58,6 +58,12 @@ constexpr int kMaxIncident = 8;
 // Cap on incident triangles per vertex of a Delaunay mesh (the assembly's
 // per-row neighbour list).
 constexpr int kMaxIncidentGeneral = 31;
+// Events per mesh for pacing queued step launches (the ring fi_mesh holds).
+constexpr int kChunkEvents = 4;
+// Launch-count predictions a mesh keeps (FP32 / FP64 x cold / warm start).
+constexpr int kPredSlots = 4;
+// Right-hand sides one multi-RHS step advances (a mesh and its channel views).
+constexpr int kMaxRhs = 3;
 
 // Builds the paper's Delaunay mesh of the mask pixels, the unknown vertices
 // and the four corner pixels (delaunay.cpp). Checks: N power of two in
@@ -163,7 +169,10 @@ struct fi_mesh {
   void* h_mirror = nullptr;       // pinned host copy of the solver state (host pointer)
   void* d_mirror = nullptr;       // the same memory as the device addresses it
   int epoch = 0;                  // id of the latest solve started on this mesh
-  hipEvent_t chunk_ev[4] = {};    // one after each queued chunk of step launches
+  // step launches the last solve of each kind took (FP32 / FP64 x cold /
+  // warm start), which paces the next one; 0: none yet
+  int64_t pred_launches[fi::kPredSlots] = {};
+  hipEvent_t chunk_ev[fi::kChunkEvents] = {};  // one after each queued chunk of step launches
   fi::CGState cg32, cg64;
   double* d_part = nullptr;   // 2 x kMaxGrid x 4 partial sums
   double* d_scal = nullptr;   // scalar slots of the fused CG kernel
@@ -217,17 +226,15 @@ struct fi_mesh {
   // channels 1 and 2 of a colour image (created on first use): views that
   // share this mesh's geometry, matrices and pixel maps and own their solver
   // state and work vectors
-  fi_mesh* chan[2] = {nullptr, nullptr};
+  fi_mesh* chan[fi::kMaxRhs - 1] = {};
   bool is_channel = false;
 };
 
 namespace fi {
 
 constexpr int kBlock = 256;      // threads per block of the vector kernels
-constexpr int kChunkEvents = 4;  // events per mesh for pacing queued step launches
 constexpr int kMaxGrid = 1024;   // cap on blocks of the fused CG kernel
 constexpr int kRedMaxBlocks = 256;  // blocks of the large-system partial-sum reduction
-constexpr int kMaxRhs = 3;       // right-hand sides one multi-RHS step advances
 
 int device_alloc(fi_mesh* M, void** p, size_t bytes);
 // Uploads a host mesh and assembles it; memory from `arena` when not NULL.

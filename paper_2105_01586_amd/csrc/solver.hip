@@ -877,7 +877,55 @@ int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
 // keeps at most kAhead chunks queued, and stops as soon as the mirror shows
 // the end of this solve. Chunks still queued then run as idle launches;
 // later work on the stream is ordered after them.
+//
+// Queued launches past the end cost a launch each (about 4 us at 512^2), so
+// the host also stops queueing at the launch count the last solve of the
+// same kind on this mesh took (plus kPredMargin); if the solve is still
+// running once all of those have run, queueing goes on as before. The
+// number of launches never changes the result: launches after the end only
+// carry the final record forward.
 constexpr int kAhead = 2;
+constexpr int kPredMargin = 2;
+static_assert(kAhead <= kChunkEvents, "every queued chunk needs its own event");
+
+// Step launches a solve used: one per iteration, the start and the end of
+// every inner solve, and the launch that found the outer tolerance met.
+int64_t launches_used(const fi_solve_stats* s) {
+  return s->iterations + 2 * (int64_t)s->refinements + 1;
+}
+
+// Which prediction slot a solve uses: precision and cold or warm start.
+template <typename T>
+int pred_slot(const double* x0) {
+  return (sizeof(T) == sizeof(double) ? 2 : 0) + (x0 ? 1 : 0);
+}
+static_assert(kPredSlots == 4, "one slot per precision and start");
+
+// Host pacing of one run of step launches: how many to queue next (even, so
+// every chunk starts at parity 0), or 0 to wait.
+struct Pacer {
+  int64_t cap;                 // launches to queue before waiting for the end
+  int64_t limit;               // launches never exceeded
+  int64_t queued = 0, launched = 0, completed = 0;  // launches; chunks; chunks
+  int next() {
+    if (launched - completed >= kAhead || queued >= limit) return 0;
+    if (queued >= cap) {
+      if (completed != launched) return 0;
+      cap = limit;  // the prediction was short: pace as without one
+    }
+    const int64_t n = std::min<int64_t>(kChunk, cap - queued);
+    return (int)(n + (n & 1));
+  }
+};
+
+Pacer make_pacer(const fi_solve_opts* o, int64_t pred) {
+  // every inner solve takes at most max_inner + 2 launches
+  const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
+  Pacer p;
+  p.limit = (max_launch / kChunk + 2) * kChunk;
+  p.cap = pred > 0 ? pred + kPredMargin : p.limit;
+  return p;
+}
 
 template <typename T>
 int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const double* x0) {
@@ -885,31 +933,33 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const d
   const int epoch = next_epoch(M);
   int rc = launch_start<T>(M, o, epoch, x0);
   if (rc) return rc;
-  // Upper bound on launches: every inner solve takes at most max_inner + 2.
-  const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
-  const int64_t max_chunks = max_launch / kChunk + 2;
-  int64_t launched = 0, completed = 0;
+  const int slot = pred_slot<T>(x0);
+  Pacer pc = make_pacer(o, M->pred_launches[slot]);
   for (;;) {
     int drc = FI_OK;
-    if (read_mirror(M, epoch, stats, &drc)) return drc;
-    if (launched < max_chunks && launched - completed < kAhead) {
-      for (int q = 0; q < kChunk; ++q) {
+    if (read_mirror(M, epoch, stats, &drc)) {
+      M->pred_launches[slot] = launches_used(stats);
+      return drc;
+    }
+    if (const int n = pc.next()) {
+      for (int q = 0; q < n; ++q) {
         rc = launch_step<T>(M, q & 1, 0);
         if (rc) return rc;
       }
-      FI_HIP_TRY(hipEventRecord(M->chunk_ev[launched % kChunkEvents], st));
-      ++launched;
+      FI_HIP_TRY(hipEventRecord(M->chunk_ev[pc.launched % kChunkEvents], st));
+      ++pc.launched;
+      pc.queued += n;
       continue;
     }
-    if (completed < launched) {
-      const hipError_t q = hipEventQuery(M->chunk_ev[completed % kChunkEvents]);
+    if (pc.completed < pc.launched) {
+      const hipError_t q = hipEventQuery(M->chunk_ev[pc.completed % kChunkEvents]);
       if (q == hipSuccess) {
-        ++completed;
+        ++pc.completed;
         continue;
       }
       if (q != hipErrorNotReady)
         return fail(FI_E_HIP, std::string("stream failed: ") + hipGetErrorString(q));
-    } else {  // everything launched has run and the solve never ended
+    } else {  // everything launched (up to the limit) has run and the solve never ended
       if (read_mirror(M, epoch, stats, &drc)) return drc;
       return fail(FI_E_HIP, "solver did not report termination");
     }
@@ -995,16 +1045,26 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
   int nrun = nc;
   for (int c = 0; c < nc; ++c) run[c] = ch[c];
   multi_prepare<T>(run, nrun, 0, L);
-  const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
-  const int64_t max_chunks = max_launch / kChunk + 2;
-  int64_t launched = 0, completed = 0;
+  // paced to the longest predicted channel (no cap while one has none)
+  int64_t pred = 0;
+  bool every = true;
+  for (int c = 0; c < nc; ++c) {
+    const int64_t p = ch[c]->pred_launches[pred_slot<T>(x0 ? x0[c] : nullptr)];
+    every = every && p > 0;
+    pred = std::max(pred, p);
+  }
+  if (!every) pred = 0;
+  Pacer pc = make_pacer(o, pred);
   auto all_done = [&]() {
     bool all = true;
     for (int c = 0; c < nc; ++c) {
       if (!done[c]) {
         int drc = FI_OK;
         done[c] = read_mirror(ch[c], epoch[c], &stats[c], &drc) != 0;
-        if (done[c] && drc && !first_rc) first_rc = drc;
+        if (done[c]) {
+          ch[c]->pred_launches[pred_slot<T>(x0 ? x0[c] : nullptr)] = launches_used(&stats[c]);
+          if (drc && !first_rc) first_rc = drc;
+        }
       }
       all = all && done[c];
     }
@@ -1019,17 +1079,18 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
       nrun = left;
       multi_prepare<T>(run, nrun, 0, L);
     }
-    if (launched < max_chunks && launched - completed < kAhead) {
-      for (int q = 0; q < kChunk; ++q)
+    if (const int n = pc.next()) {
+      for (int q = 0; q < n; ++q)
         if ((rc = multi_launch<T>(M0, L, q & 1))) return rc;
-      FI_HIP_TRY(hipEventRecord(M0->chunk_ev[launched % kChunkEvents], st));
-      ++launched;
+      FI_HIP_TRY(hipEventRecord(M0->chunk_ev[pc.launched % kChunkEvents], st));
+      ++pc.launched;
+      pc.queued += n;
       continue;
     }
-    if (completed < launched) {
-      const hipError_t q = hipEventQuery(M0->chunk_ev[completed % kChunkEvents]);
+    if (pc.completed < pc.launched) {
+      const hipError_t q = hipEventQuery(M0->chunk_ev[pc.completed % kChunkEvents]);
       if (q == hipSuccess) {
-        ++completed;
+        ++pc.completed;
         continue;
       }
       if (q != hipErrorNotReady)
@@ -1207,7 +1268,10 @@ int alloc_solver_state(fi_mesh* M) {
   std::memset(M->h_mirror, 0, sizeof(Mirror));
   FI_HIP_TRY(hipHostGetDevicePointer(&M->d_mirror, M->h_mirror, 0));
   for (int k = 0; k < kChunkEvents; ++k)
-    FI_HIP_TRY(hipEventCreateWithFlags(&M->chunk_ev[k], hipEventDisableTiming));
+    // pacing only: the host reads no device memory on the strength of these
+    // events (the outcome arrives through the mirror), so no system fence
+    FI_HIP_TRY(hipEventCreateWithFlags(&M->chunk_ev[k],
+                                       hipEventDisableTiming | hipEventDisableSystemFence));
   // the reduction counter starts at zero (the flag words are cleared too)
   hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, M->ctx->stream, M->d_flag);
   FI_HIP_TRY(hipGetLastError());
