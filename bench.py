@@ -84,9 +84,12 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(side, f_np, mask, u_gpu, what):
+def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None):
     """The oracle, as it stands, on repeated inpaintings of ``what`` until
-    about 10 s of host time have passed (at least one)."""
+    about 10 s of host time have passed (at least one). Also returns the GPU
+    result's agreement with it: max |u - u_oracle|, and with ``grad_at`` =
+    (g, GPU gradient of the MSE at g) the oracle's MSE and the gradient's
+    relative error against the oracle's."""
     from oracle import tonal
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -102,9 +105,45 @@ def cpu_baseline(side, f_np, mask, u_gpu, what):
             break
     P = side * side
     err = float(np.max(np.abs(u_gpu - u_ref))) if u_gpu is not None else None
+    if grad_at is not None:
+        g0, grad = grad_at
+        ref = pr.mse_grad(g0, f_np.ravel())
+        err = {"max_abs_pixel_err": err, "mse_oracle": pr.mse(u_ref, f_np.ravel()),
+               "grad_rel_err_vs_oracle": float(np.linalg.norm(grad - ref) / np.linalg.norm(ref))}
     return {"value": P * reps / el / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"{reps} full inpainting(s) of {what} (mesh, assembly, direct Cholesky, "
                       f"solve, interpolation, MSE), {el:.1f} s"}, err
+
+
+def fd_check(fi, mesh, f, f_np, mask, n_dir=16, eps=1e-3, seed=7):
+    """The gradient of MSE(g) = ||B g - f||^2 / P from the adjoint,
+    (2 / P) B^T (B g - f), against central differences along 16 random
+    coordinates of g (eps = 1e-3), at g = f on the mask plus N(0, 2) noise.
+    The MSE is quadratic in g, so the differences carry only the rounding and
+    solve error of the two losses (solved to 1e-12). All on the GPU. Returns
+    (g, gradient) and the report."""
+    import torch
+    rng = np.random.default_rng(seed)
+    P = f_np.size
+    g0 = f_np.ravel()[mask].astype(np.float64) + rng.normal(scale=2.0, size=mask.size)
+    g = torch.from_numpy(g0).cuda()
+    u, _ = mesh.inpaint(g=g)
+    s, _ = mesh.adjoint(u - f.to(torch.float64))
+    grad = (2.0 / P) * s.cpu().numpy()
+    tight = fi.SolveOpts(rtol=1e-12)
+    scale = float(np.max(np.abs(grad)))
+    worst = 0.0
+    for j in rng.integers(0, mask.size, size=n_dir):
+        loss = []
+        for sign in (1.0, -1.0):
+            gj = g.clone()
+            gj[j] += sign * eps
+            uj, _ = mesh.inpaint(g=gj, opts=tight)
+            loss.append(mesh.error(uj, f)[0])
+        fd = (loss[0] - loss[1]) / (2 * eps)
+        worst = max(worst, abs(fd - grad[j]) / (abs(grad[j]) + 1e-3 * scale))
+    return (g0, grad), {"directions": n_dir, "eps": eps,
+                        "max_rel_dev": worst, "scale": "|fd - grad| / (|grad| + 1e-3 max|grad|)"}
 
 
 def _gen(req):
@@ -702,10 +741,16 @@ def main():
     out["device_memory_gb"] = {"mesh_and_solver": mesh.info["device_bytes"] / 1e9,
                                "torch_peak": torch.cuda.max_memory_allocated() / 1e9,
                                "device_used_peak": peak_used[0] / 1e9}
+    g_fd = None
+    if w.side <= 1024:
+        g_fd, out["gradient_fd_check"] = fd_check(fi, mesh, f, f_np, mask)
     if not args.no_cpu_baseline:
         if w.side <= 1024:
-            cb, err = cpu_baseline(w.side, f_np, mask, u.cpu().numpy(), f"the {w.side}^2 image")
-            out["max_abs_err_vs_fp64_oracle"] = err
+            cb, acc = cpu_baseline(w.side, f_np, mask, u.cpu().numpy(), f"the {w.side}^2 image",
+                                   grad_at=g_fd)
+            out["max_abs_err_vs_fp64_oracle"] = acc["max_abs_pixel_err"]
+            out["mse_inpaint_oracle"] = acc["mse_oracle"]
+            out["gradient_fd_check"]["rel_err_vs_oracle_gradient"] = acc["grad_rel_err_vs_oracle"]
         else:
             # the oracle on the whole image is out of reach; it runs on the
             # 2048^2 crop that the parity tests use
