@@ -506,6 +506,9 @@ int fi_assemble(fi_mesh* M) {
   if (rc) return rc;
   FI_HIP_TRY(hipSetDevice(M->ctx->device));
   const int64_t n = M->n, m = M->m;
+  // Later assemblies recompute every value (free and mask rows, ELL slots)
+  // in one launch.
+  if (M->assembled_once) return launch_assemble_refill(M);
   int32_t* cnt_ff = M->d_cnt;
   int32_t* cnt_fd = M->d_cnt + (n + 1);
   // The sparsity pattern depends on the mesh only: counted and scanned on the

@@ -234,6 +234,10 @@ namespace fi {
 
 constexpr int kBlock = 256;      // threads per block of the vector kernels
 constexpr int kMaxGrid = 1024;   // cap on blocks of the fused CG kernel
+// ELL entry of K_FF: bits 0-29 the column, bit 30 padding (weight 0, column =
+// the row itself), bit 31 weight -1 (clear: -1/2).
+constexpr int32_t kEllColMask = 0x3FFFFFFF;
+constexpr int32_t kEllPadBit = 0x40000000;
 constexpr int kRedMaxBlocks = 256;  // blocks of the large-system partial-sum reduction
 
 int device_alloc(fi_mesh* M, void** p, size_t bytes);
@@ -247,6 +251,10 @@ void free_mesh(fi_mesh* M);
 // Kernel launchers (kernels.hip). All stream-ordered, no host sync.
 int launch_assemble_count(fi_mesh* M, bool free_rows);
 int launch_assemble_fill(fi_mesh* M, bool free_rows);
+// Re-assembly of a mesh whose pattern and ELL width are known: free and mask
+// rows in one launch, the free rows' ELL slots written alongside their CSR
+// entries (the same encoding as the packing of the first assembly).
+int launch_assemble_refill(fi_mesh* M);
 int scan_counts(fi_mesh* M, const int32_t* cnt, int32_t* rowptr, int64_t n);
 // Exclusive prefix sum of n ints with caller scratch of scan_tmp_ints(n) ints.
 int scan_exclusive(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* tmp);

@@ -207,6 +207,49 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_count(
   cnt_fd[i] = cd;
 }
 
+// Free row i: its K_FF and K_FD entries, diagonal and D^-1; with ell, also
+// its ELL slots (W of them, column-major with stride n_pad).
+template <int NB>
+__device__ __forceinline__ void free_row_fill(
+    int i, const int32_t* __restrict__ free_vids, const int32_t* __restrict__ vxy,
+    const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_idx, const int32_t* __restrict__ vmap,
+    const int32_t* __restrict__ ff_ptr, int32_t* __restrict__ ff_col,
+    double* __restrict__ ff_val64, float* __restrict__ ff_val32,
+    const int32_t* __restrict__ fd_ptr, int32_t* __restrict__ fd_col,
+    double* __restrict__ fd_val, double* __restrict__ diag64, double* __restrict__ dinv64,
+    float* __restrict__ dinv32, int32_t* __restrict__ ell, int n_pad, int W) {
+  int32_t nb[NB];
+  double w[NB];
+  double d;
+  const int k = stiffness_row<NB>(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
+  const int p0 = ff_ptr[i];
+  int pf = p0, pd = fd_ptr[i];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (q < k) {
+      const int32_t mv = vmap[nb[q]];
+      if (mv >= 0) {
+        ff_col[pf] = mv;
+        ff_val64[pf] = w[q];
+        ff_val32[pf] = (float)w[q];
+        if (ell && pf - p0 < W)
+          ell[(int64_t)(pf - p0) * n_pad + i] = mv | (w[q] == -1.0 ? (int32_t)0x80000000 : 0);
+        ++pf;
+      } else {
+        fd_col[pd] = -mv - 1;
+        fd_val[pd] = w[q];
+        ++pd;
+      }
+    }
+  }
+  if (ell)
+    for (int s = pf - p0; s < W; ++s) ell[(int64_t)s * n_pad + i] = kEllPadBit | i;
+  diag64[i] = d;
+  dinv64[i] = 1.0 / d;
+  dinv32[i] = (float)(1.0 / d);
+}
+
 template <int NB>
 __global__ __launch_bounds__(kBlock) void k_asm_free_fill(
     int n, const int32_t* __restrict__ free_vids, const int32_t* __restrict__ vxy,
@@ -219,30 +262,8 @@ __global__ __launch_bounds__(kBlock) void k_asm_free_fill(
     float* __restrict__ dinv32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int32_t nb[NB];
-  double w[NB];
-  double d;
-  const int k = stiffness_row<NB>(free_vids[i], vxy, tri, vt_ptr, vt_idx, nb, w, d);
-  int pf = ff_ptr[i], pd = fd_ptr[i];
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    if (q < k) {
-      const int32_t mv = vmap[nb[q]];
-      if (mv >= 0) {
-        ff_col[pf] = mv;
-        ff_val64[pf] = w[q];
-        ff_val32[pf] = (float)w[q];
-        ++pf;
-      } else {
-        fd_col[pd] = -mv - 1;
-        fd_val[pd] = w[q];
-        ++pd;
-      }
-    }
-  }
-  diag64[i] = d;
-  dinv64[i] = 1.0 / d;
-  dinv32[i] = (float)(1.0 / d);
+  free_row_fill<NB>(i, free_vids, vxy, tri, vt_ptr, vt_idx, vmap, ff_ptr, ff_col, ff_val64,
+                    ff_val32, fd_ptr, fd_col, fd_val, diag64, dinv64, dinv32, nullptr, 0, 0);
 }
 
 // Rows of the mask vertices: K_DF (free columns only).
@@ -266,15 +287,14 @@ __global__ __launch_bounds__(kBlock) void k_asm_mask_count(
   cnt_df[j] = cf;
 }
 
+// Mask row j: its K_DF entries.
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_asm_mask_fill(
-    int m, const int32_t* __restrict__ mask_vids, const int32_t* __restrict__ vxy,
+__device__ __forceinline__ void mask_row_fill(
+    int j, const int32_t* __restrict__ mask_vids, const int32_t* __restrict__ vxy,
     const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
     const int32_t* __restrict__ vt_idx, const int32_t* __restrict__ vmap,
     const int32_t* __restrict__ df_ptr, int32_t* __restrict__ df_col,
     double* __restrict__ df_val) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
   int32_t nb[NB];
   double w[NB];
   double d;
@@ -286,6 +306,54 @@ __global__ __launch_bounds__(kBlock) void k_asm_mask_fill(
       const int32_t mv = vmap[nb[q]];
       if (mv >= 0) { df_col[p] = mv; df_val[p] = w[q]; ++p; }
     }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_asm_mask_fill(
+    int m, const int32_t* __restrict__ mask_vids, const int32_t* __restrict__ vxy,
+    const int32_t* __restrict__ tri, const int32_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_idx, const int32_t* __restrict__ vmap,
+    const int32_t* __restrict__ df_ptr, int32_t* __restrict__ df_col,
+    double* __restrict__ df_val) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  mask_row_fill<NB>(j, mask_vids, vxy, tri, vt_ptr, vt_idx, vmap, df_ptr, df_col, df_val);
+}
+
+// Re-assembly in one launch: blocks [0, free_blocks) fill free rows (and
+// their ELL slots when ell is given), the rest fill mask rows.
+struct RefillArgs {
+  int n, m, free_blocks, n_pad, W;
+  const int32_t *free_vids, *mask_vids, *vxy, *tri, *vt_ptr, *vt_idx, *vmap;
+  const int32_t* ff_ptr;
+  int32_t* ff_col;
+  double* ff_val64;
+  float* ff_val32;
+  const int32_t* fd_ptr;
+  int32_t* fd_col;
+  double* fd_val;
+  double *diag64, *dinv64;
+  float* dinv32;
+  const int32_t* df_ptr;
+  int32_t* df_col;
+  double* df_val;
+  int32_t* ell;
+};
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_asm_refill(RefillArgs A) {
+  if ((int)blockIdx.x < A.free_blocks) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    free_row_fill<NB>(i, A.free_vids, A.vxy, A.tri, A.vt_ptr, A.vt_idx, A.vmap, A.ff_ptr,
+                      A.ff_col, A.ff_val64, A.ff_val32, A.fd_ptr, A.fd_col, A.fd_val, A.diag64,
+                      A.dinv64, A.dinv32, A.ell, A.n_pad, A.W);
+  } else {
+    const int j = (blockIdx.x - A.free_blocks) * blockDim.x + threadIdx.x;
+    if (j >= A.m) return;
+    mask_row_fill<NB>(j, A.mask_vids, A.vxy, A.tri, A.vt_ptr, A.vt_idx, A.vmap, A.df_ptr,
+                      A.df_col, A.df_val);
   }
 }
 
@@ -1023,6 +1091,41 @@ int assemble_fill(fi_mesh* M, bool free_rows) {
   return FI_OK;
 }
 
+template <int NB>
+int assemble_refill(fi_mesh* M) {
+  RefillArgs A;
+  A.n = (int)M->n;
+  A.m = (int)M->m;
+  A.free_blocks = grid_for(M->n);
+  A.n_pad = (int)M->n_pad;
+  A.W = M->ell_w;
+  A.free_vids = M->d_free_vids;
+  A.mask_vids = M->d_mask_vids;
+  A.vxy = M->d_vxy;
+  A.tri = M->d_tri;
+  A.vt_ptr = M->d_vt_ptr;
+  A.vt_idx = M->d_vt_idx;
+  A.vmap = M->d_vmap;
+  A.ff_ptr = M->d_ff_rowptr;
+  A.ff_col = M->d_ff_col;
+  A.ff_val64 = M->d_ff_val64;
+  A.ff_val32 = M->d_ff_val32;
+  A.fd_ptr = M->d_fd_rowptr;
+  A.fd_col = M->d_fd_col;
+  A.fd_val = M->d_fd_val;
+  A.diag64 = M->d_diag64;
+  A.dinv64 = M->d_dinv64;
+  A.dinv32 = M->d_dinv32;
+  A.df_ptr = M->d_df_rowptr;
+  A.df_col = M->d_df_col;
+  A.df_val = M->d_df_val;
+  A.ell = M->ell_w > 0 ? M->d_ell : nullptr;
+  const int grid = A.free_blocks + grid_for(M->m);
+  hipLaunchKernelGGL(k_asm_refill<NB>, dim3(grid), dim3(kBlock), 0, M->ctx->stream, A);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
 // A row has at most (incident triangles + 1) neighbours.
 int launch_assemble_count(fi_mesh* M, bool free_rows) {
   return M->host.delaunay ? assemble_count<kMaxIncidentGeneral + 1>(M, free_rows)
@@ -1032,6 +1135,11 @@ int launch_assemble_count(fi_mesh* M, bool free_rows) {
 int launch_assemble_fill(fi_mesh* M, bool free_rows) {
   return M->host.delaunay ? assemble_fill<kMaxIncidentGeneral + 1>(M, free_rows)
                           : assemble_fill<2 * kMaxIncident>(M, free_rows);
+}
+
+int launch_assemble_refill(fi_mesh* M) {
+  return M->host.delaunay ? assemble_refill<kMaxIncidentGeneral + 1>(M)
+                          : assemble_refill<2 * kMaxIncident>(M);
 }
 
 int scan_counts(fi_mesh* M, const int32_t* cnt, int32_t* rowptr, int64_t n_plus_1) {

@@ -118,8 +118,8 @@ __device__ __forceinline__ T next_r(T r, T s, T q, T a, T b) {
 // ELL entry: bits 0-29 column, bit 30 set for padding (weight 0; the column
 // is then the row itself, so every gather stays in bounds and unconditional),
 // bit 31 set for weight -1, clear for weight -1/2.
-constexpr int32_t kColMask = 0x3FFFFFFF;
-constexpr int32_t kPadBit = 0x40000000;
+constexpr int32_t kColMask = kEllColMask;
+constexpr int32_t kPadBit = kEllPadBit;
 
 __device__ __forceinline__ int ell_col(int32_t e) { return e & kColMask; }
 
