@@ -597,8 +597,8 @@ def l1_main(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not "
-                                   "supported (see DESIGN.md for how the path would shard)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus above 1 is not "
+                                   "supported (the path has no multi-GPU sharding)"}))
         sys.exit(2)
     import torch
     if args.copy_calibration:
