@@ -53,6 +53,7 @@
 #include <string>
 
 #include "internal.h"
+#include "pacer.h"
 #include "reduce.h"
 
 namespace fi {
@@ -842,7 +843,6 @@ int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0
   return FI_OK;
 }
 
-constexpr int kChunk = 8;  // step launches per paced chunk (even)
 
 
 int next_epoch(fi_mesh* M) {
@@ -876,22 +876,12 @@ int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
 // (plain launches: measured faster here than replaying a recorded graph),
 // keeps at most kAhead chunks queued, and stops as soon as the mirror shows
 // the end of this solve. Chunks still queued then run as idle launches;
-// later work on the stream is ordered after them.
-//
-// Queued launches past the end cost a launch each (about 4 us at 512^2), so
-// the host also stops queueing at the launch count the last solve of the
-// same kind on this mesh took (plus kPredMargin); if the solve is still
-// running once all of those have run, queueing goes on as before. The
-// number of launches never changes the result: launches after the end only
-// carry the final record forward.
-constexpr int kAhead = 2;
-constexpr int kPredMargin = 2;
+// later work on the stream is ordered after them. Pacing and the launch
+// prediction: pacer.h.
 static_assert(kAhead <= kChunkEvents, "every queued chunk needs its own event");
 
-// Step launches a solve used: one per iteration, the start and the end of
-// every inner solve, and the launch that found the outer tolerance met.
-int64_t launches_used(const fi_solve_stats* s) {
-  return s->iterations + 2 * (int64_t)s->refinements + 1;
+int64_t launches_of(const fi_solve_stats* s) {
+  return launches_used(s->iterations, s->refinements);
 }
 
 // Which prediction slot a solve uses: precision and cold or warm start.
@@ -901,30 +891,8 @@ int pred_slot(const double* x0) {
 }
 static_assert(kPredSlots == 4, "one slot per precision and start");
 
-// Host pacing of one run of step launches: how many to queue next (even, so
-// every chunk starts at parity 0), or 0 to wait.
-struct Pacer {
-  int64_t cap;                 // launches to queue before waiting for the end
-  int64_t limit;               // launches never exceeded
-  int64_t queued = 0, launched = 0, completed = 0;  // launches; chunks; chunks
-  int next() {
-    if (launched - completed >= kAhead || queued >= limit) return 0;
-    if (queued >= cap) {
-      if (completed != launched) return 0;
-      cap = limit;  // the prediction was short: pace as without one
-    }
-    const int64_t n = std::min<int64_t>(kChunk, cap - queued);
-    return (int)(n + (n & 1));
-  }
-};
-
-Pacer make_pacer(const fi_solve_opts* o, int64_t pred) {
-  // every inner solve takes at most max_inner + 2 launches
-  const int64_t max_launch = (int64_t)(o->max_refine + 1) * (o->max_inner + 2) + 2 * kChunk;
-  Pacer p;
-  p.limit = (max_launch / kChunk + 2) * kChunk;
-  p.cap = pred > 0 ? pred + kPredMargin : p.limit;
-  return p;
+Pacer pacer_for(const fi_solve_opts* o, int64_t pred) {
+  return make_pacer(o->max_inner, o->max_refine, pred);
 }
 
 template <typename T>
@@ -934,11 +902,11 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const d
   int rc = launch_start<T>(M, o, epoch, x0);
   if (rc) return rc;
   const int slot = pred_slot<T>(x0);
-  Pacer pc = make_pacer(o, M->pred_launches[slot]);
+  Pacer pc = pacer_for(o, M->pred_launches[slot]);
   for (;;) {
     int drc = FI_OK;
     if (read_mirror(M, epoch, stats, &drc)) {
-      M->pred_launches[slot] = launches_used(stats);
+      M->pred_launches[slot] = launches_of(stats);
       return drc;
     }
     if (const int n = pc.next()) {
@@ -947,8 +915,7 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const d
         if (rc) return rc;
       }
       FI_HIP_TRY(hipEventRecord(M->chunk_ev[pc.launched % kChunkEvents], st));
-      ++pc.launched;
-      pc.queued += n;
+      pc.queued_chunk(n);
       continue;
     }
     if (pc.completed < pc.launched) {
@@ -1054,7 +1021,7 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
     pred = std::max(pred, p);
   }
   if (!every) pred = 0;
-  Pacer pc = make_pacer(o, pred);
+  Pacer pc = pacer_for(o, pred);
   auto all_done = [&]() {
     bool all = true;
     for (int c = 0; c < nc; ++c) {
@@ -1062,7 +1029,7 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
         int drc = FI_OK;
         done[c] = read_mirror(ch[c], epoch[c], &stats[c], &drc) != 0;
         if (done[c]) {
-          ch[c]->pred_launches[pred_slot<T>(x0 ? x0[c] : nullptr)] = launches_used(&stats[c]);
+          ch[c]->pred_launches[pred_slot<T>(x0 ? x0[c] : nullptr)] = launches_of(&stats[c]);
           if (drc && !first_rc) first_rc = drc;
         }
       }
@@ -1083,8 +1050,7 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
       for (int q = 0; q < n; ++q)
         if ((rc = multi_launch<T>(M0, L, q & 1))) return rc;
       FI_HIP_TRY(hipEventRecord(M0->chunk_ev[pc.launched % kChunkEvents], st));
-      ++pc.launched;
-      pc.queued += n;
+      pc.queued_chunk(n);
       continue;
     }
     if (pc.completed < pc.launched) {
