@@ -219,3 +219,34 @@ def test_multi_kernel_timing_and_bytes(ctx):
     u, st = M.inpaint_rgb(f=torch.from_numpy(f.ravel().copy()).cuda())
     check_same_bits(u, st, grey_channels(M, f), side * side)
     M.close()
+
+
+def test_rgb512_workload_vs_oracle(ctx):
+    """The colour workload as timed: the 512^2, 4% image in three channels,
+    inpainted and tonally optimised to 1e-8 on the GPU, against the oracle's
+    inpainting and its CGLS (exact inner solves) to 1e-12."""
+    w = synth.WORKLOADS["tonal512"]
+    side = w.side
+    f = synth.make_image_rgb(w.seed, side, side, w.bumps, w.edges, w.sigma_lo,
+                             w.sigma_hi).reshape(3, -1)
+    mask = w.mask()
+    M = fi.Mesh(ctx, side, mask)
+    fd = torch.from_numpy(f.ravel().copy()).cuda()
+    u, _ = M.inpaint_rgb(f=fd)
+    mse, _ = M.error_rgb(u, fd)
+    g, st = M.tonal_opt_rgb(fd, opts=fi.TonalOpts(rtol=1e-8))
+    M.close()
+    pr = tonal.Problem(side, mask)
+    want = colour.inpaint(pr, f)
+    err = np.max(np.abs(u.cpu().numpy().reshape(3, -1) - want))
+    mse_ref = colour.mse(want, f)
+    print(f"  inpainting: max |u - oracle| {err:.2e}; mse {mse:.9f} / {mse_ref:.9f}", flush=True)
+    assert err <= 1e-6
+    assert abs(mse - mse_ref) <= 1e-6 * mse_ref
+    g_ref, _, _ = colour.tonal_cgls(pr, f, rtol=1e-12, maxit=2000)
+    for c in range(3):
+        ref = pr.mse_of_g(g_ref[c], f[c])
+        print(f"  channel {c}: tonal mse {st[c]['mse_final']:.9f} / {ref:.9f}, "
+              f"{st[c]['outer_iterations']} outer", flush=True)
+        assert st[c]["status"] == 0
+        assert abs(st[c]["mse_final"] - ref) <= 1e-6 * ref

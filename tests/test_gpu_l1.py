@@ -46,3 +46,23 @@ def test_irls_vs_oracle(ctx, side, dens, seed, delaunay):
     assert hist[-1] < hist[0]
     assert abs(st["mae_final"] - hist_ref[-1]) <= 1e-6 * hist_ref[-1]
     assert l1.huber(pr, g_ref, f, eps) <= l1.huber(pr, pr.default_g(f), f, eps)
+
+
+def test_l1512_workload_vs_oracle(ctx):
+    """The L1 workload as timed on the quadtree mesh: the 512^2, 4% image,
+    8 IRLS steps of 20 CGLS iterations (eps 0.5); the MAE after every step
+    within 1e-6 relative of the oracle's."""
+    w = synth.WORKLOADS["tonal512"]
+    f = w.image().ravel()
+    mask = w.mask()
+    eps, K, J = 0.5, 8, 20
+    M = fi.Mesh(ctx, w.side, mask)
+    g, st, hist = M.tonal_opt_l1(torch.from_numpy(f.copy()).cuda(), eps=eps, irls_iters=K,
+                                 cgls_iters=J)
+    M.close()
+    pr = tonal.Problem(w.side, mask)
+    _, hist_ref = l1.irls(pr, f, eps=eps, K=K, J=J)
+    print(f"  MAE {np.round(hist, 6)} / {np.round(hist_ref, 6)}", flush=True)
+    assert st["irls_iters"] == K
+    assert np.allclose(hist, hist_ref, rtol=1e-6, atol=0)
+    assert abs(st["mse_final"] - pr.mse_of_g(g.cpu().numpy(), f)) <= 1e-6 * st["mse_final"]
