@@ -175,3 +175,24 @@ def test_submit_rejects_bad_requests(ctx):
         r = S.poll(S.submit(f, m, tonal_iters=0))
         assert r["status"] == 0 and r["mse_tonal"] == r["mse_inpaint"]
         assert np.array_equal(r["g"], f[m].astype(np.float64))
+
+
+def test_largest_request_class(ctx):
+    """A request of the trace's largest class (2048^2; the separate
+    partial-sum reduction) beside a small one: the same bits as the
+    single-request path."""
+    big = request(2048, 0.06, 501)
+    small = request(128, 0.05, 502)
+    want_big = single_path(ctx, *big)
+    want_small = single_path(ctx, *small)
+    assert want_big[4]  # large mode
+    with fi.Server(ctx, fi.ServerOpts(max_slots=4)) as S:
+        tb = S.submit(*big, tonal_iters=ITERS)
+        ts_ = S.submit(*small, tonal_iters=ITERS)
+        rb, rs = S.poll(tb), S.poll(ts_)
+    for r, s in ((rb, want_big), (rs, want_small)):
+        assert r["status"] == 0
+        assert r["mse_inpaint"] == s[0]
+        assert np.array_equal(r["g"], s[1])
+        assert r["mse_tonal"] == s[2]
+        assert r["inner_iterations"] == s[3]
