@@ -149,6 +149,7 @@ int make_channel(fi_mesh* M, fi_mesh** out) {
   S->is_channel = true;
   S->host.N = M->host.N;
   S->host.levels = M->host.levels;
+  S->host.delaunay = M->host.delaunay;  // picks the pixel passes and their partial-sum layout
   S->N = M->N;
   S->P = M->P;
   S->V = M->V;

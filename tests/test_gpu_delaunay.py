@@ -240,3 +240,24 @@ def test_separate_reduction_on_delaunay(ctx, monkeypatch):
         assert np.array_equal(u3[c], uc.cpu().numpy())
         assert st3[c]["iterations"] == sc["iterations"]
     M.close()
+
+
+def test_tonal_rgb_on_delaunay(ctx):
+    """Colour tonal optimisation on the paper's mesh (warm adjoint solves,
+    CSR step with three right-hand sides): each channel's g and MSE equal the
+    grey path's bit for bit, and the MSE the oracle's within 1e-6."""
+    side, mask, unk, _ = case("d64")
+    f3 = synth.make_image_rgb(26, side, side, 8, 3).reshape(3, -1)
+    M = mesh(ctx, "d64")
+    opts = fi.TonalOpts(rtol=0.0, max_outer=15)
+    g, st = M.tonal_opt_rgb(torch.from_numpy(f3.ravel().copy()).cuda(), opts=opts)
+    g = g.cpu().numpy().reshape(3, -1)
+    pr = problem("d64")
+    for c in range(3):
+        gc, sc = M.tonal_opt(torch.from_numpy(f3[c].copy()).cuda(), opts=opts)
+        assert np.array_equal(g[c], gc.cpu().numpy())
+        assert st[c]["mse_final"] == sc["mse_final"]
+        g_ref, _, _ = pr.tonal_cgls(f3[c].astype(np.float64), rtol=0.0, maxit=15)
+        ref = pr.mse_of_g(g_ref, f3[c])
+        assert abs(st[c]["mse_final"] - ref) <= 1e-6 * ref
+    M.close()
