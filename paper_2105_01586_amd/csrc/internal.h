@@ -174,13 +174,11 @@ struct fi_mesh {
   int64_t pred_launches[fi::kPredSlots] = {};
   hipEvent_t chunk_ev[fi::kChunkEvents] = {};  // one after each queued chunk of step launches
   fi::CGState cg32, cg64;
-  double* d_part = nullptr;   // 2 x kMaxGrid x 4 partial sums
-  double* d_scal = nullptr;   // scalar slots of the fused CG kernel
-  int32_t* d_ctl = nullptr;   // control words: done flag, iterations, ...
+  double* d_part = nullptr;   // per-block partial sums: 2 parities x cg_grid x 4
   double* d_red = nullptr;    // reduction scratch (kMaxGrid doubles)
   double* d_red_out = nullptr;  // final reduced scalars (8 doubles)
-  double* h_red = nullptr;    // pinned host mirror of d_red_out / d_ctl
-  int32_t* h_ctl = nullptr;
+  double* h_red = nullptr;    // pinned host copies of small device results
+  int32_t* h_ctl = nullptr;   // pinned host copy of the packing flags
   int cg_grid = 0;            // blocks of the fused CG kernel
   int cg_bs = 512;            // threads per block of the fused CG kernel
   // ELL copy of the off-diagonal part of K_FF, column-major by row: slot k of

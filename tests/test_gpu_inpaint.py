@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import paper_2105_01586_amd as fi
+import synth
 from gpu_common import SMALL_CASES, case, oracle_inpaint, oracle_problem
 
 pytestmark = pytest.mark.gpu
@@ -200,19 +201,32 @@ def test_block_sizes_agree(ctx, bs, monkeypatch):
     M.close()
 
 
-@pytest.mark.parametrize("name", ["n128_k300", "c2"])
-def test_reassembly_keeps_every_bit(ctx, name):
+@pytest.mark.parametrize("name,kind", [("n128_k300", "ell"), ("c2", "ell"), ("n256_k2000", "large"),
+                                       ("n256_k2000", "delaunay")])
+def test_reassembly_keeps_every_bit(ctx, name, kind, monkeypatch):
     """Later assemblies recompute every value (free and mask rows and the ELL
     slots) in one launch: the matrices and a solve afterwards are the same
-    bits as after the first assembly."""
-    M = gpu_mesh(ctx, name)
-    _, _, f = case(name)
+    bits as after the first assembly. Also with the large-system launch shape
+    and on the Delaunay mesh (CSR, up to 32 neighbours per row)."""
+    side, mask, f = case(name)
+    if kind == "large":
+        monkeypatch.setenv("FI_CG_LARGE", "1")
+        M = fi.Mesh(ctx, side, mask)
+        monkeypatch.delenv("FI_CG_LARGE")
+        assert M.large_mode()
+    elif kind == "delaunay":
+        unk = synth.make_unknowns(15, side * side, mask, mask.size)
+        M = fi.Mesh(ctx, side, mask, unknowns=unk)
+    else:
+        M = gpu_mesh(ctx, name)
     before = M.export_csr()
     u1, st1 = M.inpaint(f=dev(f))
     for _ in range(2):
         M.assemble()
     after = M.export_csr()
     u2, st2 = M.inpaint(f=dev(f))
+    if kind != "ell":
+        M.close()
     for k in before:
         assert np.array_equal(before[k], after[k]), k
     assert torch.equal(u1, u2) and st1["iterations"] == st2["iterations"]
