@@ -69,3 +69,21 @@ def test_l1512_workload_vs_oracle(ctx, delaunay):
     assert st["irls_iters"] == K
     assert np.allclose(hist, hist_ref, rtol=1e-6, atol=0)
     assert abs(st["mse_final"] - pr.mse_of_g(g.cpu().numpy(), f)) <= 1e-6 * st["mse_final"]
+
+
+def test_irls_from_given_g(ctx):
+    """The L1 optimisation started from a given g (f on the mask plus seeded
+    noise) against the oracle's IRLS from the same g."""
+    side, dens, seed = 128, 0.05, 54
+    P = side * side
+    mask = synth.make_mask(seed, P, dens)
+    f = synth.make_image(seed, side, side, 8, 3).ravel()
+    pr = tonal.Problem(side, mask)
+    g0 = pr.default_g(f) + np.random.default_rng(18).normal(scale=4.0, size=mask.size)
+    M = fi.Mesh(ctx, side, mask)
+    g, st, hist = M.tonal_opt_l1(torch.from_numpy(f.copy()).cuda(), g=torch.from_numpy(g0.copy()).cuda(),
+                                 eps=0.5, irls_iters=3, cgls_iters=8)
+    M.close()
+    _, hist_ref = l1.irls(pr, f, eps=0.5, K=3, J=8, g0=g0)
+    print(f"  MAE {np.round(hist, 6)} / {np.round(hist_ref, 6)}", flush=True)
+    assert np.allclose(hist, hist_ref, rtol=1e-6, atol=0)

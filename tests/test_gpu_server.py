@@ -196,3 +196,19 @@ def test_largest_request_class(ctx):
         assert np.array_equal(r["g"], s[1])
         assert r["mse_tonal"] == s[2]
         assert r["inner_iterations"] == s[3]
+
+
+def test_one_slot_fp32_matches_single_path(ctx):
+    """max_slots = 1 runs requests one at a time through the single-mesh FP32
+    solver: the same bits as fi_inpaint + fi_tonal_opt, and no batched steps."""
+    reqs = [request(128, 0.05, 601), request(256, 0.03, 602)]
+    want = [single_path(ctx, *r) for r in reqs]
+    with fi.Server(ctx, fi.ServerOpts(max_slots=1)) as S:
+        tickets = [S.submit(*r, tonal_iters=ITERS) for r in reqs]
+        got = [S.poll(t) for t in tickets]
+        assert S.stats()["step_rounds"] == 0
+    for r, s in zip(got, want):
+        assert r["status"] == 0
+        assert r["mse_inpaint"] == s[0]
+        assert np.array_equal(r["g"], s[1])
+        assert r["mse_tonal"] == s[2]

@@ -141,3 +141,22 @@ def test_adjoint_warm_start(ctx, name):
         assert abs(st["mse_final"] - mse_ref) <= 1e-6 * mse_ref
         assert abs(pr.mse_of_g(g.cpu().numpy(), f) - mse_ref) <= 1e-6 * mse_ref
     assert st_w["inner_iterations"] < st_c["inner_iterations"]
+
+
+@pytest.mark.parametrize("name", ["n64_c1", "n256_k2000"])
+def test_tonal_from_given_g(ctx, name):
+    """start_from_g: CGLS from a given g (f on the mask plus seeded noise)
+    against the oracle's CGLS from the same g, 20 iterations."""
+    M = gpu_mesh(ctx, name)
+    pr = oracle_problem(name)
+    _, _, f = case(name)
+    g0 = pr.default_g(f) + np.random.default_rng(17).normal(scale=5.0, size=M.m)
+    g = dev(g0.copy())
+    g, st = M.tonal_opt(dev(f), g=g, opts=fi.TonalOpts(rtol=0.0, max_outer=20, start_from_g=True))
+    g_ref, it, _ = pr.tonal_cgls(f.astype(np.float64), g0=g0, rtol=0.0, maxit=20)
+    assert it == 20
+    mse0 = pr.mse_of_g(g0, f)
+    ref = pr.mse_of_g(g_ref, f)
+    print(f"  mse from g0 {mse0:.6f} -> {st['mse_final']:.9f} (oracle {ref:.9f})", flush=True)
+    assert abs(st["mse_initial"] - mse0) <= 1e-6 * mse0
+    assert abs(st["mse_final"] - ref) <= 1e-6 * ref
