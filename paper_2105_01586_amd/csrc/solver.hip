@@ -279,6 +279,11 @@ __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, P
 // LATE: gather the neighbours after the reduction even when the block
 // re-reduces the partials itself (fewer registers: more blocks per CU when
 // one launch carries several solves).
+// CSR entries per row loaded in one batch by the step (most rows of the
+// meshes here have fewer: the Delaunay mesh's free rows hold about 3
+// off-diagonal entries, at most 8 to 11).
+constexpr int kCsrBatch = 8;
+
 template <typename T, int W, bool SUMMED, int BS, bool LATE = false>
 __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, double* lds) {
   constexpr bool PRE = !SUMMED && !LATE;  // neighbour values loaded before the reduction
@@ -325,6 +330,35 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
         nd[k] = qn.d;
         nw[k] = ell_weight<T>(e[k]);
       }
+    }
+  }
+  // CSR rows: the first kCsrBatch entries are loaded together (column and
+  // value, then the neighbour's record; before the reduction when PRE), so a
+  // row costs two dependent rounds of loads whatever its length; longer rows
+  // finish in a loop. Every index read stays inside the arrays (they hold at
+  // least one entry): slots past the row end read the row's last entry or
+  // slot 0 and are masked.
+  constexpr int kCB = W == 0 ? kCsrBatch : 1;
+  int j0 = 0, j1 = 0;
+  int32_t cc[kCB];
+  T cv[kCB];
+  Quad<T> cq[kCB];
+  if constexpr (W == 0) {
+    j0 = A.rowptr[ic];
+    j1 = A.rowptr[ic + 1];
+    const int jl = j1 > 0 ? j1 - 1 : 0;
+#pragma unroll
+    for (int k = 0; k < kCB; ++k) {
+      const bool in = j0 + k < j1;
+      const int jc = min(j0 + k, jl);
+      const int32_t c = A.col[jc];
+      const T v = A.val[jc];
+      cc[k] = in ? c : ic;
+      cv[k] = in ? v : T(0);
+    }
+    if constexpr (PRE) {
+#pragma unroll
+      for (int k = 0; k < kCB; ++k) cq[k] = A.rq_in[cc[k]];
     }
   }
   const bool writer = lb == 0 && threadIdx.x == 0;
@@ -492,8 +526,18 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
         acc = fmaT(nw[k], nd[k] * rc, acc);
       }
     } else {
-      const int j1 = A.rowptr[i + 1];
-      for (int j = A.rowptr[i]; j < j1; ++j) {
+      if constexpr (!PRE) {
+#pragma unroll
+        for (int k = 0; k < kCB; ++k) cq[k] = A.rq_in[cc[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kCB; ++k) {
+        if (j0 + k < j1) {
+          const T rc = next_r(cq[k].r, cq[k].s, cq[k].q, a, b);
+          acc = fmaT(cv[k], cq[k].d * rc, acc);
+        }
+      }
+      for (int j = j0 + kCB; j < j1; ++j) {
         const Quad<T> qc = A.rq_in[A.col[j]];
         const T rc = next_r(qc.r, qc.s, qc.q, a, b);
         acc = fmaT(A.val[j], qc.d * rc, acc);
