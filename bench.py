@@ -295,8 +295,11 @@ def densify_main(args):
     * the same at 512^2 on the paper's own Delaunay mesh, with m unknown
       vertices drawn once.
 
-    ``value`` is inpainted Mpixel/s over all the loops (pixels of every
-    inpainting / wall time, mesh builds included)."""
+    ``value`` is inpainted Mpixel/s over all the loops with the time the
+    workload defines: the solves, interpolation and error of every round
+    (HIP events around them; the host mesh builds and the pixel selection
+    between rounds excluded). ``mpixel_per_s_wall`` is the same over wall
+    time, mesh builds included."""
     import torch
     import paper_2105_01586_amd as fi
     import synth
@@ -316,7 +319,8 @@ def densify_main(args):
                       "inpaintings": rounds + 1, "final_mask": int(order.size),
                       "wall_s": wall, "gpu_ms_total": float(np.sum(ms)),
                       "mse_first": float(mse[0]), "mse_last": float(mse[-1]),
-                      "mpixel_per_s": (rounds + 1) * side * side / wall / 1e6}
+                      "mpixel_per_s": (rounds + 1) * side * side / (float(np.sum(ms)) * 1e3),
+                      "mpixel_per_s_wall": (rounds + 1) * side * side / wall / 1e6}
         print(f"{name}: {wall:.2f} s, device {np.sum(ms):.1f} ms", file=sys.stderr, flush=True)
         return order
 
@@ -343,6 +347,7 @@ def densify_main(args):
         unknowns=synth.make_unknowns(2, Pn, mask0, m))
     total_pix = sum(r["inpaintings"] * r["side"] ** 2 for r in runs.values())
     total_wall = sum(r["wall_s"] for r in runs.values())
+    total_dev_ms = sum(r["gpu_ms_total"] for r in runs.values())
     # dominant kernel on the final 1024^2 mesh of the per-triangle run
     M = fi.Mesh(ctx, 1024, last_mask)
     fd = torch.from_numpy(f1024.ravel().copy()).cuda()
@@ -353,9 +358,10 @@ def densify_main(args):
     M.close()
     out = {
         "metric": "inpainted Mpixel/s + tonal-opt solves/s at <=1e-6 err vs FP64; p50/p99 latency",
-        "value": total_pix / total_wall / 1e6,
+        "value": total_pix / (total_dev_ms * 1e3),
         "unit": "Mpixel/s",
-        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": total_wall * 1e3,
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": total_dev_ms,
+        "mpixel_per_s_wall": total_pix / total_wall / 1e6,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (CG) + f64 (residual, refinement, error)", "data": "synthetic",
         "config": {"workload": "densify: 1024^2 top-k 1%->3% x20 rounds; paper per-triangle "
