@@ -115,6 +115,29 @@ def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None):
                       f"solve, interpolation, MSE), {el:.1f} s"}, err
 
 
+def crop_check(fi, ctx, f_np, mask):
+    """The final MSEs on the 2048^2 crop the oracle can solve (inpainting,
+    and tonal optimisation to 1e-8), against the oracle's values stored in
+    tests/golden/large8192_crop.json (written by the script beside it, which
+    calls only the oracle)."""
+    import torch
+    import synth
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
+                                       "golden", "large8192_crop.json")))
+    r0, c0 = synth.busiest_block(f_np, 2048)
+    cf, cm = synth.crop(f_np, mask, r0, c0, 2048)
+    M = fi.Mesh(ctx, 2048, cm)
+    fd = torch.from_numpy(cf.ravel().copy()).cuda()
+    u, _ = M.inpaint(f=fd)
+    mse, _, _ = M.error(u, fd)
+    _, ts = M.tonal_opt(fd, opts=fi.TonalOpts(rtol=1e-8))
+    M.close()
+    return {"crop_origin": [r0, c0], "mse_inpaint": mse, "mse_inpaint_oracle": gold["mse_inpaint"],
+            "mse_tonal": ts["mse_final"], "mse_tonal_oracle": gold["mse_tonal"],
+            "rel_diff_inpaint": abs(mse - gold["mse_inpaint"]) / gold["mse_inpaint"],
+            "rel_diff_tonal": abs(ts["mse_final"] - gold["mse_tonal"]) / gold["mse_tonal"]}
+
+
 def fd_check(fi, mesh, f, f_np, mask, n_dir=16, eps=1e-3, seed=7):
     """The gradient of MSE(g) = ||B g - f||^2 / P from the adjoint,
     (2 / P) B^T (B g - f), against central differences along 16 random
@@ -764,6 +787,8 @@ def main():
             cf, cm = synth.crop(f_np, mask, r0, c0, 2048)
             cb, _ = cpu_baseline(2048, cf, cm, None, f"the 2048^2 crop at ({r0}, {c0})")
         out["cpu_baseline"] = cb
+    if big:
+        out["crop_vs_oracle"] = crop_check(fi, ctx, f_np, mask)
     print(json.dumps(out))
     mesh.close()
     ctx.close()
