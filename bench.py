@@ -84,12 +84,13 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None):
+def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None, tonal_rtol=None):
     """The oracle, as it stands, on repeated inpaintings of ``what`` until
     about 10 s of host time have passed (at least one). Also returns the GPU
     result's agreement with it: max |u - u_oracle|, and with ``grad_at`` =
     (g, GPU gradient of the MSE at g) the oracle's MSE and the gradient's
-    relative error against the oracle's."""
+    relative error against the oracle's; with ``tonal_rtol`` the MSE after
+    the oracle's own CGLS to that tolerance (untimed)."""
     from oracle import tonal
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -110,6 +111,10 @@ def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None):
         ref = pr.mse_grad(g0, f_np.ravel())
         err = {"max_abs_pixel_err": err, "mse_oracle": pr.mse(u_ref, f_np.ravel()),
                "grad_rel_err_vs_oracle": float(np.linalg.norm(grad - ref) / np.linalg.norm(ref))}
+        if tonal_rtol is not None:
+            g_t, it_t, _ = pr.tonal_cgls(f_np.ravel().astype(np.float64), rtol=tonal_rtol)
+            err["mse_tonal_oracle"] = pr.mse_of_g(g_t, f_np.ravel())
+            err["tonal_iterations_oracle"] = it_t
     return {"value": P * reps / el / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"{reps} full inpainting(s) of {what} (mesh, assembly, direct Cholesky, "
                       f"solve, interpolation, MSE), {el:.1f} s"}, err
@@ -776,9 +781,11 @@ def main():
     if not args.no_cpu_baseline:
         if w.side <= 1024:
             cb, acc = cpu_baseline(w.side, f_np, mask, u.cpu().numpy(), f"the {w.side}^2 image",
-                                   grad_at=g_fd)
+                                   grad_at=g_fd, tonal_rtol=1e-8)
             out["max_abs_err_vs_fp64_oracle"] = acc["max_abs_pixel_err"]
             out["mse_inpaint_oracle"] = acc["mse_oracle"]
+            out["mse_tonal_oracle"] = acc["mse_tonal_oracle"]
+            out["tonal_outer_iterations_oracle"] = acc["tonal_iterations_oracle"]
             out["gradient_fd_check"]["rel_err_vs_oracle_gradient"] = acc["grad_rel_err_vs_oracle"]
         else:
             # the oracle on the whole image is out of reach; it runs on the
