@@ -84,6 +84,13 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_cores_used(t_wall0, t_cpu0):
+    """Threads the oracle actually kept busy over a sample: this process's
+    CPU time (all its threads) over the wall time."""
+    wall = time.perf_counter() - t_wall0
+    return round((time.process_time() - t_cpu0) / wall, 2) if wall > 0 else None
+
+
 def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None, tonal_rtol=None):
     """The oracle, as it stands, on repeated inpaintings of ``what`` until
     about 10 s of host time have passed (at least one). Also returns the GPU
@@ -92,8 +99,7 @@ def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None, tonal_rtol=None):
     relative error against the oracle's; with ``tonal_rtol`` the MSE after
     the oracle's own CGLS to that tolerance (untimed)."""
     from oracle import tonal
-    cores = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     reps = 0
     u_ref = None
     while True:
@@ -104,6 +110,7 @@ def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None, tonal_rtol=None):
         el = time.perf_counter() - t0
         if el > 10.0 or reps >= 100:
             break
+    cores = cpu_cores_used(t0, c0)
     P = side * side
     err = float(np.max(np.abs(u_gpu - u_ref))) if u_gpu is not None else None
     if grad_at is not None:
@@ -115,7 +122,8 @@ def cpu_baseline(side, f_np, mask, u_gpu, what, grad_at=None, tonal_rtol=None):
             g_t, it_t, _ = pr.tonal_cgls(f_np.ravel().astype(np.float64), rtol=tonal_rtol)
             err["mse_tonal_oracle"] = pr.mse_of_g(g_t, f_np.ravel())
             err["tonal_iterations_oracle"] = it_t
-    return {"value": P * reps / el / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+    return {"value": P * reps / el / 1e6, "unit": "Mpixel/s", "cores": cores,
+            "host_cores": len(os.sched_getaffinity(0)), "kind": "oracle",
             "sample": f"{reps} full inpainting(s) of {what} (mesh, assembly, direct Cholesky, "
                       f"solve, interpolation, MSE), {el:.1f} s"}, err
 
@@ -291,8 +299,7 @@ def serving_cpu_baseline(trace, reqs, iters):
     """The oracle on the first requests of side <= 256 until about 15 s:
     inpainting plus the same CGLS iterations with exact Cholesky solves."""
     from oracle import tonal
-    cores = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     pix, n = 0, 0
     for r, (f, m) in zip(trace, reqs):
         if r.side > 256:
@@ -305,7 +312,8 @@ def serving_cpu_baseline(trace, reqs, iters):
         if time.perf_counter() - t0 > 15.0:
             break
     el = time.perf_counter() - t0
-    return {"value": pix / el / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+    return {"value": pix / el / 1e6, "unit": "Mpixel/s", "cores": cpu_cores_used(t0, c0),
+            "host_cores": len(os.sched_getaffinity(0)), "kind": "oracle",
             "sample": f"{n} requests of side <= 256 from the trace (inpainting + {iters} CGLS "
                       f"iterations, direct Cholesky), {el:.1f} s"}
 
@@ -413,13 +421,12 @@ def densify_cpu_baseline(f512):
     error, selection."""
     from oracle import densify, tonal
     import synth
-    cores = len(os.sched_getaffinity(0))
     side = 512
     P = side * side
     k = synth.count_from_density(0.04, P) // 10
     mask0 = synth.make_mask(2, P, k=k)
     f = f512.ravel()
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     n = 0
     while time.perf_counter() - t0 <= 10.0 and n < 100:
         mask = mask0
@@ -433,7 +440,8 @@ def densify_cpu_baseline(f512):
             add = densify.paper_densify_step(e, pr.rast.owner, pr.mesh.T, mask, k)
             mask = np.sort(np.concatenate([mask, add]))
     el = time.perf_counter() - t0
-    return {"value": n * P / el / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+    return {"value": n * P / el / 1e6, "unit": "Mpixel/s", "cores": cpu_cores_used(t0, c0),
+            "host_cores": len(os.sched_getaffinity(0)), "kind": "oracle",
             "sample": f"{n} rounds of the per-triangle loop at 512^2 (mesh, direct Cholesky, "
                       f"inpainting, error, selection), {el:.1f} s"}
 
@@ -545,8 +553,7 @@ def colour_main(args):
     }
     if not args.no_cpu_baseline:
         from oracle import colour, tonal
-        cores = len(os.sched_getaffinity(0))
-        t0 = time.perf_counter()
+        t0, c0 = time.perf_counter(), time.process_time()
         reps = 0
         while True:
             pr = tonal.Problem(side, mask)
@@ -556,10 +563,11 @@ def colour_main(args):
             el = time.perf_counter() - t0
             if el > 10.0 or reps >= 100:
                 break
+        cores = cpu_cores_used(t0, c0)
         out["max_abs_err_vs_fp64_oracle"] = float(np.max(np.abs(u.cpu().numpy().reshape(3, -1)
                                                                 - u_ref)))
         out["cpu_baseline"] = {"value": reps * P / el / 1e6, "unit": "Mpixel/s", "cores": cores,
-                               "kind": "oracle",
+                               "host_cores": len(os.sched_getaffinity(0)), "kind": "oracle",
                                "sample": f"{reps} colour inpainting(s) of the 512^2 image (mesh, "
                                          f"assembly, one direct Cholesky, three solves, "
                                          f"interpolation, MSE), {el:.1f} s"}
