@@ -260,6 +260,12 @@ int fi_error(fi_mesh* mesh, const double* u_dev, const uint8_t* f_dev, double* m
 int fi_solve(fi_mesh* mesh, const double* b_dev, const double* x0_dev, double* x_dev,
              const fi_solve_opts* opts, fi_solve_stats* stats);
 
+/* The squared-error sum of fi_error, sum_i (u_i - f_i)^2 (MSE = sum / P),
+ * left in device memory: stream-ordered, no host synchronisation, the same
+ * bits as fi_error's sum (the same kernels and order).
+ *   sse_dev: one float64 output on the device. */
+int fi_error_dev(fi_mesh* mesh, const double* u_dev, const uint8_t* f_dev, double* sse_dev);
+
 /* Adjoint of the inpainting map, s = B^T r = t_D - K_DF K_FF^{-1} t_F with
  * t = R^T r (R: interpolation to pixels). Section 4's nested CG applies it
  * through one more solve with the same symmetric matrix.

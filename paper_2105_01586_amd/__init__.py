@@ -38,7 +38,7 @@ EXPORTED_SYMBOLS = (
     "fi_solve_opts_default", "fi_tonal_opts_default", "fi_last_error", "fi_version",
     "fi_ctx_create", "fi_ctx_set_stream", "fi_ctx_destroy", "fi_mesh_build", "fi_mesh_destroy",
     "fi_mesh_get_info", "fi_assemble", "fi_inpaint", "fi_vertex_values", "fi_error",
-    "fi_adjoint", "fi_solve", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
+    "fi_adjoint", "fi_solve", "fi_error_dev", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
     "fi_owner_map", "fi_topk_new_pixels", "fi_time_cg_kernel", "fi_cg_kernel_bytes",
     "fi_host_mesh_build", "fi_host_mesh_info", "fi_host_mesh_export", "fi_host_mesh_destroy",
     "fi_mesh_upload", "fi_grow_mask", "fi_server_opts_default", "fi_server_create",
@@ -172,6 +172,7 @@ def library() -> ctypes.CDLL:
                                       ctypes.POINTER(_SolveStats)]),
         "fi_vertex_values": (ctypes.c_int, [vp, vp]),
         "fi_error": (ctypes.c_int, [vp, vp, vp, dp, vp, vp]),
+        "fi_error_dev": (ctypes.c_int, [vp, vp, vp, vp]),
         "fi_solve": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                     ctypes.POINTER(_SolveStats)]),
         "fi_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_SolveOpts),
@@ -550,6 +551,19 @@ class Mesh:
                                       st)
         _check(rc, "fi_inpaint_rgb")
         return u, [_stats(x) for x in st]
+
+    def error_dev(self, u, f, sse=None):
+        """Sum of squared errors of u against f into a one-element float64
+        device tensor, without waiting for it (MSE = sum / P). Returns it."""
+        torch = _torch()
+        d = self._dev()
+        if sse is None:
+            sse = self._empty(1, torch.float64)
+        rc = library().fi_error_dev(self._h, _ptr(u, torch.float64, self.P, "u", d),
+                                    _ptr(f, torch.uint8, self.P, "f", d),
+                                    _ptr(sse, torch.float64, 1, "sse", d))
+        _check(rc, "fi_error_dev")
+        return sse
 
     def error_rgb(self, u, f):
         """Returns (colour MSE over all 3P values, [MSE of each channel])."""

@@ -611,6 +611,14 @@ int fi_error(fi_mesh* M, const double* u_dev, const uint8_t* f_dev, double* mse_
   return FI_OK;
 }
 
+int fi_error_dev(fi_mesh* M, const double* u_dev, const uint8_t* f_dev, double* sum_dev) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_dev || !f_dev || !sum_dev) return fail(FI_E_INVALID, "u_dev, f_dev and sse_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  return fi::sse_dev(M, u_dev, f_dev, sum_dev);
+}
+
 int fi_adjoint(fi_mesh* M, const double* r_dev, double* s_dev, const fi_solve_opts* opts,
                fi_solve_stats* stats) {
   int rc = check_mesh(M);

@@ -230,3 +230,15 @@ def test_reassembly_keeps_every_bit(ctx, name, kind, monkeypatch):
     for k in before:
         assert np.array_equal(before[k], after[k]), k
     assert torch.equal(u1, u2) and st1["iterations"] == st2["iterations"]
+
+
+def test_error_dev_matches_error(ctx):
+    """fi_error_dev leaves the squared-error sum on the device: the same bits
+    as fi_error's MSE times P."""
+    M = gpu_mesh(ctx, "c2")
+    _, _, f = case("c2")
+    fd = dev(f)
+    u, _ = M.inpaint(f=fd)
+    mse, _, _ = M.error(u, fd)
+    sse = M.error_dev(u, fd)
+    assert sse.item() / M.P == mse
