@@ -26,7 +26,10 @@ inline int grid_for(int64_t n, int per_block = kBlock) {
 // v and w of (b_v b_w + c_v c_w) / (4A), with b_i = y_j - y_k, c_i = x_k - x_j
 // for (i, j, k) cyclic (Section 2.2, P1 elements). Returns the distinct
 // neighbours with non-zero weight, sorted by vertex id, and the diagonal.
-// NB: capacity of the neighbour list (at least the incident triangles + 1).
+// NB: capacity of the neighbour list, at least the distinct neighbours of
+// any vertex. Quadtree meshes use NB = kMaxIncident: an interior vertex has a
+// closed fan (as many neighbours as triangles) and the builder keeps border
+// vertices to kMaxIncident - 1 triangles (open fan: one neighbour more).
 template <int NB>
 __device__ __forceinline__ int stiffness_row(int v, const int32_t* __restrict__ vxy,
                                              const int32_t* __restrict__ tri,
@@ -40,7 +43,7 @@ __device__ __forceinline__ int stiffness_row(int v, const int32_t* __restrict__ 
   // Quadtree rows (at most kMaxIncident triangles): every index and
   // coordinate is loaded before the arithmetic, three dependent rounds in
   // all instead of three per triangle. Other meshes walk the list.
-  constexpr bool PRE = NB == 2 * kMaxIncident;
+  constexpr bool PRE = NB == kMaxIncident;
   constexpr int MT = PRE ? kMaxIncident : 1;
   int pb[MT], pc[MT];
   int64_t pxb[MT], pyb[MT], pxc[MT], pyc[MT];
@@ -1129,17 +1132,17 @@ int assemble_refill(fi_mesh* M) {
 // A row has at most (incident triangles + 1) neighbours.
 int launch_assemble_count(fi_mesh* M, bool free_rows) {
   return M->host.delaunay ? assemble_count<kMaxIncidentGeneral + 1>(M, free_rows)
-                          : assemble_count<2 * kMaxIncident>(M, free_rows);
+                          : assemble_count<kMaxIncident>(M, free_rows);
 }
 
 int launch_assemble_fill(fi_mesh* M, bool free_rows) {
   return M->host.delaunay ? assemble_fill<kMaxIncidentGeneral + 1>(M, free_rows)
-                          : assemble_fill<2 * kMaxIncident>(M, free_rows);
+                          : assemble_fill<kMaxIncident>(M, free_rows);
 }
 
 int launch_assemble_refill(fi_mesh* M) {
   return M->host.delaunay ? assemble_refill<kMaxIncidentGeneral + 1>(M)
-                          : assemble_refill<2 * kMaxIncident>(M);
+                          : assemble_refill<kMaxIncident>(M);
 }
 
 int scan_counts(fi_mesh* M, const int32_t* cnt, int32_t* rowptr, int64_t n_plus_1) {

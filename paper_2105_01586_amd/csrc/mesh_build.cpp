@@ -240,12 +240,20 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& H) {
   // ---- vertex -> (triangle, corner) adjacency ----------------------------
   H.vt_ptr.assign((size_t)(V + 1), 0);
   for (int64_t e = 0; e < 3 * T; ++e) H.vt_ptr[(size_t)H.tri[(size_t)e] + 1]++;
+  // A vertex on the square's border has an open fan, one neighbour more than
+  // triangles; the assembly's neighbour slots hold kMaxIncident.
+  bool border_ok = true;
   for (int64_t v = 0; v < V; ++v) {
-    H.max_incident = std::max(H.max_incident, H.vt_ptr[(size_t)v + 1]);
+    const int32_t inc = H.vt_ptr[(size_t)v + 1];
+    const int32_t x = H.vxy[(size_t)(2 * v)], y = H.vxy[(size_t)(2 * v + 1)];
+    border_ok &= !(x == 0 || y == 0 || x == N || y == N) || inc <= kMaxIncident - 1;
+    H.max_incident = std::max(H.max_incident, inc);
     H.vt_ptr[(size_t)v + 1] += H.vt_ptr[(size_t)v];
   }
   if (H.max_incident > kMaxIncident)
     return fail(FI_E_INVALID, "internal: vertex with more incident triangles than expected");
+  if (!border_ok)
+    return fail(FI_E_INVALID, "internal: border vertex with more incident triangles than expected");
   H.vt_idx.resize((size_t)(3 * T));
   {
     std::vector<int32_t> fill(H.vt_ptr.begin(), H.vt_ptr.end() - 1);
