@@ -83,6 +83,45 @@ def test_host_mesh_full_and_edge_masks():
         assert np.array_equal(h["tri"], o.tri)
 
 
+def _neighbour_counts(h):
+    """Distinct neighbours and incident triangles of every vertex."""
+    tri = h["tri"].astype(np.int64)
+    V = h["vxy"].shape[0]
+    edges = np.concatenate([tri[:, [a, b]] for a in range(3) for b in range(3) if a != b])
+    edges = np.unique(edges, axis=0)
+    nbrs = np.bincount(edges[:, 0], minlength=V)
+    tris = np.bincount(tri.ravel(), minlength=V)
+    return nbrs, tris
+
+
+@pytest.mark.parametrize("N,seed,kind", [(64, 1, "random"), (128, 2, "random"), (128, 3, "border"),
+                                         (256, 4, "clusters"), (64, 5, "border")])
+def test_quadtree_neighbour_bound(N, seed, kind):
+    # The device assembly keeps 8 neighbour slots per quadtree row: a vertex
+    # inside the square has a closed fan (neighbours = triangles <= 8), one on
+    # its border an open fan (neighbours = triangles + 1), so the builder must
+    # keep border vertices to 7 triangles.
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        m = np.sort(rng.choice(N * N, size=N * N // 20, replace=False))
+    elif kind == "border":
+        b = np.concatenate([np.arange(N), (N - 1) * N + np.arange(N), np.arange(N) * N,
+                            np.arange(N) * N + N - 1])
+        m = np.unique(rng.choice(b, size=N, replace=False))
+    else:
+        c = rng.integers(0, N, size=(6, 2))
+        pts = (c[:, None, :] + rng.integers(-3, 4, size=(6, 40, 2))).reshape(-1, 2) % N
+        m = np.unique(pts[:, 0] * N + pts[:, 1])
+    h = fi.host_mesh(N, m)
+    nbrs, tris = _neighbour_counts(h)
+    x, y = h["vxy"][:, 0], h["vxy"][:, 1]
+    border = (x == 0) | (y == 0) | (x == N) | (y == N)
+    assert nbrs.max() <= 8
+    assert np.array_equal(nbrs[~border], tris[~border])
+    assert np.array_equal(nbrs[border], tris[border] + 1)
+    assert tris[border].max() <= 7
+
+
 @pytest.mark.parametrize("side,mask,code", [
     (16, [], fi.E_EMPTY_MASK),
     (16, [3, 3], fi.E_INVALID),
