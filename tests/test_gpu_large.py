@@ -3,7 +3,8 @@
 * On the 2048^2 crop (the block with the most unclipped pixels, which the
   oracle can still factor directly) the GPU must match values the oracle
   wrote to tests/golden/large8192_crop.json: sampled pixels within 1e-6,
-  inpainting and tonal MSE within 1e-6 relative.
+  inpainting and tonal MSE within 1e-6 relative; and every pixel within 1e-6
+  of an FP64 solve stopped at 1e-13.
 * On the full image, where no direct solve is affordable, the checks are
   ones that hold at any size and that the oracle can compute piece by
   piece: the quadtree leaves bit for bit against the oracle's own builder,
@@ -66,6 +67,14 @@ def test_crop_matches_golden(ctx, workload):
           f"mse {mse:.9f} golden {gold['mse_inpaint']:.9f}")
     assert err <= 1e-6
     assert abs(mse - gold["mse_inpaint"]) <= 1e-6 * gold["mse_inpaint"]
+    # every pixel of the default solve (stop at 1e-10) against an FP64 solve
+    # stopped at 1e-13: the largest image size the default is meant for
+    ut, stt = M.inpaint(f=fd, opts=fi.SolveOpts(precision=fi.PREC_FP64, rtol=1e-13))
+    assert stt["status"] == 0 and stt["rel_residual"] <= 1e-13
+    err_all = float((u - ut).abs().max())
+    print(f"  crop: every pixel against FP64 at 1e-13: max difference {err_all:.3e}", flush=True)
+    assert err_all <= 1e-6
+    del ut
     g, ts = M.tonal_opt(fd, opts=fi.TonalOpts(rtol=1e-8))
     print(f"  crop tonal: outer {ts['outer_iterations']} mse {ts['mse_final']:.9f} "
           f"golden {gold['mse_tonal']:.9f}")
