@@ -449,7 +449,7 @@ def densify_cpu_baseline(f512):
 
 
 def colour_main(args):
-    """Colour (Section 6: the method per channel on one shared mesh): the
+    """Colour (Section 5: the method per channel on one shared mesh): the
     512^2 image of the tonal512 recipe in three correlated channels
     (synth.make_image_rgb), 4% mask. One step = assembly, inpainting of all
     three channels (one multi-right-hand-side solve), colour MSE, then tonal

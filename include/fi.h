@@ -399,7 +399,8 @@ int fi_time_cg_kernel(fi_mesh* mesh, int precision, int reps, double* ms_per_lau
 int fi_cg_kernel_bytes(const fi_mesh* mesh, int precision, int64_t* bytes);
 
 /* ------------------------------------------------------------- colour --
- * Section 6 extends the method to colour images channel by channel. The
+ * Section 5 calls the extension to colour images straightforward; it is
+ * read here as the method applied channel by channel. The
  * three channels share the mask, so they share the mesh, K_FF, K_FD and the
  * interpolation; each channel is the grey problem with its own data. Arrays
  * are planar: channel c of a per-pixel array occupies [c * P, (c + 1) * P),
@@ -417,7 +418,7 @@ int fi_cg_kernel_bytes(const fi_mesh* mesh, int precision, int64_t* bytes);
  * per-image part of the mesh's memory); fi_mesh_get_info's device_bytes
  * includes it from then on. Colour calls are synchronous like the grey ones. */
 
-/* u_c = B g_c for c = 0, 1, 2 (Section 4's B, Section 6).
+/* u_c = B g_c for c = 0, 1, 2 (Section 4's B, Section 5).
  *   f_dev: uint8[3P] device, planar; used only when g_dev is NULL (then
  *          g_c = f_c on the mask). May be NULL when g_dev is given.
  *   g_dev: float64[3m] device, planar, or NULL.
@@ -438,7 +439,7 @@ int fi_inpaint_rgb(fi_mesh* mesh, const uint8_t* f_dev, const double* g_dev, dou
 int fi_error_rgb(fi_mesh* mesh, const double* u_dev, const uint8_t* f_dev, double* mse_host,
                  double* mse_ch_host);
 
-/* Tonal optimisation of a colour image (Section 4 per channel, Section 6):
+/* Tonal optimisation of a colour image (Section 4 per channel, Section 5):
  * three independent least-squares problems, each solved by the CGLS of
  * fi_tonal_opt, whose solves share the multi-right-hand-side launches.
  * A channel stops at its own relative normal residual opts->rtol (rtol 0:

@@ -29,7 +29,7 @@ that it follows:
   through the normal equations B^T B g = B^T f (Section 4, eqs. (4), (5)).
 * ``densify``: global top-k error-driven mask growth, and the paper's
   per-triangle densification (Section 3).
-* ``colour``: the method channel by channel on one shared mesh (Section 6).
+* ``colour``: the method channel by channel on one shared mesh (Section 5).
 * ``delaunay``: the paper's own mesh, a Delaunay triangulation of the mask
   pixels and the unknown vertices (Section 2.2), made unique by symbolic
   perturbation where vertices are cocircular.

@@ -1,9 +1,10 @@
-"""Colour images: the method applied channel by channel (Section 6).
+"""Colour images: the method applied channel by channel (Section 5).
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-The paper's conclusion extends the approach to colour by treating each
-channel as its own grey-value problem. The channels share the mask, so they
+Section 5 calls the extension to colour images straightforward without
+spelling it out; the reading here treats each channel as its own grey-value
+problem. The channels share the mask, so they
 share the mesh, the stiffness matrix and the operator B = R_D - R_F K_FF^-1
 K_FD of Section 4; only the data differ. Arrays here are planar: channel c
 of a per-pixel array is row c of a (3, P) array, and the stored values are a

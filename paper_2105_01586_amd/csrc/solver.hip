@@ -206,7 +206,9 @@ __device__ __forceinline__ void put_rec(Rec* out, Mirror* mirror, int epoch, int
     const uint64_t w = (uint64_t)(uint32_t)((epoch << 4) | phase) |
                        ((uint64_t)((uint32_t)total & 0xFFFFFFu) << 32) |
                        ((uint64_t)((uint32_t)ninner & 0x7Fu) << 56) | ((uint64_t)(xp & 1) << 63);
-    __hip_atomic_store(&mirror->word, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    // release: the norms above are visible to a host that reads this word
+    // with acquire (read_mirror) and sees this solve's epoch
+    __hip_atomic_store(&mirror->word, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 

@@ -1,4 +1,4 @@
-"""Colour images on the GPU (Section 6: the method per channel on one shared
+"""Colour images on the GPU (Section 5: the method per channel on one shared
 mesh), through the multi-right-hand-side step.
 
 * Bit-exact equality with the grey path, channel by channel: each channel's

@@ -1,4 +1,4 @@
-"""Pins of the oracle's colour form (Section 6: the method per channel, on
+"""Pins of the oracle's colour form (Section 5: the method per channel, on
 one shared mesh; planar (3, P) arrays; colour MSE over all 3P values).
 
 Each pin follows from the mathematics, not from the oracle's code: B is

@@ -4,6 +4,18 @@ vertices, Delaunay-triangulated; ties broken by symbolic perturbation).
 * Brute force on tiny point sets full of cocircular quadruples: the
   canonical triangles are exactly the counter-clockwise triples whose
   perturbed circumcircle holds no other vertex.
+* The same sets against a construction that shares nothing with the
+  oracle's predicates: the points are lifted to heights x^2 + y^2 + d^(id+1)
+  with a concrete d = 2^-64 (all heights scaled to exact integers), and the
+  lower convex hull of the lifted points is enumerated face by face with 3-D
+  integer cross products. The lower hull of the lifted points is the
+  Delaunay triangulation (Section 2.2's criterion); the concrete d stands in
+  for the infinitesimal perturbation because every coefficient it multiplies
+  is far below 2^64.
+* Local convexity of the lifted surface across every interior edge, again by
+  3-D cross products, on the oracle mesh of every GPU parity case: a
+  triangulation of a convex domain whose lifted surface is locally convex at
+  every edge is the lower hull, hence the unique perturbed Delaunay one.
 * scipy's Delaunay (Qhull) on point sets without degeneracies gives the same
   triangles.
 * Invariants at the parity-test sizes: every interior edge locally regular,
@@ -41,6 +53,165 @@ def brute_triangles(N, pix):
             t = (a, b, c)[k:] + (a, b, c)[:k]
             out.add(t)
     return out
+
+
+# --- lifted lower hull, independent of the oracle's predicates ------------
+_DELTA_BITS = 64  # the concrete perturbation d = 2^-64
+
+
+def _lift(N, pix, ids):
+    """Integer lifted points (x, y, H) for the vertices `ids` (ascending
+    ranks r = 0, 1, ... among them): H = (x^2 + y^2) 2^(64 (k + 1)) +
+    2^(64 (k - r)), i.e. x^2 + y^2 + d^(r+1) scaled by d^-(k+1), k = len(ids).
+    A lower id gets the larger perturbation, as e_0 >> e_1 >> ... demands."""
+    k = len(ids)
+    out = []
+    for r, v in enumerate(ids):
+        x, y = int(pix[v] % N), int(pix[v] // N)
+        h = ((x * x + y * y) << (_DELTA_BITS * (k + 1))) + (1 << (_DELTA_BITS * (k - r)))
+        out.append((x, y, h))
+    return out
+
+
+def _sub(p, q):
+    return (p[0] - q[0], p[1] - q[1], p[2] - q[2])
+
+
+def _cross(u, v):
+    return (u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0])
+
+
+def _dot(u, v):
+    return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]
+
+
+def lower_hull_triangles(N, pix):
+    """Faces (a, b, c) of the lower convex hull of the lifted vertices, each
+    counter-clockwise in the plane and rotated to start at its lowest id."""
+    V = len(pix)
+    L = _lift(N, pix, list(range(V)))
+    out = set()
+    for a, b, c in itertools.combinations(range(V), 3):
+        nrm = _cross(_sub(L[b], L[a]), _sub(L[c], L[a]))
+        if nrm[2] == 0:
+            continue  # collinear in the plane: no face
+        if nrm[2] < 0:  # orient counter-clockwise: normal pointing up
+            b, c = c, b
+            nrm = (-nrm[0], -nrm[1], -nrm[2])
+        # a lower face: every other lifted point strictly above its plane
+        if all(_dot(nrm, _sub(L[d], L[a])) > 0 for d in range(V) if d not in (a, b, c)):
+            k = min(range(3), key=lambda i: (a, b, c)[i])
+            out.add((a, b, c)[k:] + (a, b, c)[:k])
+    return out
+
+
+def lifted_locally_convex(N, pix, tris):
+    """Every interior edge (u, v) with triangles (u, v, w) and (v, u, x): x
+    lifted lies strictly above the plane of lifted u, v, w, with the
+    perturbation ranks taken among the four ids (only their order matters
+    for the sign of the symbolic determinant)."""
+    opp = {}
+    for a, b, c in np.asarray(tris).tolist():
+        for (u, v, w) in ((a, b, c), (b, c, a), (c, a, b)):
+            opp[(u, v)] = w
+    checked = 0
+    for (u, v), w in opp.items():
+        x = opp.get((v, u))
+        if x is None or u > v:
+            continue
+        ids = sorted((u, v, w, x))
+        L = dict(zip(ids, _lift(N, pix, ids)))
+        nrm = _cross(_sub(L[v], L[u]), _sub(L[w], L[u]))
+        assert nrm[2] > 0, "triangle not counter-clockwise"
+        if not _dot(nrm, _sub(L[x], L[u])) > 0:
+            return False
+        checked += 1
+    return checked > 0
+
+
+def test_lift_orders_perturbations():
+    """The lift itself: heights grow with x^2 + y^2 first, and at equal
+    x^2 + y^2 the lower id sits higher by orders of magnitude."""
+    L = _lift(8, np.array([0, 1, 8, 9]), [0, 1, 2, 3])
+    base = 1 << (_DELTA_BITS * 5)
+    assert [h // base for _, _, h in L] == [0, 1, 1, 2]
+    e = [h % base for _, _, h in L]
+    assert e == [1 << (_DELTA_BITS * (4 - r)) for r in range(4)]
+
+
+@pytest.mark.parametrize("N,k,seed", [(4, 3, 0), (5, 6, 1), (6, 9, 2), (7, 14, 3), (8, 18, 4)])
+def test_lifted_lower_hull_tiny(N, k, seed):
+    rng = np.random.default_rng(seed)
+    sel = rng.choice(N * N, size=k, replace=False)
+    mask = np.sort(sel[: k // 2])
+    unk = np.sort(sel[k // 2:])
+    M = D.build_mesh(N, mask, unk)
+    assert set(map(tuple, M.tri.tolist())) == lower_hull_triangles(N, M.pix)
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_lifted_lower_hull_full_grid(N):
+    """Every pixel a vertex: all unit squares cocircular, so every diagonal
+    is the perturbation's choice, and the lifted hull decides it alone."""
+    pix = np.arange(N * N)
+    M = D.build_mesh(N, pix[:1], pix[1:])
+    assert set(map(tuple, M.tri.tolist())) == lower_hull_triangles(N, M.pix)
+
+
+def test_lifted_check_rejects_a_flipped_diagonal():
+    """The local test is not vacuous: flipping one diagonal of the 4x4 full
+    grid's canonical mesh makes it fail."""
+    N = 4
+    pix = np.arange(N * N)
+    M = D.build_mesh(N, pix[:1], pix[1:])
+    tris = [tuple(t) for t in M.tri.tolist()]
+    assert lifted_locally_convex(N, M.pix, tris)
+    # find two triangles sharing an edge and flip it
+    opp = {}
+    for ti, (a, b, c) in enumerate(tris):
+        for (u, v, w) in ((a, b, c), (b, c, a), (c, a, b)):
+            opp[(u, v)] = (ti, w)
+    for (u, v), (t1, w) in opp.items():
+        if (v, u) in opp:
+            t2, x = opp[(v, u)]
+            break
+    flipped = [t for i, t in enumerate(tris) if i not in (t1, t2)]
+    flipped += [(w, x, v), (x, w, u)]
+    assert not lifted_locally_convex(N, M.pix, flipped)
+
+
+def _gpu_parity_case(side, dens, seed):
+    P = side * side
+    mask = synth.make_mask(seed, P, dens)
+    unk = synth.make_unknowns(seed, P, mask, mask.size)
+    return mask, unk
+
+
+# the meshes the GPU Delaunay parity tests compare against (side, density, seed)
+_PARITY_CASES = {"d16": (16, 0.10, 21), "d64": (64, 0.05, 22), "d256": (256, 0.03, 23),
+                 "d512": (512, 0.04, 2)}
+
+
+@pytest.mark.parametrize("name", list(_PARITY_CASES))
+def test_parity_meshes_regular_and_valid(name):
+    side, dens, seed = _PARITY_CASES[name]
+    mask, unk = _gpu_parity_case(side, dens, seed)
+    M = D.build_mesh(side, mask, unk)
+    assert lifted_locally_convex(side, M.pix, M.tri)
+    assert D.is_regular(side, M.pix, M.tri)
+    x = M.vxy.astype(np.int64)
+    t = M.tri
+    a2 = ((x[t[:, 1], 0] - x[t[:, 0], 0]) * (x[t[:, 2], 1] - x[t[:, 0], 1])
+          - (x[t[:, 1], 1] - x[t[:, 0], 1]) * (x[t[:, 2], 0] - x[t[:, 0], 0]))
+    assert a2.min() > 0 and a2.sum() == 2 * (side - 1) ** 2
+    # Euler: V - E + T = 1 for a triangulated disc
+    edges = set()
+    for a, b, c in t.tolist():
+        edges.update({(min(a, b), max(a, b)), (min(b, c), max(b, c)), (min(c, a), max(c, a))})
+    assert M.V - len(edges) + M.T == 1
+    # every edge in one or two triangles, the single ones on the border
+    on_hull = (x[:, 0] == 0) | (x[:, 0] == side - 1) | (x[:, 1] == 0) | (x[:, 1] == side - 1)
+    assert M.T == 2 * M.V - int(on_hull.sum()) - 2
 
 
 @pytest.mark.parametrize("N,k,seed", [(4, 3, 0), (5, 6, 1), (6, 9, 2), (7, 14, 3)])
