@@ -47,6 +47,7 @@ EXPORTED_SYMBOLS = (
     "fi_inpaint_rgb", "fi_error_rgb", "fi_tonal_opt_rgb", "fi_time_cg_multi_kernel",
     "fi_cg_multi_kernel_bytes", "fi_mesh_build_delaunay", "fi_host_mesh_build_delaunay",
     "fi_densify_delaunay", "fi_l1_opts_default", "fi_tonal_opt_l1", "fi_inpaint_image",
+    "fi_mse_dev", "fi_mse_backward",
 )
 
 
@@ -63,12 +64,14 @@ class NoConvergence(FIError):
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("inner_rtol", ctypes.c_double), ("max_inner", ctypes.c_int),
-                ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("atol", ctypes.c_double)]
 
 
 class _SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("refinements", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+                ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("residual", ctypes.c_double), ("rhs_norm", ctypes.c_double)]
 
 
 class _TonalOpts(ctypes.Structure):
@@ -173,6 +176,9 @@ def library() -> ctypes.CDLL:
         "fi_vertex_values": (ctypes.c_int, [vp, vp]),
         "fi_error": (ctypes.c_int, [vp, vp, vp, dp, vp, vp]),
         "fi_error_dev": (ctypes.c_int, [vp, vp, vp, vp]),
+        "fi_mse_dev": (ctypes.c_int, [vp, vp, vp, vp]),
+        "fi_mse_backward": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                           ctypes.POINTER(_SolveStats)]),
         "fi_solve": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                     ctypes.POINTER(_SolveStats)]),
         "fi_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_SolveOpts),
@@ -256,10 +262,11 @@ class SolveOpts:
     max_inner: int = 20000
     max_refine: int = 40
     check_every: int = 32
+    atol: float = 0.0  # 0: the library's default absolute bound; < 0: none
 
     def c(self) -> _SolveOpts:
         return _SolveOpts(self.precision, self.rtol, self.inner_rtol, self.max_inner,
-                          self.max_refine, self.check_every)
+                          self.max_refine, self.check_every, self.atol)
 
 
 @dataclass
@@ -564,6 +571,36 @@ class Mesh:
                                     _ptr(sse, torch.float64, 1, "sse", d))
         _check(rc, "fi_error_dev")
         return sse
+
+    def mse_dev(self, u, f, mse=None):
+        """MSE of u against f into a one-element float64 device tensor,
+        without waiting for it. Returns it."""
+        torch = _torch()
+        d = self._dev()
+        if mse is None:
+            mse = self._empty(1, torch.float64)
+        rc = library().fi_mse_dev(self._h, _ptr(u, torch.float64, self.P, "u", d),
+                                  _ptr(f, torch.uint8, self.P, "f", d),
+                                  _ptr(mse, torch.float64, 1, "mse", d))
+        _check(rc, "fi_mse_dev")
+        return mse
+
+    def mse_backward(self, u, f, scale=None, grad=None, opts: SolveOpts | None = None):
+        """grad = s (2 / P) B^T (u - f) with s the one-element device tensor
+        `scale` (None: 1) and u = B g. Returns (grad, stats)."""
+        torch = _torch()
+        d = self._dev()
+        if grad is None:
+            grad = self._empty(self.m, torch.float64)
+        st = _SolveStats()
+        o = (opts or SolveOpts()).c()
+        sp = None if scale is None else _ptr(scale, torch.float64, 1, "scale", d)
+        rc = library().fi_mse_backward(self._h, _ptr(u, torch.float64, self.P, "u", d),
+                                       _ptr(f, torch.uint8, self.P, "f", d), sp,
+                                       _ptr(grad, torch.float64, self.m, "grad", d),
+                                       ctypes.byref(o), ctypes.byref(st))
+        _check(rc, "fi_mse_backward")
+        return grad, _stats(st)
 
     def error_rgb(self, u, f):
         """Returns (colour MSE over all 3P values, [MSE of each channel])."""

@@ -1,12 +1,16 @@
-"""Differentiable inpainting: u = B g with the hand-written adjoint as backward.
+"""Differentiable inpainting and MSE, with the hand-written adjoint as backward.
 
 Section 4 writes the inpainting result as u = B g, with B the product of the
 interpolation matrix and the inverse of the FEM matrix, and optimises g by
-least squares. ``InpaintFn`` exposes that map to torch.autograd: the forward
-pass runs the library's inpainting (solve + interpolation) and the backward
-pass runs its adjoint, B^T grad_u (transposed interpolation + the same
-symmetric solve + coupling tail). For MSE(g) = ||B g - f||^2 / P the gradient
-is (2 / P) B^T (B g - f).
+least squares. Two torch.autograd.Functions expose that map; every step of
+their forward and backward passes runs in the library, this module only
+passes tensors through:
+
+- ``InpaintFn``: u = B g (solve + interpolation); backward B^T grad_u
+  (transposed interpolation + the same symmetric solve + coupling tail).
+- ``MseFn``: MSE(g) = ||B g - f||^2 / P (inpainting, then the error sum
+  divided by P on the device); backward s (2 / P) B^T (B g - f) for the
+  incoming d loss / d MSE = s, from the library's MSE backward.
 """
 from __future__ import annotations
 
@@ -30,6 +34,26 @@ class InpaintFn(torch.autograd.Function):
         return s, None, None
 
 
+class MseFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, g: torch.Tensor, f: torch.Tensor, mesh: Mesh,
+                opts: SolveOpts | None = None):
+        g = g.detach().contiguous()
+        u, _ = mesh.inpaint(g=g, opts=opts)
+        mse = mesh.mse_dev(u, f)
+        ctx.mesh = mesh
+        ctx.opts = opts
+        ctx.u = u
+        ctx.f = f
+        return mse.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_mse: torch.Tensor):
+        scale = grad_mse.detach().to(torch.float64).reshape(1).contiguous()
+        grad, _ = ctx.mesh.mse_backward(ctx.u, ctx.f, scale=scale, opts=ctx.opts)
+        return grad, None, None, None
+
+
 def inpaint(g: torch.Tensor, mesh: Mesh, opts: SolveOpts | None = None) -> torch.Tensor:
     """u = B g, differentiable in g."""
     return InpaintFn.apply(g, mesh, opts)
@@ -37,6 +61,6 @@ def inpaint(g: torch.Tensor, mesh: Mesh, opts: SolveOpts | None = None) -> torch
 
 def mse_loss(g: torch.Tensor, f: torch.Tensor, mesh: Mesh,
              opts: SolveOpts | None = None) -> torch.Tensor:
-    """MSE(g) = mean((B g - f)^2) with f the uint8 image (flattened)."""
-    u = inpaint(g, mesh, opts)
-    return torch.mean((u - f.reshape(-1).to(torch.float64)) ** 2)
+    """MSE(g) = mean((B g - f)^2) over all P pixels, f the uint8 image
+    (flattened), differentiable in g."""
+    return MseFn.apply(g, f.reshape(-1).contiguous(), mesh, opts)

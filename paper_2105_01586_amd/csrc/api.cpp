@@ -222,19 +222,6 @@ int check_mesh(const fi_mesh* M) {
   return FI_OK;
 }
 
-fi_solve_opts resolve_opts(const fi_solve_opts* o) {
-  fi_solve_opts d;
-  fi_solve_opts_default(&d);
-  if (!o) return d;
-  fi_solve_opts r = *o;
-  if (r.rtol <= 0) r.rtol = d.rtol;
-  if (r.inner_rtol <= 0 || r.inner_rtol >= 1) r.inner_rtol = d.inner_rtol;
-  if (r.max_inner <= 0) r.max_inner = d.max_inner;
-  if (r.max_refine <= 0) r.max_refine = d.max_refine;
-  if (r.check_every <= 0) r.check_every = d.check_every;
-  return r;
-}
-
 // u = B g for g on the device (vertex values kept in d_uvert).
 int apply_B(fi_mesh* M, const double* g, double* u_out, const fi_solve_opts* o,
             fi_solve_stats* st) {
@@ -277,6 +264,20 @@ int sse_dev(fi_mesh* M, const double* u, const uint8_t* f, double* out_dev) {
 
 }  // namespace
 
+fi_solve_opts resolve_opts(const fi_solve_opts* o) {
+  fi_solve_opts d;
+  fi_solve_opts_default(&d);
+  if (!o) return d;
+  fi_solve_opts r = *o;
+  if (r.rtol <= 0) r.rtol = d.rtol;
+  if (r.atol == 0) r.atol = d.atol;
+  if (r.inner_rtol <= 0 || r.inner_rtol >= 1) r.inner_rtol = d.inner_rtol;
+  if (r.max_inner <= 0) r.max_inner = d.max_inner;
+  if (r.max_refine <= 0) r.max_refine = d.max_refine;
+  if (r.check_every <= 0) r.check_every = d.check_every;
+  return r;
+}
+
 int channel_views(fi_mesh* M, int nc, fi_mesh** ch) {
   if (M->is_channel) return fail(FI_E_INVALID, "a channel view has no channels");
   if (nc < 1 || nc > kMaxRhs) return fail(FI_E_INVALID, "1 to 3 channels");
@@ -305,6 +306,7 @@ void fi_solve_opts_default(fi_solve_opts* o) {
   o->max_inner = 20000;
   o->max_refine = 40;
   o->check_every = 32;
+  o->atol = kDefaultAtol;
 }
 
 void fi_tonal_opts_default(fi_tonal_opts* o) {
@@ -617,6 +619,36 @@ int fi_error_dev(fi_mesh* M, const double* u_dev, const uint8_t* f_dev, double* 
   if (!u_dev || !f_dev || !sum_dev) return fail(FI_E_INVALID, "u_dev, f_dev and sse_dev are required");
   FI_HIP_TRY(hipSetDevice(M->ctx->device));
   return fi::sse_dev(M, u_dev, f_dev, sum_dev);
+}
+
+int fi_mse_dev(fi_mesh* M, const double* u_dev, const uint8_t* f_dev, double* mse_dev) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_dev || !f_dev || !mse_dev) return fail(FI_E_INVALID, "u_dev, f_dev and mse_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  rc = launch_raster(M, nullptr, u_dev, f_dev, nullptr, nullptr, nullptr, nullptr, M->d_rpart);
+  if (rc) return rc;
+  return launch_reduce(M, M->d_rpart, raster_blocks(M), 1, mse_dev, (double)M->P);
+}
+
+int fi_mse_backward(fi_mesh* M, const double* u_dev, const uint8_t* f_dev, const double* scale_dev,
+                    double* grad_dev, const fi_solve_opts* opts, fi_solve_stats* stats) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!u_dev || !f_dev || !grad_dev) return fail(FI_E_INVALID, "u_dev, f_dev and grad_dev are required");
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  if (!M->d_rgrad && (rc = device_alloc(M, (void**)&M->d_rgrad, (size_t)M->P * sizeof(double))))
+    return rc;
+  const fi_solve_opts o = resolve_opts(opts);
+  fi_solve_stats st{};
+  if ((rc = launch_mse_residual(M, f_dev, u_dev, scale_dev, M->d_rgrad))) return rc;
+  rc = apply_BT(M, M->d_rgrad, grad_dev, &o, &st);
+  if (stats) *stats = st;
+  if (rc) return rc;
+  FI_HIP_TRY(hipStreamSynchronize(M->ctx->stream));
+  if (st.status != FI_OK)
+    return fail(FI_E_NO_CONVERGENCE, "adjoint solve did not reach the tolerance");
+  return FI_OK;
 }
 
 int fi_adjoint(fi_mesh* M, const double* r_dev, double* s_dev, const fi_solve_opts* opts,

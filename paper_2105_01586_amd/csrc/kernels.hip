@@ -963,14 +963,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tail(int m, const int32_t* _
 }
 
 // ------------------------------------------------------ vector kernels ----
+// out[c] = (sum of component c over the partials) / div.
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, int nparts,
-                                                   int ncomp, double* __restrict__ out) {
+                                                   int ncomp, double div, double* __restrict__ out) {
   __shared__ double lds[4];
   for (int c = 0; c < ncomp; ++c) {
     double v[1] = {0.0};
     for (int j = threadIdx.x; j < nparts; j += kBlock) v[0] += part[(int64_t)j * ncomp + c];
     block_sum<1>(v, lds);
-    if (threadIdx.x == 0) out[c] = v[0];
+    if (threadIdx.x == 0) out[c] = v[0] / div;
   }
 }
 
@@ -1015,6 +1016,20 @@ __global__ __launch_bounds__(kBlock) void k_pixel_residual(int64_t P, const uint
                                                            double* __restrict__ r) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < P) r[i] = (double)f[i] - u[i];
+}
+
+// Pixel-space factor of the MSE gradient: r = c (u - f) with c = 2 s / P,
+// s = *scale (the caller's d loss / d MSE) or 1. Section 4: the gradient of
+// MSE(g) = ||B g - f||^2 / P is (2 / P) B^T (B g - f), so B^T r is s times it.
+__global__ __launch_bounds__(kBlock) void k_mse_residual(int64_t P, const uint8_t* __restrict__ f,
+                                                         const double* __restrict__ u,
+                                                         const double* __restrict__ scale,
+                                                         double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < P) {
+    const double c = 2.0 * (scale ? *scale : 1.0) / (double)P;
+    r[i] = c * (u[i] - (double)f[i]);
+  }
 }
 
 // Weighted residual r = w (f - u).
@@ -1365,8 +1380,9 @@ int launch_adjoint_tail(fi_mesh* M, const double* tD, const double* y, double* s
   return FI_OK;
 }
 
-int launch_reduce(fi_mesh* M, const double* part, int nparts, int ncomp, double* out) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, M->ctx->stream, part, nparts, ncomp, out);
+int launch_reduce(fi_mesh* M, const double* part, int nparts, int ncomp, double* out, double div) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, M->ctx->stream, part, nparts, ncomp, div,
+                     out);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }
@@ -1405,6 +1421,14 @@ int launch_pixel_residual(fi_mesh* M, const uint8_t* f, const double* u, double*
   else
     hipLaunchKernelGGL(k_pixel_residual, dim3(grid_for(M->P)), dim3(kBlock), 0, M->ctx->stream,
                        M->P, f, u, r);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
+}
+
+int launch_mse_residual(fi_mesh* M, const uint8_t* f, const double* u, const double* scale,
+                        double* r) {
+  hipLaunchKernelGGL(k_mse_residual, dim3(grid_for(M->P)), dim3(kBlock), 0, M->ctx->stream, M->P,
+                     f, u, scale, r);
   FI_LAUNCH_CHECK();
   return FI_OK;
 }

@@ -698,14 +698,7 @@ int fi_server_submit(fi_server* S, const fi_job_desc* d, uint64_t* ticket) {
   J->mask.assign(d->mask, d->mask + d->m);
   J->iters = d->tonal_iters;
   J->g_out = d->g_out;
-  fi_solve_opts io = d->inner;
-  fi_solve_opts def;
-  fi_solve_opts_default(&def);
-  if (io.rtol <= 0) io.rtol = def.rtol;
-  if (io.inner_rtol <= 0 || io.inner_rtol >= 1) io.inner_rtol = def.inner_rtol;
-  if (io.max_inner <= 0) io.max_inner = def.max_inner;
-  if (io.max_refine <= 0) io.max_refine = def.max_refine;
-  if (io.check_every <= 0) io.check_every = def.check_every;
+  fi_solve_opts io = resolve_opts(&d->inner);
   io.precision = S->opts.precision;
   J->io = io;
   std::lock_guard<std::mutex> lk(S->mu);

@@ -103,7 +103,7 @@ constexpr int kEpochMask = (1 << 27) - 1;
 
 // Constant parameters of a solve (written by the start launch).
 struct Params {
-  double rtol, inner_rtol, max_inner, max_refine, mixed, epoch, pad[2];
+  double rtol, inner_rtol, max_inner, max_refine, mixed, epoch, atol, pad;
 };
 
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -264,6 +264,7 @@ __global__ __launch_bounds__(BS) void k_solve_start(StepArgs<T> A, Params prm, P
     prm_out->max_refine = prm.max_refine;
     prm_out->mixed = prm.mixed;
     prm_out->epoch = prm.epoch;
+    prm_out->atol = prm.atol;
     put_rec(A.rec_out, nullptr, (int)prm.epoch, 0, kInit, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0,
             0.0);
   }
@@ -391,10 +392,12 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     // launch also sends red[1] = ||b||^2
     double rnorm = sqrt(red[0]);
     const double bnorm = Rin.ninner == 0 ? sqrt(red[1]) : Rin.bnorm;
+    // stop at ||r|| <= rtol ||b||, and (atol > 0) at ||r|| <= atol too
+    const double tol = P.atol > 0.0 ? fmin(P.rtol * bnorm, P.atol) : P.rtol * bnorm;
     int stagnant = Rin.stagnant;
     int next = 0;
     if (!isfinite(rnorm)) next = kDoneBad;
-    else if (rnorm <= P.rtol * bnorm) next = kDoneOk;
+    else if (rnorm <= tol) next = kDoneOk;
     else if (bnorm == 0.0 && Rin.ninner == 0) {
       // b = 0 with a non-zero start: the solution is x = 0
       if (live) (Rin.xp ? A.x64b : A.x64a)[i] = 0.0;
@@ -415,7 +418,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int lb, do
     }
     // Inner target: what the outer tolerance still needs, never looser than
     // inner_rtol in mixed mode.
-    const double want = 0.5 * P.rtol * bnorm / rnorm;
+    const double want = 0.5 * tol / rnorm;
     const double itol = P.mixed != 0.0 ? fmax(P.inner_rtol, want) : fmax(want, 1e-15);
     const double scale = 1.0 / rnorm;
     if (live) {
@@ -876,6 +879,7 @@ int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0
   StepArgs<T> A = make_args<T>(M, 1, 0);  // writes record and partials of slot 0
   Params prm{};
   prm.rtol = o->rtol;
+  prm.atol = o->atol;
   prm.inner_rtol = o->inner_rtol;
   prm.max_inner = o->max_inner;
   prm.max_refine = o->max_refine;
@@ -912,6 +916,8 @@ int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
   __atomic_load(&m->rnorm, &rn, __ATOMIC_RELAXED);
   __atomic_load(&m->bnorm, &bn, __ATOMIC_RELAXED);
   stats->rel_residual = bn > 0 ? rn / bn : 0.0;
+  stats->residual = rn;
+  stats->rhs_norm = bn;
   stats->status = phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
   M->d_x64 = M->d_x64buf[(w >> 63) & 1];
   if (phase == kDoneBad) *rc = fail(FI_E_INVALID, "right-hand side or residual not finite");
@@ -1125,6 +1131,8 @@ int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_
     stats[c].refinements = 0;
     stats[c].status = FI_OK;
     stats[c].rel_residual = 0.0;
+    stats[c].residual = 0.0;
+    stats[c].rhs_norm = 0.0;
   }
   if (ch[0]->n == 0) return FI_OK;
   if (opts->precision == FI_PREC_FP64) return solve_multi_dev<double>(ch, nc, opts, stats, x0);
@@ -1363,6 +1371,8 @@ int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats, con
   stats->refinements = 0;
   stats->status = FI_OK;
   stats->rel_residual = 0.0;
+  stats->residual = 0.0;
+  stats->rhs_norm = 0.0;
   if (M->n == 0) return FI_OK;
   if (opts->precision == FI_PREC_FP64) return solve_dev<double>(M, opts, stats, x0);
   return solve_dev<float>(M, opts, stats, x0);

@@ -139,18 +139,7 @@ extern "C" int fi_tonal_opt(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
     if (o.rtol < 0) o.rtol = 1e-8;
     if (o.max_outer <= 0) o.max_outer = 500;
   }
-  fi_solve_opts io;
-  fi_solve_opts_default(&io);
-  if (opts) {
-    io = opts->inner;
-    fi_solve_opts d;
-    fi_solve_opts_default(&d);
-    if (io.rtol <= 0) io.rtol = d.rtol;
-    if (io.inner_rtol <= 0 || io.inner_rtol >= 1) io.inner_rtol = d.inner_rtol;
-    if (io.max_inner <= 0) io.max_inner = d.max_inner;
-    if (io.max_refine <= 0) io.max_refine = d.max_refine;
-    if (io.check_every <= 0) io.check_every = d.check_every;
-  }
+  const fi_solve_opts io = resolve_opts(opts ? &opts->inner : nullptr);
   fi_tonal_stats ts{};
   Cgls c;
   c.M = M;
@@ -218,18 +207,7 @@ extern "C" int fi_tonal_opt_rgb(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
     if (o.rtol < 0) o.rtol = 1e-8;
     if (o.max_outer <= 0) o.max_outer = 500;
   }
-  fi_solve_opts io;
-  fi_solve_opts_default(&io);
-  if (opts) {
-    io = opts->inner;
-    fi_solve_opts d;
-    fi_solve_opts_default(&d);
-    if (io.rtol <= 0) io.rtol = d.rtol;
-    if (io.inner_rtol <= 0 || io.inner_rtol >= 1) io.inner_rtol = d.inner_rtol;
-    if (io.max_inner <= 0) io.max_inner = d.max_inner;
-    if (io.max_refine <= 0) io.max_refine = d.max_refine;
-    if (io.check_every <= 0) io.check_every = d.check_every;
-  }
+  const fi_solve_opts io = resolve_opts(opts ? &opts->inner : nullptr);
   constexpr int C = kMaxRhs;
   fi_mesh* ch[C];
   int rc = channel_views(M, C, ch);
@@ -339,13 +317,7 @@ extern "C" int fi_tonal_opt_l1(fi_mesh* M, const uint8_t* f_dev, double* g_dev,
     o = *opts;
     if (!(o.eps > 0)) return fail(FI_E_INVALID, "eps must be positive");
     if (o.irls_iters < 0 || o.cgls_iters < 0) return fail(FI_E_INVALID, "negative iteration count");
-    fi_solve_opts d;
-    fi_solve_opts_default(&d);
-    if (o.inner.rtol <= 0) o.inner.rtol = d.rtol;
-    if (o.inner.inner_rtol <= 0 || o.inner.inner_rtol >= 1) o.inner.inner_rtol = d.inner_rtol;
-    if (o.inner.max_inner <= 0) o.inner.max_inner = d.max_inner;
-    if (o.inner.max_refine <= 0) o.inner.max_refine = d.max_refine;
-    if (o.inner.check_every <= 0) o.inner.check_every = d.check_every;
+    o.inner = resolve_opts(&o.inner);
   }
   Cgls c;
   c.M = M;

@@ -38,7 +38,7 @@ def test_version_and_defaults():
     assert b"gfx950" in lib.fi_version()
     o = fi._SolveOpts()
     lib.fi_solve_opts_default(o)
-    assert o.rtol == 1e-10 and o.precision == fi.PREC_FP32_IR
+    assert o.rtol == 1e-10 and o.atol == 3e-6 and o.precision == fi.PREC_FP32_IR
     t = fi._TonalOpts()
     lib.fi_tonal_opts_default(t)
     assert t.rtol == 1e-8 and t.inner.rtol == 1e-10

@@ -152,19 +152,19 @@ def test_full_image_properties(ctx, workload):
 
 @pytest.mark.timeout(900)
 def test_full_image_pixel_error(ctx, workload):
-    # A pixel's error is the residual amplified by ||K_FF^-1||, which grows
-    # with the system: the default stop (1e-10) leaves pixels up to 4e-6 off
-    # here, 1e-11 keeps all of them within 1e-6.
+    # A pixel's error is the residual amplified by K_FF^-1: a relative stop
+    # alone (1e-10) leaves pixels up to 4e-6 off here; the default solve also
+    # runs until ||r|| <= 3e-6, which keeps all of them within 1e-6.
     w, img, mask = workload
     M = fi.Mesh(ctx, w.side, mask)
     fd = dev(img.ravel())
-    u, st = M.inpaint(f=fd, opts=fi.SolveOpts(rtol=1e-11))
+    u, st = M.inpaint(f=fd)
     ut, stt = M.inpaint(f=fd, opts=fi.SolveOpts(precision=fi.PREC_FP64, rtol=1e-13))
-    assert st["status"] == 0 and st["rel_residual"] <= 1e-11
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-10 and st["residual"] <= 3e-6
     assert stt["status"] == 0 and stt["rel_residual"] <= 1e-13
     err = float((u - ut).abs().max())
-    print(f"  full: FP32 path at 1e-11 ({st['iterations']} iterations) against FP64 at 1e-13: "
-          f"max pixel difference {err:.3e}", flush=True)
+    print(f"  full: default FP32 path ({st['iterations']} iterations, ||r|| {st['residual']:.2e}) "
+          f"against FP64 at 1e-13: max pixel difference {err:.3e}", flush=True)
     assert err <= 1e-6
     del u, ut
     M.close()

@@ -98,6 +98,36 @@ def test_autograd_gradient_and_fd(ctx, name):
     print(f"  worst FD deviation (relative) {worst:.3e}")
 
 
+@pytest.mark.parametrize("name", ["n16_k7", "n64_c1", "c2"])
+def test_mse_and_backward_in_library(ctx, name):
+    """The MSE on the device equals fi_error's MSE bit for bit; the library's
+    MSE backward, s (2 / P) B^T (B g - f), matches the oracle gradient times s
+    (s = 1 and s = -3.5) and the loss's autograd gradient under a scale."""
+    print(f"case {name}", flush=True)
+    M = gpu_mesh(ctx, name)
+    pr = oracle_problem(name)
+    _, _, f = case(name)
+    rng = np.random.default_rng(11)
+    g0 = pr.default_g(f) + rng.normal(scale=3.0, size=M.m)
+    fd_t = dev(f)
+    u, _ = M.inpaint(g=dev(g0))
+    mse_host, _, _ = M.error(u, fd_t)
+    mse_dev = M.mse_dev(u, fd_t).item()
+    assert mse_dev == mse_host
+    ref = pr.mse_grad(g0, f)
+    for s in (1.0, -3.5):
+        scale = None if s == 1.0 else dev(np.array([s]))
+        grad, st = M.mse_backward(u, fd_t, scale=scale)
+        grad = grad.cpu().numpy()
+        rel = np.linalg.norm(grad - s * ref) / np.linalg.norm(s * ref)
+        print(f"  s = {s}: rel err vs oracle {rel:.3e}, {st['iterations']} CG iterations")
+        assert st["status"] == 0 and rel <= 1e-8
+    g = dev(g0).requires_grad_(True)
+    (-3.5 * fa.mse_loss(g, fd_t, M)).backward()
+    rel = np.linalg.norm(g.grad.cpu().numpy() + 3.5 * ref) / np.linalg.norm(3.5 * ref)
+    assert rel <= 1e-8
+
+
 @pytest.mark.parametrize("precision", [fi.PREC_FP32_IR, fi.PREC_FP64])
 @pytest.mark.parametrize("name", ["n16_k7", "n64_c1", "n256_k2000", "c2"])
 def test_tonal_parity(ctx, name, precision):
