@@ -359,6 +359,21 @@ int fi_owner_map(fi_mesh* mesh, int32_t* owner_dev);
  * Errors: FI_E_INVALID if k exceeds the number of non-mask pixels. */
 int fi_topk_new_pixels(fi_mesh* mesh, const double* e_dev, int64_t k, int32_t* out_dev);
 
+/* fi_topk_new_pixels without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments, kernels and result (bit
+ * for bit) as fi_topk_new_pixels; its workspace (flags, histogram, ranks,
+ * scan partials) is a fixed 24 MiB device array inside the library, one copy
+ * per GPU, held until the process ends, instead of memory the mesh allocates
+ * on first use. It calls no hipMalloc, hipFree or other allocating routine.
+ * Limit: P <= 2^20 pixels (images up to 1024 x 1024); larger meshes give
+ * FI_E_INVALID. Every call on a GPU reuses that GPU's array (each call
+ * clears what it reads before use). Calls in one process are serialised: a
+ * call holds a library lock and waits for its stream before it returns, so
+ * two calls never use the array at the same time; a caller that bypassed
+ * this (e.g. replaying captured work of two calls concurrently) would race. */
+int fi_topk_new_pixels_noalloc(fi_mesh* mesh, const double* e_dev, int64_t k, int32_t* out_dev);
+
 /* Error-driven mask growth (Section 3: densification on the inpainting
  * error map, here its global top-k form): starting from mask0, for `rounds`
  * rounds rebuild the mesh on the current mask, inpaint with g = f on the

@@ -47,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "fi_inpaint_rgb", "fi_error_rgb", "fi_tonal_opt_rgb", "fi_time_cg_multi_kernel",
     "fi_cg_multi_kernel_bytes", "fi_mesh_build_delaunay", "fi_host_mesh_build_delaunay",
     "fi_densify_delaunay", "fi_l1_opts_default", "fi_tonal_opt_l1", "fi_inpaint_image",
-    "fi_mse_dev", "fi_mse_backward",
+    "fi_mse_dev", "fi_mse_backward", "fi_topk_new_pixels_noalloc",
 )
 
 
@@ -189,6 +189,7 @@ def library() -> ctypes.CDLL:
         "fi_mesh_export_csr": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "fi_owner_map": (ctypes.c_int, [vp, vp]),
         "fi_topk_new_pixels": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp]),
+        "fi_topk_new_pixels_noalloc": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp]),
         "fi_time_cg_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp]),
         "fi_cg_kernel_bytes": (ctypes.c_int, [vp, ctypes.c_int, i64p]),
         "fi_host_mesh_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64,
@@ -673,6 +674,18 @@ class Mesh:
                                           int(k), ctypes.c_void_p(out.data_ptr()))
         _check(rc, "fi_topk_new_pixels")
         return out[:int(k)]
+
+    def topk_new_pixels_noalloc(self, e, out):
+        """fi_topk_new_pixels into the caller's int32 tensor ``out`` (its
+        length is k), with the library's fixed workspace: no allocation."""
+        torch = _torch()
+        d = self._dev()
+        k = int(out.numel())
+        rc = library().fi_topk_new_pixels_noalloc(
+            self._h, _ptr(e, torch.float64, self.P, "e", d), k,
+            _ptr(out, torch.int32, k, "out", d) if k > 0 else None)
+        _check(rc, "fi_topk_new_pixels_noalloc")
+        return out
 
     def paper_densify_step(self, e, k: int):
         """Section 3's per-triangle step: up to k new pixels (ascending)."""

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -108,11 +109,28 @@ struct SelectSpace {
   int32_t *hist, *gt, *eq, *rank, *sel, *pos, *scan_tmp;
 };
 
-int select_space(fi_mesh* M, int64_t n, SelectSpace& W) {
+size_t select_space_bytes(int64_t n) {
   const size_t excl_bytes = ((size_t)n + 255) & ~(size_t)255;
   const size_t tmp_ints = (size_t)scan_tmp_ints(n + 1);
-  const size_t need =
-      excl_bytes + sizeof(int32_t) * ((size_t)kBins + 5 * (size_t)(n + 1) + tmp_ints);
+  return excl_bytes + sizeof(int32_t) * ((size_t)kBins + 5 * (size_t)(n + 1) + tmp_ints);
+}
+
+// Lays the workspace of a selection over n keys out from `base`
+// (select_space_bytes(n) bytes, 256-byte aligned).
+void select_space_carve(void* base, int64_t n, SelectSpace& W) {
+  const size_t excl_bytes = ((size_t)n + 255) & ~(size_t)255;
+  W.excl = (uint8_t*)base;
+  W.hist = (int32_t*)((char*)base + excl_bytes);
+  W.gt = W.hist + kBins;
+  W.eq = W.gt + (n + 1);
+  W.rank = W.eq + (n + 1);
+  W.sel = W.rank + (n + 1);
+  W.pos = W.sel + (n + 1);
+  W.scan_tmp = W.pos + (n + 1);
+}
+
+int select_space(fi_mesh* M, int64_t n, SelectSpace& W) {
+  const size_t need = select_space_bytes(n);
   if ((int64_t)need > M->topk_bytes) {
     void* p = nullptr;
     int rc = device_alloc(M, &p, need);
@@ -120,25 +138,18 @@ int select_space(fi_mesh* M, int64_t n, SelectSpace& W) {
     M->d_topk = p;
     M->topk_bytes = (int64_t)need;
   }
-  W.excl = (uint8_t*)M->d_topk;
-  W.hist = (int32_t*)((char*)M->d_topk + excl_bytes);
-  W.gt = W.hist + kBins;
-  W.eq = W.gt + (n + 1);
-  W.rank = W.eq + (n + 1);
-  W.sel = W.rank + (n + 1);
-  W.pos = W.sel + (n + 1);
-  W.scan_tmp = W.pos + (n + 1);
+  select_space_carve(M->d_topk, n, W);
   return FI_OK;
 }
 
 // The k entries of largest key among those not excluded (ties: lower index),
 // written in ascending index order to out. With fewer than k candidates,
 // *taken < k of them (all) are written.
+// h: host memory for one histogram (kBins ints).
 int select_topk(hipStream_t st, int64_t n, const double* key, SelectSpace& W, int64_t k,
-                int32_t* out, int64_t* taken) {
+                int32_t* out, int64_t* taken, int32_t* h) {
   *taken = 0;
   if (k == 0 || n == 0) return FI_OK;
-  std::vector<int32_t> h(kBins);
   uint64_t prefix = 0, hi_mask = 0;
   // candidates in total: a histogram of the top digit counts them all
   int64_t remaining = k;  // rank (1-based, from the top) still to locate
@@ -150,8 +161,7 @@ int select_topk(hipStream_t st, int64_t n, const double* key, SelectSpace& W, in
     hipLaunchKernelGGL(k_hist, dim3(g), dim3(kBlock), 0, st, n, key, W.excl, shift, prefix,
                        hi_mask, W.hist);
     FI_HIP_TRY(hipGetLastError());
-    FI_HIP_TRY(hipMemcpyAsync(h.data(), W.hist, sizeof(int32_t) * kBins, hipMemcpyDeviceToHost,
-                              st));
+    FI_HIP_TRY(hipMemcpyAsync(h, W.hist, sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
     FI_HIP_TRY(hipStreamSynchronize(st));
     if (pass == 0) {
       int64_t total = 0;
@@ -186,25 +196,32 @@ int select_topk(hipStream_t st, int64_t n, const double* key, SelectSpace& W, in
   return FI_OK;
 }
 
-}  // namespace
-
-int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out) {
-  if (k == 0) return FI_OK;
+// The global top-k step on the workspace W (laid out for P keys) with the
+// host histogram buffer h.
+int topk_in(fi_mesh* M, const double* e, int64_t k, int32_t* out, SelectSpace& W, int32_t* h) {
   hipStream_t st = M->ctx->stream;
   const int64_t P = M->P;
-  SelectSpace W;
-  int rc = select_space(M, P, W);
-  if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u8, dim3(blocks(P)), dim3(kBlock), 0, st, P, W.excl);
   hipLaunchKernelGGL(k_mark_mask, dim3(blocks(M->m)), dim3(kBlock), 0, st, (int)M->m,
                      M->d_mask_pix, W.excl);
   FI_HIP_TRY(hipGetLastError());
   int64_t taken = 0;
-  rc = select_topk(st, P, e, W, k, out, &taken);
+  int rc = select_topk(st, P, e, W, k, out, &taken, h);
   if (rc) return rc;
   if (taken < k) return fail(FI_E_INVALID, "top-k: fewer candidates than requested");
   FI_HIP_TRY(hipStreamSynchronize(st));
   return FI_OK;
+}
+
+}  // namespace
+
+int topk_new_pixels(fi_mesh* M, const double* e, int64_t k, int32_t* out) {
+  if (k == 0) return FI_OK;
+  SelectSpace W;
+  int rc = select_space(M, M->P, W);
+  if (rc) return rc;
+  std::vector<int32_t> h(kBins);
+  return topk_in(M, e, k, out, W, h.data());
 }
 
 // Section 3's densification step: triangles in descending order of their
@@ -238,7 +255,8 @@ int paper_densify_step(fi_mesh* M, const double* e, int64_t k, int32_t* out, int
                      W.excl);
   FI_HIP_TRY(hipGetLastError());
   int64_t taken = 0;
-  if ((rc = select_topk(st, T, M->d_tri_err, W, k, M->d_sel_tri, &taken))) return rc;
+  std::vector<int32_t> h(kBins);
+  if ((rc = select_topk(st, T, M->d_tri_err, W, k, M->d_sel_tri, &taken, h.data()))) return rc;
   // their pixels, in ascending pixel order: flag, scan, scatter over P
   int32_t* flag = W.gt;  // reuse (n + 1 ints each)
   hipLaunchKernelGGL(k_zero_i32, dim3(blocks(P + 1)), dim3(kBlock), 0, st, P + 1, flag);
@@ -253,4 +271,58 @@ int paper_densify_step(fi_mesh* M, const double* e, int64_t k, int32_t* out, int
   *added = taken;
   return FI_OK;
 }
+
 }  // namespace fi
+
+// Workspace of the allocation-free top-k entry point: a file-scope device
+// array, one copy per GPU the library runs on, held until the process ends.
+// In host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device (fi::scratch_on).
+constexpr int64_t kNoAllocMaxPixels = (int64_t)1 << 20;  // a 1024 x 1024 image
+constexpr size_t kScratchBytes = (size_t)24 << 20;       // >= select_space_bytes(2^20)
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace fi {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;          // held for a whole call of the entry point
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each device
+int32_t g_noalloc_hist[kBins];     // host copy of one histogram
+
+// Device address of `scratch` on `dev` (the current device); g_noalloc_mu held.
+int scratch_on(int dev, void** ptr) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FI_E_INVALID, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FI_E_HIP, std::string("scratch symbol address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return FI_OK;
+}
+
+}  // namespace
+}  // namespace fi
+
+using namespace fi;
+
+extern "C" int fi_topk_new_pixels_noalloc(fi_mesh* M, const double* e_dev, int64_t k,
+                                          int32_t* out_dev) {
+  if (!M || !M->ctx) return fail(FI_E_INVALID, "mesh is NULL");
+  if (!e_dev || (!out_dev && k > 0)) return fail(FI_E_INVALID, "e_dev and out_dev are required");
+  if (k < 0 || k > M->P - M->m) return fail(FI_E_INVALID, "k out of range");
+  if (M->P > kNoAllocMaxPixels || select_space_bytes(M->P) > kScratchBytes)
+    return fail(FI_E_INVALID, "fi_topk_new_pixels_noalloc: more than 2^20 pixels");
+  if (k == 0) return FI_OK;
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  void* base = nullptr;
+  int rc = scratch_on(M->ctx->device, &base);
+  if (rc) return rc;
+  SelectSpace W;
+  select_space_carve(base, M->P, W);
+  return topk_in(M, e_dev, k, out_dev, W, g_noalloc_hist);
+}
