@@ -1,0 +1,223 @@
+// Row blocks with halos for the s-step CG launch (plain C++, no device code).
+//
+// The s-step launch advances S iterations of Jacobi PCG per launch. Each
+// block applies the preconditioned operator S times to its rows' vectors, so
+// it needs the rows within S hops of its own in the matrix graph. The free
+// rows are therefore renumbered along a Z-order (Morton) curve of their
+// lattice coordinates, so that a block's BS consecutive rows form a compact
+// patch, and each block gets:
+//   - its region: its own rows (local index 0 .. nown-1), then the rows at
+//     graph distance 1, 2, ..., S from them (ascending within each ring);
+//   - a local matrix for the rows of its region at distance <= S - 1: for
+//     each such row, up to 8 entries, each the local index of the neighbour
+//     (bits 0-13), bit 14 for padding (the entry then points at the row
+//     itself with weight 0), bit 15 for weight -1 (clear: -1/2). On the
+//     quadtree mesh every off-diagonal entry of K_FF is -1/2 or -1.
+// Rows of a block are [b * BS, min(n, (b + 1) * BS)) in the new order.
+//
+// Inputs come from the library's column-major ELL of K_FF (natural order):
+// slot k of row i at ell[k * n_pad + i], column in bits 0-29, bit 30 padding,
+// bit 31 weight -1.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <thread>
+#include <vector>
+
+namespace fi {
+
+constexpr int kPlanLocalBits = 14;
+constexpr int32_t kPlanLocalMax = 1 << kPlanLocalBits;  // region rows per block, at most
+constexpr uint16_t kPlanPad = 1u << 14;
+constexpr uint16_t kPlanMinusOne = 1u << 15;
+constexpr int kPlanSlots = 8;  // entries per local matrix row
+
+struct BlockPlan {
+  int32_t halo_off;  // first halo row of the block in SsPlan::halo
+  int32_t lmat_off;  // first local matrix row of the block in SsPlan::lmat (rows of 8)
+  int32_t nown;      // own rows
+  int32_t n1;        // region rows at distance <= 1
+  int32_t ninner;    // region rows at distance <= S - 1 (rows of the local matrix)
+  int32_t nreg;      // region rows in all (distance <= S)
+  int32_t pad0, pad1;
+};
+static_assert(sizeof(BlockPlan) == 32, "block table layout");
+
+struct SsPlan {
+  int S = 0, BS = 0;
+  int64_t n = 0;
+  int32_t grid = 0;              // blocks (a multiple of 8)
+  int32_t max_region = 0;        // largest nreg over the blocks
+  std::vector<int32_t> perm;     // new index -> natural row
+  std::vector<BlockPlan> blocks;
+  std::vector<int32_t> halo;     // halo rows (new indices), block after block
+  std::vector<uint16_t> lmat;    // local matrix rows, kPlanSlots entries each
+};
+
+// Interleaves the bits of x (even positions) and y (odd positions).
+inline uint64_t morton_key(uint32_t x, uint32_t y) {
+  auto spread = [](uint64_t v) {
+    v &= 0xFFFFFFFFull;
+    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1);
+}
+
+// Builds the plan. xy: lattice coordinates of the free rows (natural order,
+// 2 per row); ell: the ELL copy described above (W slots). Returns false if
+// a region exceeds max_region rows (at most kPlanLocalMax) or a row has more
+// than kPlanSlots entries (the caller then keeps the one-iteration launch).
+inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int32_t* ell,
+                          int64_t n_pad, int W, int threads, int max_region, SsPlan& out) {
+  out = SsPlan{};
+  out.S = S;
+  out.BS = BS;
+  out.n = n;
+  if (n <= 0 || W > kPlanSlots || S < 1 || max_region > kPlanLocalMax || max_region < BS)
+    return false;
+  // Z-order of the free rows (ties cannot occur: rows sit at distinct points)
+  std::vector<uint64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) key[i] = morton_key((uint32_t)xy[2 * i], (uint32_t)xy[2 * i + 1]);
+  out.perm.resize(n);
+  for (int64_t i = 0; i < n; ++i) out.perm[i] = (int32_t)i;
+  std::sort(out.perm.begin(), out.perm.end(),
+            [&](int32_t a, int32_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
+  std::vector<int32_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[out.perm[i]] = (int32_t)i;
+  // neighbours in the new order: column (new index) and weight code
+  std::vector<int32_t> nb((size_t)n * kPlanSlots, -1);
+  std::vector<uint8_t> nbw((size_t)n * kPlanSlots, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t r = out.perm[i];
+    int c = 0;
+    for (int k = 0; k < W; ++k) {
+      const int32_t e = ell[(size_t)k * n_pad + r];
+      if (e & 0x40000000) continue;
+      nb[(size_t)i * kPlanSlots + c] = inv[e & 0x3FFFFFFF];
+      nbw[(size_t)i * kPlanSlots + c] = e < 0 ? 1 : 0;
+      ++c;
+    }
+  }
+  const int64_t nblk = (n + BS - 1) / BS;
+  out.grid = (int32_t)((nblk + 7) / 8 * 8);
+  out.blocks.assign(out.grid, BlockPlan{});
+  // per block: region (BFS by rings) and local matrix, built in parallel
+  struct Part {
+    std::vector<int32_t> halo;
+    std::vector<uint16_t> lmat;
+    bool ok = true;
+  };
+  std::vector<Part> parts(out.grid);
+  auto work = [&](int t, int nt) {
+    // region membership: open addressing over new indices (row -> local
+    // index), twice the largest region, cleared after each block
+    constexpr uint32_t kTab = 2u * (uint32_t)kPlanLocalMax;
+    std::vector<int32_t> tkey(kTab, -1), tval(kTab, -1);
+    std::vector<uint32_t> used;
+    auto slot = [&](int32_t row) {
+      uint32_t h = ((uint32_t)row * 2654435761u) & (kTab - 1);
+      while (tkey[h] != -1 && tkey[h] != row) h = (h + 1) & (kTab - 1);
+      return h;
+    };
+    std::vector<int32_t> next;
+    for (int64_t b = t; b < nblk; b += nt) {
+      Part& P = parts[b];
+      BlockPlan& B = out.blocks[b];
+      const int64_t r0 = b * BS, r1 = std::min<int64_t>(n, r0 + BS);
+      std::vector<int32_t> reg;
+      auto add = [&](int32_t row) {
+        const uint32_t h = slot(row);
+        if (tkey[h] == row) return;
+        tkey[h] = row;
+        tval[h] = (int32_t)reg.size();
+        used.push_back(h);
+        reg.push_back(row);
+      };
+      for (int64_t i = r0; i < r1; ++i) add((int32_t)i);
+      B.nown = (int32_t)(r1 - r0);
+      size_t ring_lo = 0;
+      for (int d = 1; d <= S && P.ok; ++d) {
+        next.clear();
+        const size_t ring_hi = reg.size();
+        for (size_t q = ring_lo; q < ring_hi; ++q) {
+          const int64_t i = reg[q];
+          for (int k = 0; k < kPlanSlots; ++k) {
+            const int32_t c = nb[(size_t)i * kPlanSlots + k];
+            if (c >= 0 && tkey[slot(c)] != c) {
+              const uint32_t h = slot(c);
+              tkey[h] = c;  // reserve; the local index is set below, in ring order
+              used.push_back(h);
+              next.push_back(c);
+              if (reg.size() + next.size() > (size_t)max_region) {
+                P.ok = false;
+                break;
+              }
+            }
+          }
+          if (!P.ok) break;
+        }
+        std::sort(next.begin(), next.end());
+        ring_lo = reg.size();
+        for (int32_t c : next) {
+          tval[slot(c)] = (int32_t)reg.size();
+          reg.push_back(c);
+        }
+        if (d == 1) B.n1 = (int32_t)reg.size();
+        if (d == S - 1) B.ninner = (int32_t)reg.size();
+      }
+      if (S == 1) B.ninner = B.nown;
+      B.nreg = (int32_t)reg.size();
+      if (P.ok) {
+        P.halo.assign(reg.begin() + B.nown, reg.end());
+        P.lmat.assign((size_t)B.ninner * kPlanSlots, 0);
+        for (int32_t l = 0; l < B.ninner; ++l) {
+          const int64_t i = reg[l];
+          for (int k = 0; k < kPlanSlots; ++k) {
+            const int32_t c = nb[(size_t)i * kPlanSlots + k];
+            uint16_t e = (uint16_t)(kPlanPad | (uint16_t)l);
+            if (c >= 0)
+              e = (uint16_t)((uint16_t)tval[slot(c)] |
+                             (nbw[(size_t)i * kPlanSlots + k] ? kPlanMinusOne : 0));
+            P.lmat[(size_t)l * kPlanSlots + k] = e;
+          }
+        }
+      }
+      for (uint32_t h : used) {
+        tkey[h] = -1;
+        tval[h] = -1;
+      }
+      used.clear();
+    }
+  };
+  const int nt = std::max(1, std::min<int>(threads, (int)std::min<int64_t>(nblk, 64)));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work, t, nt);
+  work(0, nt);
+  for (auto& th : pool) th.join();
+  int64_t hoff = 0, loff = 0;
+  for (int32_t b = 0; b < out.grid; ++b) {
+    if (!parts[b].ok) return false;
+    BlockPlan& B = out.blocks[b];
+    B.halo_off = (int32_t)hoff;
+    B.lmat_off = (int32_t)loff;
+    hoff += (int64_t)parts[b].halo.size();
+    loff += B.ninner;
+    out.max_region = std::max(out.max_region, B.nreg);
+    if (hoff > INT32_MAX || loff > INT32_MAX / kPlanSlots) return false;
+  }
+  out.halo.reserve(hoff);
+  out.lmat.reserve((size_t)loff * kPlanSlots);
+  for (int32_t b = 0; b < out.grid; ++b) {
+    out.halo.insert(out.halo.end(), parts[b].halo.begin(), parts[b].halo.end());
+    out.lmat.insert(out.lmat.end(), parts[b].lmat.begin(), parts[b].lmat.end());
+  }
+  return true;
+}
+
+}  // namespace fi
