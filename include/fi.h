@@ -147,9 +147,14 @@ typedef struct fi_mesh_info {
   int64_t nnz_ff; /* stored entries of K_FF, diagonal included */
   int64_t nnz_fd; /* stored entries of K_FD */
   int64_t device_bytes; /* device memory held by the mesh */
-  int64_t cg_blocks;    /* blocks of one CG step launch (0 before assembly) */
+  int64_t cg_blocks;    /* blocks of one FP32 CG step launch (0 before assembly) */
   int64_t cg_block_size; /* threads per block of that launch */
   int64_t large_mode;   /* 1: a separate launch sums the step's partial sums */
+  int64_t cg_iters_per_launch; /* CG iterations one FP32 step launch advances:
+                                  3 on the quadtree mesh (blocks of Z-ordered
+                                  rows with 3-hop halos), else 1 */
+  int64_t cg_max_region;  /* rows of the largest block region (3 per launch), or 0 */
+  int64_t cg_region_rows; /* region rows over all blocks (own rows included), or 0 */
 } fi_mesh_info;
 
 /* Default solve options: FP32 inner PCG with FP64 refinement to 1e-10. */

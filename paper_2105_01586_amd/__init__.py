@@ -99,7 +99,8 @@ class _L1Stats(ctypes.Structure):
 class _MeshInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("N", "P", "V", "T", "L", "n", "m", "nnz_ff", "nnz_fd", "device_bytes",
-                 "cg_blocks", "cg_block_size", "large_mode")]
+                 "cg_blocks", "cg_block_size", "large_mode", "cg_iters_per_launch",
+                 "cg_max_region", "cg_region_rows")]
 
 
 class _ServerOpts(ctypes.Structure):

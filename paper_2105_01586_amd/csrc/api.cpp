@@ -498,9 +498,12 @@ int fi_mesh_get_info(const fi_mesh* M, fi_mesh_info* info) {
   info->device_bytes = M->device_bytes;
   for (const fi_mesh* c : M->chan)
     if (c) info->device_bytes += c->device_bytes;
-  info->cg_blocks = M->cg_grid;
+  info->cg_blocks = M->ss ? M->ss->grid : M->cg_grid;
   info->cg_block_size = M->cg_bs;
-  info->large_mode = M->large_mode ? 1 : 0;
+  info->large_mode = (M->ss ? M->ss->large : M->large_mode) ? 1 : 0;
+  info->cg_iters_per_launch = M->ss ? kSsIters : 1;
+  info->cg_max_region = M->ss ? M->ss->max_region : 0;
+  info->cg_region_rows = M->ss ? M->ss->region_rows : 0;
   return FI_OK;
 }
 

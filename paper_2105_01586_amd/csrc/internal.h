@@ -101,6 +101,28 @@ class Arena {
   std::map<size_t, size_t> live_;   // offset -> bytes
 };
 
+// The S-iteration CG launch (sstep.hip): its plan on the device and its
+// vectors, all in the plan's Z-order numbering of the free rows.
+struct SsState {
+  int grid = 0;             // blocks of one launch (a multiple of 8)
+  int max_region = 0;       // largest block region (rows)
+  bool large = false;       // a separate launch sums the Gram partials
+  int64_t region_rows = 0;  // region rows over all blocks (own rows included)
+  int64_t lmat_rows = 0;    // local matrix rows over all blocks
+  int32_t* perm = nullptr;  // new index -> natural free row
+  void* blocks = nullptr;   // BlockPlan per block
+  int32_t* region = nullptr;  // region rows of every block, own rows first
+  void* lmat = nullptr;     // 8 x uint16 per local matrix row
+  float* W[2] = {nullptr, nullptr};  // per row: P_0..P_S, Z_0..Z_{S-1}, D^-1 (8 floats)
+  float* x = nullptr;       // FP32 correction of the inner solve
+  float* d = nullptr;       // diagonal of K_FF
+  double* b = nullptr;      // right-hand side
+  double* r64 = nullptr;    // FP64 residual
+  double* x64[2] = {nullptr, nullptr};  // FP64 iterate, by buffer parity
+  double* part = nullptr;   // Gram partials: 2 parities x 32 values x grid (value-major)
+  double* red = nullptr;    // reduced Gram (large systems): 32 doubles
+};
+
 struct CGState {  // state of one fused-CG inner solver in precision T
   void* x = nullptr;
   void* p = nullptr;
@@ -174,6 +196,7 @@ struct fi_mesh {
   int64_t pred_launches[fi::kPredSlots] = {};
   hipEvent_t chunk_ev[fi::kChunkEvents] = {};  // one after each queued chunk of step launches
   fi::CGState cg32, cg64;
+  fi::SsState* ss = nullptr;  // the S-iteration launch's plan and state (FP32 solves), or NULL
   double* d_part = nullptr;   // per-block partial sums: 2 parities x cg_grid x 4
   double* d_red = nullptr;    // reduction scratch (kMaxGrid doubles)
   double* d_red_out = nullptr;  // final reduced scalars (8 doubles)
@@ -324,6 +347,30 @@ int64_t cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision);
 // calls it, and a channel view gets its own with the parent's launch shape.
 int alloc_solver_state(fi_mesh* M);
 int solver_channel_setup(fi_mesh* S, const fi_mesh* M);
+
+// The S-iteration CG launch (sstep.hip). ss_setup builds its plan after the
+// first assembly of a quadtree mesh (nothing for other meshes, or when
+// FI_CG_SSTEP=0) and refreshes the matrix values after later ones.
+constexpr int kSsIters = 3;  // CG iterations per launch
+int ss_setup(fi_mesh* M);
+void ss_release(fi_mesh* M);
+// FP32 solve of K_FF x = b64 from x0 (natural order, may be NULL) with the
+// S-iteration launch; the result in d_x64 (natural order).
+int ss_solve(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats, const double* x0);
+int ss_time_kernel(fi_mesh* M, int reps, double* ms);
+int64_t ss_kernel_bytes(const fi_mesh* M);
+// The same for the channel views ch[0..nc-1] of one mesh in one launch per
+// step (each channel the bits of its own ss_solve), and its timing.
+int ss_solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats,
+                   const double* const* x0);
+int ss_time_multi(fi_mesh* const* ch, int nc, int reps, double* ms);
+int ss_channel_setup(fi_mesh* S, const fi_mesh* M);
+// Batched steps of meshes that all have the plan (see batch_launch_steps),
+// and the start of such a solve.
+int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count);
+int ss_arm(fi_mesh* M, const fi_solve_opts* opts, int epoch, const double* x0);
+// Device bytes the S-iteration state of a system with n rows may take.
+int64_t ss_footprint(int64_t n);
 
 // Multi-RHS solves (solver.hip): K_FF x_c = b64 of channel view c, for the nc
 // views in ch (ch[0] the mesh itself), advanced together by one step launch

@@ -161,6 +161,8 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   // CGLS workspace and the request's buffers
   add(m, 8); add(m, 8); add(P, 8); add(P, 8); add(n, 8); add(8, 8);
   add(P, 1); add(m, 8);
+  // the S-iteration solver's plan and vectors
+  total += ss_footprint(n);
   (void)iters;
   return total;
 }

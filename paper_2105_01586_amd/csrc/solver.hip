@@ -53,6 +53,7 @@
 #include <string>
 
 #include "internal.h"
+#include "cg_common.h"
 #include "pacer.h"
 #include "reduce.h"
 
@@ -65,49 +66,6 @@ inline int grid_for(int64_t n) {
   return (int)(g < 1 ? 1 : g);
 }
 
-enum Phase : int32_t { kInit = 1, kIter = 2, kDoneOk = 3, kDoneNoConv = 4, kDoneBad = 5 };
-
-// Solver state, one record per launch parity.
-struct Rec {
-  int32_t phase;
-  int32_t iter;       // iteration within the current inner solve
-  int32_t total;      // iterations over all inner solves
-  int32_t ninner;     // inner solves started
-  int32_t stagnant;   // consecutive refinements that did not halve ||r||
-  int32_t xp;         // x64 buffer holding the iterate
-  int32_t epoch;      // solve this record belongs to (set by the start launch)
-  int32_t seq;        // launches since the start
-  double gamma_prev, alpha_prev, rho_ref;
-  double tol2;        // inner tolerance, squared
-  double rnorm;       // FP64 residual norm at the start of this inner solve
-  double bnorm;
-  double pad2, pad3;
-};
-static_assert(sizeof(Rec) == 96, "record layout");
-
-// What the host sees of a solve: the launch that ends it writes the outcome
-// into pinned host memory with system-scope stores (they go through to host
-// memory; nobody waits for them). Other launches do not write here: a store
-// to host memory costs a working launch several microseconds. `word` holds,
-// in one 64-bit store,
-//   bits  0-3   phase            bits 4-30  epoch (the solve)
-//   bits 32-55  iterations       bits 56-62 inner solves     bit 63 x64 buffer,
-// so the host reads phase, epoch and counts consistently; the residual norms
-// are stored first, to the same cache line.
-struct Mirror {
-  uint64_t word;
-  int64_t pad;
-  double rnorm, bnorm;
-};
-constexpr int kEpochMask = (1 << 27) - 1;
-
-// Constant parameters of a solve (written by the start launch).
-struct Params {
-  double rtol, inner_rtol, max_inner, max_refine, mixed, epoch, atol, pad;
-};
-
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // New residual of row j from the previous state: r - alpha (s + beta q).
 // Owners and neighbours call the same function, so both see the same bits.
@@ -136,14 +94,6 @@ struct alignas(4 * sizeof(T)) Quad {
   T r, s, q, d;
 };
 
-// Blocks are dispatched round-robin over the 8 XCDs (hardware block b runs on
-// XCD b % 8; the grid is a multiple of 8). Logical block (b % 8) * (G / 8) +
-// b / 8 gives each XCD one contiguous slab of rows, so the neighbour values a
-// block gathers mostly sit in its own XCD's L2.
-__device__ __forceinline__ int logical_block() {
-  const int b = blockIdx.x, per = gridDim.x >> 3;
-  return (b & 7) * per + (b >> 3);
-}
 
 template <typename T>
 struct StepArgs {
@@ -175,42 +125,6 @@ struct StepArgs {
   int force;              // timing only: always iterate, ignore stop tests
 };
 
-// Builds a record from explicit fields (no copy of an input record, whose
-// unused bytes the compiler would otherwise carry through the kernel), and
-// reports it to the host mirror.
-__device__ __forceinline__ void put_rec(Rec* out, Mirror* mirror, int epoch, int seq, int phase,
-                                        int iter, int total, int ninner, int stagnant, int xp,
-                                        double gamma_prev, double alpha_prev, double rho_ref,
-                                        double tol2, double rnorm, double bnorm) {
-  Rec r;
-  r.phase = phase;
-  r.iter = iter;
-  r.total = total;
-  r.ninner = ninner;
-  r.stagnant = stagnant;
-  r.xp = xp;
-  r.epoch = epoch;
-  r.seq = seq;
-  r.gamma_prev = gamma_prev;
-  r.alpha_prev = alpha_prev;
-  r.rho_ref = rho_ref;
-  r.tol2 = tol2;
-  r.rnorm = rnorm;
-  r.bnorm = bnorm;
-  r.pad2 = 0.0;
-  r.pad3 = 0.0;
-  *out = r;
-  if (mirror && phase >= kDoneOk) {
-    __hip_atomic_store(&mirror->rnorm, rnorm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&mirror->bnorm, bnorm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    const uint64_t w = (uint64_t)(uint32_t)((epoch << 4) | phase) |
-                       ((uint64_t)((uint32_t)total & 0xFFFFFFu) << 32) |
-                       ((uint64_t)((uint32_t)ninner & 0x7Fu) << 56) | ((uint64_t)(xp & 1) << 63);
-    // release: the norms above are visible to a host that reads this word
-    // with acquire (read_mirror) and sees this solve's epoch
-    __hip_atomic_store(&mirror->word, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-}
 
 // Partial sums of block `lb` (the logical block: the index is what fixes the
 // order in which the next launch adds them up).
@@ -895,35 +809,6 @@ int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0
 
 
 
-int next_epoch(fi_mesh* M) {
-  M->epoch = (M->epoch + 1) & kEpochMask;
-  if (M->epoch == 0) M->epoch = 1;  // 0 never names a solve
-  return M->epoch;
-}
-
-// Reads the host mirror: 1 with stats filled when solve `epoch` has ended,
-// 0 while it runs.
-int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
-  Mirror* m = (Mirror*)M->h_mirror;
-  const uint64_t w = __atomic_load_n(&m->word, __ATOMIC_ACQUIRE);
-  *rc = FI_OK;
-  if ((int)((w & 0x7FFFFFFFu) >> 4) != epoch) return 0;
-  const int phase = (int)(w & 15);
-  if (phase < kDoneOk) return 0;
-  stats->iterations = (int64_t)((w >> 32) & 0xFFFFFFu);
-  stats->refinements = (int32_t)((w >> 56) & 0x7Fu);
-  double rn, bn;
-  __atomic_load(&m->rnorm, &rn, __ATOMIC_RELAXED);
-  __atomic_load(&m->bnorm, &bn, __ATOMIC_RELAXED);
-  stats->rel_residual = bn > 0 ? rn / bn : 0.0;
-  stats->residual = rn;
-  stats->rhs_norm = bn;
-  stats->status = phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
-  M->d_x64 = M->d_x64buf[(w >> 63) & 1];
-  if (phase == kDoneBad) *rc = fail(FI_E_INVALID, "right-hand side or residual not finite");
-  return 1;
-}
-
 // The host queues chunks of kChunk step launches, each followed by an event
 // (plain launches: measured faster here than replaying a recorded graph),
 // keeps at most kAhead chunks queued, and stops as soon as the mirror shows
@@ -931,10 +816,6 @@ int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc) {
 // later work on the stream is ordered after them. Pacing and the launch
 // prediction: pacer.h.
 static_assert(kAhead <= kChunkEvents, "every queued chunk needs its own event");
-
-int64_t launches_of(const fi_solve_stats* s) {
-  return launches_used(s->iterations, s->refinements);
-}
 
 // Which prediction slot a solve uses: precision and cold or warm start.
 template <typename T>
@@ -957,8 +838,9 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const d
   Pacer pc = pacer_for(o, M->pred_launches[slot]);
   for (;;) {
     int drc = FI_OK;
-    if (read_mirror(M, epoch, stats, &drc)) {
-      M->pred_launches[slot] = launches_of(stats);
+    int64_t nl = 0;
+    if (read_mirror(M, epoch, stats, &drc, &nl)) {
+      M->pred_launches[slot] = nl;
       return drc;
     }
     if (const int n = pc.next()) {
@@ -979,7 +861,7 @@ int solve_dev(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const d
       if (q != hipErrorNotReady)
         return fail(FI_E_HIP, std::string("stream failed: ") + hipGetErrorString(q));
     } else {  // everything launched (up to the limit) has run and the solve never ended
-      if (read_mirror(M, epoch, stats, &drc)) return drc;
+      if (read_mirror(M, epoch, stats, &drc, nullptr)) return drc;
       return fail(FI_E_HIP, "solver did not report termination");
     }
     __builtin_ia32_pause();
@@ -1079,9 +961,10 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
     for (int c = 0; c < nc; ++c) {
       if (!done[c]) {
         int drc = FI_OK;
-        done[c] = read_mirror(ch[c], epoch[c], &stats[c], &drc) != 0;
+        int64_t nl = 0;
+        done[c] = read_mirror(ch[c], epoch[c], &stats[c], &drc, &nl) != 0;
         if (done[c]) {
-          ch[c]->pred_launches[pred_slot<T>(x0 ? x0[c] : nullptr)] = launches_of(&stats[c]);
+          ch[c]->pred_launches[pred_slot<T>(x0 ? x0[c] : nullptr)] = nl;
           if (drc && !first_rc) first_rc = drc;
         }
       }
@@ -1123,6 +1006,38 @@ int solve_multi_dev(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve
 
 }  // namespace
 
+int next_epoch(fi_mesh* M) {
+  M->epoch = (M->epoch + 1) & kEpochMask;
+  if (M->epoch == 0) M->epoch = 1;  // 0 never names a solve
+  return M->epoch;
+}
+
+// Reads the host mirror: 1 with stats filled when solve `epoch` has ended,
+// 0 while it runs.
+int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc, int64_t* launches) {
+  Mirror* m = (Mirror*)M->h_mirror;
+  const uint64_t w = __atomic_load_n(&m->word, __ATOMIC_ACQUIRE);
+  *rc = FI_OK;
+  if ((int)((w & 0x7FFFFFFFu) >> 4) != epoch) return 0;
+  const int phase = (int)(w & 15);
+  if (phase < kDoneOk) return 0;
+  stats->iterations = (int64_t)((w >> 32) & 0xFFFFFFu);
+  stats->refinements = (int32_t)((w >> 56) & 0x7Fu);
+  double rn, bn;
+  int64_t nl;
+  __atomic_load(&m->launches, &nl, __ATOMIC_RELAXED);
+  if (launches) *launches = nl;
+  __atomic_load(&m->rnorm, &rn, __ATOMIC_RELAXED);
+  __atomic_load(&m->bnorm, &bn, __ATOMIC_RELAXED);
+  stats->rel_residual = bn > 0 ? rn / bn : 0.0;
+  stats->residual = rn;
+  stats->rhs_norm = bn;
+  stats->status = phase == kDoneOk ? FI_OK : FI_E_NO_CONVERGENCE;
+  M->d_x64 = M->d_x64buf[(w >> 63) & 1];
+  if (phase == kDoneBad) *rc = fail(FI_E_INVALID, "right-hand side or residual not finite");
+  return 1;
+}
+
 int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats,
                 const double* const* x0) {
   if (nc < 1 || nc > kMaxRhs) return fail(FI_E_INVALID, "1 to 3 right-hand sides per solve");
@@ -1136,6 +1051,7 @@ int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_
   }
   if (ch[0]->n == 0) return FI_OK;
   if (opts->precision == FI_PREC_FP64) return solve_multi_dev<double>(ch, nc, opts, stats, x0);
+  if (ch[0]->ss) return ss_solve_multi(ch, nc, opts, stats, x0);
   return solve_multi_dev<float>(ch, nc, opts, stats, x0);
 }
 
@@ -1145,6 +1061,7 @@ int time_multi_kernel(fi_mesh* const* ch, int nc, int precision, int reps, doubl
   fi_mesh* M0 = ch[0];
   if (M0->n == 0 || reps < 1 || nc < 1 || nc > kMaxRhs)
     return fail(FI_E_INVALID, "nothing to time");
+  if (precision != FI_PREC_FP64 && M0->ss) return ss_time_multi(ch, nc, reps, ms);
   hipStream_t st = M0->ctx->stream;
   const bool d = precision == FI_PREC_FP64;
   fi_solve_opts o;
@@ -1185,8 +1102,20 @@ int time_multi_kernel(fi_mesh* const* ch, int nc, int precision, int reps, doubl
   return FI_OK;
 }
 
-int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int count) {
-  if (act.empty() || count <= 0) return FI_OK;
+int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& all, int count) {
+  if (all.empty() || count <= 0) return FI_OK;
+  // meshes with the S-iteration plan step in their own launches
+  std::vector<fi_mesh*> ssm;
+  std::vector<BatchSlot> act;
+  for (const BatchSlot& s : all) {
+    if (s.M->ss) ssm.push_back(s.M);
+    else act.push_back(s);
+  }
+  if (!ssm.empty()) {
+    const int rc = ss_batch_launch(st, ssm, count);
+    if (rc) return rc;
+  }
+  if (act.empty()) return FI_OK;
   for (const BatchSlot& s : act)
     if (s.M->ell_w <= 0 || s.M->cg_bs != kBatchBS || s.M->n <= 0)
       return fail(FI_E_INVALID, "mesh cannot take part in a batched solve");
@@ -1251,16 +1180,18 @@ int batch_launch_steps(hipStream_t st, const std::vector<BatchSlot>& act, int co
 int solve_arm(fi_mesh* M, const fi_solve_opts* o, int* epoch, const double* x0) {
   if (M->n <= 0) return fail(FI_E_INVALID, "nothing to solve");
   *epoch = next_epoch(M);
+  if (M->ss) return ss_arm(M, o, *epoch, x0);
   return launch_start<float>(M, o, *epoch, x0);
 }
 
 int solve_poll(fi_mesh* M, int epoch, fi_solve_stats* stats, int* done) {
   int rc = FI_OK;
-  *done = read_mirror(M, epoch, stats, &rc);
+  *done = read_mirror(M, epoch, stats, &rc, nullptr);
   return rc;
 }
 
 void solver_release(fi_mesh* M) {
+  ss_release(M);
   for (int k = 0; k < kChunkEvents; ++k) {
     if (M->chunk_ev[k]) (void)hipEventDestroy(M->chunk_ev[k]);
     M->chunk_ev[k] = nullptr;
@@ -1305,7 +1236,8 @@ int solver_channel_setup(fi_mesh* S, const fi_mesh* M) {
   S->n_pad = M->n_pad;
   S->ell_w = M->ell_w;
   S->d_ell = M->d_ell;
-  return alloc_solver_state(S);
+  const int rc = alloc_solver_state(S);
+  return rc ? rc : ss_channel_setup(S, M);
 }
 
 // Called after every assembly: picks the launch shape and packs the ELL copy.
@@ -1361,7 +1293,8 @@ int solver_setup(fi_mesh* M) {
       if (M->h_ctl[0] != 0) M->ell_w = 0;  // values other than -1/2, -1: use CSR
     }
   }
-  return FI_OK;
+  // the S-iteration launch: its plan (first assembly) or its values
+  return ss_setup(M);
 }
 
 // Solves K_FF x = b64 (both in the mesh workspace) from x0 (device, n; NULL
@@ -1375,6 +1308,7 @@ int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats, con
   stats->rhs_norm = 0.0;
   if (M->n == 0) return FI_OK;
   if (opts->precision == FI_PREC_FP64) return solve_dev<double>(M, opts, stats, x0);
+  if (M->ss) return ss_solve(M, opts, stats, x0);
   return solve_dev<float>(M, opts, stats, x0);
 }
 
@@ -1382,6 +1316,7 @@ int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats, con
 // phase) between two HIP events on the context stream.
 int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
   if (M->n == 0 || reps < 1) return fail(FI_E_INVALID, "nothing to time");
+  if (precision != FI_PREC_FP64 && M->ss) return ss_time_kernel(M, reps, ms);
   hipStream_t st = M->ctx->stream;
   const bool d = precision == FI_PREC_FP64;
   fi_solve_opts o;
@@ -1419,11 +1354,14 @@ int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
 // plus row pointers), and per row the reads of r, s, q, D^-1, x, p and the
 // writes of x, p, r, s, q.
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision) {
+  if (precision != FI_PREC_FP64 && M->ss) return ss_kernel_bytes(M);
   return cg_multi_kernel_bytes(M, 1, precision);
 }
 
 // With nrhs solves per launch the matrix counts once.
 int64_t cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision) {
+  if (precision != FI_PREC_FP64 && M->ss)  // the plan and diagonal once, the vectors per solve
+    return ss_kernel_bytes(M) + (int64_t)(nrhs - 1) * M->n * (32 + 32 + 8);
   const int64_t w = precision == FI_PREC_FP64 ? 8 : 4;
   const int64_t mat = M->ell_w > 0 ? M->nnz_off * 4  // encoded entries; padding not counted
                                    : M->nnz_off * (4 + w) + (M->n + 1) * 4;

@@ -4,10 +4,12 @@
 // block applies the preconditioned operator S times to its rows' vectors, so
 // it needs the rows within S hops of its own in the matrix graph. The free
 // rows are therefore renumbered along a Z-order (Morton) curve of their
-// lattice coordinates, so that a block's BS consecutive rows form a compact
+// lattice coordinates (the last lattice row and column clamped onto the one
+// before), so that a block's BS consecutive rows form a compact
 // patch, and each block gets:
 //   - its region: its own rows (local index 0 .. nown-1), then the rows at
-//     graph distance 1, 2, ..., S from them (ascending within each ring);
+//     graph distance 1, 2, ..., S from them (ascending within each ring),
+//     listed in full (own rows included) so that a region row is one load;
 //   - a local matrix for the rows of its region at distance <= S - 1: for
 //     each such row, up to 8 entries, each the local index of the neighbour
 //     (bits 0-13), bit 14 for padding (the entry then points at the row
@@ -34,8 +36,8 @@ constexpr uint16_t kPlanMinusOne = 1u << 15;
 constexpr int kPlanSlots = 8;  // entries per local matrix row
 
 struct BlockPlan {
-  int32_t halo_off;  // first halo row of the block in SsPlan::halo
-  int32_t lmat_off;  // first local matrix row of the block in SsPlan::lmat (rows of 8)
+  int32_t reg_off;   // first region row of the block in SsPlan::region (0 when empty)
+  int32_t lmat_off;  // first local matrix row of the block in SsPlan::lmat (rows of 8; 0 when empty)
   int32_t nown;      // own rows
   int32_t n1;        // region rows at distance <= 1
   int32_t ninner;    // region rows at distance <= S - 1 (rows of the local matrix)
@@ -51,7 +53,7 @@ struct SsPlan {
   int32_t max_region = 0;        // largest nreg over the blocks
   std::vector<int32_t> perm;     // new index -> natural row
   std::vector<BlockPlan> blocks;
-  std::vector<int32_t> halo;     // halo rows (new indices), block after block
+  std::vector<int32_t> region;   // region rows (new indices), block after block
   std::vector<uint16_t> lmat;    // local matrix rows, kPlanSlots entries each
 };
 
@@ -81,9 +83,20 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   out.n = n;
   if (n <= 0 || W > kPlanSlots || S < 1 || max_region > kPlanLocalMax || max_region < BS)
     return false;
-  // Z-order of the free rows (ties cannot occur: rows sit at distinct points)
+  // Z-order of the free rows. The lattice runs from 0 to N (a power of two),
+  // and its last row and column would take a bit of their own in the key,
+  // which would string them out into blocks that are thin strips with wide
+  // halos; coordinates are therefore clamped to N - 1, which keeps those
+  // vertices next to their neighbours (ties go to the lower natural row).
+  int32_t maxc = 0;
+  for (int64_t i = 0; i < 2 * n; ++i) maxc = std::max(maxc, xy[i]);
+  uint32_t top = 1;
+  while (maxc > 1 && top * 2 <= (uint32_t)maxc) top *= 2;
+  const uint32_t clampc = maxc > 1 ? top - 1 : (uint32_t)maxc;
   std::vector<uint64_t> key(n);
-  for (int64_t i = 0; i < n; ++i) key[i] = morton_key((uint32_t)xy[2 * i], (uint32_t)xy[2 * i + 1]);
+  for (int64_t i = 0; i < n; ++i)
+    key[i] = morton_key(std::min((uint32_t)xy[2 * i], clampc),
+                        std::min((uint32_t)xy[2 * i + 1], clampc));
   out.perm.resize(n);
   for (int64_t i = 0; i < n; ++i) out.perm[i] = (int32_t)i;
   std::sort(out.perm.begin(), out.perm.end(),
@@ -109,7 +122,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   out.blocks.assign(out.grid, BlockPlan{});
   // per block: region (BFS by rings) and local matrix, built in parallel
   struct Part {
-    std::vector<int32_t> halo;
+    std::vector<int32_t> region;
     std::vector<uint16_t> lmat;
     bool ok = true;
   };
@@ -174,7 +187,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
       if (S == 1) B.ninner = B.nown;
       B.nreg = (int32_t)reg.size();
       if (P.ok) {
-        P.halo.assign(reg.begin() + B.nown, reg.end());
+        P.region.assign(reg.begin(), reg.end());
         P.lmat.assign((size_t)B.ninner * kPlanSlots, 0);
         for (int32_t l = 0; l < B.ninner; ++l) {
           const int64_t i = reg[l];
@@ -200,21 +213,26 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   for (int t = 1; t < nt; ++t) pool.emplace_back(work, t, nt);
   work(0, nt);
   for (auto& th : pool) th.join();
-  int64_t hoff = 0, loff = 0;
+  int64_t roff = 0, loff = 0;
   for (int32_t b = 0; b < out.grid; ++b) {
     if (!parts[b].ok) return false;
     BlockPlan& B = out.blocks[b];
-    B.halo_off = (int32_t)hoff;
-    B.lmat_off = (int32_t)loff;
-    hoff += (int64_t)parts[b].halo.size();
+    // an empty block points at the start of both lists (valid, unused rows)
+    B.reg_off = B.nreg > 0 ? (int32_t)roff : 0;
+    B.lmat_off = B.ninner > 0 ? (int32_t)loff : 0;
+    roff += (int64_t)parts[b].region.size();
     loff += B.ninner;
     out.max_region = std::max(out.max_region, B.nreg);
-    if (hoff > INT32_MAX || loff > INT32_MAX / kPlanSlots) return false;
+    if (roff > INT32_MAX || loff > INT32_MAX / kPlanSlots) return false;
   }
-  out.halo.reserve(hoff);
+  // the device memory a plan may take is bounded (region and local matrix
+  // rows at most three per free row), so memory can be reserved before it
+  // is built
+  if (roff > 3 * n || loff > 3 * n) return false;
+  out.region.reserve(roff);
   out.lmat.reserve((size_t)loff * kPlanSlots);
   for (int32_t b = 0; b < out.grid; ++b) {
-    out.halo.insert(out.halo.end(), parts[b].halo.begin(), parts[b].halo.end());
+    out.region.insert(out.region.end(), parts[b].region.begin(), parts[b].region.end());
     out.lmat.insert(out.lmat.end(), parts[b].lmat.begin(), parts[b].lmat.end());
   }
   return true;

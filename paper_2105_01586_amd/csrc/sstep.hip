@@ -1,0 +1,1310 @@
+// Jacobi-preconditioned CG with S = 3 iterations per launch (the s-step, or
+// communication-avoiding, form of the same method), for FP32 inner solves
+// on the quadtree mesh, with FP64 iterative refinement.
+//
+// Section 2.2 solves the SPD FEM system with conjugate gradients. One CG
+// iteration needs a global reduction, so the one-iteration step kernel
+// (solver.hip) pays one kernel boundary per iteration; on systems that fit
+// in the caches that boundary, not memory traffic, sets the time. Here one
+// launch advances S iterations:
+//   - each block owns BS consecutive rows of a Z-order numbering of the free
+//     rows and reads the basis of the previous launch on its region (its rows
+//     and the rows within S hops, ss_plan.h);
+//   - every block reduces the Gram matrix G = W^T D W of the previous basis
+//     W = [P_0..P_S, Z_0..Z_{S-1}] (FP64, 28 values), then runs the S CG
+//     iterations on coefficient vectors of length 2S+1 (redundantly, the same
+//     in every block): with M = D^-1 K and T the change of basis of M,
+//        alpha = (z, r) / (p, K p) = zc'G zc / pc'G T pc,
+//        xc += alpha pc,  zc -= alpha T pc,  beta = zc'G zc (new / old),
+//        pc = zc + beta pc;
+//   - it forms p = W pc and z = W zc on its region, adds W xc to the
+//     correction of its rows, and builds the next basis in LDS: the
+//     Chebyshev polynomials of M on [0, 2] (its spectrum), rho_0 = v,
+//     rho_1 = (M - I) v = D^-1 K_off v, rho_k+1 = 2 (M - I) rho_k - rho_k-1,
+//     for p (S + 1 of them) and z (S), on the shrinking rings of its region;
+//   - it writes its rows' new basis and its partial Gram sums.
+// In exact arithmetic the iterates are those of Jacobi PCG. The inner solve
+// stops when (r, z) falls below its tolerance squared times the starting
+// (r, z); the launch that finds this adds the correction in FP64 and forms
+// the FP64 residual b - K x on its rows (from the rows within one hop), and
+// the next launch starts the next inner solve or ends the solve, exactly as
+// in the one-iteration kernel.
+//
+// Every per-launch quantity (basis, partial sums, record, FP64 iterate) is
+// double buffered by launch parity, so blocks of one launch never read each
+// other's writes. No atomics: every sum has a fixed order, results are
+// reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "cg_common.h"
+#include "internal.h"
+#include "pacer.h"
+#include "reduce.h"
+#include "ss_plan.h"
+
+namespace fi {
+
+namespace {
+
+constexpr int S = kSsIters;
+static_assert(S == 3, "the launch below is written for three iterations");
+constexpr int NB = 2 * S + 1;           // basis vectors: P_0..P_S, Z_0..Z_{S-1}
+constexpr int NG = NB * (NB + 1) / 2;   // Gram entries (upper triangle)
+constexpr int NGP = 32;                 // Gram slots per block (NG used)
+constexpr int BS = 512;                 // threads and own rows per block
+constexpr int kSmallGrid = 1024;        // blocks up to which each block re-reduces the partials
+constexpr int kMaxRegion = 2048;        // region rows per block (LDS: 5 floats per row)
+constexpr int kZ0 = S + 1;              // index of Z_0 in the basis
+
+// Index of G[a][b] (a <= b) in the upper triangle, row by row.
+__host__ __device__ constexpr int gi(int a, int b) {
+  return a <= b ? a * NB - a * (a - 1) / 2 + (b - a) : b * NB - b * (b - 1) / 2 + (a - b);
+}
+
+struct SsArgs {
+  int n;
+  int grid;
+  const int32_t* perm;
+  const BlockPlan* blocks;
+  const int32_t* region;  // region rows of every block (own rows first)
+  const uint4* lmat;
+  const float4* Win;   // 2 float4 per row: P_0..P_3 | Z_0..Z_2, D^-1
+  float4* Wout;
+  float* x;
+  const float* d;
+  double* b;
+  double* r64;
+  double* x64a;
+  double* x64b;
+  double* xout;        // natural-order result (written when the solve ends)
+  const double* part_in;
+  double* part_out;
+  const Rec* rec_in;
+  Rec* rec_out;
+  const Params* prm;
+  Mirror* mirror;
+  int force;           // timing only: always iterate
+};
+
+__device__ __forceinline__ float lm_weight(uint32_t e) {
+  return (e & kPlanPad) ? 0.0f : ((e & kPlanMinusOne) ? -1.0f : -0.5f);
+}
+
+__device__ __forceinline__ uint32_t lm_entry(const uint4& m, int k) {
+  const uint32_t w = k < 2 ? m.x : k < 4 ? m.y : k < 6 ? m.z : m.w;
+  return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+// Region row l of a block -> row (new numbering).
+__device__ __forceinline__ int region_row(const SsArgs& A, const BlockPlan& B, int base, int l) {
+  (void)base;
+  return A.region[B.reg_off + l];
+}
+
+// sum_k w_k v[idx_k] over one local matrix row, for p and z at once
+// (FP32, slot order; v holds (p, z) per region row).
+__device__ __forceinline__ float2 lm_apply(const uint4& m, const float2* v) {
+  float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int k = 0; k < kPlanSlots; ++k) {
+    const uint32_t e = lm_entry(m, k);
+    const float w = lm_weight(e);
+    const float2 x = v[e & (kPlanLocalMax - 1)];
+    acc.x = __builtin_fmaf(w, x.x, acc.x);
+    acc.y = __builtin_fmaf(w, x.y, acc.y);
+  }
+  return acc;
+}
+
+// Coefficients of M v for v = sum c_a rho_a (P block 0..S, Z block S+1..2S;
+// the top coefficient of each block is zero wherever this is used):
+// M rho_0 = rho_1 + rho_0, M rho_k = rho_k+1 / 2 + rho_k + rho_k-1 / 2.
+__device__ __forceinline__ void tcoef(const double (&c)[NB], double (&o)[NB]) {
+#pragma unroll
+  for (int a = 0; a < NB; ++a) o[a] = 0.0;
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk) {
+    const int base = blk == 0 ? 0 : kZ0, m = blk == 0 ? S + 1 : S;
+#pragma unroll
+    for (int k = 0; k < m - 1; ++k) {
+      const double ck = c[base + k];
+      if (k == 0) {
+        o[base + 1] += ck;
+        o[base] += ck;
+      } else {
+        o[base + k + 1] += 0.5 * ck;
+        o[base + k] += ck;
+        o[base + k - 1] += 0.5 * ck;
+      }
+    }
+  }
+}
+
+// G v for G symmetric, stored as its upper triangle (seven independent
+// FMA chains).
+__device__ __forceinline__ void gmul(const double (&G)[NG], const double (&v)[NB],
+                                     double (&o)[NB]) {
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    double t = G[gi(a, 0)] * v[0];
+#pragma unroll
+    for (int b = 1; b < NB; ++b) t = __builtin_fma(G[gi(a, b)], v[b], t);
+    o[a] = t;
+  }
+}
+
+__device__ __forceinline__ double dotv(const double (&x)[NB], const double (&y)[NB]) {
+  double t = x[0] * y[0];
+#pragma unroll
+  for (int a = 1; a < NB; ++a) t = __builtin_fma(x[a], y[a], t);
+  return t;
+}
+
+// a / b from the hardware reciprocal and two Newton steps (within an ulp
+// or so; the iteration's scalars are a chain of these divisions).
+__device__ __forceinline__ double qdiv(double a, double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  y = __builtin_fma(y, __builtin_fma(-b, y, 1.0), y);
+  y = __builtin_fma(y, __builtin_fma(-b, y, 1.0), y);
+  return a * y;
+}
+
+// sum_a w_a c_a in FP64 over the 7 basis values of one row.
+__device__ __forceinline__ double combine(const float4& a0, const float4& a1,
+                                          const double (&c)[NB]) {
+  double s = (double)a0.x * c[0];
+  s = __builtin_fma((double)a0.y, c[1], s);
+  s = __builtin_fma((double)a0.z, c[2], s);
+  s = __builtin_fma((double)a0.w, c[3], s);
+  s = __builtin_fma((double)a1.x, c[4], s);
+  s = __builtin_fma((double)a1.y, c[5], s);
+  s = __builtin_fma((double)a1.z, c[6], s);
+  return s;
+}
+
+// Writes the block's partial sums: slot v at part_out[v * grid + lb], from
+// thread 16 v (which holds it).
+__device__ __forceinline__ void store_slot(const SsArgs& A, int lb, double v) {
+  if ((threadIdx.x & 15) == 0 && (threadIdx.x >> 4) < NGP)
+    A.part_out[(size_t)(threadIdx.x >> 4) * A.grid + lb] = v;
+}
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// Sum over the 16 lanes of each DPP row, every lane of the row receiving it
+// (neighbours, pairs, half-row and row mirrors; each step adds two equal
+// partial sums, in either order).
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  return v;
+}
+
+// The block's partial Gram sums G_ab = sum over its rows of d w_a w_b, on
+// the FP64 matrix cores: each wave stages its 64 rows' values (and d) in LDS
+// and adds W' (D W) over them with 16 products of 16 x 4 by 4 x 16 (lane l
+// supplies element (row 4 m + l / 16, value l % 16); values 7..15 are 0;
+// the products of FP32 values and the small half-integer d are exact in
+// FP64); the waves' sums are then added in wave order. Returns value v's
+// total in thread 16 v (v < NG), 0 elsewhere. wst: BS x 8 floats; wg: 8 x NGP.
+__device__ __forceinline__ double block_gram(const float (&w)[NB], float dd, float* wst,
+                                             double* wg) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  float4* st = (float4*)(wst + 8 * t);
+  st[0] = make_float4(w[0], w[1], w[2], w[3]);
+  st[1] = make_float4(w[4], w[5], w[6], dd);
+  __builtin_amdgcn_wave_barrier();  // each wave reads only its own rows
+  const int col = lane & 15, kq = lane >> 4;
+  // all operands first (unconditional reads, masked after), then the products
+  float xv[16], dv[16];
+  const int cc = col < NB ? col : 0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const float* row = wst + 8 * (64 * wave + 4 * m + kq);
+    xv[m] = row[cc];
+    dv[m] = row[7];
+  }
+  d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const double a = col < NB ? (double)xv[m] : 0.0;
+    const double b = (double)dv[m] * a;
+    if (m & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc1, 0, 0, 0);
+    else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc0, 0, 0, 0);
+  }
+  // lane l holds D[4 v + l / 16][l % 16] in element v
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int i = 4 * v + kq, j = col;
+    if (i <= j && j < NB) wg[wave * NGP + gi(i, j)] = acc0[v] + acc1[v];
+  }
+  __syncthreads();
+  const int v = t >> 4;
+  double s = 0.0;
+  if ((t & 15) == 0 && v < NG) {
+    s = wg[v];
+#pragma unroll
+    for (int q = 1; q < BS / 64; ++q) s += wg[q * NGP + v];
+  }
+  return s;
+}
+
+// The launch's Gram matrix of the previous basis: the totals of the
+// previous launch's partial sums, summed by every block in a fixed order
+// (value v by the 16 lanes of one DPP row, partials j, j + 16, ... each, in
+// chunks of 16 loads issued together), or read as totals summed by a
+// separate launch (large systems). gram_issue starts the first chunk's
+// loads, so that other loads can follow before the sum waits for them.
+struct GramLoads {
+  double a[16];
+};
+
+template <bool LARGE>
+__device__ __forceinline__ void gram_issue(const SsArgs& A, GramLoads& L) {
+  if constexpr (!LARGE) {
+    const int v = threadIdx.x >> 4, j = threadIdx.x & 15;
+    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.grid;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int q = j + 16 * k;
+      L.a[k] = pv[q < A.grid ? q : 0];
+    }
+  }
+}
+
+template <bool LARGE>
+__device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L, double (&G)[NG],
+                                            double* red) {
+  if constexpr (LARGE) {
+#pragma unroll
+    for (int v = 0; v < NG; ++v) G[v] = A.part_in[v];
+  } else {
+    const int v = threadIdx.x >> 4, j = threadIdx.x & 15;
+    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.grid;
+    double h[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) h[k] = (j + 16 * k < A.grid) ? L.a[k] : 0.0;
+#pragma unroll
+    for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+      for (int k = 0; k < w; ++k) h[k] += h[k + w];  // pairwise, fixed order
+    double acc = h[0];
+    for (int c0 = 256; c0 < A.grid; c0 += 256) {
+      double a[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int q = c0 + j + 16 * k;
+        a[k] = pv[q < A.grid ? q : 0];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += (c0 + j + 16 * k < A.grid) ? a[k] : 0.0;
+    }
+    if (v >= NG) acc = 0.0;
+    acc += dpp_move<0xB1>(acc);
+    acc += dpp_move<0x4E>(acc);
+    acc += dpp_move<0x141>(acc);
+    acc += dpp_move<0x140>(acc);
+    if (j == 0 && v < NG) red[v] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NG; ++q) G[q] = red[q];
+  }
+}
+
+// A thread's first two region rows (l = t and l = t + BS), loaded before the
+// Gram reduction: row, basis record, local matrix row. Most regions have at
+// most 2 BS rows; later rows are loaded where they are used.
+struct Pre {
+  int i[2];        // rows (new numbering), 0 past the region
+  float4 a[2], b[2];
+  uint4 m[2];      // local matrix rows (zeros past the inner rows)
+};
+
+// Rows and local matrix rows (loads that need only the block table). The
+// loads are unconditional, at clamped positions that stay inside the lists
+// (an empty block points at their start); entries past the region or past
+// the inner rows are never used.
+__device__ __forceinline__ void prefetch_rows(const SsArgs& A, const BlockPlan& B, Pre& R) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int l = t + k * BS;
+    R.i[k] = A.region[B.reg_off + max(0, min(l, B.nreg - 1))];
+    R.m[k] = A.lmat[B.lmat_off + max(0, min(l, B.ninner - 1))];
+  }
+}
+
+// The rows' basis records (loads that need the rows; every row is valid).
+__device__ __forceinline__ void prefetch_recs(const SsArgs& A, Pre& R) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    R.a[k] = A.Win[2 * (size_t)R.i[k]];
+    R.b[k] = A.Win[2 * (size_t)R.i[k] + 1];
+  }
+}
+
+// Region row l = t + k BS: its row, record and local matrix row.
+__device__ __forceinline__ int row_at(const SsArgs& A, const BlockPlan& B, int base, const Pre& R,
+                                      int l, int k) {
+  return k < 2 ? R.i[k] : region_row(A, B, base, l);
+}
+__device__ __forceinline__ void rec_at(const SsArgs& A, const Pre& R, int i, int k, float4& a,
+                                       float4& b) {
+  if (k < 2) {
+    a = R.a[k];
+    b = R.b[k];
+  } else {
+    a = A.Win[2 * (size_t)i];
+    b = A.Win[2 * (size_t)i + 1];
+  }
+}
+__device__ __forceinline__ uint4 lm_at(const SsArgs& A, const BlockPlan& B, const Pre& R, int l,
+                                       int k) {
+  return k < 2 ? R.m[k] : A.lmat[B.lmat_off + l];
+}
+
+// The next basis from level 0 (pz0 = (p, z) on the whole region, ld =
+// D^-1), in LDS: round k computes level k on the rows within S - k hops.
+// Returns the own row's seven values (thread t: row t, zeros past nown).
+__device__ __forceinline__ void build_basis(const SsArgs& A, const BlockPlan& B, const Pre& R,
+                                            float2* pz0, float2* pz1, const float* ld,
+                                            float (&w)[NB]) {
+  const int t = threadIdx.x;
+  const bool own = t < B.nown;
+  float2 l0 = make_float2(0.f, 0.f), l1 = l0, l2 = l0;
+  float p3 = 0.0f;
+  __syncthreads();
+  // level 1: rows within S - 1 hops
+  for (int l = t, k = 0; l < B.ninner; l += BS, ++k) {
+    const uint4 m = lm_at(A, B, R, l, k);
+    const float dv = ld[l];
+    const float2 acc = lm_apply(m, pz0);
+    pz1[l] = make_float2(dv * acc.x, dv * acc.y);
+  }
+  __syncthreads();
+  if (own) {
+    l0 = pz0[t];
+    l1 = pz1[t];
+  }
+  // level 2 over level 0 (each row reads its own level 0 before writing it;
+  // the neighbours' values come from level 1)
+  for (int l = t, k = 0; l < B.n1; l += BS, ++k) {
+    const uint4 m = lm_at(A, B, R, l, k);
+    const float dv2 = 2.0f * ld[l];
+    const float2 acc = lm_apply(m, pz1);
+    const float2 old = pz0[l];
+    pz0[l] = make_float2(__builtin_fmaf(dv2, acc.x, -old.x), __builtin_fmaf(dv2, acc.y, -old.y));
+  }
+  __syncthreads();
+  // level 3 of p on the own rows
+  if (own) {
+    l2 = pz0[t];
+    p3 = __builtin_fmaf(2.0f * ld[t], lm_apply(R.m[0], pz0).x, -l1.x);
+  }
+  w[0] = l0.x;
+  w[1] = l1.x;
+  w[2] = l2.x;
+  w[3] = p3;
+  w[kZ0] = l0.y;
+  w[kZ0 + 1] = l1.y;
+  w[kZ0 + 2] = l2.y;
+}
+
+// Stores the own row's new basis and the block's partial Gram sums.
+__device__ __forceinline__ void finish_basis(const SsArgs& A, const BlockPlan& B, int lb, int base,
+                                             const float (&w)[NB], float dinv, float dd,
+                                             float* wst, double* wred) {
+  const int t = threadIdx.x;
+  if (t < B.nown) {
+    A.Wout[2 * (size_t)(base + t)] = make_float4(w[0], w[1], w[2], w[3]);
+    A.Wout[2 * (size_t)(base + t) + 1] = make_float4(w[4], w[5], w[6], dinv);
+  }
+  store_slot(A, lb, block_gram(w, t < B.nown ? dd : 0.0f, wst, wred));
+}
+
+template <bool LARGE>
+__device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dyn, double* red,
+                                        double* wred, double* coef, float* wst) {
+  const int t = threadIdx.x;
+  const Rec Rin = *A.rec_in;
+  const Params P = *A.prm;
+  const BlockPlan B = A.blocks[lb];
+  const int base = lb * BS;
+  const bool own = t < B.nown;
+  const int ro = own ? base + t : 0;
+  // loads that depend neither on the phase nor on the Gram matrix: the first
+  // region rows' records, the own row's correction and diagonal (unconditional
+  // at row 0 past the own rows; those values are never used)
+  Pre R;
+  prefetch_rows(A, B, R);
+  GramLoads L;
+  gram_issue<LARGE>(A, L);
+  prefetch_recs(A, R);
+  const float xo = A.x[ro];
+  const float dd = A.d[ro];
+  double G[NG];
+  gram_finish<LARGE>(A, L, G, red);
+  const int phase = A.force ? (int)kIter : Rin.phase;
+  const bool writer = lb == 0 && t == 0;
+  const int RM = A.blocks[0].pad0;  // region rows the LDS is laid out for
+  float2* pz0 = (float2*)dyn;
+  float2* pz1 = (float2*)(dyn + 2 * RM);
+  float* ld = dyn + 4 * RM;
+  const float dinv_own = R.b[0].w;
+
+  if (phase >= kDoneOk) {  // a launch queued after the end: carry the record
+    if (writer)
+      put_rec(A.rec_out, nullptr, Rin.epoch, Rin.seq, Rin.phase, Rin.iter, Rin.total, Rin.ninner,
+              Rin.stagnant, Rin.xp, Rin.gamma_prev, Rin.alpha_prev, Rin.rho_ref, Rin.tol2,
+              Rin.rnorm, Rin.bnorm);
+    return;
+  }
+
+  if (phase == kInit) {
+    // G[0] = ||r64||^2 from the start or refinement launch; the start launch
+    // also sends G[1] = ||b||^2
+    double rnorm = sqrt(G[0]);
+    const double bnorm = Rin.ninner == 0 ? sqrt(G[1]) : Rin.bnorm;
+    const double tol = P.atol > 0.0 ? fmin(P.rtol * bnorm, P.atol) : P.rtol * bnorm;
+    int stagnant = Rin.stagnant;
+    int next = 0;
+    bool zero = false;
+    if (!isfinite(rnorm)) next = kDoneBad;
+    else if (rnorm <= tol) next = kDoneOk;
+    else if (bnorm == 0.0 && Rin.ninner == 0) {  // b = 0 with a non-zero start: x = 0
+      zero = true;
+      rnorm = 0.0;
+      next = kDoneOk;
+    }
+    else if ((double)Rin.ninner >= P.max_refine) next = kDoneNoConv;
+    else if (Rin.ninner > 0) {
+      stagnant = rnorm > 0.5 * Rin.rnorm ? stagnant + 1 : 0;
+      if (stagnant >= 3) next = kDoneNoConv;
+    }
+    if (next) {
+      // the result, in the natural order of the free rows
+      if (own) A.xout[A.perm[ro]] = zero ? 0.0 : (Rin.xp ? A.x64b : A.x64a)[ro];
+      if (writer)
+        put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, next, Rin.iter, Rin.total,
+                Rin.ninner, stagnant, 0, Rin.gamma_prev, Rin.alpha_prev, Rin.rho_ref, Rin.tol2,
+                rnorm, bnorm);
+      return;
+    }
+    const double want = 0.5 * tol / rnorm;
+    const double itol = fmax(P.inner_rtol, want);
+    const double scale = 1.0 / rnorm;
+    for (int l = t, k = 0; l < B.nreg; l += BS, ++k) {
+      const int i = row_at(A, B, base, R, l, k);
+      float4 a, b;
+      rec_at(A, R, i, k, a, b);
+      const float r = (float)(A.r64[i] * scale);
+      const float z = b.w * r;
+      pz0[l] = make_float2(z, z);
+      ld[l] = b.w;
+    }
+    if (own) A.x[ro] = 0.0f;
+    float w[NB];
+    build_basis(A, B, R, pz0, pz1, ld, w);
+    finish_basis(A, B, lb, base, w, dinv_own, dd, wst, wred);
+    if (writer)
+      put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kIter, 0, Rin.total, Rin.ninner + 1,
+              stagnant, Rin.xp, 0.0, 0.0, 0.0, itol * itol, rnorm, bnorm);
+    return;
+  }
+
+  // ---- kIter: S iterations on the coefficients -----------------------------
+  // One wave runs them (every other wave would repeat the same FP64 chain on
+  // the same SIMDs) and hands the coefficients over through LDS.
+  int iter = Rin.iter;
+  double rz = iter == 0 ? G[gi(kZ0, kZ0)] : Rin.gamma_prev;
+  const double rho_ref = iter == 0 ? rz : Rin.rho_ref;
+  double pc[NB], zc[NB], xc[NB];
+  bool stop = false;
+  if (t < 64) {
+    // G z is kept up to date (z -= alpha T p gives G z -= alpha G T p, which
+    // the step has formed anyway), so each step needs one product with G.
+    const double* Gsrc = LARGE ? A.part_in : red;  // the reduced Gram matrix
+    double Gw[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) Gw[q] = Gsrc[q];
+    double gz[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      pc[a] = a == 0 ? 1.0 : 0.0;
+      zc[a] = a == kZ0 ? 1.0 : 0.0;
+      xc[a] = 0.0;
+      gz[a] = Gw[gi(a, kZ0)];
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      if (!stop) {
+        double tp[NB], gtp[NB];
+        tcoef(pc, tp);
+        gmul(Gw, tp, gtp);
+        const double alpha = qdiv(rz, dotv(pc, gtp));
+        if (!A.force && (!(alpha > 0.0) || !isfinite(alpha))) {
+          stop = true;  // breakdown: refine with what has been reached
+        } else {
+#pragma unroll
+          for (int a = 0; a < NB; ++a) {
+            xc[a] = __builtin_fma(alpha, pc[a], xc[a]);
+            zc[a] = __builtin_fma(-alpha, tp[a], zc[a]);
+            gz[a] = __builtin_fma(-alpha, gtp[a], gz[a]);
+          }
+          ++iter;
+          const double rzn = dotv(zc, gz);
+          if (!A.force && (!(rzn > Rin.tol2 * rho_ref) || (double)iter >= P.max_inner)) {
+            stop = true;
+          } else {
+            const double beta = qdiv(rzn, rz);
+            rz = rzn;
+#pragma unroll
+            for (int a = 0; a < NB; ++a) pc[a] = __builtin_fma(beta, pc[a], zc[a]);
+          }
+        }
+      }
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        coef[a] = pc[a];
+        coef[NB + a] = zc[a];
+        coef[2 * NB + a] = xc[a];
+      }
+      coef[3 * NB] = rz;
+      coef[3 * NB + 1] = (double)iter;
+      coef[3 * NB + 2] = stop ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    pc[a] = coef[a];
+    zc[a] = coef[NB + a];
+    xc[a] = coef[2 * NB + a];
+  }
+  rz = coef[3 * NB];
+  iter = (int)coef[3 * NB + 1];
+  stop = coef[3 * NB + 2] != 0.0;
+
+  if (stop) {
+    // Inner solve over: x64 += rnorm * (x + W xc) on the rows within one hop,
+    // then r64 = b - K x64 on the own rows (FP64), and ||r64||^2.
+    const double* xo64 = Rin.xp ? A.x64b : A.x64a;
+    double* xn64 = Rin.xp ? A.x64a : A.x64b;
+    double* lx = (double*)dyn;
+    const double sc = Rin.rnorm;
+    for (int l = t, k = 0; l < B.n1; l += BS, ++k) {
+      const int i = row_at(A, B, base, R, l, k);
+      float4 a, b;
+      rec_at(A, R, i, k, a, b);
+      const float xv = k == 0 ? (own ? xo : A.x[i]) : A.x[i];
+      lx[l] = __builtin_fma(sc, (double)xv + combine(a, b, xc), xo64[i]);
+    }
+    __syncthreads();
+    double v0 = 0.0;
+    if (own) {
+      const double xi = lx[t];
+      double acc = (double)dd * xi;
+#pragma unroll
+      for (int k = 0; k < kPlanSlots; ++k) {
+        const uint32_t e = lm_entry(R.m[0], k);
+        acc = __builtin_fma((double)lm_weight(e), lx[e & (kPlanLocalMax - 1)], acc);
+      }
+      const double ri = A.b[ro] - acc;
+      xn64[ro] = xi;
+      A.r64[ro] = ri;
+      v0 = ri * ri;
+    }
+    double v[1] = {v0};
+    block_sum_once<1, BS / 64>(v, wred);
+    store_slot(A, lb, threadIdx.x == 0 ? v[0] : 0.0);  // slot 0; other slots 0
+    if (writer)
+      put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kInit, iter, Rin.total + iter,
+              Rin.ninner, Rin.stagnant, Rin.xp ^ 1, rz, 0.0, rho_ref, Rin.tol2, Rin.rnorm,
+              Rin.bnorm);
+    return;
+  }
+
+  // p = W pc, z = W zc on the region; x += W xc on the own rows
+  for (int l = t, k = 0; l < B.nreg; l += BS, ++k) {
+    float4 a, b;
+    rec_at(A, R, k < 2 ? 0 : region_row(A, B, base, l), k, a, b);
+    pz0[l] = make_float2((float)combine(a, b, pc), (float)combine(a, b, zc));
+    ld[l] = b.w;
+  }
+  if (own) A.x[ro] = (float)((double)xo + combine(R.a[0], R.b[0], xc));
+  float w[NB];
+  build_basis(A, B, R, pz0, pz1, ld, w);
+  finish_basis(A, B, lb, base, w, dinv_own, dd, wst, wred);
+  if (writer)
+    put_rec(A.rec_out, A.mirror, Rin.epoch, Rin.seq + 1, kIter, iter, Rin.total, Rin.ninner,
+            Rin.stagnant, Rin.xp, rz, 0.0, rho_ref, Rin.tol2, Rin.rnorm, Rin.bnorm);
+}
+
+template <bool LARGE>
+__global__ __launch_bounds__(BS) void k_ss_step(SsArgs A) {
+  extern __shared__ float dyn[];
+  __shared__ double red[NGP];
+  __shared__ double wred[(BS / 64) * NGP];  // per-wave Gram sums
+  __shared__ double coef[3 * NB + 3];       // the iteration's coefficients
+  __shared__ float4 wst[BS * 2];            // rows' basis values for the matrix cores
+  ss_body<LARGE>(A, logical_block(), dyn, red, wred, coef, (float*)wst);
+}
+
+// Several right-hand sides with one matrix (the channels of a colour image):
+// the k-th block of XCD x takes solve k % nrhs and row block
+// x (G / 8) + k / nrhs, so the solves' blocks for the same rows run side by
+// side on one XCD and share the rows' plan and matrix in its L2. Each block
+// runs the single-solve body on its solve's arguments and the row block the
+// single-solve launch would give it: every solve gets the bits of its own
+// single solve.
+struct SsMultiArgs {
+  int nrhs;
+  SsArgs a[kMaxRhs];
+};
+
+template <bool LARGE>
+__global__ __launch_bounds__(BS) void k_ss_multi(SsMultiArgs M) {
+  extern __shared__ float dyn[];
+  __shared__ double red[NGP];
+  __shared__ double wred[(BS / 64) * NGP];
+  __shared__ double coef[3 * NB + 3];
+  __shared__ float4 wst[BS * 2];
+  const int nr = M.nrhs;
+  const int per = (int)(gridDim.x / nr) >> 3;
+  const int k = blockIdx.x >> 3;
+  ss_body<LARGE>(M.a[k % nr], (blockIdx.x & 7) * per + k / nr, dyn, red, wred, coef,
+                 (float*)wst);
+}
+
+// Several meshes' solves in one launch (the server): the grid is the
+// concatenation of every slot's own grid (each a multiple of 8); a block
+// finds its slot from the start offsets and runs the single-mesh body with
+// its slot-local block index, so a solve gives the same bits alone or in any
+// batch. A slot whose solve has ended only carries its record forward.
+constexpr int kSsArgSlots = 20;
+
+struct SsBatchArgs {
+  int n;
+  int32_t start[kSsArgSlots + 1];
+  SsArgs a[kSsArgSlots];
+};
+static_assert(sizeof(SsBatchArgs) <= 4096, "kernel arguments of a batched launch");
+
+template <bool LARGE>
+__global__ __launch_bounds__(BS) void k_ss_batch(SsBatchArgs Bt) {
+  extern __shared__ float dyn[];
+  __shared__ double red[NGP];
+  __shared__ double wred[(BS / 64) * NGP];
+  __shared__ double coef[3 * NB + 3];
+  __shared__ float4 wst[BS * 2];
+  const int lb = logical_block();
+  int j = 0;  // slot of this block (uniform)
+#pragma unroll
+  for (int k = 1; k < kSsArgSlots; ++k) j += (k < Bt.n && Bt.start[k] <= lb) ? 1 : 0;
+  const SsArgs& A = Bt.a[j];
+  const int lblk = lb - Bt.start[j];
+  if (A.rec_in->phase >= kDoneOk) {
+    if (lblk == 0 && threadIdx.x == 0) *A.rec_out = *A.rec_in;
+    return;
+  }
+  ss_body<LARGE>(A, lblk, dyn, red, wred, coef, (float*)wst);
+}
+
+// Start of a solve: b and x0 in the launch's numbering, x64 = x0 (0 when
+// x0 is NULL), r64 = b - K_FF x0 in FP64, ||r64||^2 and ||b||^2, the first
+// record. b_nat and x0 are in the natural order of the free rows.
+__global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* prm_out,
+                                                 const double* __restrict__ b_nat,
+                                                 const double* __restrict__ x0) {
+  extern __shared__ float dyn[];
+  __shared__ double wred[(BS / 64) * 2];
+  const int t = threadIdx.x, lb = logical_block();
+  const BlockPlan B = A.blocks[lb];
+  const int base = lb * BS;
+  const bool own = t < B.nown;
+  const int ro = own ? base + t : 0;
+  double* lx = (double*)dyn;
+  if (x0) {
+    for (int l = t; l < B.n1; l += BS) lx[l] = x0[A.perm[region_row(A, B, base, l)]];
+    __syncthreads();
+  }
+  double v[2] = {0.0, 0.0};
+  if (own) {
+    const double bi = b_nat[A.perm[ro]];
+    double ri = bi, xi = 0.0;
+    if (x0) {
+      const uint4 m = A.lmat[B.lmat_off + t];
+      xi = lx[t];
+      double acc = (double)A.d[ro] * xi;
+#pragma unroll
+      for (int k = 0; k < kPlanSlots; ++k) {
+        const uint32_t e = lm_entry(m, k);
+        acc = __builtin_fma((double)lm_weight(e), lx[e & (kPlanLocalMax - 1)], acc);
+      }
+      ri = bi - acc;
+    }
+    A.b[ro] = bi;
+    A.x64a[ro] = xi;
+    A.r64[ro] = ri;
+    v[0] = ri * ri;
+    v[1] = bi * bi;
+  }
+  block_sum_once<2, BS / 64>(v, wred);
+  store_slot(A, lb, threadIdx.x == 0 ? v[0] : threadIdx.x == 16 ? v[1] : 0.0);
+  if (lb == 0 && t == 0) {
+    prm_out->rtol = prm.rtol;
+    prm_out->inner_rtol = prm.inner_rtol;
+    prm_out->max_inner = prm.max_inner;
+    prm_out->max_refine = prm.max_refine;
+    prm_out->mixed = prm.mixed;
+    prm_out->epoch = prm.epoch;
+    prm_out->atol = prm.atol;
+    put_rec(A.rec_out, nullptr, (int)prm.epoch, 0, kInit, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0,
+            0.0);
+  }
+}
+
+// Large systems: the Gram partials summed by a separate launch, one block
+// per value, each thread over a strided set in order, then the block.
+__global__ __launch_bounds__(kBlock) void k_ss_reduce(const double* __restrict__ part, int grid,
+                                                      double* __restrict__ out) {
+  __shared__ double lds[4];
+  const int v = blockIdx.x;
+  double s[1] = {0.0};
+  for (int q = threadIdx.x; q < grid; q += kBlock) s[0] += part[(size_t)v * grid + q];
+  block_sum<1>(s, lds);
+  if (threadIdx.x == 0) out[v] = s[0];
+}
+
+// The same for several systems: block b sums value b % NG of system b / NG.
+struct SsReduceArgs {
+  int n;
+  int32_t grid[kSsArgSlots];
+  const double* part[kSsArgSlots];
+  double* out[kSsArgSlots];
+};
+
+__global__ __launch_bounds__(kBlock) void k_ss_reduce_many(SsReduceArgs R) {
+  __shared__ double lds[4];
+  const int q = blockIdx.x / NG, v = blockIdx.x % NG;
+  const int grid = R.grid[q];
+  const double* part = R.part[q];
+  double s[1] = {0.0};
+  for (int i = threadIdx.x; i < grid; i += kBlock) s[0] += part[(size_t)v * grid + i];
+  block_sum<1>(s, lds);
+  if (threadIdx.x == 0) R.out[q][v] = s[0];
+}
+
+// Values of the plan's rows after an assembly: the FP32 diagonal and D^-1
+// (slot 7 of both basis buffers), in the plan's numbering.
+__global__ __launch_bounds__(kBlock) void k_ss_values(int n, const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ diag64,
+                                                      const float* __restrict__ dinv32,
+                                                      float* __restrict__ d, float* __restrict__ W0,
+                                                      float* __restrict__ W1) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int r = perm[i];
+  if (d) d[i] = (float)diag64[r];
+  W0[8 * (size_t)i + 7] = dinv32[r];
+  W1[8 * (size_t)i + 7] = dinv32[r];
+}
+
+// ---------------------------------------------------------------- host ----
+SsArgs ss_args(fi_mesh* M, int par, int force) {
+  SsState& Z = *M->ss;
+  SsArgs A;
+  A.n = (int)M->n;
+  A.grid = Z.grid;
+  A.perm = Z.perm;
+  A.blocks = (const BlockPlan*)Z.blocks;
+  A.region = Z.region;
+  A.lmat = (const uint4*)Z.lmat;
+  A.Win = (const float4*)Z.W[par];
+  A.Wout = (float4*)Z.W[par ^ 1];
+  A.x = Z.x;
+  A.d = Z.d;
+  A.b = Z.b;
+  A.r64 = Z.r64;
+  A.x64a = Z.x64[0];
+  A.x64b = Z.x64[1];
+  A.xout = M->d_x64buf[0];
+  A.part_in = Z.large ? Z.red : Z.part + (size_t)par * NGP * Z.grid;
+  A.part_out = Z.part + (size_t)(par ^ 1) * NGP * Z.grid;
+  A.rec_in = (const Rec*)M->d_rec + par;
+  A.rec_out = (Rec*)M->d_rec + (par ^ 1);
+  A.prm = (const Params*)M->d_prm;
+  A.mirror = (Mirror*)M->d_mirror;
+  A.force = force;
+  return A;
+}
+
+size_t ss_lds_bytes(const SsState& Z) { return (size_t)5 * Z.max_region * sizeof(float); }
+
+int ss_reduce_after(fi_mesh* M, int par) {
+  SsState& Z = *M->ss;
+  hipLaunchKernelGGL(k_ss_reduce, dim3(NG), dim3(kBlock), 0, M->ctx->stream,
+                     (const double*)(Z.part + (size_t)(par ^ 1) * NGP * Z.grid), Z.grid, Z.red);
+  FI_HIP_TRY(hipGetLastError());
+  return FI_OK;
+}
+
+int ss_launch_step(fi_mesh* M, int par, int force) {
+  SsState& Z = *M->ss;
+  SsArgs A = ss_args(M, par, force);
+  void* args[1] = {&A};
+  void* fn = Z.large ? (void*)k_ss_step<true> : (void*)k_ss_step<false>;
+  FI_HIP_TRY(hipLaunchKernel(fn, dim3(Z.grid), dim3(BS), args, ss_lds_bytes(Z), M->ctx->stream));
+  return Z.large ? ss_reduce_after(M, par) : FI_OK;
+}
+
+int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0) {
+  SsState& Z = *M->ss;
+  SsArgs A = ss_args(M, 1, 0);  // writes record and partials of slot 0
+  Params prm{};
+  prm.rtol = o->rtol;
+  prm.atol = o->atol;
+  prm.inner_rtol = o->inner_rtol;
+  prm.max_inner = o->max_inner;
+  prm.max_refine = o->max_refine;
+  prm.mixed = 1.0;
+  prm.epoch = epoch;
+  Params* pout = (Params*)M->d_prm;
+  const double* bnat = M->d_b64;
+  void* args[5] = {&A, &prm, &pout, &bnat, &x0};
+  FI_HIP_TRY(hipLaunchKernel((void*)k_ss_start, dim3(Z.grid), dim3(BS), args, ss_lds_bytes(Z),
+                             M->ctx->stream));
+  return Z.large ? ss_reduce_after(M, 1) : FI_OK;
+}
+
+int slot_of(const double* x0) { return 0 + (x0 ? 1 : 0); }  // FP32 cold / warm prediction slots
+
+}  // namespace
+
+// Builds the plan after the first assembly of a quadtree mesh; later calls
+// refresh the values that come from the matrix.
+int ss_setup(fi_mesh* M) {
+  hipStream_t st = M->ctx->stream;
+  if (!M->ss) {
+    if (M->ell_w <= 0 || M->n <= 0 || M->is_channel) return FI_OK;
+    if (const char* env = std::getenv("FI_CG_SSTEP"))
+      if (std::atoi(env) == 0) return FI_OK;
+    const int64_t n = M->n;
+    std::vector<int32_t> ell((size_t)M->ell_w * M->n_pad);
+    FI_HIP_TRY(hipMemcpyAsync(ell.data(), M->d_ell, ell.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+    FI_HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int32_t> xy((size_t)2 * n);
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t v = M->host.free_vids[i];
+      xy[2 * i] = M->host.vxy[2 * (size_t)v];
+      xy[2 * i + 1] = M->host.vxy[2 * (size_t)v + 1];
+    }
+    const int threads = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    SsPlan plan;
+    if (!build_ss_plan(S, BS, n, xy.data(), ell.data(), M->n_pad, M->ell_w, threads, kMaxRegion,
+                       plan))
+      return FI_OK;  // keep the one-iteration launch
+    SsState* Z = new SsState();
+    Z->grid = plan.grid;
+    Z->max_region = plan.max_region;
+    Z->region_rows = (int64_t)plan.region.size();
+    Z->lmat_rows = (int64_t)plan.lmat.size() / kPlanSlots;
+    bool large = Z->grid > kSmallGrid;
+    if (const char* env = std::getenv("FI_CG_LARGE"))
+      if (std::atoi(env) == 1) large = true;
+    Z->large = large;
+    // the LDS layout size travels in the first block's spare field
+    plan.blocks[0].pad0 = plan.max_region;
+    M->ss = Z;
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    int rc = 0;
+    if ((rc = device_alloc(M, (void**)&Z->perm, nn * 4)) ||
+        (rc = device_alloc(M, &Z->blocks, plan.blocks.size() * sizeof(BlockPlan))) ||
+        (rc = device_alloc(M, (void**)&Z->region, std::max<size_t>(plan.region.size(), 1) * 4)) ||
+        (rc = device_alloc(M, &Z->lmat, std::max<size_t>(plan.lmat.size(), 8) * 2)) ||
+        (rc = device_alloc(M, (void**)&Z->W[0], nn * 32)) ||
+        (rc = device_alloc(M, (void**)&Z->W[1], nn * 32)) ||
+        (rc = device_alloc(M, (void**)&Z->x, nn * 4)) ||
+        (rc = device_alloc(M, (void**)&Z->d, nn * 4)) ||
+        (rc = device_alloc(M, (void**)&Z->b, nn * 8)) ||
+        (rc = device_alloc(M, (void**)&Z->r64, nn * 8)) ||
+        (rc = device_alloc(M, (void**)&Z->x64[0], nn * 8)) ||
+        (rc = device_alloc(M, (void**)&Z->x64[1], nn * 8)) ||
+        (rc = device_alloc(M, (void**)&Z->part, (size_t)2 * NGP * Z->grid * 8)) ||
+        (rc = device_alloc(M, (void**)&Z->red, NGP * 8)))
+      return rc;
+    FI_HIP_TRY(hipMemcpyAsync(Z->perm, plan.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+    FI_HIP_TRY(hipMemcpyAsync(Z->blocks, plan.blocks.data(), plan.blocks.size() * sizeof(BlockPlan),
+                              hipMemcpyHostToDevice, st));
+    if (!plan.region.empty())
+      FI_HIP_TRY(hipMemcpyAsync(Z->region, plan.region.data(), plan.region.size() * 4,
+                                hipMemcpyHostToDevice, st));
+    if (!plan.lmat.empty())
+      FI_HIP_TRY(hipMemcpyAsync(Z->lmat, plan.lmat.data(), plan.lmat.size() * 2,
+                                hipMemcpyHostToDevice, st));
+    // every basis slot starts finite (the first launch reads only D^-1)
+    FI_HIP_TRY(hipMemsetAsync(Z->W[0], 0, nn * 32, st));
+    FI_HIP_TRY(hipMemsetAsync(Z->W[1], 0, nn * 32, st));
+    // the host copies above come from vectors that end with this call
+    FI_HIP_TRY(hipStreamSynchronize(st));
+  }
+  SsState& Z = *M->ss;
+  hipLaunchKernelGGL(k_ss_values, dim3((unsigned)((M->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     st, (int)M->n, Z.perm, M->d_diag64, M->d_dinv32, Z.d, Z.W[0], Z.W[1]);
+  FI_HIP_TRY(hipGetLastError());
+  return FI_OK;
+}
+
+void ss_release(fi_mesh* M) {
+  delete M->ss;  // its device memory is in the mesh's allocations
+  M->ss = nullptr;
+}
+
+int ss_solve(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const double* x0) {
+  hipStream_t st = M->ctx->stream;
+  const int epoch = next_epoch(M);
+  int rc = ss_launch_start(M, o, epoch, x0);
+  if (rc) return rc;
+  const int slot = slot_of(x0);
+  Pacer pc = make_pacer(o->max_inner, o->max_refine, M->pred_launches[slot]);
+  for (;;) {
+    int drc = FI_OK;
+    int64_t nl = 0;
+    if (read_mirror(M, epoch, stats, &drc, &nl)) {
+      M->pred_launches[slot] = nl;
+      return drc;
+    }
+    if (const int nq = pc.next()) {
+      for (int q = 0; q < nq; ++q)
+        if ((rc = ss_launch_step(M, q & 1, 0))) return rc;
+      FI_HIP_TRY(hipEventRecord(M->chunk_ev[pc.launched % kChunkEvents], st));
+      pc.queued_chunk(nq);
+      continue;
+    }
+    if (pc.completed < pc.launched) {
+      const hipError_t q = hipEventQuery(M->chunk_ev[pc.completed % kChunkEvents]);
+      if (q == hipSuccess) {
+        ++pc.completed;
+        continue;
+      }
+      if (q != hipErrorNotReady)
+        return fail(FI_E_HIP, std::string("stream failed: ") + hipGetErrorString(q));
+    } else {
+      if (read_mirror(M, epoch, stats, &drc, nullptr)) return drc;
+      return fail(FI_E_HIP, "solver did not report termination");
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+namespace {
+
+void* multi_fn(bool large) { return large ? (void*)k_ss_multi<true> : (void*)k_ss_multi<false>; }
+void* batch_fn(bool large) { return large ? (void*)k_ss_batch<true> : (void*)k_ss_batch<false>; }
+
+// Launch arguments of a multi-RHS step for both parities.
+struct SsMultiLaunch {
+  SsMultiArgs a[2];
+  SsReduceArgs r[2];
+};
+
+void ss_multi_prepare(fi_mesh* const* ch, int nc, int force, SsMultiLaunch& L) {
+  for (int par = 0; par < 2; ++par) {
+    L.a[par] = SsMultiArgs{};
+    L.a[par].nrhs = nc;
+    L.r[par] = SsReduceArgs{};
+    L.r[par].n = nc;
+    for (int c = 0; c < nc; ++c) {
+      L.a[par].a[c] = ss_args(ch[c], par, force);
+      L.r[par].grid[c] = ch[c]->ss->grid;
+      L.r[par].part[c] = ch[c]->ss->part + (size_t)(par ^ 1) * NGP * ch[c]->ss->grid;
+      L.r[par].out[c] = ch[c]->ss->red;
+    }
+  }
+}
+
+int ss_multi_launch(fi_mesh* M0, SsMultiLaunch& L, int par) {
+  SsState& Z = *M0->ss;
+  void* args[1] = {&L.a[par]};
+  const unsigned grid = (unsigned)L.a[par].nrhs * (unsigned)Z.grid;
+  FI_HIP_TRY(hipLaunchKernel(multi_fn(Z.large), dim3(grid), dim3(BS), args, ss_lds_bytes(Z),
+                             M0->ctx->stream));
+  if (!Z.large) return FI_OK;
+  void* rargs[1] = {&L.r[par]};
+  FI_HIP_TRY(hipLaunchKernel((void*)k_ss_reduce_many, dim3(NG * L.r[par].n), dim3(kBlock), rargs, 0,
+                             M0->ctx->stream));
+  return FI_OK;
+}
+
+}  // namespace
+
+// The channels' solves advance together, one launch per step, paced like
+// ss_solve (events of channel 0), until every channel's mirror shows its end;
+// a channel whose solve has ended leaves the launches from the next chunk on.
+int ss_solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve_stats* stats,
+                   const double* const* x0) {
+  fi_mesh* M0 = ch[0];
+  hipStream_t st = M0->ctx->stream;
+  int epoch[kMaxRhs];
+  bool done[kMaxRhs] = {};
+  int rc = FI_OK, first_rc = FI_OK;
+  for (int c = 0; c < nc; ++c) {
+    epoch[c] = next_epoch(ch[c]);
+    if ((rc = ss_launch_start(ch[c], o, epoch[c], x0 ? x0[c] : nullptr))) return rc;
+  }
+  SsMultiLaunch L;
+  fi_mesh* run[kMaxRhs];
+  int nrun = nc;
+  for (int c = 0; c < nc; ++c) run[c] = ch[c];
+  ss_multi_prepare(run, nrun, 0, L);
+  int64_t pred = 0;
+  bool every = true;
+  for (int c = 0; c < nc; ++c) {
+    const int64_t p = ch[c]->pred_launches[slot_of(x0 ? x0[c] : nullptr)];
+    every = every && p > 0;
+    pred = std::max(pred, p);
+  }
+  if (!every) pred = 0;
+  Pacer pc = make_pacer(o->max_inner, o->max_refine, pred);
+  auto all_done = [&]() {
+    bool all = true;
+    for (int c = 0; c < nc; ++c) {
+      if (!done[c]) {
+        int drc = FI_OK;
+        int64_t nl = 0;
+        done[c] = read_mirror(ch[c], epoch[c], &stats[c], &drc, &nl) != 0;
+        if (done[c]) {
+          ch[c]->pred_launches[slot_of(x0 ? x0[c] : nullptr)] = nl;
+          if (drc && !first_rc) first_rc = drc;
+        }
+      }
+      all = all && done[c];
+    }
+    return all;
+  };
+  for (;;) {
+    if (all_done()) return first_rc;
+    int left = 0;
+    for (int c = 0; c < nc; ++c)
+      if (!done[c]) run[left++] = ch[c];
+    if (left < nrun) {
+      nrun = left;
+      ss_multi_prepare(run, nrun, 0, L);
+    }
+    if (const int nq = pc.next()) {
+      for (int q = 0; q < nq; ++q)
+        if ((rc = ss_multi_launch(M0, L, q & 1))) return rc;
+      FI_HIP_TRY(hipEventRecord(M0->chunk_ev[pc.launched % kChunkEvents], st));
+      pc.queued_chunk(nq);
+      continue;
+    }
+    if (pc.completed < pc.launched) {
+      const hipError_t q = hipEventQuery(M0->chunk_ev[pc.completed % kChunkEvents]);
+      if (q == hipSuccess) {
+        ++pc.completed;
+        continue;
+      }
+      if (q != hipErrorNotReady)
+        return fail(FI_E_HIP, std::string("stream failed: ") + hipGetErrorString(q));
+    } else {
+      if (all_done()) return first_rc;
+      return fail(FI_E_HIP, "solver did not report termination");
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// Times `reps` multi-RHS launches forced to iterate.
+int ss_time_multi(fi_mesh* const* ch, int nc, int reps, double* ms) {
+  fi_mesh* M0 = ch[0];
+  hipStream_t st = M0->ctx->stream;
+  fi_solve_opts o;
+  fi_solve_opts_default(&o);
+  int rc = FI_OK;
+  for (int c = 0; c < nc; ++c)
+    if ((rc = ss_launch_start(ch[c], &o, next_epoch(ch[c]), nullptr))) return rc;
+  SsMultiLaunch L;
+  ss_multi_prepare(ch, nc, 0, L);
+  if ((rc = ss_multi_launch(M0, L, 0))) return rc;  // the initial bases
+  ss_multi_prepare(ch, nc, 1, L);
+  hipEvent_t e0, e1;
+  FI_HIP_TRY(hipEventCreate(&e0));
+  FI_HIP_TRY(hipEventCreate(&e1));
+  for (int k = 0; k < 4; ++k)
+    if ((rc = ss_multi_launch(M0, L, (k + 1) & 1))) return rc;
+  FI_HIP_TRY(hipEventRecord(e0, st));
+  for (int k = 0; k < reps; ++k)
+    if ((rc = ss_multi_launch(M0, L, (k + 1) & 1))) return rc;
+  FI_HIP_TRY(hipEventRecord(e1, st));
+  FI_HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  FI_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  return FI_OK;
+}
+
+// `count` (even) launches over the meshes in `ms` (all with the S-iteration
+// plan), parity 0 first: one launch per kind (small or large systems) and
+// per kSsArgSlots meshes, and for large systems one reduction launch after.
+int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) {
+  struct Launch {
+    SsBatchArgs b[2];
+    SsReduceArgs r[2];
+    int64_t grid;
+    bool large;
+    size_t lds;
+  };
+  std::vector<fi_mesh*> order(ms);
+  std::stable_sort(order.begin(), order.end(),
+                   [](fi_mesh* a, fi_mesh* b) { return (int)a->ss->large < (int)b->ss->large; });
+  std::vector<Launch> L;
+  for (size_t j0 = 0; j0 < order.size();) {
+    Launch l{};
+    size_t j1 = j0;
+    while (j1 < order.size() && j1 - j0 < (size_t)kSsArgSlots &&
+           order[j1]->ss->large == order[j0]->ss->large)
+      ++j1;
+    l.large = order[j0]->ss->large;
+    int64_t total = 0;
+    for (int par = 0; par < 2; ++par) {
+      l.b[par].n = (int)(j1 - j0);
+      l.r[par].n = (int)(j1 - j0);
+    }
+    for (size_t j = j0; j < j1; ++j) {
+      fi_mesh* M = order[j];
+      const int q = (int)(j - j0);
+      for (int par = 0; par < 2; ++par) {
+        l.b[par].start[q] = (int32_t)total;
+        l.b[par].a[q] = ss_args(M, par, 0);
+        l.r[par].grid[q] = M->ss->grid;
+        l.r[par].part[q] = M->ss->part + (size_t)(par ^ 1) * NGP * M->ss->grid;
+        l.r[par].out[q] = M->ss->red;
+      }
+      total += M->ss->grid;
+      l.lds = std::max(l.lds, ss_lds_bytes(*M->ss));
+    }
+    if (total >= (int64_t)1 << 30) return fail(FI_E_INVALID, "batch grid too large");
+    for (int par = 0; par < 2; ++par) l.b[par].start[j1 - j0] = (int32_t)total;
+    l.grid = total;
+    L.push_back(l);
+    j0 = j1;
+  }
+  for (int k = 0; k < count; ++k) {
+    const int par = k & 1;
+    for (Launch& l : L) {
+      void* args[1] = {&l.b[par]};
+      FI_HIP_TRY(hipLaunchKernel(batch_fn(l.large), dim3((unsigned)l.grid), dim3(BS), args, l.lds,
+                                 st));
+    }
+    for (Launch& l : L) {
+      if (!l.large) continue;
+      void* rargs[1] = {&l.r[par]};
+      FI_HIP_TRY(hipLaunchKernel((void*)k_ss_reduce_many, dim3(NG * l.r[par].n), dim3(kBlock),
+                                 rargs, 0, st));
+    }
+  }
+  return FI_OK;
+}
+
+int ss_arm(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0) {
+  return ss_launch_start(M, o, epoch, x0);
+}
+
+// A channel view's own vectors, with the parent's plan and diagonal.
+int ss_channel_setup(fi_mesh* S, const fi_mesh* M) {
+  if (!M->ss) return FI_OK;
+  const SsState& P = *M->ss;
+  SsState* Z = new SsState();
+  *Z = P;  // plan, shape and the shared diagonal
+  S->ss = Z;
+  const size_t nn = (size_t)std::max<int64_t>(M->n, 1);
+  int rc = 0;
+  if ((rc = device_alloc(S, (void**)&Z->W[0], nn * 32)) ||
+      (rc = device_alloc(S, (void**)&Z->W[1], nn * 32)) ||
+      (rc = device_alloc(S, (void**)&Z->x, nn * 4)) ||
+      (rc = device_alloc(S, (void**)&Z->b, nn * 8)) ||
+      (rc = device_alloc(S, (void**)&Z->r64, nn * 8)) ||
+      (rc = device_alloc(S, (void**)&Z->x64[0], nn * 8)) ||
+      (rc = device_alloc(S, (void**)&Z->x64[1], nn * 8)) ||
+      (rc = device_alloc(S, (void**)&Z->part, (size_t)2 * NGP * Z->grid * 8)) ||
+      (rc = device_alloc(S, (void**)&Z->red, NGP * 8)))
+    return rc;
+  hipStream_t st = M->ctx->stream;
+  FI_HIP_TRY(hipMemsetAsync(Z->W[0], 0, nn * 32, st));
+  FI_HIP_TRY(hipMemsetAsync(Z->W[1], 0, nn * 32, st));
+  hipLaunchKernelGGL(k_ss_values, dim3((unsigned)((M->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     st, (int)M->n, Z->perm, M->d_diag64, M->d_dinv32, (float*)nullptr, Z->W[0],
+                     Z->W[1]);
+  FI_HIP_TRY(hipGetLastError());
+  return FI_OK;
+}
+
+// Device bytes the S-iteration state of a system of n rows may take (each
+// allocation rounded to 256 bytes): the plan (at most three region and
+// local matrix rows per free row), the two basis buffers, the FP32 and FP64
+// vectors, the partial sums.
+int64_t ss_footprint(int64_t n) {
+  const int64_t grid = ((n + BS - 1) / BS + 7) / 8 * 8;
+  int64_t total = 0;
+  auto add = [&](int64_t bytes) {
+    total += std::max<int64_t>(256, (std::max<int64_t>(bytes, 1) + 255) & ~(int64_t)255);
+  };
+  add(4 * n); add(32 * grid); add(4 * 3 * n); add(16 * 3 * n);
+  add(32 * n); add(32 * n); add(4 * n); add(4 * n);
+  add(8 * n); add(8 * n); add(8 * n); add(8 * n);
+  add(8 * 2 * NGP * grid); add(8 * NGP);
+  return total;
+}
+
+// Times `reps` launches forced to iterate, between two HIP events on the
+// context stream (large systems: with their reduction launch).
+int ss_time_kernel(fi_mesh* M, int reps, double* ms) {
+  hipStream_t st = M->ctx->stream;
+  fi_solve_opts o;
+  fi_solve_opts_default(&o);
+  int rc = ss_launch_start(M, &o, next_epoch(M), nullptr);
+  if (rc) return rc;
+  if ((rc = ss_launch_step(M, 0, 0))) return rc;  // the initial basis
+  hipEvent_t e0, e1;
+  FI_HIP_TRY(hipEventCreate(&e0));
+  FI_HIP_TRY(hipEventCreate(&e1));
+  for (int k = 0; k < 4; ++k)
+    if ((rc = ss_launch_step(M, (k + 1) & 1, 1))) return rc;
+  FI_HIP_TRY(hipEventRecord(e0, st));
+  for (int k = 0; k < reps; ++k)
+    if ((rc = ss_launch_step(M, (k + 1) & 1, 1))) return rc;
+  FI_HIP_TRY(hipEventRecord(e1, st));
+  FI_HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  FI_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  return FI_OK;
+}
+
+// Bytes one launch must move: per row, the previous basis read and the new
+// one written (7 floats and D^-1 each way: one 32-byte record), the
+// correction read and written, the diagonal; the matrix once (one 16-bit entry per stored
+// off-diagonal of K_FF). Halo rows read again by neighbouring blocks and the
+// padding of the local matrix rows are not counted.
+int64_t ss_kernel_bytes(const fi_mesh* M) {
+  const int64_t n = M->n;
+  return n * (4 * (NB + 1) * 2 + 8 + 4) + 2 * M->nnz_off;
+}
+
+}  // namespace fi

@@ -2,7 +2,7 @@
 // the plan back, for the Python checks in test_ss_plan.py.
 //   in:  int64 n, n_pad; int32 W, S, BS, threads; int32 xy[2n]; int32 ell[W * n_pad]
 //   out: int32 ok, grid, max_region; int32 perm[n]; int32 blocks[grid * 8];
-//        int64 nhalo; int32 halo[nhalo]; int64 nlmat; uint16 lmat[nlmat]
+//        int64 nregion; int32 region[nregion]; int64 nlmat; uint16 lmat[nlmat]
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -35,9 +35,9 @@ int main(int argc, char** argv) {
   if (built) {
     std::fwrite(plan.perm.data(), 4, plan.perm.size(), o);
     std::fwrite(plan.blocks.data(), sizeof(fi::BlockPlan), plan.blocks.size(), o);
-    const int64_t nh = (int64_t)plan.halo.size(), nl = (int64_t)plan.lmat.size();
+    const int64_t nh = (int64_t)plan.region.size(), nl = (int64_t)plan.lmat.size();
     std::fwrite(&nh, 8, 1, o);
-    std::fwrite(plan.halo.data(), 4, plan.halo.size(), o);
+    std::fwrite(plan.region.data(), 4, plan.region.size(), o);
     std::fwrite(&nl, 8, 1, o);
     std::fwrite(plan.lmat.data(), 2, plan.lmat.size(), o);
   }
