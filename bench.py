@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("solver.hip", "reduce.h", "internal.h")
+KERNEL_SOURCES = ("solver.hip", "sstep.hip", "ss_plan.h", "cg_common.h", "reduce.h", "internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -44,6 +44,30 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_2105_01586_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def cg_kernel_name(info, nrhs: int = 1) -> str:
+    """The FP32 CG step kernel a mesh uses, for the roofline label."""
+    mode = "summed by a second launch" if info["large_mode"] else "block re-reduce"
+    if info["cg_iters_per_launch"] > 1:
+        what = "k_ss_multi" if nrhs > 1 else "k_ss_step"
+        return (f"{what}<3 iterations per launch, {mode}, 512 rows + 3-hop halo per block"
+                + (f", {nrhs} right-hand sides" if nrhs > 1 else "") + ">")
+    what = "k_step_multi" if nrhs > 1 else "k_step"
+    return f"{what}<float, {mode}, 512>"
+
+
+def ss_model_bytes(info):
+    """Bytes the three-iteration launch itself moves, by its layout: per own
+    row the 32-byte basis record read and written, the correction read and
+    written, the diagonal; per region row (halo rows too) its row index and a
+    16-byte local matrix row (which only rows within two hops have: an upper
+    bound) and, for halo rows, the record read again. None for the
+    one-iteration kernel."""
+    if info["cg_iters_per_launch"] <= 1:
+        return None
+    n, reg = info["n"], info["cg_region_rows"]
+    return n * (32 + 32 + 8 + 4) + reg * (4 + 16) + (reg - n) * 32
 
 
 def recorded_traffic(workload: str):
@@ -326,8 +350,9 @@ def serving_main(args):
         "server_stats": {"closed_loop": st_closed, "at_rate": st1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("serving"),
-                     "kernel": f"k_step<float> on the {trace[big].side}^2 / "
+                     "kernel": f"{cg_kernel_name(M.info)} on the {trace[big].side}^2 / "
                                f"{trace[big].density:.1%} request",
+                     "iterations_per_launch": M.info["cg_iters_per_launch"],
                      "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
     }
     if not args.no_cpu_baseline:
@@ -447,7 +472,8 @@ def densify_main(args):
         "runs": runs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("densify"),
-                     "kernel": "k_step<float> on the final 1024^2 mesh",
+                     "kernel": f"{cg_kernel_name(M.info)} on the final 1024^2 mesh",
+                     "iterations_per_launch": M.info["cg_iters_per_launch"],
                      "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
     }
     if not args.no_cpu_baseline:
@@ -588,7 +614,8 @@ def colour_main(args):
                             "inpaint_speedup": inp_g / inp, "tonal_speedup": ton_g / ton},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("rgb512"),
-                     "kernel": "k_step_multi<float, 3 right-hand sides, block re-reduce, 512>",
+                     "kernel": cg_kernel_name(mesh.info, 3),
+                     "iterations_per_launch": mesh.info["cg_iters_per_launch"],
                      "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3,
                      "one_rhs_step_us": k1 * 1e3},
     }
@@ -654,6 +681,7 @@ def l1_main(args):
         if name == "quadtree":
             kms = M.time_cg_kernel(fi.PREC_FP32_IR, args.kernel_reps)
             kbytes = M.cg_kernel_bytes(fi.PREC_FP32_IR)
+            qinfo = M.info
         M.close()
     q = runs["quadtree"]
     achieved = kbytes / (kms * 1e-3) / 1e9
@@ -668,7 +696,8 @@ def l1_main(args):
         "runs": runs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("tonal512"),
-                     "kernel": "k_step<float> on the quadtree mesh",
+                     "kernel": f"{cg_kernel_name(qinfo)} on the quadtree mesh",
+                     "iterations_per_launch": qinfo["cg_iters_per_launch"],
                      "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
     }
     if not args.no_cpu_baseline:
@@ -834,10 +863,18 @@ def main():
         "fp64_gpu": fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.workload),
-                     "kernel": f"k_step<float, {mesh.info['large_mode'] and 'summed' or 'block re-reduce'}, "
-                               f"ELL width from the mesh, {mesh.info['cg_block_size']}>",
-                     "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
+                     "kernel": cg_kernel_name(mesh.info),
+                     "iterations_per_launch": mesh.info["cg_iters_per_launch"],
+                     "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3,
+                     "kernel_model_bytes_per_launch": ss_model_bytes(mesh.info)},
     }
+    mb = out["roofline"]["kernel_model_bytes_per_launch"]
+    if mb is not None:
+        # The three-iteration launch reads the matrix once for three
+        # iterations, so it moves fewer bytes than three one-iteration
+        # launches: its own byte count over the same time is its HBM use.
+        out["roofline"]["kernel_model_GBs"] = mb / (kms * 1e-3) / 1e9
+        out["roofline"]["kernel_model_frac"] = mb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS
     out["device_memory_gb"] = {"mesh_and_solver": mesh.info["device_bytes"] / 1e9,
                                "torch_peak": torch.cuda.max_memory_allocated() / 1e9,
                                "device_used_peak": peak_used[0] / 1e9}

@@ -437,15 +437,20 @@ int fi_densify_delaunay(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32
                         int rounds, const fi_solve_opts* opts, int32_t* mask_out,
                         double* mse_out, double* gpu_ms_out, int64_t* mask_size_out);
 
-/* Timing helper: runs `reps` iterations of the fused FP32 (precision =
- * FI_PREC_FP32_IR) or FP64 (FI_PREC_FP64) CG iteration kernel on this mesh's
- * current solver state between two HIP events recorded on the context
- * stream, and returns the mean milliseconds per launch. The solver state is
- * left undefined. */
+/* Timing helper: runs `reps` launches of the FP32 (precision =
+ * FI_PREC_FP32_IR) or FP64 (FI_PREC_FP64) CG step kernel on this mesh,
+ * forced to iterate, between two HIP events recorded on the context stream,
+ * and returns the mean milliseconds per launch. An FP32 launch advances
+ * fi_mesh_info.cg_iters_per_launch iterations. The solver state is left
+ * undefined. */
 int fi_time_cg_kernel(fi_mesh* mesh, int precision, int reps, double* ms_per_launch);
 
-/* Algorithmic bytes one launch of the fused CG iteration kernel must move
- * (matrix, row pointers, and each vector read or written once). */
+/* Algorithmic bytes of the CG iterations one step launch advances: per
+ * iteration the matrix (one 4-byte code per stored off-diagonal entry on the
+ * quadtree mesh; column, value and row pointers otherwise) and each vector
+ * of one-pass Jacobi PCG read or written once, times the iterations per
+ * launch. (The three-iteration launch moves fewer bytes than three
+ * one-iteration launches; this counts the work, not its layout.) */
 int fi_cg_kernel_bytes(const fi_mesh* mesh, int precision, int64_t* bytes);
 
 /* ------------------------------------------------------------- colour --

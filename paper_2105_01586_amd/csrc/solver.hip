@@ -1349,23 +1349,23 @@ int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
   return FI_OK;
 }
 
-// Bytes one CG iteration must move: the matrix (one int32 per stored
-// off-diagonal entry in the encoded layout, or column + value per CSR entry
-// plus row pointers), and per row the reads of r, s, q, D^-1, x, p and the
-// writes of x, p, r, s, q.
+// Algorithmic bytes of the CG iterations one step launch advances: per
+// iteration, the matrix (one int32 per stored off-diagonal entry in the
+// encoded layout, or column + value per CSR entry plus row pointers), and per
+// row the reads of r, s, q, D^-1, x, p and the writes of x, p, r, s, q; times
+// the iterations per launch (3 with the S-iteration plan, which itself moves
+// fewer bytes: ss_kernel_bytes).
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision) {
-  if (precision != FI_PREC_FP64 && M->ss) return ss_kernel_bytes(M);
   return cg_multi_kernel_bytes(M, 1, precision);
 }
 
 // With nrhs solves per launch the matrix counts once.
 int64_t cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision) {
-  if (precision != FI_PREC_FP64 && M->ss)  // the plan and diagonal once, the vectors per solve
-    return ss_kernel_bytes(M) + (int64_t)(nrhs - 1) * M->n * (32 + 32 + 8);
   const int64_t w = precision == FI_PREC_FP64 ? 8 : 4;
   const int64_t mat = M->ell_w > 0 ? M->nnz_off * 4  // encoded entries; padding not counted
                                    : M->nnz_off * (4 + w) + (M->n + 1) * 4;
-  return mat + (int64_t)nrhs * M->n * w * 11;
+  const int64_t per_iter = mat + (int64_t)nrhs * M->n * w * 11;
+  return (precision != FI_PREC_FP64 && M->ss) ? kSsIters * per_iter : per_iter;
 }
 
 }  // namespace fi

@@ -219,6 +219,7 @@ __device__ __forceinline__ double row_sum(double v) {
 __device__ __forceinline__ double block_gram(const float (&w)[NB], float dd, float* wst,
                                              double* wg) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __syncthreads();  // wst shares LDS with the basis levels read last
   float4* st = (float4*)(wst + 8 * t);
   st[0] = make_float4(w[0], w[1], w[2], w[3]);
   st[1] = make_float4(w[4], w[5], w[6], dd);
@@ -282,12 +283,8 @@ __device__ __forceinline__ void gram_issue(const SsArgs& A, GramLoads& L) {
 }
 
 template <bool LARGE>
-__device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L, double (&G)[NG],
-                                            double* red) {
-  if constexpr (LARGE) {
-#pragma unroll
-    for (int v = 0; v < NG; ++v) G[v] = A.part_in[v];
-  } else {
+__device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L, double* red) {
+  if constexpr (!LARGE) {
     const int v = threadIdx.x >> 4, j = threadIdx.x & 15;
     const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.grid;
     double h[16];
@@ -315,8 +312,6 @@ __device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L,
     acc += dpp_move<0x140>(acc);
     if (j == 0 && v < NG) red[v] = acc;
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NG; ++q) G[q] = red[q];
   }
 }
 
@@ -451,8 +446,9 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
   prefetch_recs(A, R);
   const float xo = A.x[ro];
   const float dd = A.d[ro];
-  double G[NG];
-  gram_finish<LARGE>(A, L, G, red);
+  gram_finish<LARGE>(A, L, red);
+  // the reduced Gram matrix: in LDS, or summed by the previous reduction launch
+  const double* Gsrc = LARGE ? A.part_in : red;
   const int phase = A.force ? (int)kIter : Rin.phase;
   const bool writer = lb == 0 && t == 0;
   const int RM = A.blocks[0].pad0;  // region rows the LDS is laid out for
@@ -472,8 +468,8 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
   if (phase == kInit) {
     // G[0] = ||r64||^2 from the start or refinement launch; the start launch
     // also sends G[1] = ||b||^2
-    double rnorm = sqrt(G[0]);
-    const double bnorm = Rin.ninner == 0 ? sqrt(G[1]) : Rin.bnorm;
+    double rnorm = sqrt(Gsrc[0]);
+    const double bnorm = Rin.ninner == 0 ? sqrt(Gsrc[1]) : Rin.bnorm;
     const double tol = P.atol > 0.0 ? fmin(P.rtol * bnorm, P.atol) : P.rtol * bnorm;
     int stagnant = Rin.stagnant;
     int next = 0;
@@ -525,14 +521,13 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
   // One wave runs them (every other wave would repeat the same FP64 chain on
   // the same SIMDs) and hands the coefficients over through LDS.
   int iter = Rin.iter;
-  double rz = iter == 0 ? G[gi(kZ0, kZ0)] : Rin.gamma_prev;
+  double rz = iter == 0 ? Gsrc[gi(kZ0, kZ0)] : Rin.gamma_prev;
   const double rho_ref = iter == 0 ? rz : Rin.rho_ref;
   double pc[NB], zc[NB], xc[NB];
   bool stop = false;
   if (t < 64) {
     // G z is kept up to date (z -= alpha T p gives G z -= alpha G T p, which
     // the step has formed anyway), so each step needs one product with G.
-    const double* Gsrc = LARGE ? A.part_in : red;  // the reduced Gram matrix
     double Gw[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) Gw[q] = Gsrc[q];
@@ -657,8 +652,7 @@ __global__ __launch_bounds__(BS) void k_ss_step(SsArgs A) {
   __shared__ double red[NGP];
   __shared__ double wred[(BS / 64) * NGP];  // per-wave Gram sums
   __shared__ double coef[3 * NB + 3];       // the iteration's coefficients
-  __shared__ float4 wst[BS * 2];            // rows' basis values for the matrix cores
-  ss_body<LARGE>(A, logical_block(), dyn, red, wred, coef, (float*)wst);
+  ss_body<LARGE>(A, logical_block(), dyn, red, wred, coef, dyn);
 }
 
 // Several right-hand sides with one matrix (the channels of a colour image):
@@ -679,12 +673,10 @@ __global__ __launch_bounds__(BS) void k_ss_multi(SsMultiArgs M) {
   __shared__ double red[NGP];
   __shared__ double wred[(BS / 64) * NGP];
   __shared__ double coef[3 * NB + 3];
-  __shared__ float4 wst[BS * 2];
   const int nr = M.nrhs;
   const int per = (int)(gridDim.x / nr) >> 3;
   const int k = blockIdx.x >> 3;
-  ss_body<LARGE>(M.a[k % nr], (blockIdx.x & 7) * per + k / nr, dyn, red, wred, coef,
-                 (float*)wst);
+  ss_body<LARGE>(M.a[k % nr], (blockIdx.x & 7) * per + k / nr, dyn, red, wred, coef, dyn);
 }
 
 // Several meshes' solves in one launch (the server): the grid is the
@@ -707,7 +699,6 @@ __global__ __launch_bounds__(BS) void k_ss_batch(SsBatchArgs Bt) {
   __shared__ double red[NGP];
   __shared__ double wred[(BS / 64) * NGP];
   __shared__ double coef[3 * NB + 3];
-  __shared__ float4 wst[BS * 2];
   const int lb = logical_block();
   int j = 0;  // slot of this block (uniform)
 #pragma unroll
@@ -718,7 +709,7 @@ __global__ __launch_bounds__(BS) void k_ss_batch(SsBatchArgs Bt) {
     if (lblk == 0 && threadIdx.x == 0) *A.rec_out = *A.rec_in;
     return;
   }
-  ss_body<LARGE>(A, lblk, dyn, red, wred, coef, (float*)wst);
+  ss_body<LARGE>(A, lblk, dyn, red, wred, coef, dyn);
 }
 
 // Start of a solve: b and x0 in the launch's numbering, x64 = x0 (0 when
@@ -850,7 +841,11 @@ SsArgs ss_args(fi_mesh* M, int par, int force) {
   return A;
 }
 
-size_t ss_lds_bytes(const SsState& Z) { return (size_t)5 * Z.max_region * sizeof(float); }
+// Dynamic LDS of a launch: the basis levels (5 floats per region row), and
+// at least room for the rows' values staged for the matrix cores.
+size_t ss_lds_bytes(const SsState& Z) {
+  return std::max((size_t)5 * Z.max_region * sizeof(float), (size_t)BS * 8 * sizeof(float));
+}
 
 int ss_reduce_after(fi_mesh* M, int par) {
   SsState& Z = *M->ss;
