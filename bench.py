@@ -736,6 +736,11 @@ def main():
     import paper_2105_01586_amd as fi
     import synth
 
+    t_start = time.perf_counter()
+
+    def progress(what):
+        print(f"[{time.perf_counter() - t_start:7.1f} s] {what}", file=sys.stderr, flush=True)
+
     w = synth.WORKLOADS[args.workload]
     big = w.side > 2048
     if args.steps is None:
@@ -749,6 +754,7 @@ def main():
     stream = torch.cuda.current_stream(0)
     ctx = fi.Context(0, stream)
     mesh = fi.Mesh(ctx, w.side, mask)
+    progress(f"mesh built: {mesh.n} unknowns")
     f = torch.from_numpy(f_np.ravel().copy()).to(dev)
     u = torch.empty(P, dtype=torch.float64, device=dev)
     g = torch.empty(mesh.m, dtype=torch.float64, device=dev)
@@ -787,12 +793,14 @@ def main():
     for _ in range(args.warmup):
         step(warm)
     torch.cuda.synchronize()
+    progress(f"{args.warmup} warm-up steps done")
     recs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(recs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    progress(f"{args.steps} timed steps done")
     inp_ms = [a.elapsed_time(b) for a, b, *_ in recs]
     ton_ms = [b.elapsed_time(c) for _, b, c, *_ in recs]
     st, ts = recs[-1][3], recs[-1][4]
@@ -818,17 +826,31 @@ def main():
                 t64.append(a.elapsed_time(b))
         fp64 = {"inpaint_mpix_s": P / (np.mean(t64) * 1e3), "iterations": st64["iterations"]}
         _, st = mesh.inpaint(f=f, u=u, opts=inner_inp)   # leave the FP32 result in u
+        progress("plain FP64 comparator done")
 
     # every pixel against a tight FP64 solve on the GPU
     u_tight, st_t = mesh.inpaint(f=f, opts=fi.SolveOpts(precision=fi.PREC_FP64, rtol=1e-13))
     err_tight = float((u - u_tight).abs().max())
     del u_tight
+    progress("tight FP64 check done")
 
-    # dominant kernel: fused FP32 CG iteration, timed on the library's stream
+    # checks that launch solves of their own run before the kernel timing,
+    # so that the timed launches are the last of the run (profiles pick them
+    # from the trace's end)
+    g_fd = fd_res = crop_res = None
+    if w.side <= 1024:
+        g_fd, fd_res = fd_check(fi, mesh, f, f_np, mask)
+        progress("finite-difference check done")
+    if big:
+        crop_res = crop_check(fi, ctx, f_np, mask)
+        progress("crop check done")
+
+    # dominant kernel: the FP32 CG launch, timed on the library's stream
     kms = mesh.time_cg_kernel(fi.PREC_FP32_IR, args.kernel_reps)
     kbytes = mesh.cg_kernel_bytes(fi.PREC_FP32_IR)
     achieved = kbytes / (kms * 1e-3) / 1e9
     torch.cuda.synchronize()
+    progress("kernel timing done")
 
     out = {
         "metric": "inpainted Mpixel/s + tonal-opt solves/s at <=1e-6 err vs FP64; p50/p99 latency",
@@ -878,9 +900,8 @@ def main():
     out["device_memory_gb"] = {"mesh_and_solver": mesh.info["device_bytes"] / 1e9,
                                "torch_peak": torch.cuda.max_memory_allocated() / 1e9,
                                "device_used_peak": peak_used[0] / 1e9}
-    g_fd = None
-    if w.side <= 1024:
-        g_fd, out["gradient_fd_check"] = fd_check(fi, mesh, f, f_np, mask)
+    if fd_res is not None:
+        out["gradient_fd_check"] = fd_res
     if not args.no_cpu_baseline:
         if w.side <= 1024:
             cb, acc = cpu_baseline(w.side, f_np, mask, u.cpu().numpy(), f"the {w.side}^2 image",
@@ -898,7 +919,7 @@ def main():
             cb, _ = cpu_baseline(2048, cf, cm, None, f"the 2048^2 crop at ({r0}, {c0})")
         out["cpu_baseline"] = cb
     if big:
-        out["crop_vs_oracle"] = crop_check(fi, ctx, f_np, mask)
+        out["crop_vs_oracle"] = crop_res
     print(json.dumps(out))
     mesh.close()
     ctx.close()

@@ -121,6 +121,12 @@ struct SsState {
   double* x64[2] = {nullptr, nullptr};  // FP64 iterate, by buffer parity
   double* part = nullptr;   // Gram partials: 2 parities x 32 values x grid (value-major)
   double* red = nullptr;    // reduced Gram (large systems): 32 doubles
+  // large systems: the reduction launch's first-level sums (32 per block of
+  // 256 partials), its completion counter, and the coefficients of the next
+  // step launch's iterations, which it computes once for all blocks
+  double* level1 = nullptr;
+  int* counter = nullptr;
+  double* ctl = nullptr;
 };
 
 struct CGState {  // state of one fused-CG inner solver in precision T

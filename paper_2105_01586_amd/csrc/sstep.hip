@@ -62,6 +62,14 @@ constexpr int BS = 512;                 // threads and own rows per block
 constexpr int kSmallGrid = 1024;        // blocks up to which each block re-reduces the partials
 constexpr int kMaxRegion = 2048;        // region rows per block (LDS: 5 floats per row)
 constexpr int kZ0 = S + 1;              // index of Z_0 in the basis
+// A value's partial sums (one per block) are a row of the partials buffer
+// whose length, the grid rounded up to this, is a whole number of chunks of
+// 256 zero-padded entries: every reduction loads whole chunks, unmasked.
+constexpr int kPartPad = 256;
+
+__host__ __device__ constexpr int part_stride(int grid) {
+  return (grid + kPartPad - 1) / kPartPad * kPartPad;
+}
 
 // Index of G[a][b] (a <= b) in the upper triangle, row by row.
 __host__ __device__ constexpr int gi(int a, int b) {
@@ -71,6 +79,7 @@ __host__ __device__ constexpr int gi(int a, int b) {
 struct SsArgs {
   int n;
   int grid;
+  int gstride;         // length of a value's row of partial sums (part_stride)
   const int32_t* perm;
   const BlockPlan* blocks;
   const int32_t* region;  // region rows of every block (own rows first)
@@ -90,6 +99,7 @@ struct SsArgs {
   Rec* rec_out;
   const Params* prm;
   Mirror* mirror;
+  const double* ctl;   // large systems: the coefficients of this launch's iterations
   int force;           // timing only: always iterate
 };
 
@@ -193,7 +203,7 @@ __device__ __forceinline__ double combine(const float4& a0, const float4& a1,
 // thread 16 v (which holds it).
 __device__ __forceinline__ void store_slot(const SsArgs& A, int lb, double v) {
   if ((threadIdx.x & 15) == 0 && (threadIdx.x >> 4) < NGP)
-    A.part_out[(size_t)(threadIdx.x >> 4) * A.grid + lb] = v;
+    A.part_out[(size_t)(threadIdx.x >> 4) * A.gstride + lb] = v;
 }
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -273,12 +283,9 @@ template <bool LARGE>
 __device__ __forceinline__ void gram_issue(const SsArgs& A, GramLoads& L) {
   if constexpr (!LARGE) {
     const int v = threadIdx.x >> 4, j = threadIdx.x & 15;
-    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.grid;
+    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.gstride + j;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int q = j + 16 * k;
-      L.a[k] = pv[q < A.grid ? q : 0];
-    }
+    for (int k = 0; k < 16; ++k) L.a[k] = pv[16 * k];  // padding entries are 0
   }
 }
 
@@ -286,10 +293,10 @@ template <bool LARGE>
 __device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L, double* red) {
   if constexpr (!LARGE) {
     const int v = threadIdx.x >> 4, j = threadIdx.x & 15;
-    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.grid;
+    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.gstride + j;
     double h[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) h[k] = (j + 16 * k < A.grid) ? L.a[k] : 0.0;
+    for (int k = 0; k < 16; ++k) h[k] = L.a[k];
 #pragma unroll
     for (int w = 8; w >= 1; w >>= 1)
 #pragma unroll
@@ -298,12 +305,9 @@ __device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L,
     for (int c0 = 256; c0 < A.grid; c0 += 256) {
       double a[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int q = c0 + j + 16 * k;
-        a[k] = pv[q < A.grid ? q : 0];
-      }
+      for (int k = 0; k < 16; ++k) a[k] = pv[c0 + 16 * k];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc += (c0 + j + 16 * k < A.grid) ? a[k] : 0.0;
+      for (int k = 0; k < 16; ++k) acc += a[k];
     }
     if (v >= NG) acc = 0.0;
     acc += dpp_move<0xB1>(acc);
@@ -426,6 +430,72 @@ __device__ __forceinline__ void finish_basis(const SsArgs& A, const BlockPlan& B
   store_slot(A, lb, block_gram(w, t < B.nown ? dd : 0.0f, wst, wred));
 }
 
+// The S CG iterations of one launch on the coefficient vectors (one wave,
+// every lane alike; lane 0 writes out = pc, zc, xc, (r, z), iteration count,
+// stop flag: 3 NB + 3 doubles). G is the Gram matrix of the launch's basis,
+// Rin the record the launch reads. G z is kept up to date (z -= alpha T p
+// gives G z -= alpha G T p, which the step has formed anyway), so each step
+// needs one product with G.
+__device__ __forceinline__ void ss_recur(const double* Gsrc, const Rec& Rin, const Params& P,
+                                         int force, double* out) {
+  int iter = Rin.iter;
+  double rz = iter == 0 ? Gsrc[gi(kZ0, kZ0)] : Rin.gamma_prev;
+  const double rho_ref = iter == 0 ? rz : Rin.rho_ref;
+  double pc[NB], zc[NB], xc[NB];
+  bool stop = false;
+  double Gw[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) Gw[q] = Gsrc[q];
+  double gz[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    pc[a] = a == 0 ? 1.0 : 0.0;
+    zc[a] = a == kZ0 ? 1.0 : 0.0;
+    xc[a] = 0.0;
+    gz[a] = Gw[gi(a, kZ0)];
+  }
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    if (!stop) {
+      double tp[NB], gtp[NB];
+      tcoef(pc, tp);
+      gmul(Gw, tp, gtp);
+      const double alpha = qdiv(rz, dotv(pc, gtp));
+      if (!force && (!(alpha > 0.0) || !isfinite(alpha))) {
+        stop = true;  // breakdown: refine with what has been reached
+      } else {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          xc[a] = __builtin_fma(alpha, pc[a], xc[a]);
+          zc[a] = __builtin_fma(-alpha, tp[a], zc[a]);
+          gz[a] = __builtin_fma(-alpha, gtp[a], gz[a]);
+        }
+        ++iter;
+        const double rzn = dotv(zc, gz);
+        if (!force && (!(rzn > Rin.tol2 * rho_ref) || (double)iter >= P.max_inner)) {
+          stop = true;
+        } else {
+          const double beta = qdiv(rzn, rz);
+          rz = rzn;
+#pragma unroll
+          for (int a = 0; a < NB; ++a) pc[a] = __builtin_fma(beta, pc[a], zc[a]);
+        }
+      }
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      out[a] = pc[a];
+      out[NB + a] = zc[a];
+      out[2 * NB + a] = xc[a];
+    }
+    out[3 * NB] = rz;
+    out[3 * NB + 1] = (double)iter;
+    out[3 * NB + 2] = stop ? 1.0 : 0.0;
+  }
+}
+
 template <bool LARGE>
 __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dyn, double* red,
                                         double* wred, double* coef, float* wst) {
@@ -519,77 +589,27 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
 
   // ---- kIter: S iterations on the coefficients -----------------------------
   // One wave runs them (every other wave would repeat the same FP64 chain on
-  // the same SIMDs) and hands the coefficients over through LDS.
-  int iter = Rin.iter;
-  double rz = iter == 0 ? Gsrc[gi(kZ0, kZ0)] : Rin.gamma_prev;
-  const double rho_ref = iter == 0 ? rz : Rin.rho_ref;
-  double pc[NB], zc[NB], xc[NB];
-  bool stop = false;
-  if (t < 64) {
-    // G z is kept up to date (z -= alpha T p gives G z -= alpha G T p, which
-    // the step has formed anyway), so each step needs one product with G.
-    double Gw[NG];
-#pragma unroll
-    for (int q = 0; q < NG; ++q) Gw[q] = Gsrc[q];
-    double gz[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      pc[a] = a == 0 ? 1.0 : 0.0;
-      zc[a] = a == kZ0 ? 1.0 : 0.0;
-      xc[a] = 0.0;
-      gz[a] = Gw[gi(a, kZ0)];
-    }
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      if (!stop) {
-        double tp[NB], gtp[NB];
-        tcoef(pc, tp);
-        gmul(Gw, tp, gtp);
-        const double alpha = qdiv(rz, dotv(pc, gtp));
-        if (!A.force && (!(alpha > 0.0) || !isfinite(alpha))) {
-          stop = true;  // breakdown: refine with what has been reached
-        } else {
-#pragma unroll
-          for (int a = 0; a < NB; ++a) {
-            xc[a] = __builtin_fma(alpha, pc[a], xc[a]);
-            zc[a] = __builtin_fma(-alpha, tp[a], zc[a]);
-            gz[a] = __builtin_fma(-alpha, gtp[a], gz[a]);
-          }
-          ++iter;
-          const double rzn = dotv(zc, gz);
-          if (!A.force && (!(rzn > Rin.tol2 * rho_ref) || (double)iter >= P.max_inner)) {
-            stop = true;
-          } else {
-            const double beta = qdiv(rzn, rz);
-            rz = rzn;
-#pragma unroll
-            for (int a = 0; a < NB; ++a) pc[a] = __builtin_fma(beta, pc[a], zc[a]);
-          }
-        }
-      }
-    }
-    if (t == 0) {
-#pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        coef[a] = pc[a];
-        coef[NB + a] = zc[a];
-        coef[2 * NB + a] = xc[a];
-      }
-      coef[3 * NB] = rz;
-      coef[3 * NB + 1] = (double)iter;
-      coef[3 * NB + 2] = stop ? 1.0 : 0.0;
-    }
+  // the same SIMDs) and hands the coefficients over through LDS; for large
+  // systems the reduction launch has run them once for every block.
+  const int iter0 = Rin.iter;
+  const double rho_ref = iter0 == 0 ? Gsrc[gi(kZ0, kZ0)] : Rin.rho_ref;
+  const double* cf = coef;
+  if constexpr (LARGE) {
+    cf = A.ctl;
+  } else {
+    if (t < 64) ss_recur(Gsrc, Rin, P, A.force, coef);
+    __syncthreads();
   }
-  __syncthreads();
+  double pc[NB], zc[NB], xc[NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
-    pc[a] = coef[a];
-    zc[a] = coef[NB + a];
-    xc[a] = coef[2 * NB + a];
+    pc[a] = cf[a];
+    zc[a] = cf[NB + a];
+    xc[a] = cf[2 * NB + a];
   }
-  rz = coef[3 * NB];
-  iter = (int)coef[3 * NB + 1];
-  stop = coef[3 * NB + 2] != 0.0;
+  const double rz = cf[3 * NB];
+  const int iter = (int)cf[3 * NB + 1];
+  const bool stop = cf[3 * NB + 2] != 0.0;
 
   if (stop) {
     // Inner solve over: x64 += rnorm * (x + W xc) on the rows within one hop,
@@ -766,35 +786,94 @@ __global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* p
   }
 }
 
-// Large systems: the Gram partials summed by a separate launch, one block
-// per value, each thread over a strided set in order, then the block.
-__global__ __launch_bounds__(kBlock) void k_ss_reduce(const double* __restrict__ part, int grid,
-                                                      double* __restrict__ out) {
-  __shared__ double lds[4];
-  const int v = blockIdx.x;
-  double s[1] = {0.0};
-  for (int q = threadIdx.x; q < grid; q += kBlock) s[0] += part[(size_t)v * grid + q];
-  block_sum<1>(s, lds);
-  if (threadIdx.x == 0) out[v] = s[0];
-}
+// Large systems: a separate launch sums the Gram partials of the step launch
+// before it and runs the next launch's iterations on the coefficients once,
+// for every block of that launch. First level: block b sums partials
+// [256 b, 256 b + 256) of every value (value v by the 16 lanes of one DPP
+// row, partials j, j + 16, ... each, as in the step's own re-reduction);
+// the block that finishes last (integer counter) sums the first-level sums
+// in block order, stores the totals and, when the next launch iterates,
+// the coefficients. Several systems (channels, batched meshes) share one
+// launch, each with its own blocks.
+constexpr int kGramChunk = 256;  // partials per first-level block
 
-// The same for several systems: block b sums value b % NG of system b / NG.
-struct SsReduceArgs {
-  int n;
-  int32_t grid[kSsArgSlots];
-  const double* part[kSsArgSlots];
-  double* out[kSsArgSlots];
+struct SsRedSys {
+  const double* part;  // NGP rows of partials (value-major, rows of part_stride(grid))
+  double* level1;      // first-level sums, NGP per block
+  int* counter;        // blocks done (0 between launches)
+  double* out;         // NGP totals
+  const Rec* rec;      // the record the next step launch reads
+  const Params* prm;
+  double* ctl;         // that launch's coefficients (3 NB + 3 doubles)
+  int grid;
+  int force;
 };
 
-__global__ __launch_bounds__(kBlock) void k_ss_reduce_many(SsReduceArgs R) {
-  __shared__ double lds[4];
-  const int q = blockIdx.x / NG, v = blockIdx.x % NG;
-  const int grid = R.grid[q];
-  const double* part = R.part[q];
-  double s[1] = {0.0};
-  for (int i = threadIdx.x; i < grid; i += kBlock) s[0] += part[(size_t)v * grid + i];
-  block_sum<1>(s, lds);
-  if (threadIdx.x == 0) R.out[q][v] = s[0];
+struct SsRedArgs {
+  int n;
+  int32_t start[kSsArgSlots + 1];  // first block of each system
+  SsRedSys s[kSsArgSlots];
+};
+static_assert(sizeof(SsRedArgs) <= 4096, "kernel arguments of a reduction launch");
+
+__host__ __device__ constexpr int gram_blocks(int grid) { return part_stride(grid) / kGramChunk; }
+static_assert(kPartPad % kGramChunk == 0, "a row is a whole number of first-level chunks");
+
+__global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
+  __shared__ double tot[NGP];
+  __shared__ int last;
+  int j = 0;  // system of this block (uniform)
+#pragma unroll
+  for (int k = 1; k < kSsArgSlots; ++k) j += (k < R.n && R.start[k] <= (int)blockIdx.x) ? 1 : 0;
+  const SsRedSys& Y = R.s[j];
+  const int b = (int)blockIdx.x - R.start[j], nb = R.start[j + 1] - R.start[j];
+  const int t = threadIdx.x, v = t >> 4, l = t & 15;
+  const int vv = v < NG ? v : 0;
+  {
+    const double* pv = Y.part + (size_t)vv * part_stride(Y.grid) + b * kGramChunk + l;
+    double h[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) h[k] = pv[16 * k];  // padding entries are 0
+#pragma unroll
+    for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+      for (int k = 0; k < w; ++k) h[k] += h[k + w];
+    const double sum = row_sum(h[0]);
+    if (l == 0 && v < NG) {
+      __hip_atomic_store(&Y.level1[(size_t)b * NGP + v], sum, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+    }
+  }
+  __syncthreads();
+  if (t == 0) last = atomicAdd(Y.counter, 1) == nb - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc = 0.0;
+  for (int q0 = 0; q0 < nb; q0 += 256) {
+    double h[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int q = q0 + l + 16 * k;
+      h[k] = q < nb ? __hip_atomic_load(&Y.level1[(size_t)q * NGP + vv], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)
+                    : 0.0;
+    }
+#pragma unroll
+    for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+      for (int k = 0; k < w; ++k) h[k] += h[k + w];
+    acc += h[0];
+  }
+  acc = row_sum(acc);
+  if (l == 0 && v < NG) {
+    tot[v] = acc;
+    Y.out[v] = acc;
+  }
+  __syncthreads();
+  if (t == 0) __hip_atomic_store(Y.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t < 64 && (Y.force || Y.rec->phase == kIter)) ss_recur(tot, *Y.rec, *Y.prm, Y.force, Y.ctl);
 }
 
 // Values of the plan's rows after an assembly: the FP32 diagonal and D^-1
@@ -818,6 +897,7 @@ SsArgs ss_args(fi_mesh* M, int par, int force) {
   SsArgs A;
   A.n = (int)M->n;
   A.grid = Z.grid;
+  A.gstride = part_stride(Z.grid);
   A.perm = Z.perm;
   A.blocks = (const BlockPlan*)Z.blocks;
   A.region = Z.region;
@@ -831,14 +911,49 @@ SsArgs ss_args(fi_mesh* M, int par, int force) {
   A.x64a = Z.x64[0];
   A.x64b = Z.x64[1];
   A.xout = M->d_x64buf[0];
-  A.part_in = Z.large ? Z.red : Z.part + (size_t)par * NGP * Z.grid;
-  A.part_out = Z.part + (size_t)(par ^ 1) * NGP * Z.grid;
+  A.part_in = Z.large ? Z.red : Z.part + (size_t)par * NGP * A.gstride;
+  A.part_out = Z.part + (size_t)(par ^ 1) * NGP * A.gstride;
   A.rec_in = (const Rec*)M->d_rec + par;
   A.rec_out = (Rec*)M->d_rec + (par ^ 1);
   A.prm = (const Params*)M->d_prm;
   A.mirror = (Mirror*)M->d_mirror;
+  A.ctl = Z.ctl;
   A.force = force;
   return A;
+}
+
+// The reduction after a step launch of parity par: its partials, and the
+// record and coefficients of the next launch.
+SsRedSys red_sys(fi_mesh* M, int par, int force) {
+  SsState& Z = *M->ss;
+  SsRedSys y;
+  y.part = Z.part + (size_t)(par ^ 1) * NGP * part_stride(Z.grid);
+  y.level1 = Z.level1;
+  y.counter = Z.counter;
+  y.out = Z.red;
+  y.rec = (const Rec*)M->d_rec + (par ^ 1);
+  y.prm = (const Params*)M->d_prm;
+  y.ctl = Z.ctl;
+  y.grid = Z.grid;
+  y.force = force;
+  return y;
+}
+
+// Appends system y to a reduction launch (false when the launch is full).
+bool red_add(SsRedArgs& R, const SsRedSys& y) {
+  if (R.n >= kSsArgSlots) return false;
+  if (R.n == 0) R.start[0] = 0;
+  R.s[R.n] = y;
+  R.start[R.n + 1] = R.start[R.n] + gram_blocks(y.grid);
+  ++R.n;
+  return true;
+}
+
+int red_launch(const SsRedArgs& R, hipStream_t st) {
+  if (R.n == 0) return FI_OK;
+  void* args[1] = {(void*)&R};
+  FI_HIP_TRY(hipLaunchKernel((void*)k_ss_gram, dim3((unsigned)R.start[R.n]), dim3(BS), args, 0, st));
+  return FI_OK;
 }
 
 // Dynamic LDS of a launch: the basis levels (5 floats per region row), and
@@ -847,12 +962,10 @@ size_t ss_lds_bytes(const SsState& Z) {
   return std::max((size_t)5 * Z.max_region * sizeof(float), (size_t)BS * 8 * sizeof(float));
 }
 
-int ss_reduce_after(fi_mesh* M, int par) {
-  SsState& Z = *M->ss;
-  hipLaunchKernelGGL(k_ss_reduce, dim3(NG), dim3(kBlock), 0, M->ctx->stream,
-                     (const double*)(Z.part + (size_t)(par ^ 1) * NGP * Z.grid), Z.grid, Z.red);
-  FI_HIP_TRY(hipGetLastError());
-  return FI_OK;
+int ss_reduce_after(fi_mesh* M, int par, int force) {
+  SsRedArgs R{};
+  red_add(R, red_sys(M, par, force));
+  return red_launch(R, M->ctx->stream);
 }
 
 int ss_launch_step(fi_mesh* M, int par, int force) {
@@ -861,7 +974,7 @@ int ss_launch_step(fi_mesh* M, int par, int force) {
   void* args[1] = {&A};
   void* fn = Z.large ? (void*)k_ss_step<true> : (void*)k_ss_step<false>;
   FI_HIP_TRY(hipLaunchKernel(fn, dim3(Z.grid), dim3(BS), args, ss_lds_bytes(Z), M->ctx->stream));
-  return Z.large ? ss_reduce_after(M, par) : FI_OK;
+  return Z.large ? ss_reduce_after(M, par, force) : FI_OK;
 }
 
 int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0) {
@@ -880,7 +993,27 @@ int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double*
   void* args[5] = {&A, &prm, &pout, &bnat, &x0};
   FI_HIP_TRY(hipLaunchKernel((void*)k_ss_start, dim3(Z.grid), dim3(BS), args, ss_lds_bytes(Z),
                              M->ctx->stream));
-  return Z.large ? ss_reduce_after(M, 1) : FI_OK;
+  return Z.large ? ss_reduce_after(M, 1, 0) : FI_OK;
+}
+
+// Both parities of the partial sums.
+size_t part_bytes(int grid) { return (size_t)2 * NGP * part_stride(grid) * sizeof(double); }
+
+// Large systems: the reduction launch's first-level sums, its counter (zero)
+// and the coefficient block.
+int large_alloc(fi_mesh* M, SsState& Z) {
+  Z.level1 = nullptr;
+  Z.counter = nullptr;
+  Z.ctl = nullptr;
+  if (!Z.large) return FI_OK;
+  int rc = 0;
+  if ((rc = device_alloc(M, (void**)&Z.level1, (size_t)gram_blocks(Z.grid) * NGP * 8)) ||
+      (rc = device_alloc(M, (void**)&Z.counter, 256)) ||
+      (rc = device_alloc(M, (void**)&Z.ctl, NGP * 8)))
+    return rc;
+  FI_HIP_TRY(hipMemsetAsync(Z.counter, 0, 256, M->ctx->stream));
+  FI_HIP_TRY(hipMemsetAsync(Z.ctl, 0, NGP * 8, M->ctx->stream));
+  return FI_OK;
 }
 
 int slot_of(const double* x0) { return 0 + (x0 ? 1 : 0); }  // FP32 cold / warm prediction slots
@@ -937,8 +1070,9 @@ int ss_setup(fi_mesh* M) {
         (rc = device_alloc(M, (void**)&Z->r64, nn * 8)) ||
         (rc = device_alloc(M, (void**)&Z->x64[0], nn * 8)) ||
         (rc = device_alloc(M, (void**)&Z->x64[1], nn * 8)) ||
-        (rc = device_alloc(M, (void**)&Z->part, (size_t)2 * NGP * Z->grid * 8)) ||
-        (rc = device_alloc(M, (void**)&Z->red, NGP * 8)))
+        (rc = device_alloc(M, (void**)&Z->part, part_bytes(Z->grid))) ||
+        (rc = device_alloc(M, (void**)&Z->red, NGP * 8)) ||
+        (rc = large_alloc(M, *Z)))
       return rc;
     FI_HIP_TRY(hipMemcpyAsync(Z->perm, plan.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
     FI_HIP_TRY(hipMemcpyAsync(Z->blocks, plan.blocks.data(), plan.blocks.size() * sizeof(BlockPlan),
@@ -951,6 +1085,7 @@ int ss_setup(fi_mesh* M) {
                                 hipMemcpyHostToDevice, st));
     // every basis slot starts finite (the first launch reads only D^-1)
     FI_HIP_TRY(hipMemsetAsync(Z->W[0], 0, nn * 32, st));
+    FI_HIP_TRY(hipMemsetAsync(Z->part, 0, part_bytes(Z->grid), st));  // the padding stays 0
     FI_HIP_TRY(hipMemsetAsync(Z->W[1], 0, nn * 32, st));
     // the host copies above come from vectors that end with this call
     FI_HIP_TRY(hipStreamSynchronize(st));
@@ -1012,20 +1147,17 @@ void* batch_fn(bool large) { return large ? (void*)k_ss_batch<true> : (void*)k_s
 // Launch arguments of a multi-RHS step for both parities.
 struct SsMultiLaunch {
   SsMultiArgs a[2];
-  SsReduceArgs r[2];
+  SsRedArgs r[2];
 };
 
 void ss_multi_prepare(fi_mesh* const* ch, int nc, int force, SsMultiLaunch& L) {
   for (int par = 0; par < 2; ++par) {
     L.a[par] = SsMultiArgs{};
     L.a[par].nrhs = nc;
-    L.r[par] = SsReduceArgs{};
-    L.r[par].n = nc;
+    L.r[par] = SsRedArgs{};
     for (int c = 0; c < nc; ++c) {
       L.a[par].a[c] = ss_args(ch[c], par, force);
-      L.r[par].grid[c] = ch[c]->ss->grid;
-      L.r[par].part[c] = ch[c]->ss->part + (size_t)(par ^ 1) * NGP * ch[c]->ss->grid;
-      L.r[par].out[c] = ch[c]->ss->red;
+      if (ch[c]->ss->large) red_add(L.r[par], red_sys(ch[c], par, force));
     }
   }
 }
@@ -1036,11 +1168,7 @@ int ss_multi_launch(fi_mesh* M0, SsMultiLaunch& L, int par) {
   const unsigned grid = (unsigned)L.a[par].nrhs * (unsigned)Z.grid;
   FI_HIP_TRY(hipLaunchKernel(multi_fn(Z.large), dim3(grid), dim3(BS), args, ss_lds_bytes(Z),
                              M0->ctx->stream));
-  if (!Z.large) return FI_OK;
-  void* rargs[1] = {&L.r[par]};
-  FI_HIP_TRY(hipLaunchKernel((void*)k_ss_reduce_many, dim3(NG * L.r[par].n), dim3(kBlock), rargs, 0,
-                             M0->ctx->stream));
-  return FI_OK;
+  return Z.large ? red_launch(L.r[par], M0->ctx->stream) : FI_OK;
 }
 
 }  // namespace
@@ -1158,7 +1286,7 @@ int ss_time_multi(fi_mesh* const* ch, int nc, int reps, double* ms) {
 int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) {
   struct Launch {
     SsBatchArgs b[2];
-    SsReduceArgs r[2];
+    SsRedArgs r[2];
     int64_t grid;
     bool large;
     size_t lds;
@@ -1175,19 +1303,14 @@ int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) 
       ++j1;
     l.large = order[j0]->ss->large;
     int64_t total = 0;
-    for (int par = 0; par < 2; ++par) {
-      l.b[par].n = (int)(j1 - j0);
-      l.r[par].n = (int)(j1 - j0);
-    }
+    for (int par = 0; par < 2; ++par) l.b[par].n = (int)(j1 - j0);
     for (size_t j = j0; j < j1; ++j) {
       fi_mesh* M = order[j];
       const int q = (int)(j - j0);
       for (int par = 0; par < 2; ++par) {
         l.b[par].start[q] = (int32_t)total;
         l.b[par].a[q] = ss_args(M, par, 0);
-        l.r[par].grid[q] = M->ss->grid;
-        l.r[par].part[q] = M->ss->part + (size_t)(par ^ 1) * NGP * M->ss->grid;
-        l.r[par].out[q] = M->ss->red;
+        if (l.large) red_add(l.r[par], red_sys(M, par, 0));
       }
       total += M->ss->grid;
       l.lds = std::max(l.lds, ss_lds_bytes(*M->ss));
@@ -1207,9 +1330,8 @@ int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) 
     }
     for (Launch& l : L) {
       if (!l.large) continue;
-      void* rargs[1] = {&l.r[par]};
-      FI_HIP_TRY(hipLaunchKernel((void*)k_ss_reduce_many, dim3(NG * l.r[par].n), dim3(kBlock),
-                                 rargs, 0, st));
+      const int rc = red_launch(l.r[par], st);
+      if (rc) return rc;
     }
   }
   return FI_OK;
@@ -1235,12 +1357,13 @@ int ss_channel_setup(fi_mesh* S, const fi_mesh* M) {
       (rc = device_alloc(S, (void**)&Z->r64, nn * 8)) ||
       (rc = device_alloc(S, (void**)&Z->x64[0], nn * 8)) ||
       (rc = device_alloc(S, (void**)&Z->x64[1], nn * 8)) ||
-      (rc = device_alloc(S, (void**)&Z->part, (size_t)2 * NGP * Z->grid * 8)) ||
-      (rc = device_alloc(S, (void**)&Z->red, NGP * 8)))
+      (rc = device_alloc(S, (void**)&Z->part, part_bytes(Z->grid))) ||
+      (rc = device_alloc(S, (void**)&Z->red, NGP * 8)) || (rc = large_alloc(S, *Z)))
     return rc;
   hipStream_t st = M->ctx->stream;
   FI_HIP_TRY(hipMemsetAsync(Z->W[0], 0, nn * 32, st));
   FI_HIP_TRY(hipMemsetAsync(Z->W[1], 0, nn * 32, st));
+  FI_HIP_TRY(hipMemsetAsync(Z->part, 0, part_bytes(Z->grid), st));  // the padding stays 0
   hipLaunchKernelGGL(k_ss_values, dim3((unsigned)((M->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      st, (int)M->n, Z->perm, M->d_diag64, M->d_dinv32, (float*)nullptr, Z->W[0],
                      Z->W[1]);
@@ -1251,7 +1374,7 @@ int ss_channel_setup(fi_mesh* S, const fi_mesh* M) {
 // Device bytes the S-iteration state of a system of n rows may take (each
 // allocation rounded to 256 bytes): the plan (at most three region and
 // local matrix rows per free row), the two basis buffers, the FP32 and FP64
-// vectors, the partial sums.
+// vectors, the partial sums, the reduction launch's state.
 int64_t ss_footprint(int64_t n) {
   const int64_t grid = ((n + BS - 1) / BS + 7) / 8 * 8;
   int64_t total = 0;
@@ -1261,7 +1384,8 @@ int64_t ss_footprint(int64_t n) {
   add(4 * n); add(32 * grid); add(4 * 3 * n); add(16 * 3 * n);
   add(32 * n); add(32 * n); add(4 * n); add(4 * n);
   add(8 * n); add(8 * n); add(8 * n); add(8 * n);
-  add(8 * 2 * NGP * grid); add(8 * NGP);
+  add(8 * 2 * NGP * part_stride((int)grid)); add(8 * NGP);
+  add(8 * NGP * gram_blocks((int)grid)); add(256); add(8 * NGP);  // large systems
   return total;
 }
 
