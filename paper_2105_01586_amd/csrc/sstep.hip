@@ -59,7 +59,12 @@ constexpr int NB = 2 * S + 1;           // basis vectors: P_0..P_S, Z_0..Z_{S-1}
 constexpr int NG = NB * (NB + 1) / 2;   // Gram entries (upper triangle)
 constexpr int NGP = 32;                 // Gram slots per block (NG used)
 constexpr int BS = 512;                 // threads and own rows per block
-constexpr int kSmallGrid = 1024;        // blocks up to which each block re-reduces the partials
+// Blocks up to which a single solve's blocks re-reduce the partials
+// themselves (one block per compute unit at most: those launches run in
+// one round even at the occupancy the in-block iterations allow); larger
+// grids, and multi-solve or batched launches past it, sum them in a
+// reduction launch. Up to 256 blocks both ways give the same bits.
+constexpr int kSmallGrid = 256;
 constexpr int kMaxRegion = 2048;        // region rows per block (LDS: 5 floats per row)
 constexpr int kZ0 = S + 1;              // index of Z_0 in the basis
 // A value's partial sums (one per block) are a row of the partials buffer
@@ -688,7 +693,7 @@ struct SsMultiArgs {
 };
 
 template <bool LARGE>
-__global__ __launch_bounds__(BS) void k_ss_multi(SsMultiArgs M) {
+__device__ __forceinline__ void multi_body(const SsMultiArgs& M) {
   extern __shared__ float dyn[];
   __shared__ double red[NGP];
   __shared__ double wred[(BS / 64) * NGP];
@@ -697,6 +702,14 @@ __global__ __launch_bounds__(BS) void k_ss_multi(SsMultiArgs M) {
   const int per = (int)(gridDim.x / nr) >> 3;
   const int k = blockIdx.x >> 3;
   ss_body<LARGE>(M.a[k % nr], (blockIdx.x & 7) * per + k / nr, dyn, red, wred, coef, dyn);
+}
+
+// The launch that re-reduces in every block fits its solves' blocks in one
+// round; the other runs three blocks per compute unit (at most 80 VGPRs).
+__global__ __launch_bounds__(BS) void k_ss_multi_small(SsMultiArgs M) { multi_body<false>(M); }
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(6))) void k_ss_multi_large(
+    SsMultiArgs M) {
+  multi_body<true>(M);
 }
 
 // Several meshes' solves in one launch (the server): the grid is the
@@ -839,6 +852,16 @@ __global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
 #pragma unroll
       for (int k = 0; k < w; ++k) h[k] += h[k + w];
     const double sum = row_sum(h[0]);
+    if (nb == 1) {  // one chunk: its sums are the totals
+      if (l == 0 && v < NG) {
+        tot[v] = sum;
+        Y.out[v] = sum;
+      }
+      __syncthreads();
+      if (t < 64 && (Y.force || Y.rec->phase == kIter))
+        ss_recur(tot, *Y.rec, *Y.prm, Y.force, Y.ctl);
+      return;
+    }
     if (l == 0 && v < NG) {
       __hip_atomic_store(&Y.level1[(size_t)b * NGP + v], sum, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -892,7 +915,9 @@ __global__ __launch_bounds__(kBlock) void k_ss_values(int n, const int32_t* __re
 }
 
 // ---------------------------------------------------------------- host ----
-SsArgs ss_args(fi_mesh* M, int par, int force) {
+// Launch arguments; `large`: the partials are summed by a reduction launch
+// (the step reads the totals and the coefficients it computed).
+SsArgs ss_args(fi_mesh* M, int par, int force, bool large) {
   SsState& Z = *M->ss;
   SsArgs A;
   A.n = (int)M->n;
@@ -911,7 +936,7 @@ SsArgs ss_args(fi_mesh* M, int par, int force) {
   A.x64a = Z.x64[0];
   A.x64b = Z.x64[1];
   A.xout = M->d_x64buf[0];
-  A.part_in = Z.large ? Z.red : Z.part + (size_t)par * NGP * A.gstride;
+  A.part_in = large ? Z.red : Z.part + (size_t)par * NGP * A.gstride;
   A.part_out = Z.part + (size_t)(par ^ 1) * NGP * A.gstride;
   A.rec_in = (const Rec*)M->d_rec + par;
   A.rec_out = (Rec*)M->d_rec + (par ^ 1);
@@ -970,16 +995,16 @@ int ss_reduce_after(fi_mesh* M, int par, int force) {
 
 int ss_launch_step(fi_mesh* M, int par, int force) {
   SsState& Z = *M->ss;
-  SsArgs A = ss_args(M, par, force);
+  SsArgs A = ss_args(M, par, force, Z.large);
   void* args[1] = {&A};
   void* fn = Z.large ? (void*)k_ss_step<true> : (void*)k_ss_step<false>;
   FI_HIP_TRY(hipLaunchKernel(fn, dim3(Z.grid), dim3(BS), args, ss_lds_bytes(Z), M->ctx->stream));
   return Z.large ? ss_reduce_after(M, par, force) : FI_OK;
 }
 
-int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0) {
+int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0, bool large) {
   SsState& Z = *M->ss;
-  SsArgs A = ss_args(M, 1, 0);  // writes record and partials of slot 0
+  SsArgs A = ss_args(M, 1, 0, large);  // writes record and partials of slot 0
   Params prm{};
   prm.rtol = o->rtol;
   prm.atol = o->atol;
@@ -993,19 +1018,19 @@ int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double*
   void* args[5] = {&A, &prm, &pout, &bnat, &x0};
   FI_HIP_TRY(hipLaunchKernel((void*)k_ss_start, dim3(Z.grid), dim3(BS), args, ss_lds_bytes(Z),
                              M->ctx->stream));
-  return Z.large ? ss_reduce_after(M, 1, 0) : FI_OK;
+  return large ? ss_reduce_after(M, 1, 0) : FI_OK;
 }
 
 // Both parities of the partial sums.
 size_t part_bytes(int grid) { return (size_t)2 * NGP * part_stride(grid) * sizeof(double); }
 
-// Large systems: the reduction launch's first-level sums, its counter (zero)
-// and the coefficient block.
+// The reduction launch's first-level sums, its counter (zero) and the
+// coefficient block (every mesh: multi-solve and batched launches may sum
+// a small system's partials that way too).
 int large_alloc(fi_mesh* M, SsState& Z) {
   Z.level1 = nullptr;
   Z.counter = nullptr;
   Z.ctl = nullptr;
-  if (!Z.large) return FI_OK;
   int rc = 0;
   if ((rc = device_alloc(M, (void**)&Z.level1, (size_t)gram_blocks(Z.grid) * NGP * 8)) ||
       (rc = device_alloc(M, (void**)&Z.counter, 256)) ||
@@ -1105,7 +1130,7 @@ void ss_release(fi_mesh* M) {
 int ss_solve(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const double* x0) {
   hipStream_t st = M->ctx->stream;
   const int epoch = next_epoch(M);
-  int rc = ss_launch_start(M, o, epoch, x0);
+  int rc = ss_launch_start(M, o, epoch, x0, M->ss->large);
   if (rc) return rc;
   const int slot = slot_of(x0);
   Pacer pc = make_pacer(o->max_inner, o->max_refine, M->pred_launches[slot]);
@@ -1141,23 +1166,30 @@ int ss_solve(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const do
 
 namespace {
 
-void* multi_fn(bool large) { return large ? (void*)k_ss_multi<true> : (void*)k_ss_multi<false>; }
-void* batch_fn(bool large) { return large ? (void*)k_ss_batch<true> : (void*)k_ss_batch<false>; }
+void* multi_fn(bool large) { return large ? (void*)k_ss_multi_large : (void*)k_ss_multi_small; }
 
 // Launch arguments of a multi-RHS step for both parities.
 struct SsMultiLaunch {
   SsMultiArgs a[2];
   SsRedArgs r[2];
+  bool large;
 };
 
-void ss_multi_prepare(fi_mesh* const* ch, int nc, int force, SsMultiLaunch& L) {
+// Multi-solve launches sum the partials in a reduction launch when their
+// blocks would not fit in one round otherwise.
+bool multi_large(fi_mesh* const* ch, int nc) {
+  return ch[0]->ss->large || (int64_t)nc * ch[0]->ss->grid > kSmallGrid;
+}
+
+void ss_multi_prepare(fi_mesh* const* ch, int nc, int force, bool large, SsMultiLaunch& L) {
+  L.large = large;
   for (int par = 0; par < 2; ++par) {
     L.a[par] = SsMultiArgs{};
     L.a[par].nrhs = nc;
     L.r[par] = SsRedArgs{};
     for (int c = 0; c < nc; ++c) {
-      L.a[par].a[c] = ss_args(ch[c], par, force);
-      if (ch[c]->ss->large) red_add(L.r[par], red_sys(ch[c], par, force));
+      L.a[par].a[c] = ss_args(ch[c], par, force, large);
+      if (large) red_add(L.r[par], red_sys(ch[c], par, force));
     }
   }
 }
@@ -1166,9 +1198,9 @@ int ss_multi_launch(fi_mesh* M0, SsMultiLaunch& L, int par) {
   SsState& Z = *M0->ss;
   void* args[1] = {&L.a[par]};
   const unsigned grid = (unsigned)L.a[par].nrhs * (unsigned)Z.grid;
-  FI_HIP_TRY(hipLaunchKernel(multi_fn(Z.large), dim3(grid), dim3(BS), args, ss_lds_bytes(Z),
+  FI_HIP_TRY(hipLaunchKernel(multi_fn(L.large), dim3(grid), dim3(BS), args, ss_lds_bytes(Z),
                              M0->ctx->stream));
-  return Z.large ? red_launch(L.r[par], M0->ctx->stream) : FI_OK;
+  return L.large ? red_launch(L.r[par], M0->ctx->stream) : FI_OK;
 }
 
 }  // namespace
@@ -1183,15 +1215,17 @@ int ss_solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve_
   int epoch[kMaxRhs];
   bool done[kMaxRhs] = {};
   int rc = FI_OK, first_rc = FI_OK;
+  // the mode stays for the whole solve, also once fewer channels are left
+  const bool large = multi_large(ch, nc);
   for (int c = 0; c < nc; ++c) {
     epoch[c] = next_epoch(ch[c]);
-    if ((rc = ss_launch_start(ch[c], o, epoch[c], x0 ? x0[c] : nullptr))) return rc;
+    if ((rc = ss_launch_start(ch[c], o, epoch[c], x0 ? x0[c] : nullptr, large))) return rc;
   }
   SsMultiLaunch L;
   fi_mesh* run[kMaxRhs];
   int nrun = nc;
   for (int c = 0; c < nc; ++c) run[c] = ch[c];
-  ss_multi_prepare(run, nrun, 0, L);
+  ss_multi_prepare(run, nrun, 0, large, L);
   int64_t pred = 0;
   bool every = true;
   for (int c = 0; c < nc; ++c) {
@@ -1224,7 +1258,7 @@ int ss_solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* o, fi_solve_
       if (!done[c]) run[left++] = ch[c];
     if (left < nrun) {
       nrun = left;
-      ss_multi_prepare(run, nrun, 0, L);
+      ss_multi_prepare(run, nrun, 0, large, L);
     }
     if (const int nq = pc.next()) {
       for (int q = 0; q < nq; ++q)
@@ -1256,12 +1290,13 @@ int ss_time_multi(fi_mesh* const* ch, int nc, int reps, double* ms) {
   fi_solve_opts o;
   fi_solve_opts_default(&o);
   int rc = FI_OK;
+  const bool large = multi_large(ch, nc);
   for (int c = 0; c < nc; ++c)
-    if ((rc = ss_launch_start(ch[c], &o, next_epoch(ch[c]), nullptr))) return rc;
+    if ((rc = ss_launch_start(ch[c], &o, next_epoch(ch[c]), nullptr, large))) return rc;
   SsMultiLaunch L;
-  ss_multi_prepare(ch, nc, 0, L);
+  ss_multi_prepare(ch, nc, 0, large, L);
   if ((rc = ss_multi_launch(M0, L, 0))) return rc;  // the initial bases
-  ss_multi_prepare(ch, nc, 1, L);
+  ss_multi_prepare(ch, nc, 1, large, L);
   hipEvent_t e0, e1;
   FI_HIP_TRY(hipEventCreate(&e0));
   FI_HIP_TRY(hipEventCreate(&e1));
@@ -1281,27 +1316,23 @@ int ss_time_multi(fi_mesh* const* ch, int nc, int reps, double* ms) {
 }
 
 // `count` (even) launches over the meshes in `ms` (all with the S-iteration
-// plan), parity 0 first: one launch per kind (small or large systems) and
-// per kSsArgSlots meshes, and for large systems one reduction launch after.
+// plan), parity 0 first: one launch per kSsArgSlots meshes, each followed by
+// its reduction launch. Batched solves always sum their partials in the
+// reduction launch (armed so by ss_arm), whatever the batch holds, so a
+// solve's mode never depends on its neighbours; for systems of up to
+// kSmallGrid blocks that gives the bits of the single-solve launch.
 int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) {
   struct Launch {
     SsBatchArgs b[2];
     SsRedArgs r[2];
     int64_t grid;
-    bool large;
     size_t lds;
   };
-  std::vector<fi_mesh*> order(ms);
-  std::stable_sort(order.begin(), order.end(),
-                   [](fi_mesh* a, fi_mesh* b) { return (int)a->ss->large < (int)b->ss->large; });
+  const std::vector<fi_mesh*>& order = ms;
   std::vector<Launch> L;
   for (size_t j0 = 0; j0 < order.size();) {
     Launch l{};
-    size_t j1 = j0;
-    while (j1 < order.size() && j1 - j0 < (size_t)kSsArgSlots &&
-           order[j1]->ss->large == order[j0]->ss->large)
-      ++j1;
-    l.large = order[j0]->ss->large;
+    const size_t j1 = std::min(order.size(), j0 + (size_t)kSsArgSlots);
     int64_t total = 0;
     for (int par = 0; par < 2; ++par) l.b[par].n = (int)(j1 - j0);
     for (size_t j = j0; j < j1; ++j) {
@@ -1309,8 +1340,8 @@ int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) 
       const int q = (int)(j - j0);
       for (int par = 0; par < 2; ++par) {
         l.b[par].start[q] = (int32_t)total;
-        l.b[par].a[q] = ss_args(M, par, 0);
-        if (l.large) red_add(l.r[par], red_sys(M, par, 0));
+        l.b[par].a[q] = ss_args(M, par, 0, true);
+        red_add(l.r[par], red_sys(M, par, 0));
       }
       total += M->ss->grid;
       l.lds = std::max(l.lds, ss_lds_bytes(*M->ss));
@@ -1325,11 +1356,10 @@ int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) 
     const int par = k & 1;
     for (Launch& l : L) {
       void* args[1] = {&l.b[par]};
-      FI_HIP_TRY(hipLaunchKernel(batch_fn(l.large), dim3((unsigned)l.grid), dim3(BS), args, l.lds,
-                                 st));
+      FI_HIP_TRY(hipLaunchKernel((void*)k_ss_batch<true>, dim3((unsigned)l.grid), dim3(BS), args,
+                                 l.lds, st));
     }
     for (Launch& l : L) {
-      if (!l.large) continue;
       const int rc = red_launch(l.r[par], st);
       if (rc) return rc;
     }
@@ -1338,7 +1368,7 @@ int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) 
 }
 
 int ss_arm(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0) {
-  return ss_launch_start(M, o, epoch, x0);
+  return ss_launch_start(M, o, epoch, x0, true);  // batched solves: ss_batch_launch
 }
 
 // A channel view's own vectors, with the parent's plan and diagonal.
@@ -1395,7 +1425,7 @@ int ss_time_kernel(fi_mesh* M, int reps, double* ms) {
   hipStream_t st = M->ctx->stream;
   fi_solve_opts o;
   fi_solve_opts_default(&o);
-  int rc = ss_launch_start(M, &o, next_epoch(M), nullptr);
+  int rc = ss_launch_start(M, &o, next_epoch(M), nullptr, M->ss->large);
   if (rc) return rc;
   if ((rc = ss_launch_step(M, 0, 0))) return rc;  // the initial basis
   hipEvent_t e0, e1;
