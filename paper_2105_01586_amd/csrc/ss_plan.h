@@ -11,10 +11,12 @@
 //     graph distance 1, 2, ..., S from them (ascending within each ring),
 //     listed in full (own rows included) so that a region row is one load;
 //   - a local matrix for the rows of its region at distance <= S - 1: for
-//     each such row, up to 8 entries, each the local index of the neighbour
-//     (bits 0-13), bit 14 for padding (the entry then points at the row
-//     itself with weight 0), bit 15 for weight -1 (clear: -1/2). On the
-//     quadtree mesh every off-diagonal entry of K_FF is -1/2 or -1.
+//     each such row, 8 entries, each the neighbour's slot (bits 0-13: its
+//     local index + 1; slot 0 is a zero the launch keeps in front of its
+//     region values, so every entry is one unconditional load), bit 15 for
+//     weight -1 (clear: -1/2), bit 14 marking padding (slot 0, weight bit
+//     clear). On the quadtree mesh every off-diagonal entry of K_FF is -1/2
+//     or -1.
 // Rows of a block are [b * BS, min(n, (b + 1) * BS)) in the new order.
 //
 // Inputs come from the library's column-major ELL of K_FF (natural order):
@@ -30,7 +32,7 @@
 namespace fi {
 
 constexpr int kPlanLocalBits = 14;
-constexpr int32_t kPlanLocalMax = 1 << kPlanLocalBits;  // region rows per block, at most
+constexpr int32_t kPlanLocalMax = 1 << kPlanLocalBits;  // slots: region rows per block + 1, at most
 constexpr uint16_t kPlanPad = 1u << 14;
 constexpr uint16_t kPlanMinusOne = 1u << 15;
 constexpr int kPlanSlots = 8;  // entries per local matrix row
@@ -73,7 +75,7 @@ inline uint64_t morton_key(uint32_t x, uint32_t y) {
 
 // Builds the plan. xy: lattice coordinates of the free rows (natural order,
 // 2 per row); ell: the ELL copy described above (W slots). Returns false if
-// a region exceeds max_region rows (at most kPlanLocalMax) or a row has more
+// a region exceeds max_region rows (below kPlanLocalMax) or a row has more
 // than kPlanSlots entries (the caller then keeps the one-iteration launch).
 inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int32_t* ell,
                           int64_t n_pad, int W, int threads, int max_region, SsPlan& out) {
@@ -81,7 +83,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   out.S = S;
   out.BS = BS;
   out.n = n;
-  if (n <= 0 || W > kPlanSlots || S < 1 || max_region > kPlanLocalMax || max_region < BS)
+  if (n <= 0 || W > kPlanSlots || S < 1 || max_region >= kPlanLocalMax || max_region < BS)
     return false;
   // Z-order of the free rows. The lattice runs from 0 to N (a power of two),
   // and its last row and column would take a bit of their own in the key,
@@ -193,9 +195,9 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
           const int64_t i = reg[l];
           for (int k = 0; k < kPlanSlots; ++k) {
             const int32_t c = nb[(size_t)i * kPlanSlots + k];
-            uint16_t e = (uint16_t)(kPlanPad | (uint16_t)l);
+            uint16_t e = kPlanPad;  // the zero slot
             if (c >= 0)
-              e = (uint16_t)((uint16_t)tval[slot(c)] |
+              e = (uint16_t)((uint16_t)(tval[slot(c)] + 1) |
                              (nbw[(size_t)i * kPlanSlots + k] ? kPlanMinusOne : 0));
             P.lmat[(size_t)l * kPlanSlots + k] = e;
           }

@@ -108,8 +108,10 @@ struct SsArgs {
   int force;           // timing only: always iterate
 };
 
+// -1 or -1/2 from bit 15 (the bit pattern of -1/2 with its exponent raised
+// by one); a padding entry points at the zero slot, so its weight is moot.
 __device__ __forceinline__ float lm_weight(uint32_t e) {
-  return (e & kPlanPad) ? 0.0f : ((e & kPlanMinusOne) ? -1.0f : -0.5f);
+  return __uint_as_float(0xBF000000u | ((e & kPlanMinusOne) << 8));
 }
 
 __device__ __forceinline__ uint32_t lm_entry(const uint4& m, int k) {
@@ -123,15 +125,16 @@ __device__ __forceinline__ int region_row(const SsArgs& A, const BlockPlan& B, i
   return A.region[B.reg_off + l];
 }
 
-// sum_k w_k v[idx_k] over one local matrix row, for p and z at once
-// (FP32, slot order; v holds (p, z) per region row).
-__device__ __forceinline__ float2 lm_apply(const uint4& m, const float2* v) {
+// sum_k w_k vs[idx_k] over one local matrix row, for p and z at once
+// (FP32, slot order; vs holds (p, z) per LDS slot: 0 the zero slot, l + 1
+// region row l).
+__device__ __forceinline__ float2 lm_apply(const uint4& m, const float2* vs) {
   float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
   for (int k = 0; k < kPlanSlots; ++k) {
     const uint32_t e = lm_entry(m, k);
     const float w = lm_weight(e);
-    const float2 x = v[e & (kPlanLocalMax - 1)];
+    const float2 x = vs[e & (kPlanLocalMax - 1)];
     acc.x = __builtin_fmaf(w, x.x, acc.x);
     acc.y = __builtin_fmaf(w, x.y, acc.y);
   }
@@ -226,11 +229,15 @@ __device__ __forceinline__ double row_sum(double v) {
 
 // The block's partial Gram sums G_ab = sum over its rows of d w_a w_b, on
 // the FP64 matrix cores: each wave stages its 64 rows' values (and d) in LDS
-// and adds W' (D W) over them with 16 products of 16 x 4 by 4 x 16 (lane l
-// supplies element (row 4 m + l / 16, value l % 16); values 7..15 are 0;
-// the products of FP32 values and the small half-integer d are exact in
-// FP64); the waves' sums are then added in wave order. Returns value v's
-// total in thread 16 v (v < NG), 0 elsewhere. wst: BS x 8 floats; wg: 8 x NGP.
+// and adds W' (D W) over them with 8 products of 16 x 4 by 4 x 16. Each
+// product takes two groups of four rows: lane l supplies element (row
+// 8 m + 4 h + l / 16, value c) with h = (l % 16) / 8, c = l % 8, so the
+// first group's sums land in the 8 x 8 block at (0, 0) of the product and
+// the second group's in the block at (8, 8) (the other blocks mix the two
+// groups and are not used); values 7 and 15 are 0. The products of FP32
+// values and the small half-integer d are exact in FP64. The waves' sums
+// are then added in wave order. Returns value v's total in thread 16 v
+// (v < NG), 0 elsewhere. wst: BS x 8 floats; wg: 8 x NGP.
 __device__ __forceinline__ double block_gram(const float (&w)[NB], float dd, float* wst,
                                              double* wg) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -239,29 +246,31 @@ __device__ __forceinline__ double block_gram(const float (&w)[NB], float dd, flo
   st[0] = make_float4(w[0], w[1], w[2], w[3]);
   st[1] = make_float4(w[4], w[5], w[6], dd);
   __builtin_amdgcn_wave_barrier();  // each wave reads only its own rows
-  const int col = lane & 15, kq = lane >> 4;
+  const int col = lane & 15, kq = lane >> 4, h = col >> 3, c = col & 7;
   // all operands first (unconditional reads, masked after), then the products
-  float xv[16], dv[16];
-  const int cc = col < NB ? col : 0;
+  float xv[8], dv[8];
+  const int cc = c < NB ? c : 0;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const float* row = wst + 8 * (64 * wave + 4 * m + kq);
+  for (int m = 0; m < 8; ++m) {
+    const float* row = wst + 8 * (64 * wave + 8 * m + 4 * h + kq);
     xv[m] = row[cc];
     dv[m] = row[7];
   }
   d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const double a = col < NB ? (double)xv[m] : 0.0;
+  for (int m = 0; m < 8; ++m) {
+    const double a = c < NB ? (double)xv[m] : 0.0;
     const double b = (double)dv[m] * a;
     if (m & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc1, 0, 0, 0);
     else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc0, 0, 0, 0);
   }
-  // lane l holds D[4 v + l / 16][l % 16] in element v
+  // lane l holds D[4 v + l / 16][l % 16] in element v: G[i][j] = D[i][j] +
+  // D[8 + i][8 + j], the second term from lane l + 8 (row rotation by 8)
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
+    const double g = (acc0[v] + acc1[v]) + dpp_move<0x128>(acc0[v + 2] + acc1[v + 2]);
     const int i = 4 * v + kq, j = col;
-    if (i <= j && j < NB) wg[wave * NGP + gi(i, j)] = acc0[v] + acc1[v];
+    if (i <= j && j < NB) wg[wave * NGP + gi(i, j)] = g;
   }
   __syncthreads();
   const int v = t >> 4;
@@ -378,12 +387,20 @@ __device__ __forceinline__ uint4 lm_at(const SsArgs& A, const BlockPlan& B, cons
 
 // The next basis from level 0 (pz0 = (p, z) on the whole region, ld =
 // D^-1), in LDS: round k computes level k on the rows within S - k hops.
-// Returns the own row's seven values (thread t: row t, zeros past nown).
+// pz0 and pz1 point at region row 0 of their slot arrays, whose slot 0 (at
+// index -1) holds zeros. Returns the own row's seven values (thread t: row
+// t, zeros past nown).
 __device__ __forceinline__ void build_basis(const SsArgs& A, const BlockPlan& B, const Pre& R,
                                             float2* pz0, float2* pz1, const float* ld,
                                             float (&w)[NB]) {
   const int t = threadIdx.x;
   const bool own = t < B.nown;
+  const float2* s0 = pz0 - 1;
+  const float2* s1 = pz1 - 1;
+  if (t == 0) {
+    pz0[-1] = make_float2(0.f, 0.f);
+    pz1[-1] = make_float2(0.f, 0.f);
+  }
   float2 l0 = make_float2(0.f, 0.f), l1 = l0, l2 = l0;
   float p3 = 0.0f;
   __syncthreads();
@@ -391,7 +408,7 @@ __device__ __forceinline__ void build_basis(const SsArgs& A, const BlockPlan& B,
   for (int l = t, k = 0; l < B.ninner; l += BS, ++k) {
     const uint4 m = lm_at(A, B, R, l, k);
     const float dv = ld[l];
-    const float2 acc = lm_apply(m, pz0);
+    const float2 acc = lm_apply(m, s0);
     pz1[l] = make_float2(dv * acc.x, dv * acc.y);
   }
   __syncthreads();
@@ -404,7 +421,7 @@ __device__ __forceinline__ void build_basis(const SsArgs& A, const BlockPlan& B,
   for (int l = t, k = 0; l < B.n1; l += BS, ++k) {
     const uint4 m = lm_at(A, B, R, l, k);
     const float dv2 = 2.0f * ld[l];
-    const float2 acc = lm_apply(m, pz1);
+    const float2 acc = lm_apply(m, s1);
     const float2 old = pz0[l];
     pz0[l] = make_float2(__builtin_fmaf(dv2, acc.x, -old.x), __builtin_fmaf(dv2, acc.y, -old.y));
   }
@@ -412,7 +429,7 @@ __device__ __forceinline__ void build_basis(const SsArgs& A, const BlockPlan& B,
   // level 3 of p on the own rows
   if (own) {
     l2 = pz0[t];
-    p3 = __builtin_fmaf(2.0f * ld[t], lm_apply(R.m[0], pz0).x, -l1.x);
+    p3 = __builtin_fmaf(2.0f * ld[t], lm_apply(R.m[0], s0).x, -l1.x);
   }
   w[0] = l0.x;
   w[1] = l1.x;
@@ -526,10 +543,11 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
   const double* Gsrc = LARGE ? A.part_in : red;
   const int phase = A.force ? (int)kIter : Rin.phase;
   const bool writer = lb == 0 && t == 0;
+  // LDS: two slot arrays of (p, z) (zero slot, then the region rows), D^-1
   const int RM = A.blocks[0].pad0;  // region rows the LDS is laid out for
-  float2* pz0 = (float2*)dyn;
-  float2* pz1 = (float2*)(dyn + 2 * RM);
-  float* ld = dyn + 4 * RM;
+  float2* pz0 = (float2*)dyn + 1;
+  float2* pz1 = (float2*)dyn + RM + 2;
+  float* ld = dyn + 4 * (RM + 1);
   const float dinv_own = R.b[0].w;
 
   if (phase >= kDoneOk) {  // a launch queued after the end: carry the record
@@ -621,7 +639,8 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
     // then r64 = b - K x64 on the own rows (FP64), and ||r64||^2.
     const double* xo64 = Rin.xp ? A.x64b : A.x64a;
     double* xn64 = Rin.xp ? A.x64a : A.x64b;
-    double* lx = (double*)dyn;
+    double* lx = (double*)dyn + 1;  // slot array, zero slot at -1
+    if (t == 0) lx[-1] = 0.0;
     const double sc = Rin.rnorm;
     for (int l = t, k = 0; l < B.n1; l += BS, ++k) {
       const int i = row_at(A, B, base, R, l, k);
@@ -638,7 +657,7 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
 #pragma unroll
       for (int k = 0; k < kPlanSlots; ++k) {
         const uint32_t e = lm_entry(R.m[0], k);
-        acc = __builtin_fma((double)lm_weight(e), lx[e & (kPlanLocalMax - 1)], acc);
+        acc = __builtin_fma((double)lm_weight(e), lx[(int)(e & (kPlanLocalMax - 1)) - 1], acc);
       }
       const double ri = A.b[ro] - acc;
       xn64[ro] = xi;
@@ -758,8 +777,9 @@ __global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* p
   const int base = lb * BS;
   const bool own = t < B.nown;
   const int ro = own ? base + t : 0;
-  double* lx = (double*)dyn;
+  double* lx = (double*)dyn + 1;  // slot array, zero slot at -1
   if (x0) {
+    if (t == 0) lx[-1] = 0.0;
     for (int l = t; l < B.n1; l += BS) lx[l] = x0[A.perm[region_row(A, B, base, l)]];
     __syncthreads();
   }
@@ -774,7 +794,7 @@ __global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* p
 #pragma unroll
       for (int k = 0; k < kPlanSlots; ++k) {
         const uint32_t e = lm_entry(m, k);
-        acc = __builtin_fma((double)lm_weight(e), lx[e & (kPlanLocalMax - 1)], acc);
+        acc = __builtin_fma((double)lm_weight(e), lx[(int)(e & (kPlanLocalMax - 1)) - 1], acc);
       }
       ri = bi - acc;
     }
@@ -981,10 +1001,11 @@ int red_launch(const SsRedArgs& R, hipStream_t st) {
   return FI_OK;
 }
 
-// Dynamic LDS of a launch: the basis levels (5 floats per region row), and
-// at least room for the rows' values staged for the matrix cores.
+// Dynamic LDS of a launch: the basis levels (5 floats per region row, and
+// the two zero slots), and at least room for the rows' values staged for
+// the matrix cores.
 size_t ss_lds_bytes(const SsState& Z) {
-  return std::max((size_t)5 * Z.max_region * sizeof(float), (size_t)BS * 8 * sizeof(float));
+  return std::max((size_t)(5 * Z.max_region + 4) * sizeof(float), (size_t)BS * 8 * sizeof(float));
 }
 
 int ss_reduce_after(fi_mesh* M, int par, int force) {

@@ -26,7 +26,7 @@ int main(int argc, char** argv) {
   if (!ok) return 2;
   fi::SsPlan plan;
   const int32_t built = fi::build_ss_plan(S, BS, n, xy.data(), ell.data(), n_pad, W, threads,
-                                             fi::kPlanLocalMax, plan);
+                                             fi::kPlanLocalMax - 1, plan);
   FILE* o = std::fopen(argv[2], "wb");
   if (!o) return 2;
   std::fwrite(&built, 4, 1, o);

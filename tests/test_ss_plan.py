@@ -4,8 +4,8 @@ with g++ and run on the oracle's K_FF (CPU only).
 Checks, per block: the own rows are the block's slice of a Z-order numbering
 of the free rows (last lattice row and column clamped onto the one before); the region holds exactly the rows within S hops of them,
 in rings of increasing distance; every local matrix row decodes to that
-row's entries of K_FF (neighbour and weight -1/2 or -1, padding pointing at
-the row itself). Then the Chebyshev basis the launch builds from region data
+row's entries of K_FF (neighbour slot and weight -1/2 or -1, padding pointing
+at the zero slot). Then the Chebyshev basis the launch builds from region data
 alone (rho_0 = v, rho_1 = D^-1 A_off v, rho_k+1 = 2 D^-1 A_off rho_k - rho_k-1)
 is compared, on every block's own rows, with the same basis computed on the
 whole system: S levels must agree to rounding.
@@ -144,9 +144,10 @@ def check_plan(plan, K_FF, xy, S, BS):
             for e in lm[l]:
                 e = int(e)
                 if e & PAD:
-                    assert e & 0x3FFF == l and not e & M1
+                    assert e & 0x3FFF == 0 and not e & M1
                     continue
-                got[int(reg[e & 0x3FFF])] = -1.0 if e & M1 else -0.5
+                assert e & 0x3FFF >= 1
+                got[int(reg[(e & 0x3FFF) - 1])] = -1.0 if e & M1 else -0.5
             assert got == want, (b, l)
         regions.append(reg)
     return Aoff, regions
@@ -166,11 +167,13 @@ def check_basis(plan, Aoff, regions, d, S, seed=0):
             continue
         _, lmat_off, nown, _, ninner, nreg = plan["blocks"][b][:6]
         lm = plan["lmat"][lmat_off:lmat_off + ninner].astype(np.int64)
+        # as the launch evaluates it: every entry one load from the slot
+        # array (slot 0 a zero, slot l + 1 region row l), weight from bit 15
         idx = lm & 0x3FFF
-        w = np.where(lm & PAD, 0.0, np.where(lm & M1, -1.0, -0.5))
+        w = np.where(lm & M1, -1.0, -0.5)
         lev = [v[reg]]
         for k in range(S):
-            prev = lev[-1]
+            prev = np.concatenate([[0.0], lev[-1]])
             nxt = np.full(nreg, np.nan)
             t = dinv[reg[:ninner]] * (w * prev[idx]).sum(axis=1)
             nxt[:ninner] = t if k == 0 else 2.0 * t - lev[-2][:ninner]
