@@ -892,17 +892,20 @@ __global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
   if (t == 0) last = atomicAdd(Y.counter, 1) == nb - 1;
   __syncthreads();
   if (!last) return;
-  __threadfence();
+  __threadfence();  // acquire: the other blocks' first-level sums are visible
   double acc = 0.0;
   for (int q0 = 0; q0 < nb; q0 += 256) {
+    // plain loads, issued together (atomic loads would be waited for one
+    // by one); clamped in range, the values past nb masked after
+    const double* l1 = Y.level1 + vv;
     double h[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int q = q0 + l + 16 * k;
-      h[k] = q < nb ? __hip_atomic_load(&Y.level1[(size_t)q * NGP + vv], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT)
-                    : 0.0;
+      h[k] = l1[(size_t)(q < nb ? q : 0) * NGP];
     }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) h[k] = (q0 + l + 16 * k < nb) ? h[k] : 0.0;
 #pragma unroll
     for (int w = 8; w >= 1; w >>= 1)
 #pragma unroll
