@@ -873,6 +873,7 @@ def main():
         "tonal_ms": ton_mean,
         "tonal_solves_per_s": 1000.0 / ton_mean,
         "cg_iterations_inpaint": st["iterations"],
+        "launches_inpaint": st["launches"],
         "refinements_inpaint": st["refinements"],
         "rel_residual_inpaint": st["rel_residual"],
         "rtol_inpaint": inner_inp.rtol, "residual_inpaint": st["residual"],

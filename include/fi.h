@@ -94,6 +94,10 @@ typedef struct fi_solve_stats {
   double rel_residual; /* final ||b - K_FF x||_2 / ||b||_2 in FP64 */
   double residual;     /* final ||b - K_FF x||_2 in FP64 */
   double rhs_norm;     /* ||b||_2 */
+  int64_t launches;    /* step launches until the solve ended (the start launch
+                          and launches queued past the end not counted; each
+                          advances up to fi_mesh_info.cg_iters_per_launch
+                          iterations, or applies a refinement) */
 } fi_solve_stats;
 
 typedef struct fi_tonal_opts {

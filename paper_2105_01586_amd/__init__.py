@@ -71,7 +71,8 @@ class _SolveOpts(ctypes.Structure):
 class _SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("refinements", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("residual", ctypes.c_double), ("rhs_norm", ctypes.c_double)]
+                ("residual", ctypes.c_double), ("rhs_norm", ctypes.c_double),
+                ("launches", ctypes.c_int64)]
 
 
 class _TonalOpts(ctypes.Structure):

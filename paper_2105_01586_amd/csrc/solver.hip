@@ -1027,6 +1027,7 @@ int read_mirror(fi_mesh* M, int epoch, fi_solve_stats* stats, int* rc, int64_t* 
   int64_t nl;
   __atomic_load(&m->launches, &nl, __ATOMIC_RELAXED);
   if (launches) *launches = nl;
+  stats->launches = nl;
   __atomic_load(&m->rnorm, &rn, __ATOMIC_RELAXED);
   __atomic_load(&m->bnorm, &bn, __ATOMIC_RELAXED);
   stats->rel_residual = bn > 0 ? rn / bn : 0.0;
@@ -1048,6 +1049,7 @@ int solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_
     stats[c].rel_residual = 0.0;
     stats[c].residual = 0.0;
     stats[c].rhs_norm = 0.0;
+    stats[c].launches = 0;
   }
   if (ch[0]->n == 0) return FI_OK;
   if (opts->precision == FI_PREC_FP64) return solve_multi_dev<double>(ch, nc, opts, stats, x0);
@@ -1306,6 +1308,7 @@ int solve_free(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats, con
   stats->rel_residual = 0.0;
   stats->residual = 0.0;
   stats->rhs_norm = 0.0;
+  stats->launches = 0;
   if (M->n == 0) return FI_OK;
   if (opts->precision == FI_PREC_FP64) return solve_dev<double>(M, opts, stats, x0);
   if (M->ss) return ss_solve(M, opts, stats, x0);

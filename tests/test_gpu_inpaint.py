@@ -190,6 +190,44 @@ def test_large_launch_shape_parity(ctx, precision, monkeypatch):
     M.close()
 
 
+def test_three_iterations_per_launch(ctx, monkeypatch):
+    """The FP32 solve on the quadtree mesh advances three CG iterations per
+    launch: the 512^2 solve takes at least 1.8 times fewer launches than
+    the one-iteration launch (FI_CG_SSTEP=0), both within the pixel bar."""
+    side, mask, f = case("c2")
+    ref = oracle_inpaint("c2")
+    M3 = gpu_mesh(ctx, "c2")
+    monkeypatch.setenv("FI_CG_SSTEP", "0")
+    M1 = fi.Mesh(ctx, side, mask)
+    monkeypatch.delenv("FI_CG_SSTEP")
+    assert M3.info["cg_iters_per_launch"] == 3 and M1.info["cg_iters_per_launch"] == 1
+    u3, st3 = M3.inpaint(f=dev(f))
+    u1, st1 = M1.inpaint(f=dev(f))
+    M1.close()
+    print(f"  launches {st3['launches']} (3 per launch) against {st1['launches']}; "
+          f"iterations {st3['iterations']} / {st1['iterations']}")
+    for u in (u3, u1):
+        assert np.max(np.abs(u.cpu().numpy() - ref)) <= PIX_TOL
+    assert st3["launches"] > 0 and 1.8 * st3["launches"] <= st1["launches"]
+
+
+def test_reduction_launch_same_bits_up_to_256_blocks(ctx, monkeypatch):
+    """Up to 256 blocks the reduction launch (used by batched and multi-solve
+    launches) sums the Gram partials in the order the blocks themselves use,
+    so a solve gives the same bits either way."""
+    side, mask, f = case("c2")
+    M = gpu_mesh(ctx, "c2")
+    assert M.info["cg_blocks"] <= 256 and not M.large_mode()
+    monkeypatch.setenv("FI_CG_LARGE", "1")
+    ML = fi.Mesh(ctx, side, mask)
+    monkeypatch.delenv("FI_CG_LARGE")
+    assert ML.large_mode()
+    u, st = M.inpaint(f=dev(f))
+    uL, stL = ML.inpaint(f=dev(f))
+    ML.close()
+    assert torch.equal(u, uL) and st["iterations"] == stL["iterations"]
+
+
 @pytest.mark.parametrize("bs", ["256", "512"])
 def test_block_sizes_agree(ctx, bs, monkeypatch):
     monkeypatch.setenv("FI_CG_BLOCK", bs)
