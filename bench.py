@@ -898,7 +898,10 @@ def main():
         # launches: its own byte count over the same time is its HBM use.
         out["roofline"]["kernel_model_GBs"] = mb / (kms * 1e-3) / 1e9
         out["roofline"]["kernel_model_frac"] = mb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    # the mesh's memory after assembly, and after the run (state the first
+    # FP64 solve and the first tonal optimisation allocate included)
     out["device_memory_gb"] = {"mesh_and_solver": mesh.info["device_bytes"] / 1e9,
+                               "mesh_and_solver_after_run": mesh.device_bytes() / 1e9,
                                "torch_peak": torch.cuda.max_memory_allocated() / 1e9,
                                "device_used_peak": peak_used[0] / 1e9}
     if fd_res is not None:

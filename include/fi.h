@@ -541,6 +541,10 @@ int fi_cg_multi_kernel_bytes(const fi_mesh* mesh, int nrhs, int precision, int64
  *
  * Device memory: one allocation of hbm_budget bytes at creation (the arena);
  * requests take and return parts of it without further device allocation.
+ * Admission by footprint: a request becomes resident once one contiguous
+ * region of its footprint bound is free in the arena; its mesh and buffers
+ * are carved out of that region, which returns to the arena when the
+ * request finishes (arena_used_bytes counts whole regions).
  * All request data is copied at submission, so the caller's buffers (except
  * g_out) may be reused at once. */
 typedef struct fi_server fi_server;
@@ -573,7 +577,8 @@ typedef struct fi_job_result {
   int64_t inner_iterations; /* CG iterations of all the request's solves */
   double t_submit, t_admit, t_start, t_done; /* seconds on the server clock:
                             submitted, mesh uploaded, resident, finished */
-  int64_t device_bytes;   /* arena bytes the request held */
+  int64_t device_bytes;   /* bytes of its region the request's mesh and
+                             buffers took (at most footprint_bound) */
   int64_t footprint_bound; /* its admission bound */
   char error[128];        /* message when status != FI_OK */
 } fi_job_result;

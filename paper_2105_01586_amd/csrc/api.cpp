@@ -88,8 +88,9 @@ namespace {
 
 #define TRY(x) do { rc = (x); if (rc) return rc; } while (0)
 
-// Vectors of one right-hand side: the solve's b, iterate and residual, the
-// CG vectors of both precisions, and the per-pixel / per-vertex work vectors.
+// Vectors of one right-hand side: the solve's b, iterate and residual and
+// the per-pixel / per-vertex work vectors (the one-iteration CG vectors are
+// allocated by their first solve).
 int alloc_rhs_space(fi_mesh* M) {
   int rc = 0;
   const int64_t n = M->n, m = M->m, V = M->V, T = M->T;
@@ -98,14 +99,9 @@ int alloc_rhs_space(fi_mesh* M) {
   TRY(alloc_n(M, &M->d_x64buf[1], n));
   M->d_x64 = M->d_x64buf[0];
   TRY(alloc_n(M, &M->d_r64, n));
-  float* f32[4];
-  double* f64[4];
-  for (int k = 0; k < 2; ++k) TRY(alloc_n(M, &f32[k], n));
-  for (int k = 2; k < 4; ++k) TRY(alloc_n(M, &f32[k], 4 * n));  // (r, s, q, D^-1) records
-  for (int k = 0; k < 2; ++k) TRY(alloc_n(M, &f64[k], n));
-  for (int k = 2; k < 4; ++k) TRY(alloc_n(M, &f64[k], 4 * n));
-  M->cg32 = CGState{f32[0], f32[1], {f32[2], f32[3]}};
-  M->cg64 = CGState{f64[0], f64[1], {f64[2], f64[3]}};
+  // the one-iteration CG vectors come with the first solve that uses them
+  M->cg32 = CGState{};
+  M->cg64 = CGState{};
   TRY(alloc_n(M, &M->d_red, kMaxGrid));
   TRY(alloc_n(M, &M->d_red_out, 8));
   TRY(alloc_n(M, &M->d_uvert, V));

@@ -86,7 +86,8 @@ struct DevBuf {
 class Arena {
  public:
   int init(int device, size_t bytes);  // one hipMalloc of `bytes`
-  void release();                      // hipFree of the whole block
+  void init_view(void* base, size_t bytes);  // over memory another arena owns
+  void release();                      // hipFree of the whole block (if owned)
   void* alloc(size_t bytes);           // nullptr when no free range fits
   void free(void* p);
   size_t capacity() const { return cap_; }
@@ -96,6 +97,7 @@ class Arena {
  private:
   mutable std::mutex mu_;
   char* base_ = nullptr;
+  bool owned_ = false;
   size_t cap_ = 0, used_ = 0, peak_ = 0;
   std::map<size_t, size_t> free_;   // offset -> bytes
   std::map<size_t, size_t> live_;   // offset -> bytes

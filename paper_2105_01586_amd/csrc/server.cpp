@@ -50,6 +50,7 @@ int Arena::init(int device, size_t bytes) {
   }
   std::lock_guard<std::mutex> lk(mu_);
   base_ = (char*)p;
+  owned_ = true;
   cap_ = bytes;
   used_ = peak_ = 0;
   free_.clear();
@@ -58,10 +59,22 @@ int Arena::init(int device, size_t bytes) {
   return FI_OK;
 }
 
+void Arena::init_view(void* base, size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu_);
+  base_ = (char*)base;
+  owned_ = false;
+  cap_ = bytes & ~(size_t)255;
+  used_ = peak_ = 0;
+  free_.clear();
+  live_.clear();
+  if (cap_) free_[0] = cap_;
+}
+
 void Arena::release() {
   std::lock_guard<std::mutex> lk(mu_);
-  if (base_) (void)hipFree(base_);
+  if (base_ && owned_) (void)hipFree(base_);
   base_ = nullptr;
+  owned_ = false;
   cap_ = used_ = 0;
   free_.clear();
   live_.clear();
@@ -187,7 +200,13 @@ struct Job {
   uint8_t* d_f = nullptr;
   double* d_g = nullptr;
   double* h_out = nullptr;  // pinned: g (m), then the CGLS scalars (8)
-  int64_t reserved = 0;
+  // The request's device memory: one contiguous region of the server's
+  // arena, as large as the footprint bound, taken at admission; the mesh
+  // and the request's buffers are carved out of it (sub), so a request never
+  // waits for or fails on memory once admitted, whatever the arena's
+  // fragmentation, and memory the solver allocates on first use is there.
+  void* region = nullptr;
+  std::unique_ptr<Arena> sub;
   Cgls c;
   int slot = -1;
   bool solving = false, advance = false, finished = false, done = false;
@@ -220,7 +239,6 @@ struct fi_server {
   std::deque<fi::Job*> ready;        // uploaded, waiting for a slot
   std::deque<fi::Job*> reap;         // finished: pinned buffers to free
   std::unordered_map<uint64_t, fi::Job*> jobs;
-  int64_t reserved = 0;              // footprint bounds of uploads in progress
   uint64_t next_ticket = 1;
   bool stopping = false;
   int in_flight = 0;                 // submitted and not yet finished
@@ -275,26 +293,17 @@ int build_job(fi_server* S, Job* J) {
   J->bound = bound;
   if (bound > (int64_t)S->arena.capacity())
     return fail(FI_E_NOMEM, "request needs more device memory than the server's budget");
-  {  // admission: wait until the bound fits beside what is resident
+  {  // admission: wait until a contiguous region of the bound is free
     std::unique_lock<std::mutex> lk(S->mu);
-    S->cv_build.wait(lk, [&] {
-      return S->reserved + (int64_t)S->arena.used() + bound <= (int64_t)S->arena.capacity();
-    });
-    S->reserved += bound;
+    S->cv_build.wait(lk, [&] { return (J->region = S->arena.alloc((size_t)bound)) != nullptr; });
   }
-  auto unreserve = [&] {
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->reserved -= bound;
-    S->cv_build.notify_all();
-  };
+  J->sub.reset(new Arena());
+  J->sub->init_view(J->region, ((size_t)bound + 255) & ~(size_t)255);
   fi_mesh* M = nullptr;
   hm = keep.release();
-  rc = mesh_upload(&S->ctx_build, &hm, &S->arena, &M);
+  rc = mesh_upload(&S->ctx_build, &hm, J->sub.get(), &M);
   if (hm) fi_host_mesh_destroy(hm);
-  if (rc) {
-    unreserve();
-    return rc;
-  }
+  if (rc) return rc;
   J->M = M;
   J->c.M = M;
   rc = device_alloc(M, (void**)&J->d_f, (size_t)M->P);
@@ -310,7 +319,6 @@ int build_job(fi_server* S, Job* J) {
     if (e != hipSuccess) rc = fail(FI_E_HIP, hipGetErrorString(e));
   }
   J->device_bytes = M->device_bytes;
-  unreserve();
   if (rc) return rc;
   std::vector<uint8_t>().swap(J->f);  // the image now lives on the device
   J->c.f = J->d_f;
@@ -319,11 +327,11 @@ int build_job(fi_server* S, Job* J) {
   return FI_OK;
 }
 
+// Returns the request's region to the arena (callers notify the builders).
 void release_job_memory(fi_server* S, Job* J) {
-  if (J->M) {
-    for (void* p : J->M->allocations) S->arena.free(p);
-    J->M->allocations.clear();
-  }
+  if (J->M) J->M->allocations.clear();  // they lie in the region
+  if (J->region) S->arena.free(J->region);
+  J->region = nullptr;
 }
 
 void builder_main(fi_server* S) {

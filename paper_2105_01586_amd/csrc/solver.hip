@@ -788,8 +788,29 @@ int launch_step(fi_mesh* M, int par, int force) {
   return FI_OK;
 }
 
+// The one-iteration launch's vectors in precision T (x, p and the two
+// record buffers), allocated by the first solve that uses them: a quadtree
+// mesh with the S-iteration plan never does in FP32, and FP64 only when
+// asked for.
+template <typename T>
+int ensure_cg_state(fi_mesh* M) {
+  CGState& S = Prec<T>::st(M);
+  if (S.x) return FI_OK;
+  const size_t n = (size_t)std::max<int64_t>(M->n, 1);
+  void* p[4] = {nullptr, nullptr, nullptr, nullptr};
+  int rc = 0;
+  if ((rc = device_alloc(M, &p[0], n * sizeof(T))) || (rc = device_alloc(M, &p[1], n * sizeof(T))) ||
+      (rc = device_alloc(M, &p[2], 4 * n * sizeof(T))) ||
+      (rc = device_alloc(M, &p[3], 4 * n * sizeof(T))))
+    return rc;
+  S = CGState{p[0], p[1], {p[2], p[3]}};
+  return FI_OK;
+}
+
+// Every solve in the one-iteration launch starts here.
 template <typename T>
 int launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double* x0 = nullptr) {
+  if (const int rc = ensure_cg_state<T>(M)) return rc;
   StepArgs<T> A = make_args<T>(M, 1, 0);  // writes record and partials of slot 0
   Params prm{};
   prm.rtol = o->rtol;
