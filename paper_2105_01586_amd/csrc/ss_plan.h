@@ -73,6 +73,15 @@ inline uint64_t morton_key(uint32_t x, uint32_t y) {
   return spread(x) | (spread(y) << 1);
 }
 
+// Runs body(t, nt) on nt threads (the calling thread is thread 0).
+template <typename F>
+inline void run_threads(int nt, F&& body) {
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(body, t, nt);
+  body(0, nt);
+  for (auto& th : pool) th.join();
+}
+
 // Builds the plan. xy: lattice coordinates of the free rows (natural order,
 // 2 per row); ell: the ELL copy described above (W slots). Returns false if
 // a region exceeds max_region rows (below kPlanLocalMax) or a row has more
@@ -95,30 +104,56 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   uint32_t top = 1;
   while (maxc > 1 && top * 2 <= (uint32_t)maxc) top *= 2;
   const uint32_t clampc = maxc > 1 ? top - 1 : (uint32_t)maxc;
+  const int nthr = std::max(1, threads);
+  auto range = [&](int t, int nt) {
+    return std::pair<int64_t, int64_t>(n * t / nt, n * (t + 1) / nt);
+  };
   std::vector<uint64_t> key(n);
-  for (int64_t i = 0; i < n; ++i)
+  uint64_t kmax = 0;
+  for (int64_t i = 0; i < n; ++i) {
     key[i] = morton_key(std::min((uint32_t)xy[2 * i], clampc),
                         std::min((uint32_t)xy[2 * i + 1], clampc));
-  out.perm.resize(n);
-  for (int64_t i = 0; i < n; ++i) out.perm[i] = (int32_t)i;
-  std::sort(out.perm.begin(), out.perm.end(),
-            [&](int32_t a, int32_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
+    kmax = std::max(kmax, key[i]);
+  }
+  // stable least-significant-digit radix sort of the rows by key (11 bits
+  // a pass), so equal keys keep the natural order
+  {
+    std::vector<int32_t> a(n), b(n);
+    for (int64_t i = 0; i < n; ++i) a[i] = (int32_t)i;
+    std::vector<int64_t> cnt(1 << 11);
+    for (int shift = 0; shift == 0 || (kmax >> shift) != 0; shift += 11) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int64_t i = 0; i < n; ++i) ++cnt[(key[a[i]] >> shift) & 2047];
+      int64_t sum = 0;
+      for (auto& c : cnt) {
+        const int64_t v = c;
+        c = sum;
+        sum += v;
+      }
+      for (int64_t i = 0; i < n; ++i) b[cnt[(key[a[i]] >> shift) & 2047]++] = a[i];
+      a.swap(b);
+    }
+    out.perm.assign(a.begin(), a.end());
+  }
   std::vector<int32_t> inv(n);
   for (int64_t i = 0; i < n; ++i) inv[out.perm[i]] = (int32_t)i;
   // neighbours in the new order: column (new index) and weight code
   std::vector<int32_t> nb((size_t)n * kPlanSlots, -1);
   std::vector<uint8_t> nbw((size_t)n * kPlanSlots, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t r = out.perm[i];
-    int c = 0;
-    for (int k = 0; k < W; ++k) {
-      const int32_t e = ell[(size_t)k * n_pad + r];
-      if (e & 0x40000000) continue;
-      nb[(size_t)i * kPlanSlots + c] = inv[e & 0x3FFFFFFF];
-      nbw[(size_t)i * kPlanSlots + c] = e < 0 ? 1 : 0;
-      ++c;
+  run_threads(nthr, [&](int t, int nt) {
+    const auto [i0, i1] = range(t, nt);
+    for (int64_t i = i0; i < i1; ++i) {
+      const int64_t r = out.perm[i];
+      int c = 0;
+      for (int k = 0; k < W; ++k) {
+        const int32_t e = ell[(size_t)k * n_pad + r];
+        if (e & 0x40000000) continue;
+        nb[(size_t)i * kPlanSlots + c] = inv[e & 0x3FFFFFFF];
+        nbw[(size_t)i * kPlanSlots + c] = e < 0 ? 1 : 0;
+        ++c;
+      }
     }
-  }
+  });
   const int64_t nblk = (n + BS - 1) / BS;
   out.grid = (int32_t)((nblk + 7) / 8 * 8);
   out.blocks.assign(out.grid, BlockPlan{});
@@ -210,11 +245,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
       used.clear();
     }
   };
-  const int nt = std::max(1, std::min<int>(threads, (int)std::min<int64_t>(nblk, 64)));
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nt; ++t) pool.emplace_back(work, t, nt);
-  work(0, nt);
-  for (auto& th : pool) th.join();
+  run_threads(std::max(1, std::min<int>(nthr, (int)std::min<int64_t>(nblk, 64))), work);
   int64_t roff = 0, loff = 0;
   for (int32_t b = 0; b < out.grid; ++b) {
     if (!parts[b].ok) return false;
@@ -231,12 +262,16 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   // rows at most three per free row), so memory can be reserved before it
   // is built
   if (roff > 3 * n || loff > 3 * n) return false;
-  out.region.reserve(roff);
-  out.lmat.reserve((size_t)loff * kPlanSlots);
-  for (int32_t b = 0; b < out.grid; ++b) {
-    out.region.insert(out.region.end(), parts[b].region.begin(), parts[b].region.end());
-    out.lmat.insert(out.lmat.end(), parts[b].lmat.begin(), parts[b].lmat.end());
-  }
+  out.region.resize(roff);
+  out.lmat.resize((size_t)loff * kPlanSlots);
+  run_threads(std::max(1, std::min<int>(nthr, (int)std::min<int64_t>(nblk, 64))), [&](int t, int nt) {
+    for (int64_t b = t; b < nblk; b += nt) {
+      const BlockPlan& B = out.blocks[b];
+      std::copy(parts[b].region.begin(), parts[b].region.end(), out.region.begin() + B.reg_off);
+      std::copy(parts[b].lmat.begin(), parts[b].lmat.end(),
+                out.lmat.begin() + (size_t)B.lmat_off * kPlanSlots);
+    }
+  });
   return true;
 }
 
