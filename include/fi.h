@@ -76,7 +76,9 @@ typedef struct fi_solve_opts {
                         (1e-10 left 3.9e-6 at 8192^2, 2.4e-6 at 2048^2 with a
                         10% mask). The default atol, 3e-6, keeps every pixel
                         of those images within 1e-6 (at most 3e-7 measured). */
-  double inner_rtol; /* each inner solve reduces its residual by this factor */
+  double inner_rtol; /* each inner solve reduces its residual by this factor
+                        (default 1e-5); the final stop above, not this, sets
+                        the accuracy */
   int max_inner;     /* iteration cap of one inner solve */
   int max_refine;    /* cap on refinement steps (outer FP64 residual checks) */
   int check_every;   /* unused (the host reads the solver state once per

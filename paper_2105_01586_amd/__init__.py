@@ -261,7 +261,7 @@ class SolveOpts:
     """Options of one harmonic-extension solve (defaults as in the C library)."""
     precision: int = PREC_FP32_IR
     rtol: float = 1e-10
-    inner_rtol: float = 1e-4
+    inner_rtol: float = 1e-5
     max_inner: int = 20000
     max_refine: int = 40
     check_every: int = 32

@@ -298,7 +298,7 @@ void fi_solve_opts_default(fi_solve_opts* o) {
   if (!o) return;
   o->precision = FI_PREC_FP32_IR;
   o->rtol = 1e-10;
-  o->inner_rtol = 1e-4;
+  o->inner_rtol = 1e-5;
   o->max_inner = 20000;
   o->max_refine = 40;
   o->check_every = 32;
