@@ -123,11 +123,10 @@ struct SsState {
   double* x64[2] = {nullptr, nullptr};  // FP64 iterate, by buffer parity
   double* part = nullptr;   // Gram partials: 2 parities x 32 values x grid (value-major)
   double* red = nullptr;    // reduced Gram (large systems): 32 doubles
-  // large systems: the reduction launch's first-level sums (32 per block of
-  // 256 partials), its completion counter, and the coefficients of the next
-  // step launch's iterations, which it computes once for all blocks
+  // the reduction launch's first-level sums (32 per block of 1024 partials)
+  // and the coefficients of the next step launch's iterations, which it
+  // computes once for all blocks
   double* level1 = nullptr;
-  int* counter = nullptr;
   double* ctl = nullptr;
 };
 

@@ -822,18 +822,21 @@ __global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* p
 // Large systems: a separate launch sums the Gram partials of the step launch
 // before it and runs the next launch's iterations on the coefficients once,
 // for every block of that launch. First level: block b sums partials
-// [256 b, 256 b + 256) of every value (value v by the 16 lanes of one DPP
-// row, partials j, j + 16, ... each, as in the step's own re-reduction);
-// the block that finishes last (integer counter) sums the first-level sums
-// in block order, stores the totals and, when the next launch iterates,
-// the coefficients. Several systems (channels, batched meshes) share one
-// launch, each with its own blocks.
-constexpr int kGramChunk = 256;  // partials per first-level block
+// [1024 b, 1024 b + 1024) of every value (value v by the 16 lanes of one DPP
+// row, partials j, j + 16, ... each, as in the step's own re-reduction); a
+// system of one such block is done there (totals, and the coefficients when
+// the next launch iterates), larger ones in a second launch of one block per
+// system that sums the first-level sums in block order. Several systems
+// (channels, batched meshes) share the launches, each with its own blocks.
+// Partials per first-level block: four chunks of 256, summed per lane as the
+// step's own re-reduction sums them (a tree over the first chunk's sixteen,
+// then the other chunks' values in turn), so up to 1024 blocks the one
+// first-level block gives the step's own bits.
+constexpr int kGramChunk = 1024;
 
 struct SsRedSys {
   const double* part;  // NGP rows of partials (value-major, rows of part_stride(grid))
   double* level1;      // first-level sums, NGP per block
-  int* counter;        // blocks done (0 between launches)
   double* out;         // NGP totals
   const Rec* rec;      // the record the next step launch reads
   const Params* prm;
@@ -849,12 +852,13 @@ struct SsRedArgs {
 };
 static_assert(sizeof(SsRedArgs) <= 4096, "kernel arguments of a reduction launch");
 
-__host__ __device__ constexpr int gram_blocks(int grid) { return part_stride(grid) / kGramChunk; }
-static_assert(kPartPad % kGramChunk == 0, "a row is a whole number of first-level chunks");
+__host__ __device__ constexpr int gram_blocks(int grid) {
+  return (part_stride(grid) + kGramChunk - 1) / kGramChunk;
+}
+static_assert(kGramChunk % kPartPad == 0, "a first-level block covers whole padded chunks");
 
 __global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
   __shared__ double tot[NGP];
-  __shared__ int last;
   int j = 0;  // system of this block (uniform)
 #pragma unroll
   for (int k = 1; k < kSsArgSlots; ++k) j += (k < R.n && R.start[k] <= (int)blockIdx.x) ? 1 : 0;
@@ -862,47 +866,58 @@ __global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
   const int b = (int)blockIdx.x - R.start[j], nb = R.start[j + 1] - R.start[j];
   const int t = threadIdx.x, v = t >> 4, l = t & 15;
   const int vv = v < NG ? v : 0;
-  {
-    const double* pv = Y.part + (size_t)vv * part_stride(Y.grid) + b * kGramChunk + l;
-    double h[16];
+  const int gs = part_stride(Y.grid), c0 = b * kGramChunk;
+  const double* pv = Y.part + (size_t)vv * gs + c0 + l;
+  // every chunk's loads first (a chunk past the row is skipped as a whole)
+  constexpr int kSub = kGramChunk / kPartPad;
+  double h[kSub][16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) h[k] = pv[16 * k];  // padding entries are 0
+  for (int c = 0; c < kSub; ++c) {
+    const bool in = c == 0 || c0 + c * kPartPad < gs;  // uniform
 #pragma unroll
-    for (int w = 8; w >= 1; w >>= 1)
-#pragma unroll
-      for (int k = 0; k < w; ++k) h[k] += h[k + w];
-    const double sum = row_sum(h[0]);
-    if (nb == 1) {  // one chunk: its sums are the totals
-      if (l == 0 && v < NG) {
-        tot[v] = sum;
-        Y.out[v] = sum;
-      }
-      __syncthreads();
-      if (t < 64 && (Y.force || Y.rec->phase == kIter))
-        ss_recur(tot, *Y.rec, *Y.prm, Y.force, Y.ctl);
-      return;
-    }
-    if (l == 0 && v < NG) {
-      __hip_atomic_store(&Y.level1[(size_t)b * NGP + v], sum, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-    }
+    for (int k = 0; k < 16; ++k) h[c][k] = in ? pv[c * kPartPad + 16 * k] : 0.0;
   }
-  __syncthreads();
-  if (t == 0) last = atomicAdd(Y.counter, 1) == nb - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();  // acquire: the other blocks' first-level sums are visible
+#pragma unroll
+  for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+    for (int k = 0; k < w; ++k) h[0][k] += h[0][k + w];
+  double acc = h[0][0];
+#pragma unroll
+  for (int c = 1; c < kSub; ++c)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += h[c][k];  // zeros past the row
+  const double sum = row_sum(acc);
+  if (nb == 1) {  // one block: its sums are the totals
+    if (l == 0 && v < NG) {
+      tot[v] = sum;
+      Y.out[v] = sum;
+    }
+    __syncthreads();
+    if (t < 64 && (Y.force || Y.rec->phase == kIter)) ss_recur(tot, *Y.rec, *Y.prm, Y.force, Y.ctl);
+    return;
+  }
+  if (l == 0 && v < NG) Y.level1[(size_t)b * NGP + v] = sum;
+}
+
+// Second level, for systems of more than one first-level block (one block
+// per system): the first-level sums in block order, the totals, and the
+// coefficients of the next launch.
+__global__ __launch_bounds__(BS) void k_ss_gram_final(SsRedArgs R) {
+  __shared__ double tot[NGP];
+  const int j = blockIdx.x;
+  const SsRedSys& Y = R.s[j];
+  const int nb = R.start[j + 1] - R.start[j];
+  if (nb <= 1) return;  // summed by the first level
+  const int t = threadIdx.x, v = t >> 4, l = t & 15;
+  const int vv = v < NG ? v : 0;
+  const double* l1 = Y.level1 + vv;
   double acc = 0.0;
   for (int q0 = 0; q0 < nb; q0 += 256) {
-    // plain loads, issued together (atomic loads would be waited for one
-    // by one); clamped in range, the values past nb masked after
-    const double* l1 = Y.level1 + vv;
     double h[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int q = q0 + l + 16 * k;
-      h[k] = l1[(size_t)(q < nb ? q : 0) * NGP];
+      h[k] = l1[(size_t)(q < nb ? q : 0) * NGP];  // clamped in range, masked after
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) h[k] = (q0 + l + 16 * k < nb) ? h[k] : 0.0;
@@ -918,7 +933,6 @@ __global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
     Y.out[v] = acc;
   }
   __syncthreads();
-  if (t == 0) __hip_atomic_store(Y.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (t < 64 && (Y.force || Y.rec->phase == kIter)) ss_recur(tot, *Y.rec, *Y.prm, Y.force, Y.ctl);
 }
 
@@ -977,7 +991,6 @@ SsRedSys red_sys(fi_mesh* M, int par, int force) {
   SsRedSys y;
   y.part = Z.part + (size_t)(par ^ 1) * NGP * part_stride(Z.grid);
   y.level1 = Z.level1;
-  y.counter = Z.counter;
   y.out = Z.red;
   y.rec = (const Rec*)M->d_rec + (par ^ 1);
   y.prm = (const Params*)M->d_prm;
@@ -1001,6 +1014,10 @@ int red_launch(const SsRedArgs& R, hipStream_t st) {
   if (R.n == 0) return FI_OK;
   void* args[1] = {(void*)&R};
   FI_HIP_TRY(hipLaunchKernel((void*)k_ss_gram, dim3((unsigned)R.start[R.n]), dim3(BS), args, 0, st));
+  bool two = false;
+  for (int k = 0; k < R.n; ++k) two = two || R.start[k + 1] - R.start[k] > 1;
+  if (two)
+    FI_HIP_TRY(hipLaunchKernel((void*)k_ss_gram_final, dim3((unsigned)R.n), dim3(BS), args, 0, st));
   return FI_OK;
 }
 
@@ -1048,19 +1065,15 @@ int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double*
 // Both parities of the partial sums.
 size_t part_bytes(int grid) { return (size_t)2 * NGP * part_stride(grid) * sizeof(double); }
 
-// The reduction launch's first-level sums, its counter (zero) and the
-// coefficient block (every mesh: multi-solve and batched launches may sum
+// The reduction launch's first-level sums and the coefficient block (every mesh: multi-solve and batched launches may sum
 // a small system's partials that way too).
 int large_alloc(fi_mesh* M, SsState& Z) {
   Z.level1 = nullptr;
-  Z.counter = nullptr;
   Z.ctl = nullptr;
   int rc = 0;
   if ((rc = device_alloc(M, (void**)&Z.level1, (size_t)gram_blocks(Z.grid) * NGP * 8)) ||
-      (rc = device_alloc(M, (void**)&Z.counter, 256)) ||
       (rc = device_alloc(M, (void**)&Z.ctl, NGP * 8)))
     return rc;
-  FI_HIP_TRY(hipMemsetAsync(Z.counter, 0, 256, M->ctx->stream));
   FI_HIP_TRY(hipMemsetAsync(Z.ctl, 0, NGP * 8, M->ctx->stream));
   return FI_OK;
 }
@@ -1439,7 +1452,7 @@ int64_t ss_footprint(int64_t n) {
   add(32 * n); add(32 * n); add(4 * n); add(4 * n);
   add(8 * n); add(8 * n); add(8 * n); add(8 * n);
   add(8 * 2 * NGP * part_stride((int)grid)); add(8 * NGP);
-  add(8 * NGP * gram_blocks((int)grid)); add(256); add(8 * NGP);  // large systems
+  add(8 * NGP * gram_blocks((int)grid)); add(8 * NGP);  // the reduction launch
   return total;
 }
 
