@@ -107,7 +107,6 @@ int alloc_rhs_space(fi_mesh* M) {
   TRY(alloc_n(M, &M->d_uvert, V));
   TRY(alloc_n(M, &M->d_g, m));
   TRY(alloc_n(M, &M->d_tpart, 3 * T));
-  TRY(alloc_n(M, &M->d_tF, n));
   TRY(alloc_n(M, &M->d_tD, m));
   TRY(alloc_n(M, &M->d_rpart, raster_blocks(M)));
   FI_HIP_TRY(hipHostMalloc((void**)&M->h_red, 8 * sizeof(double), hipHostMallocDefault));
@@ -235,10 +234,8 @@ int apply_B(fi_mesh* M, const double* g, double* u_out, const fi_solve_opts* o,
 int apply_BT(fi_mesh* M, const double* r, double* s, const fi_solve_opts* o, fi_solve_stats* st) {
   int rc = launch_raster_transpose(M, r, M->d_tpart);
   if (rc) return rc;
-  rc = launch_gather_vertex(M, M->d_tpart, M->d_tF, M->d_tD);
+  rc = launch_gather_vertex(M, M->d_tpart, M->d_b64, M->d_tD);  // t_F: the solve's b
   if (rc) return rc;
-  FI_HIP_TRY(hipMemcpyAsync(M->d_b64, M->d_tF, (size_t)M->n * sizeof(double),
-                            hipMemcpyDeviceToDevice, M->ctx->stream));
   rc = solve_free(M, o, st);
   if (rc) return rc;
   return launch_adjoint_tail(M, M->d_tD, M->d_x64, s);

@@ -228,7 +228,6 @@ struct fi_mesh {
   double* d_uvert = nullptr;  // V
   double* d_g = nullptr;      // m (working copy of g)
   double* d_tpart = nullptr;  // 3T adjoint partials
-  double* d_tF = nullptr;     // n
   double* d_tD = nullptr;     // m
   double* d_rpart = nullptr;  // raster partial sums (one per leaf block)
   int32_t* d_owner = nullptr;      // P: owner triangle of every pixel

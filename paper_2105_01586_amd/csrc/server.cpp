@@ -162,7 +162,7 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   add(n, 4); add(n, 4); add(4 * n, 4); add(4 * n, 4);
   add(n, 8); add(n, 8); add(4 * n, 8); add(4 * n, 8);
   add(kMaxGrid, 8); add(8, 8);
-  add(V, 8); add(m, 8); add(3 * T, 8); add(n, 8); add(m, 8); add((L + kBlock - 1) / kBlock, 8);
+  add(V, 8); add(m, 8); add(3 * T, 8); add(m, 8); add((L + kBlock - 1) / kBlock, 8);
   add(P, 4); add(P, 4); add(T + 1, 4);  // owner map and per-triangle pixel lists
   // matrices
   add(deg_free, 4); add(deg_free, 8); add(deg_free, 4); add(deg_free, 4); add(deg_free, 8);

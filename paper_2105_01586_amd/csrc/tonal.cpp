@@ -42,9 +42,8 @@ int Cgls::pre() {
       return launch_lift(M, g, M->d_b64);
     case kAdjoint:  // B^T r: t = R^T r, solve with t_F
       if ((rc = launch_raster_transpose(M, M->d_tr, M->d_tpart, wsqrt))) return rc;
-      if ((rc = launch_gather_vertex(M, M->d_tpart, M->d_tF, M->d_tD))) return rc;
-      FI_HIP_TRY(hipMemcpyAsync(M->d_b64, M->d_tF, (size_t)M->n * sizeof(double),
-                                hipMemcpyDeviceToDevice, M->ctx->stream));
+      // t_F straight into the solve's right-hand side
+      if ((rc = launch_gather_vertex(M, M->d_tpart, M->d_b64, M->d_tD))) return rc;
       if (warm) x0 = M->d_ywarm;
       return FI_OK;
     case kApplyP:  // q = B p
