@@ -121,7 +121,7 @@ struct SsState {
   double* b = nullptr;      // right-hand side
   double* r64 = nullptr;    // FP64 residual
   double* x64[2] = {nullptr, nullptr};  // FP64 iterate, by buffer parity
-  double* part = nullptr;   // Gram partials: 2 parities x 32 values x grid (value-major)
+  float* part = nullptr;    // Gram partials (FP32): 2 parities x 32 value rows (value-major)
   double* red = nullptr;    // reduced Gram (large systems): 32 doubles
   // the reduction launch's first-level sums (32 per block of 1024 partials)
   // and the coefficients of the next step launch's iterations, which it

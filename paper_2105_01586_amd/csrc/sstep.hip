@@ -11,7 +11,8 @@
 //     rows and reads the basis of the previous launch on its region (its rows
 //     and the rows within S hops, ss_plan.h);
 //   - every block reduces the Gram matrix G = W^T D W of the previous basis
-//     W = [P_0..P_S, Z_0..Z_{S-1}] (FP64, 28 values), then runs the S CG
+//     W = [P_0..P_S, Z_0..Z_{S-1}] (28 values; block sums exact or FP64,
+//     stored in FP32, totals in FP64), then runs the S CG
 //     iterations on coefficient vectors of length 2S+1 (redundantly, the same
 //     in every block): with M = D^-1 K and T the change of basis of M,
 //        alpha = (z, r) / (p, K p) = zc'G zc / pc'G T pc,
@@ -98,8 +99,9 @@ struct SsArgs {
   double* x64a;
   double* x64b;
   double* xout;        // natural-order result (written when the solve ends)
-  const double* part_in;
-  double* part_out;
+  const float* part_in;   // partial sums of the previous launch (FP32)
+  float* part_out;
+  const double* tot_in;   // their totals, summed by the reduction launch
   const Rec* rec_in;
   Rec* rec_out;
   const Params* prm;
@@ -207,11 +209,15 @@ __device__ __forceinline__ double combine(const float4& a0, const float4& a1,
   return s;
 }
 
-// Writes the block's partial sums: slot v at part_out[v * grid + lb], from
-// thread 16 v (which holds it).
+// Writes the block's partial sums: slot v at part_out[v * gstride + lb],
+// from thread 16 v (which holds it), rounded to FP32. Each block's sums are
+// exact or FP64 up to here; what the rounding leaves (a relative 6e-8 per
+// block) is far below what the FP32 basis vectors carry, and the totals are
+// summed in FP64. Halving the bytes every block of the next launch reads
+// took 5% off a 512^2 launch, with the same iteration counts.
 __device__ __forceinline__ void store_slot(const SsArgs& A, int lb, double v) {
   if ((threadIdx.x & 15) == 0 && (threadIdx.x >> 4) < NGP)
-    A.part_out[(size_t)(threadIdx.x >> 4) * A.gstride + lb] = v;
+    A.part_out[(size_t)(threadIdx.x >> 4) * A.gstride + lb] = (float)v;
 }
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -290,14 +296,14 @@ __device__ __forceinline__ double block_gram(const float (&w)[NB], float dd, flo
 // separate launch (large systems). gram_issue starts the first chunk's
 // loads, so that other loads can follow before the sum waits for them.
 struct GramLoads {
-  double a[16];
+  float a[16];
 };
 
 template <bool LARGE>
 __device__ __forceinline__ void gram_issue(const SsArgs& A, GramLoads& L) {
   if constexpr (!LARGE) {
     const int v = threadIdx.x >> 4, j = threadIdx.x & 15;
-    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.gstride + j;
+    const float* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.gstride + j;
 #pragma unroll
     for (int k = 0; k < 16; ++k) L.a[k] = pv[16 * k];  // padding entries are 0
   }
@@ -307,21 +313,21 @@ template <bool LARGE>
 __device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L, double* red) {
   if constexpr (!LARGE) {
     const int v = threadIdx.x >> 4, j = threadIdx.x & 15;
-    const double* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.gstride + j;
+    const float* pv = A.part_in + (size_t)(v < NG ? v : 0) * A.gstride + j;
     double h[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) h[k] = L.a[k];
+    for (int k = 0; k < 16; ++k) h[k] = (double)L.a[k];
 #pragma unroll
     for (int w = 8; w >= 1; w >>= 1)
 #pragma unroll
       for (int k = 0; k < w; ++k) h[k] += h[k + w];  // pairwise, fixed order
     double acc = h[0];
     for (int c0 = 256; c0 < A.grid; c0 += 256) {
-      double a[16];
+      float a[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) a[k] = pv[c0 + 16 * k];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc += a[k];
+      for (int k = 0; k < 16; ++k) acc += (double)a[k];
     }
     if (v >= NG) acc = 0.0;
     acc += dpp_move<0xB1>(acc);
@@ -540,7 +546,7 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
   const float dd = A.d[ro];
   gram_finish<LARGE>(A, L, red);
   // the reduced Gram matrix: in LDS, or summed by the previous reduction launch
-  const double* Gsrc = LARGE ? A.part_in : red;
+  const double* Gsrc = LARGE ? A.tot_in : red;
   const int phase = A.force ? (int)kIter : Rin.phase;
   const bool writer = lb == 0 && t == 0;
   // LDS: two slot arrays of (p, z) (zero slot, then the region rows), D^-1
@@ -835,7 +841,7 @@ __global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* p
 constexpr int kGramChunk = 1024;
 
 struct SsRedSys {
-  const double* part;  // NGP rows of partials (value-major, rows of part_stride(grid))
+  const float* part;  // NGP rows of partials (value-major, rows of part_stride(grid))
   double* level1;      // first-level sums, NGP per block
   double* out;         // NGP totals
   const Rec* rec;      // the record the next step launch reads
@@ -867,7 +873,7 @@ __global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
   const int t = threadIdx.x, v = t >> 4, l = t & 15;
   const int vv = v < NG ? v : 0;
   const int gs = part_stride(Y.grid), c0 = b * kGramChunk;
-  const double* pv = Y.part + (size_t)vv * gs + c0 + l;
+  const float* pv = Y.part + (size_t)vv * gs + c0 + l;
   // every chunk's loads first (a chunk past the row is skipped as a whole)
   constexpr int kSub = kGramChunk / kPartPad;
   double h[kSub][16];
@@ -875,7 +881,7 @@ __global__ __launch_bounds__(BS) void k_ss_gram(SsRedArgs R) {
   for (int c = 0; c < kSub; ++c) {
     const bool in = c == 0 || c0 + c * kPartPad < gs;  // uniform
 #pragma unroll
-    for (int k = 0; k < 16; ++k) h[c][k] = in ? pv[c * kPartPad + 16 * k] : 0.0;
+    for (int k = 0; k < 16; ++k) h[c][k] = in ? (double)pv[c * kPartPad + 16 * k] : 0.0;
   }
 #pragma unroll
   for (int w = 8; w >= 1; w >>= 1)
@@ -955,6 +961,7 @@ __global__ __launch_bounds__(kBlock) void k_ss_values(int n, const int32_t* __re
 // Launch arguments; `large`: the partials are summed by a reduction launch
 // (the step reads the totals and the coefficients it computed).
 SsArgs ss_args(fi_mesh* M, int par, int force, bool large) {
+  (void)large;  // the kernel instantiation decides which inputs it reads
   SsState& Z = *M->ss;
   SsArgs A;
   A.n = (int)M->n;
@@ -973,7 +980,8 @@ SsArgs ss_args(fi_mesh* M, int par, int force, bool large) {
   A.x64a = Z.x64[0];
   A.x64b = Z.x64[1];
   A.xout = M->d_x64buf[0];
-  A.part_in = large ? Z.red : Z.part + (size_t)par * NGP * A.gstride;
+  A.part_in = Z.part + (size_t)par * NGP * A.gstride;
+  A.tot_in = Z.red;
   A.part_out = Z.part + (size_t)(par ^ 1) * NGP * A.gstride;
   A.rec_in = (const Rec*)M->d_rec + par;
   A.rec_out = (Rec*)M->d_rec + (par ^ 1);
@@ -1063,7 +1071,7 @@ int ss_launch_start(fi_mesh* M, const fi_solve_opts* o, int epoch, const double*
 }
 
 // Both parities of the partial sums.
-size_t part_bytes(int grid) { return (size_t)2 * NGP * part_stride(grid) * sizeof(double); }
+size_t part_bytes(int grid) { return (size_t)2 * NGP * part_stride(grid) * sizeof(float); }
 
 // The reduction launch's first-level sums and the coefficient block (every mesh: multi-solve and batched launches may sum
 // a small system's partials that way too).
