@@ -364,7 +364,6 @@ void ss_release(fi_mesh* M);
 // S-iteration launch; the result in d_x64 (natural order).
 int ss_solve(fi_mesh* M, const fi_solve_opts* opts, fi_solve_stats* stats, const double* x0);
 int ss_time_kernel(fi_mesh* M, int reps, double* ms);
-int64_t ss_kernel_bytes(const fi_mesh* M);
 // The same for the channel views ch[0..nc-1] of one mesh in one launch per
 // step (each channel the bits of its own ss_solve), and its timing.
 int ss_solve_multi(fi_mesh* const* ch, int nc, const fi_solve_opts* opts, fi_solve_stats* stats,

@@ -1377,8 +1377,9 @@ int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
 // iteration, the matrix (one int32 per stored off-diagonal entry in the
 // encoded layout, or column + value per CSR entry plus row pointers), and per
 // row the reads of r, s, q, D^-1, x, p and the writes of x, p, r, s, q; times
-// the iterations per launch (3 with the S-iteration plan, which itself moves
-// fewer bytes: ss_kernel_bytes).
+// the iterations per launch (3 with the S-iteration plan, whose launch itself
+// moves fewer bytes: it reads the matrix and the vectors once for three
+// iterations).
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision) {
   return cg_multi_kernel_bytes(M, 1, precision);
 }

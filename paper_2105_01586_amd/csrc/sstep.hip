@@ -751,7 +751,7 @@ struct SsBatchArgs {
 };
 static_assert(sizeof(SsBatchArgs) <= 4096, "kernel arguments of a batched launch");
 
-template <bool LARGE>
+// Batched solves always take the reduction launch (ss_arm, ss_batch_launch).
 __global__ __launch_bounds__(BS) void k_ss_batch(SsBatchArgs Bt) {
   extern __shared__ float dyn[];
   __shared__ double red[NGP];
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(BS) void k_ss_batch(SsBatchArgs Bt) {
     if (lblk == 0 && threadIdx.x == 0) *A.rec_out = *A.rec_in;
     return;
   }
-  ss_body<LARGE>(A, lblk, dyn, red, wred, coef, dyn);
+  ss_body<true>(A, lblk, dyn, red, wred, coef, dyn);
 }
 
 // Start of a solve: b and x0 in the launch's numbering, x64 = x0 (0 when
@@ -1401,7 +1401,7 @@ int ss_batch_launch(hipStream_t st, const std::vector<fi_mesh*>& ms, int count) 
     const int par = k & 1;
     for (Launch& l : L) {
       void* args[1] = {&l.b[par]};
-      FI_HIP_TRY(hipLaunchKernel((void*)k_ss_batch<true>, dim3((unsigned)l.grid), dim3(BS), args,
+      FI_HIP_TRY(hipLaunchKernel((void*)k_ss_batch, dim3((unsigned)l.grid), dim3(BS), args,
                                  l.lds, st));
     }
     for (Launch& l : L) {
@@ -1489,16 +1489,6 @@ int ss_time_kernel(fi_mesh* M, int reps, double* ms) {
   (void)hipEventDestroy(e1);
   *ms = (double)t / reps;
   return FI_OK;
-}
-
-// Bytes one launch must move: per row, the previous basis read and the new
-// one written (7 floats and D^-1 each way: one 32-byte record), the
-// correction read and written, the diagonal; the matrix once (one 16-bit entry per stored
-// off-diagonal of K_FF). Halo rows read again by neighbouring blocks and the
-// padding of the local matrix rows are not counted.
-int64_t ss_kernel_bytes(const fi_mesh* M) {
-  const int64_t n = M->n;
-  return n * (4 * (NB + 1) * 2 + 8 + 4) + 2 * M->nnz_off;
 }
 
 }  // namespace fi
