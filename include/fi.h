@@ -451,12 +451,18 @@ int fi_densify_delaunay(fi_ctx* ctx, int side, const uint8_t* f_dev, const int32
  * undefined. */
 int fi_time_cg_kernel(fi_mesh* mesh, int precision, int reps, double* ms_per_launch);
 
-/* Algorithmic bytes of the CG iterations one step launch advances: per
- * iteration the matrix (one 4-byte code per stored off-diagonal entry on the
- * quadtree mesh; column, value and row pointers otherwise) and each vector
- * of one-pass Jacobi PCG read or written once, times the iterations per
- * launch. (The three-iteration launch moves fewer bytes than three
- * one-iteration launches; this counts the work, not its layout.) */
+/* Algorithmic bytes of one step launch, what it must move at the least:
+ * - the one-iteration launch: the matrix (one 4-byte code per stored
+ *   off-diagonal entry on the quadtree mesh; column, value and row pointers
+ *   otherwise) and each vector of one-pass Jacobi PCG read or written once
+ *   (4 nnz_off + 44 n in FP32);
+ * - the three-iteration launch (FP32 on the quadtree mesh): per row the
+ *   basis record read and the new one written (32 bytes each), the
+ *   correction read and written and the diagonal read (4 bytes each), and
+ *   the matrix once as 16-bit entries: 76 n + 2 nnz_off. It reads the matrix
+ *   and the vectors once for three iterations; the halo rows that
+ *   neighbouring blocks read again, the region lists and the local matrix
+ *   padding are its layout's overhead, not counted here. */
 int fi_cg_kernel_bytes(const fi_mesh* mesh, int precision, int64_t* bytes);
 
 /* ------------------------------------------------------------- colour --
@@ -521,8 +527,8 @@ int fi_time_cg_multi_kernel(fi_mesh* mesh, int nrhs, int precision, int reps,
                             double* ms_per_launch);
 
 /* Algorithmic bytes of one multi-right-hand-side step launch over nrhs
- * channels: the encoded matrix once, and per channel each vector read or
- * written once (as fi_cg_kernel_bytes). */
+ * channels: the matrix once, and per channel each vector read or written
+ * once (as fi_cg_kernel_bytes). */
 int fi_cg_multi_kernel_bytes(const fi_mesh* mesh, int nrhs, int precision, int64_t* bytes);
 
 /* ------------------------------------------------------------- serving --

@@ -1373,13 +1373,13 @@ int time_cg_kernel(fi_mesh* M, int precision, int reps, double* ms) {
   return FI_OK;
 }
 
-// Algorithmic bytes of the CG iterations one step launch advances: per
-// iteration, the matrix (one int32 per stored off-diagonal entry in the
-// encoded layout, or column + value per CSR entry plus row pointers), and per
-// row the reads of r, s, q, D^-1, x, p and the writes of x, p, r, s, q; times
-// the iterations per launch (3 with the S-iteration plan, whose launch itself
-// moves fewer bytes: it reads the matrix and the vectors once for three
-// iterations).
+// Algorithmic bytes of one step launch. One iteration per launch: the matrix
+// (one int32 per stored off-diagonal entry in the encoded layout, or column +
+// value per CSR entry plus row pointers), and per row the reads of r, s, q,
+// D^-1, x, p and the writes of x, p, r, s, q. Three iterations per launch (the
+// S-iteration plan): per row and solve the basis record read and written
+// (32 bytes each), the correction read and written, the diagonal (4 bytes
+// each), and the matrix once as 16-bit entries.
 int64_t cg_kernel_bytes(const fi_mesh* M, int precision) {
   return cg_multi_kernel_bytes(M, 1, precision);
 }
@@ -1389,8 +1389,9 @@ int64_t cg_multi_kernel_bytes(const fi_mesh* M, int nrhs, int precision) {
   const int64_t w = precision == FI_PREC_FP64 ? 8 : 4;
   const int64_t mat = M->ell_w > 0 ? M->nnz_off * 4  // encoded entries; padding not counted
                                    : M->nnz_off * (4 + w) + (M->n + 1) * 4;
-  const int64_t per_iter = mat + (int64_t)nrhs * M->n * w * 11;
-  return (precision != FI_PREC_FP64 && M->ss) ? kSsIters * per_iter : per_iter;
+  if (precision != FI_PREC_FP64 && M->ss)
+    return M->nnz_off * 2 + (int64_t)nrhs * M->n * (32 + 32 + 4 + 4 + 4);
+  return mat + (int64_t)nrhs * M->n * w * 11;
 }
 
 }  // namespace fi

@@ -210,11 +210,14 @@ def test_multi_kernel_timing_and_bytes(ctx):
     b1 = M.cg_kernel_bytes()
     b3 = M.cg_multi_kernel_bytes(3)
     nnz_off = M.info["nnz_ff"] - M.n
-    # per iteration: 4 bytes per matrix entry and 44 per row and solve (the
-    # matrix once for all solves), times the iterations one launch advances
-    k = M.info["cg_iters_per_launch"]
-    assert b3 == k * (4 * nnz_off + 3 * 44 * M.n)
-    assert b1 == k * (4 * nnz_off + 44 * M.n)
+    # the three-iteration launch: 2 bytes per matrix entry (once for all
+    # solves) and 76 per row and solve (basis records read and written,
+    # correction read and written, diagonal); one iteration per launch: 4 per
+    # entry and 44 per row and solve
+    if M.info["cg_iters_per_launch"] == 3:
+        assert b3 == 2 * nnz_off + 3 * 76 * M.n and b1 == 2 * nnz_off + 76 * M.n
+    else:
+        assert b3 == 4 * nnz_off + 3 * 44 * M.n and b1 == 4 * nnz_off + 44 * M.n
     for nrhs in (1, 2, 3):
         assert M.time_cg_multi_kernel(nrhs, reps=20) > 0
     assert M.device_bytes() > M.info["device_bytes"]  # channel state now exists
