@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -108,49 +109,73 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   auto range = [&](int t, int nt) {
     return std::pair<int64_t, int64_t>(n * t / nt, n * (t + 1) / nt);
   };
-  std::vector<uint64_t> key(n);
-  uint64_t kmax = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    key[i] = morton_key(std::min((uint32_t)xy[2 * i], clampc),
-                        std::min((uint32_t)xy[2 * i + 1], clampc));
-    kmax = std::max(kmax, key[i]);
-  }
-  // stable least-significant-digit radix sort of the rows by key (11 bits
+  // (key, row) pairs, key in the high 32 bits (keys take 2 bits per
+  // coordinate bit, coordinates stay below 2^14)
+  std::vector<uint64_t> kr(n);
+  std::vector<uint64_t> tmax(nthr, 0);
+  run_threads(nthr, [&](int t, int nt) {
+    const auto [i0, i1] = range(t, nt);
+    uint64_t m = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+      const uint64_t k = morton_key(std::min((uint32_t)xy[2 * i], clampc),
+                                    std::min((uint32_t)xy[2 * i + 1], clampc));
+      m = std::max(m, k);
+      kr[i] = (k << 32) | (uint64_t)i;
+    }
+    tmax[t] = m;
+  });
+  const uint64_t kmax = *std::max_element(tmax.begin(), tmax.end());
+  if (kmax >> 32) return false;
+  // stable least-significant-digit radix sort of the pairs by key (11 bits
   // a pass), so equal keys keep the natural order
   {
-    std::vector<int32_t> a(n), b(n);
-    for (int64_t i = 0; i < n; ++i) a[i] = (int32_t)i;
+    std::vector<uint64_t> b(n);
     std::vector<int64_t> cnt(1 << 11);
-    for (int shift = 0; shift == 0 || (kmax >> shift) != 0; shift += 11) {
+    for (int shift = 32; shift == 32 || (kmax >> (shift - 32)) != 0; shift += 11) {
       std::fill(cnt.begin(), cnt.end(), 0);
-      for (int64_t i = 0; i < n; ++i) ++cnt[(key[a[i]] >> shift) & 2047];
+      for (int64_t i = 0; i < n; ++i) ++cnt[(kr[i] >> shift) & 2047];
       int64_t sum = 0;
       for (auto& c : cnt) {
         const int64_t v = c;
         c = sum;
         sum += v;
       }
-      for (int64_t i = 0; i < n; ++i) b[cnt[(key[a[i]] >> shift) & 2047]++] = a[i];
-      a.swap(b);
+      for (int64_t i = 0; i < n; ++i) b[cnt[(kr[i] >> shift) & 2047]++] = kr[i];
+      kr.swap(b);
     }
-    out.perm.assign(a.begin(), a.end());
   }
+  out.perm.resize(n);
   std::vector<int32_t> inv(n);
-  for (int64_t i = 0; i < n; ++i) inv[out.perm[i]] = (int32_t)i;
-  // neighbours in the new order: column (new index) and weight code
-  std::vector<int32_t> nb((size_t)n * kPlanSlots, -1);
-  std::vector<uint8_t> nbw((size_t)n * kPlanSlots, 0);
   run_threads(nthr, [&](int t, int nt) {
     const auto [i0, i1] = range(t, nt);
     for (int64_t i = i0; i < i1; ++i) {
-      const int64_t r = out.perm[i];
+      const int32_t r = (int32_t)(kr[i] & 0xFFFFFFFFu);
+      out.perm[i] = r;
+      inv[r] = (int32_t)i;
+    }
+  });
+  // neighbours in the new order: column (new index) and weight code, by
+  // natural rows (the ELL is read in order; each row's list lands at its
+  // new index)
+  std::unique_ptr<int32_t[]> nbp(new int32_t[(size_t)n * kPlanSlots]);
+  std::unique_ptr<uint8_t[]> nbwp(new uint8_t[(size_t)n * kPlanSlots]);
+  int32_t* const nb = nbp.get();
+  uint8_t* const nbw = nbwp.get();
+  run_threads(nthr, [&](int t, int nt) {
+    const auto [r0, r1] = range(t, nt);
+    for (int64_t r = r0; r < r1; ++r) {
+      const size_t o = (size_t)inv[r] * kPlanSlots;
       int c = 0;
       for (int k = 0; k < W; ++k) {
         const int32_t e = ell[(size_t)k * n_pad + r];
         if (e & 0x40000000) continue;
-        nb[(size_t)i * kPlanSlots + c] = inv[e & 0x3FFFFFFF];
-        nbw[(size_t)i * kPlanSlots + c] = e < 0 ? 1 : 0;
+        nb[o + c] = inv[e & 0x3FFFFFFF];
+        nbw[o + c] = e < 0 ? 1 : 0;
         ++c;
+      }
+      for (; c < kPlanSlots; ++c) {
+        nb[o + c] = -1;
+        nbw[o + c] = 0;
       }
     }
   });
