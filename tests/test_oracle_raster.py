@@ -3,7 +3,9 @@
 Pins: linear functions of (x, y) at the vertices are reproduced exactly at
 every pixel (a P1 interpolant is exact on linear data); weights are
 non-negative and sum to one; mask pixels get their stored value exactly; the
-owner rule is re-derived by a global scan over all triangles; error sums.
+owner rule is re-derived by a global scan over all triangles; error sums, and
+each triangle's error total against errors planted at pixels with one
+geometric owner.
 """
 import math
 
@@ -83,3 +85,35 @@ def test_error_measures():
     uu = np.zeros(16)
     ff = np.concatenate([np.ones(8), np.full(8, 3.0)])
     assert err.mse(uu, ff) == 5.0
+
+
+@pytest.mark.parametrize("N,k,seed", CASES[1:4])
+def test_triangle_error_per_triangle(N, k, seed):
+    """Each triangle's error total (Section 3's local error) pinned one by one:
+    errors planted at pixels that lie in exactly one triangle (found by a
+    geometric scan, not by the rasteriser's owner map) land on that triangle
+    alone, and every other triangle reads zero."""
+    rng = np.random.default_rng(seed + 100)
+    pr = tonal.Problem(N, random_mask(rng, N, k))
+    M = pr.mesh
+    p = M.vxy[M.tri]
+    one_owner = {}
+    for pix in range(N * N):
+        x, y = pix % N, pix // N
+        o = []
+        for i in range(3):
+            A, B = p[:, i], p[:, (i + 1) % 3]
+            o.append((B[:, 0] - A[:, 0]) * (y - A[:, 1]) - (B[:, 1] - A[:, 1]) * (x - A[:, 0]))
+        cands = np.nonzero((o[0] >= 0) & (o[1] >= 0) & (o[2] >= 0))[0]
+        if len(cands) == 1:
+            one_owner[pix] = int(cands[0])
+    assert len(one_owner) > 0
+    picked = rng.choice(sorted(one_owner), size=min(12, len(one_owner)), replace=False)
+    u = np.zeros(N * N)
+    f = np.zeros(N * N)
+    want = np.zeros(M.T)
+    for j, pix in enumerate(picked):
+        d = 2.0 ** (j % 5) * (1 if j % 2 else -1)
+        f[pix] = d
+        want[one_owner[int(pix)]] += d * d
+    assert np.array_equal(pr.triangle_error(u, f), want)
