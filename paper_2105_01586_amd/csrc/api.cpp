@@ -30,16 +30,62 @@ int device_alloc(fi_mesh* M, void** p, size_t bytes) {
     M->device_bytes += (int64_t)bytes;
     return FI_OK;
   }
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(e == hipErrorOutOfMemory ? FI_E_NOMEM : FI_E_HIP,
-                std::string("device allocation failed: ") + hipGetErrorString(e));
+  size_t got = bytes;
+  *p = M->cache ? M->cache->take(bytes, &got) : nullptr;
+  if (!*p) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory && M->cache) {  // the kept blocks may be what is missing
+      (void)hipGetLastError();
+      M->cache->release_all();
+      e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+      return fail(e == hipErrorOutOfMemory ? FI_E_NOMEM : FI_E_HIP,
+                  std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
   }
   M->allocations.push_back(*p);
+  M->alloc_sizes.push_back(got);
   M->device_bytes += (int64_t)bytes;
   return FI_OK;
+}
+
+void* DeviceCache::take(size_t bytes, size_t* got) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = kept_.lower_bound(bytes);
+  if (it == kept_.end() || it->first > bytes + bytes / 4 + ((size_t)1 << 20)) return nullptr;
+  void* p = it->second;
+  *got = it->first;
+  kept_bytes_ -= it->first;
+  kept_.erase(it);
+  return p;
+}
+
+void DeviceCache::give(void* p, size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (kept_bytes_ + bytes <= kKeepBytes) {
+      kept_.emplace(bytes, p);
+      kept_bytes_ += bytes;
+      return;
+    }
+  }
+  (void)hipSetDevice(device_);
+  (void)hipFree(p);
+}
+
+void DeviceCache::release_all() {
+  std::multimap<size_t, void*> blocks;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    blocks.swap(kept_);
+    kept_bytes_ = 0;
+  }
+  if (blocks.empty()) return;
+  (void)hipSetDevice(device_);
+  for (auto& b : blocks) (void)hipFree(b.second);
 }
 
 namespace {
@@ -73,11 +119,15 @@ void free_mesh(fi_mesh* M) {
     solver_release(M);
     for (void* p : M->allocations) M->arena->free(p);
   } else {
-    // hipFree waits for outstanding work on the device; the context (and its
-    // stream) may already be gone, so only the device id is used here.
+    // The device must be done with the blocks before they are freed or kept
+    // for another mesh; the context (and its stream) may already be gone, so
+    // only the device id is used here (the cache is shared with the mesh).
     (void)hipDeviceSynchronize();
     solver_release(M);
-    for (void* p : M->allocations) (void)hipFree(p);
+    for (size_t k = 0; k < M->allocations.size(); ++k) {
+      if (M->cache) M->cache->give(M->allocations[k], M->alloc_sizes[k]);
+      else (void)hipFree(M->allocations[k]);
+    }
   }
   if (M->h_red) (void)hipHostFree(M->h_red);
   if (M->h_ctl) (void)hipHostFree(M->h_ctl);
@@ -141,6 +191,7 @@ int make_channel(fi_mesh* M, fi_mesh** out) {
   S->ctx = M->ctx;
   S->device = M->device;
   S->arena = M->arena;
+  S->cache = M->cache;
   S->is_channel = true;
   S->host.N = M->host.N;
   S->host.levels = M->host.levels;
@@ -325,6 +376,7 @@ int fi_ctx_create(int device, void* stream, fi_ctx** out) {
   fi_ctx* c = new fi_ctx();
   c->device = device;
   c->stream = (hipStream_t)stream;
+  c->cache = std::make_shared<DeviceCache>(device);
   *out = c;
   return FI_OK;
 }
@@ -439,6 +491,7 @@ int fi::mesh_upload(fi_ctx* ctx, fi_host_mesh** host, Arena* arena, fi_mesh** ou
   M->ctx = ctx;
   M->device = ctx->device;
   M->arena = arena;
+  if (!arena) M->cache = ctx->cache;
   M->host = std::move((*host)->mesh);
   int rc = FI_OK;
   const HostMesh& H = M->host;

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -103,6 +104,31 @@ class Arena {
   std::map<size_t, size_t> live_;   // offset -> bytes
 };
 
+// Device blocks a context keeps after the meshes that used them are
+// destroyed, for the meshes built after them. hipMalloc and hipFree each
+// update the device's page tables, and hipFree waits for the device, so a
+// loop that builds a mesh per round would pay both for every array of every
+// mesh. A request takes the smallest kept block of at least its size and at
+// most a quarter (plus 1 MiB) above it; blocks are given back only after
+// the device has finished with them. Up to kKeepBytes are kept; the rest is
+// freed, and everything is freed when a hipMalloc fails and when the last
+// owner (the context or one of its meshes) goes away.
+class DeviceCache {
+ public:
+  static constexpr size_t kKeepBytes = (size_t)2 << 30;
+  explicit DeviceCache(int device) : device_(device) {}
+  ~DeviceCache() { release_all(); }
+  void* take(size_t bytes, size_t* got);
+  void give(void* p, size_t bytes);
+  void release_all();
+
+ private:
+  std::mutex mu_;
+  int device_;
+  size_t kept_bytes_ = 0;
+  std::multimap<size_t, void*> kept_;  // block size -> block
+};
+
 // The S-iteration CG launch (sstep.hip): its plan on the device and its
 // vectors, all in the plan's Z-order numbering of the free rows.
 struct SsState {
@@ -141,6 +167,7 @@ struct CGState {  // state of one fused-CG inner solver in precision T
 struct fi_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  std::shared_ptr<fi::DeviceCache> cache;  // shared with the meshes built on it
 };
 
 struct fi_host_mesh {
@@ -158,7 +185,9 @@ struct fi_mesh {
   int64_t nnz_df = 0;   // entries of K_DF
   int64_t device_bytes = 0;
   std::vector<void*> allocations;
+  std::vector<size_t> alloc_sizes;  // block sizes of `allocations` (outside an arena)
   fi::Arena* arena = nullptr;  // set: memory comes from (and returns to) it
+  std::shared_ptr<fi::DeviceCache> cache;  // the context's, outside an arena
 
   // geometry (device)
   int32_t* d_vxy = nullptr;

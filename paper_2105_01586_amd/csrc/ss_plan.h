@@ -27,8 +27,9 @@
 #include <algorithm>
 #include <cstdint>
 #include <memory>
-#include <thread>
 #include <vector>
+
+#include "host_pool.h"
 
 namespace fi {
 
@@ -74,19 +75,12 @@ inline uint64_t morton_key(uint32_t x, uint32_t y) {
   return spread(x) | (spread(y) << 1);
 }
 
-// Runs body(t, nt) on nt threads (the calling thread is thread 0).
-template <typename F>
-inline void run_threads(int nt, F&& body) {
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nt; ++t) pool.emplace_back(body, t, nt);
-  body(0, nt);
-  for (auto& th : pool) th.join();
-}
-
 // Builds the plan. xy: lattice coordinates of the free rows (natural order,
 // 2 per row); ell: the ELL copy described above (W slots). Returns false if
 // a region exceeds max_region rows (below kPlanLocalMax) or a row has more
 // than kPlanSlots entries (the caller then keeps the one-iteration launch).
+// Each pass is split into `threads` tasks that run on the host pool; the
+// plan does not depend on that number.
 inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int32_t* ell,
                           int64_t n_pad, int W, int threads, int max_region, SsPlan& out) {
   out = SsPlan{};
@@ -113,7 +107,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   // coordinate bit, coordinates stay below 2^14)
   std::vector<uint64_t> kr(n);
   std::vector<uint64_t> tmax(nthr, 0);
-  run_threads(nthr, [&](int t, int nt) {
+  pool_run(nthr, [&](int64_t t, int64_t nt) {
     const auto [i0, i1] = range(t, nt);
     uint64_t m = 0;
     for (int64_t i = i0; i < i1; ++i) {
@@ -127,27 +121,39 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   const uint64_t kmax = *std::max_element(tmax.begin(), tmax.end());
   if (kmax >> 32) return false;
   // stable least-significant-digit radix sort of the pairs by key (11 bits
-  // a pass), so equal keys keep the natural order
+  // a pass), so equal keys keep the natural order: each of the nthr chunks
+  // counts its digits, and scatters its pairs in order after the pairs of
+  // lower digits and of earlier chunks with the same digit
   {
     std::vector<uint64_t> b(n);
-    std::vector<int64_t> cnt(1 << 11);
+    std::vector<int64_t> cnt((size_t)nthr << 11);
     for (int shift = 32; shift == 32 || (kmax >> (shift - 32)) != 0; shift += 11) {
-      std::fill(cnt.begin(), cnt.end(), 0);
-      for (int64_t i = 0; i < n; ++i) ++cnt[(kr[i] >> shift) & 2047];
+      pool_run(nthr, [&](int64_t t, int64_t nt) {
+        const auto [i0, i1] = range((int)t, (int)nt);
+        int64_t* c = &cnt[(size_t)t << 11];
+        std::fill(c, c + 2048, 0);
+        for (int64_t i = i0; i < i1; ++i) ++c[(kr[i] >> shift) & 2047];
+      });
       int64_t sum = 0;
-      for (auto& c : cnt) {
-        const int64_t v = c;
-        c = sum;
-        sum += v;
-      }
-      for (int64_t i = 0; i < n; ++i) b[cnt[(kr[i] >> shift) & 2047]++] = kr[i];
+      for (int d = 0; d < 2048; ++d)
+        for (int t = 0; t < nthr; ++t) {
+          int64_t& c = cnt[((size_t)t << 11) + d];
+          const int64_t v = c;
+          c = sum;
+          sum += v;
+        }
+      pool_run(nthr, [&](int64_t t, int64_t nt) {
+        const auto [i0, i1] = range((int)t, (int)nt);
+        int64_t* c = &cnt[(size_t)t << 11];
+        for (int64_t i = i0; i < i1; ++i) b[c[(kr[i] >> shift) & 2047]++] = kr[i];
+      });
       kr.swap(b);
     }
   }
   out.perm.resize(n);
   std::vector<int32_t> inv(n);
-  run_threads(nthr, [&](int t, int nt) {
-    const auto [i0, i1] = range(t, nt);
+  pool_run(nthr, [&](int64_t t, int64_t nt) {
+    const auto [i0, i1] = range((int)t, (int)nt);
     for (int64_t i = i0; i < i1; ++i) {
       const int32_t r = (int32_t)(kr[i] & 0xFFFFFFFFu);
       out.perm[i] = r;
@@ -161,8 +167,8 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   std::unique_ptr<uint8_t[]> nbwp(new uint8_t[(size_t)n * kPlanSlots]);
   int32_t* const nb = nbp.get();
   uint8_t* const nbw = nbwp.get();
-  run_threads(nthr, [&](int t, int nt) {
-    const auto [r0, r1] = range(t, nt);
+  pool_run(nthr, [&](int64_t t, int64_t nt) {
+    const auto [r0, r1] = range((int)t, (int)nt);
     for (int64_t r = r0; r < r1; ++r) {
       const size_t o = (size_t)inv[r] * kPlanSlots;
       int c = 0;
@@ -189,7 +195,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
     bool ok = true;
   };
   std::vector<Part> parts(out.grid);
-  auto work = [&](int t, int nt) {
+  auto work = [&](int64_t t, int64_t nt) {
     // region membership: open addressing over new indices (row -> local
     // index), twice the largest region, cleared after each block
     constexpr uint32_t kTab = 2u * (uint32_t)kPlanLocalMax;
@@ -270,7 +276,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
       used.clear();
     }
   };
-  run_threads(std::max(1, std::min<int>(nthr, (int)std::min<int64_t>(nblk, 64))), work);
+  pool_run(std::min<int64_t>(nthr, nblk), work);
   int64_t roff = 0, loff = 0;
   for (int32_t b = 0; b < out.grid; ++b) {
     if (!parts[b].ok) return false;
@@ -289,7 +295,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   if (roff > 3 * n || loff > 3 * n) return false;
   out.region.resize(roff);
   out.lmat.resize((size_t)loff * kPlanSlots);
-  run_threads(std::max(1, std::min<int>(nthr, (int)std::min<int64_t>(nblk, 64))), [&](int t, int nt) {
+  pool_run(std::min<int64_t>(nthr, nblk), [&](int64_t t, int64_t nt) {
     for (int64_t b = t; b < nblk; b += nt) {
       const BlockPlan& B = out.blocks[b];
       std::copy(parts[b].region.begin(), parts[b].region.end(), out.region.begin() + B.reg_off);

@@ -41,7 +41,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "cg_common.h"
@@ -1109,9 +1108,8 @@ int ss_setup(fi_mesh* M) {
       xy[2 * i] = M->host.vxy[2 * (size_t)v];
       xy[2 * i + 1] = M->host.vxy[2 * (size_t)v + 1];
     }
-    const int threads = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
     SsPlan plan;
-    if (!build_ss_plan(S, BS, n, xy.data(), ell.data(), M->n_pad, M->ell_w, threads, kMaxRegion,
+    if (!build_ss_plan(S, BS, n, xy.data(), ell.data(), M->n_pad, M->ell_w, 16, kMaxRegion,
                        plan))
       return FI_OK;  // keep the one-iteration launch
     SsState* Z = new SsState();

@@ -54,11 +54,11 @@ def ell_of(K_FF, W):
     return ell.astype(np.uint32).view(np.int32), n_pad
 
 
-def run_plan(exe, tmp_path, xy, ell, n, n_pad, W, S, BS):
+def run_plan(exe, tmp_path, xy, ell, n, n_pad, W, S, BS, tasks=4):
     fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
     with open(fin, "wb") as f:
         np.array([n, n_pad], dtype=np.int64).tofile(f)
-        np.array([W, S, BS, 4], dtype=np.int32).tofile(f)
+        np.array([W, S, BS, tasks], dtype=np.int32).tofile(f)
         np.ascontiguousarray(xy, dtype=np.int32).tofile(f)
         np.ascontiguousarray(ell, dtype=np.int32).tofile(f)
     subprocess.run([exe, fin, fout], check=True, timeout=300)
@@ -194,6 +194,22 @@ def test_plan_small(exe, tmp_path, side, k, S, BS):
     assert plan["ok"]
     Aoff, regions = check_plan(plan, K, xy, S, BS)
     check_basis(plan, Aoff, regions, K.diagonal()[plan["perm"]], S)
+
+
+def test_plan_independent_of_task_count(exe, tmp_path):
+    # every pass is split into tasks on the host pool; the plan is the same
+    # for any split
+    mask = synth.make_mask(128, 128 * 128, k=500)
+    M = om.build_mesh(128, mask)
+    K = fem.assemble(M).K_FF
+    xy = M.vxy[M.free_vids]
+    ell, n_pad = ell_of(K, 8)
+    plans = [run_plan(exe, tmp_path, xy, ell, K.shape[0], n_pad, 8, 3, 256, tasks=t)
+             for t in (1, 3, 16)]
+    for p in plans[1:]:
+        assert plans[0]["ok"] and p["ok"] and p["grid"] == plans[0]["grid"]
+        for key in ("perm", "blocks", "region", "lmat"):
+            assert np.array_equal(p[key], plans[0][key]), key
 
 
 @pytest.mark.slow
