@@ -76,6 +76,31 @@ void DeviceCache::give(void* p, size_t bytes) {
   (void)hipFree(p);
 }
 
+DeviceCache::~DeviceCache() {
+  release_all();
+  if (staging_) (void)hipHostFree(staging_);
+}
+
+void* DeviceCache::staging(size_t bytes, std::unique_lock<std::mutex>& hold) {
+  if (bytes > kStagingMax) return nullptr;
+  hold = std::unique_lock<std::mutex>(staging_mu_);
+  if (staging_bytes_ < bytes) {
+    (void)hipSetDevice(device_);
+    if (staging_) (void)hipHostFree(staging_);
+    staging_ = nullptr;
+    staging_bytes_ = 0;
+    const size_t want = std::min(kStagingMax, std::max(bytes, staging_bytes_ * 2));
+    if (hipHostMalloc(&staging_, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      staging_ = nullptr;
+      hold.unlock();
+      return nullptr;
+    }
+    staging_bytes_ = want;
+  }
+  return staging_;
+}
+
 void DeviceCache::release_all() {
   std::multimap<size_t, void*> blocks;
   {
@@ -95,8 +120,8 @@ int alloc_n(fi_mesh* M, T** p, int64_t n) {
   return device_alloc(M, (void**)p, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
 }
 
-template <typename T>
-int upload(fi_mesh* M, T** p, const std::vector<T>& h) {
+template <typename T, typename A>
+int upload(fi_mesh* M, T** p, const std::vector<T, A>& h) {
   int rc = alloc_n(M, p, (int64_t)h.size());
   if (rc) return rc;
   if (!h.empty())

@@ -1,6 +1,12 @@
-// A process-wide pool of host worker threads for the library's host-side
-// builders (the quadtree mesh, the s-step plan). Plain C++, no device code.
+// Host-side helpers of the library's builders (the quadtree mesh, the s-step
+// plan). Plain C++, no device code.
 //
+// HostVec: a vector whose resize() leaves new elements uninitialised, so
+// that a large array is first written (and its pages first touched) by the
+// tasks that fill it, in parallel, instead of being zeroed by one thread
+// beforehand; elements must be of trivial types.
+//
+// HostPool: a process-wide pool of host worker threads.
 // run(ntasks, body) calls body(task, ntasks) once for every task in
 // [0, ntasks): the calling thread and the parked workers take tasks from a
 // shared counter, and run returns when every task has finished. Work is split
@@ -16,10 +22,37 @@
 #include <cstdint>
 #include <functional>
 #include <mutex>
+#include <memory>
+#include <new>
 #include <thread>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace fi {
+
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    static_assert(std::is_trivially_default_constructible<U>::value, "trivial types only");
+    ::new ((void*)p) U;
+  }
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    ::new ((void*)p) U(std::forward<Args>(args)...);
+  }
+};
+
+template <class T>
+using HostVec = std::vector<T, NoInit<T>>;
 
 class HostPool {
  public:

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/fi.h"
+#include "host_pool.h"
 
 namespace fi {
 
@@ -31,16 +32,16 @@ int fail(int code, const std::string& msg);
 struct HostMesh {
   int N = 0;                       // image side (power of two)
   int levels = 0;                  // log2(N)
-  std::vector<int32_t> leaves;     // (L+1) x 4: x0, y0, level, first triangle;
+  HostVec<int32_t> leaves;     // (L+1) x 4: x0, y0, level, first triangle;
                                    // the extra row holds (0, 0, 0, T)
-  std::vector<int32_t> vxy;        // V x 2: x, y
-  std::vector<int32_t> tri;        // T x 3 vertex ids, positive orientation
-  std::vector<int32_t> vmap;       // V: free row (>= 0) or -(mask slot + 1)
-  std::vector<int32_t> free_vids;  // n
-  std::vector<int32_t> mask_vids;  // m
-  std::vector<int32_t> mask_pix;   // m: linear pixel index of each mask slot
-  std::vector<int32_t> vt_ptr;     // V+1: incident (triangle, corner) lists
-  std::vector<int32_t> vt_idx;     // 3T: 3 * triangle + corner, ascending
+  HostVec<int32_t> vxy;        // V x 2: x, y
+  HostVec<int32_t> tri;        // T x 3 vertex ids, positive orientation
+  HostVec<int32_t> vmap;       // V: free row (>= 0) or -(mask slot + 1)
+  HostVec<int32_t> free_vids;  // n
+  HostVec<int32_t> mask_vids;  // m
+  HostVec<int32_t> mask_pix;   // m: linear pixel index of each mask slot
+  HostVec<int32_t> vt_ptr;     // V+1: incident (triangle, corner) lists
+  HostVec<int32_t> vt_idx;     // 3T: 3 * triangle + corner, ascending
   int max_incident = 0;            // largest incident-triangle count
   bool delaunay = false;           // the Delaunay mesh (no quadtree leaves)
 
@@ -117,16 +118,24 @@ class DeviceCache {
  public:
   static constexpr size_t kKeepBytes = (size_t)2 << 30;
   explicit DeviceCache(int device) : device_(device) {}
-  ~DeviceCache() { release_all(); }
+  ~DeviceCache();
   void* take(size_t bytes, size_t* got);
   void give(void* p, size_t bytes);
   void release_all();
+  // Pinned host memory of at least `bytes` (up to kStagingMax; null past it
+  // or on failure) for copies from the device, kept and grown across calls.
+  // One user at a time: the buffer is the caller's while `hold` is locked.
+  static constexpr size_t kStagingMax = (size_t)256 << 20;
+  void* staging(size_t bytes, std::unique_lock<std::mutex>& hold);
 
  private:
   std::mutex mu_;
   int device_;
   size_t kept_bytes_ = 0;
   std::multimap<size_t, void*> kept_;  // block size -> block
+  std::mutex staging_mu_;
+  void* staging_ = nullptr;
+  size_t staging_bytes_ = 0;
 };
 
 // The S-iteration CG launch (sstep.hip): its plan on the device and its

@@ -210,8 +210,8 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& H) {
   std::vector<int64_t> loff(pieces.size());
   for (size_t k = 0; k < pieces.size(); ++k) loff[k] = (int64_t)pieces[k].hang.size();
   const int64_t L = exclusive_scan(loff);
-  std::vector<int32_t> leaf_xyl((size_t)(3 * L));
-  std::vector<uint8_t> hang((size_t)L);
+  HostVec<int32_t> leaf_xyl((size_t)(3 * L));
+  HostVec<uint8_t> hang((size_t)L);
   pool_run((int64_t)pieces.size(), [&](int64_t k, int64_t) {
     const LeafList& p = pieces[(size_t)k];
     std::copy(p.xyl.begin(), p.xyl.end(), leaf_xyl.begin() + 3 * loff[(size_t)k]);
@@ -325,7 +325,12 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& H) {
   H.leaves[(size_t)(4 * L + 3)] = (int32_t)T;
 
   // ---- Dirichlet / free split -----------------------------------------
-  H.vmap.assign((size_t)V, 0);
+  const int64_t vch = chunks_for(V);
+  H.vmap.resize((size_t)V);
+  pool_run(vch, [&](int64_t t, int64_t nt) {
+    const auto [v0, v1] = split_range(V, nt, t);
+    std::fill(H.vmap.begin() + v0, H.vmap.begin() + v1, 0);
+  });
   H.mask_vids.resize((size_t)m);
   H.mask_pix.assign(mask, mask + m);
   std::atomic<bool> not_vertex{false};
@@ -343,7 +348,6 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& H) {
     }
   });
   if (not_vertex.load()) return fail(FI_E_INVALID, "internal: a mask pixel is not a vertex");
-  const int64_t vch = chunks_for(V);
   std::vector<int64_t> foff((size_t)vch);
   pool_run(vch, [&](int64_t t, int64_t nt) {
     const auto [v0, v1] = split_range(V, nt, t);
@@ -364,7 +368,11 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& H) {
   });
 
   // ---- vertex -> (triangle, corner) adjacency ----------------------------
-  H.vt_ptr.assign((size_t)(V + 1), 0);
+  H.vt_ptr.resize((size_t)(V + 1));
+  pool_run(vch, [&](int64_t t, int64_t nt) {
+    const auto [v0, v1] = split_range(V + 1, nt, t);
+    std::fill(H.vt_ptr.begin() + v0, H.vt_ptr.begin() + v1, 0);
+  });
   const int64_t E = 3 * T;
   const int64_t ech = chunks_for(E);
   pool_run(ech, [&](int64_t t, int64_t nt) {
@@ -400,19 +408,21 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& H) {
     return fail(FI_E_INVALID, "internal: vertex with more incident triangles than expected");
   if (!border_ok)
     return fail(FI_E_INVALID, "internal: border vertex with more incident triangles than expected");
+  // list starts, and a copy of them that the fill below advances
+  HostVec<int32_t> fill((size_t)V);
   pool_run(vch, [&](int64_t t, int64_t nt) {
     const auto [v0, v1] = split_range(V, nt, t);
     int64_t acc = coff[(size_t)t];
     for (int64_t v = v0; v < v1; ++v) {
       const int32_t inc = H.vt_ptr[(size_t)v + 1];
       H.vt_ptr[(size_t)v] = (int32_t)acc;  // slot v is no longer read as a count
+      fill[(size_t)v] = (int32_t)acc;
       acc += inc;
     }
   });
   H.vt_ptr[(size_t)V] = (int32_t)E;
   H.vt_idx.resize((size_t)E);
   {
-    std::vector<int32_t> fill(H.vt_ptr.begin(), H.vt_ptr.end() - 1);
     pool_run(ech, [&](int64_t t, int64_t nt) {
       const auto [e0, e1] = split_range(E, nt, t);
       for (int64_t e = e0; e < e1; ++e) {

@@ -55,10 +55,10 @@ struct SsPlan {
   int64_t n = 0;
   int32_t grid = 0;              // blocks (a multiple of 8)
   int32_t max_region = 0;        // largest nreg over the blocks
-  std::vector<int32_t> perm;     // new index -> natural row
+  HostVec<int32_t> perm;         // new index -> natural row
   std::vector<BlockPlan> blocks;
-  std::vector<int32_t> region;   // region rows (new indices), block after block
-  std::vector<uint16_t> lmat;    // local matrix rows, kPlanSlots entries each
+  HostVec<int32_t> region;       // region rows (new indices), block after block
+  HostVec<uint16_t> lmat;        // local matrix rows, kPlanSlots entries each
 };
 
 // Interleaves the bits of x (even positions) and y (odd positions).
@@ -105,7 +105,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   };
   // (key, row) pairs, key in the high 32 bits (keys take 2 bits per
   // coordinate bit, coordinates stay below 2^14)
-  std::vector<uint64_t> kr(n);
+  HostVec<uint64_t> kr(n);
   std::vector<uint64_t> tmax(nthr, 0);
   pool_run(nthr, [&](int64_t t, int64_t nt) {
     const auto [i0, i1] = range(t, nt);
@@ -125,7 +125,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   // counts its digits, and scatters its pairs in order after the pairs of
   // lower digits and of earlier chunks with the same digit
   {
-    std::vector<uint64_t> b(n);
+    HostVec<uint64_t> b(n);
     std::vector<int64_t> cnt((size_t)nthr << 11);
     for (int shift = 32; shift == 32 || (kmax >> (shift - 32)) != 0; shift += 11) {
       pool_run(nthr, [&](int64_t t, int64_t nt) {
@@ -151,7 +151,7 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
     }
   }
   out.perm.resize(n);
-  std::vector<int32_t> inv(n);
+  HostVec<int32_t> inv(n);
   pool_run(nthr, [&](int64_t t, int64_t nt) {
     const auto [i0, i1] = range((int)t, (int)nt);
     for (int64_t i = i0; i < i1; ++i) {

@@ -1098,20 +1098,32 @@ int ss_setup(fi_mesh* M) {
     if (const char* env = std::getenv("FI_CG_SSTEP"))
       if (std::atoi(env) == 0) return FI_OK;
     const int64_t n = M->n;
-    std::vector<int32_t> ell((size_t)M->ell_w * M->n_pad);
-    FI_HIP_TRY(hipMemcpyAsync(ell.data(), M->d_ell, ell.size() * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, st));
-    FI_HIP_TRY(hipStreamSynchronize(st));
-    std::vector<int32_t> xy((size_t)2 * n);
-    for (int64_t i = 0; i < n; ++i) {
-      const int32_t v = M->host.free_vids[i];
-      xy[2 * i] = M->host.vxy[2 * (size_t)v];
-      xy[2 * i + 1] = M->host.vxy[2 * (size_t)v + 1];
+    // the ELL comes back through the context's pinned staging buffer when it
+    // fits there (several times faster than a copy to pageable memory)
+    const size_t ell_words = (size_t)M->ell_w * M->n_pad;
+    std::unique_lock<std::mutex> staging_hold;
+    int32_t* ell = M->cache ? (int32_t*)M->cache->staging(ell_words * 4, staging_hold) : nullptr;
+    std::vector<int32_t> ell_pageable;
+    if (!ell) {
+      ell_pageable.resize(ell_words);
+      ell = ell_pageable.data();
     }
+    FI_HIP_TRY(hipMemcpyAsync(ell, M->d_ell, ell_words * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FI_HIP_TRY(hipStreamSynchronize(st));
+    HostVec<int32_t> xy((size_t)2 * n);
+    pool_run(16, [&](int64_t t, int64_t nt) {
+      const auto [i0, i1] = split_range(n, nt, t);
+      for (int64_t i = i0; i < i1; ++i) {
+        const int32_t v = M->host.free_vids[i];
+        xy[2 * i] = M->host.vxy[2 * (size_t)v];
+        xy[2 * i + 1] = M->host.vxy[2 * (size_t)v + 1];
+      }
+    });
     SsPlan plan;
-    if (!build_ss_plan(S, BS, n, xy.data(), ell.data(), M->n_pad, M->ell_w, 16, kMaxRegion,
+    if (!build_ss_plan(S, BS, n, xy.data(), ell, M->n_pad, M->ell_w, 16, kMaxRegion,
                        plan))
       return FI_OK;  // keep the one-iteration launch
+    if (staging_hold.owns_lock()) staging_hold.unlock();
     SsState* Z = new SsState();
     Z->grid = plan.grid;
     Z->max_region = plan.max_region;
