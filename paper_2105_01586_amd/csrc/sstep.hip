@@ -348,17 +348,24 @@ struct Pre {
 };
 
 // Rows and local matrix rows (loads that need only the block table). The
-// loads are unconditional, at clamped positions that stay inside the lists
-// (an empty block points at their start); entries past the region or past
-// the inner rows are never used.
-__device__ __forceinline__ void prefetch_rows(const SsArgs& A, const BlockPlan& B, Pre& R) {
+// own rows are the block's consecutive rows (the region list starts with
+// them): large systems, which are bound by HBM traffic, read only the halo
+// rows from the list (4 bytes per row and launch less); at small sizes, bound
+// by latency, the unconditional load of every row measured faster. Loads are
+// at clamped positions that stay inside the lists (an empty block points at
+// their start); entries past the region or past the inner rows are never
+// used.
+template <bool LARGE>
+__device__ __forceinline__ void prefetch_rows(const SsArgs& A, const BlockPlan& B, int base,
+                                              Pre& R) {
   const int t = threadIdx.x;
+  if constexpr (LARGE)
+    R.i[0] = t < B.nown ? base + t : A.region[B.reg_off + max(0, min(t, B.nreg - 1))];
+  else
+    R.i[0] = A.region[B.reg_off + max(0, min(t, B.nreg - 1))];
+  R.i[1] = A.region[B.reg_off + max(0, min(t + BS, B.nreg - 1))];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int l = t + k * BS;
-    R.i[k] = A.region[B.reg_off + max(0, min(l, B.nreg - 1))];
-    R.m[k] = A.lmat[B.lmat_off + max(0, min(l, B.ninner - 1))];
-  }
+  for (int k = 0; k < 2; ++k) R.m[k] = A.lmat[B.lmat_off + max(0, min(t + k * BS, B.ninner - 1))];
 }
 
 // The rows' basis records (loads that need the rows; every row is valid).
@@ -537,7 +544,7 @@ __device__ __forceinline__ void ss_body(const SsArgs& A, const int lb, float* dy
   // region rows' records, the own row's correction and diagonal (unconditional
   // at row 0 past the own rows; those values are never used)
   Pre R;
-  prefetch_rows(A, B, R);
+  prefetch_rows<LARGE>(A, B, base, R);
   GramLoads L;
   gram_issue<LARGE>(A, L);
   prefetch_recs(A, R);
@@ -827,17 +834,16 @@ __global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* p
 // Large systems: a separate launch sums the Gram partials of the step launch
 // before it and runs the next launch's iterations on the coefficients once,
 // for every block of that launch. First level: block b sums partials
-// [1024 b, 1024 b + 1024) of every value (value v by the 16 lanes of one DPP
-// row, partials j, j + 16, ... each, as in the step's own re-reduction); a
-// system of one such block is done there (totals, and the coefficients when
-// the next launch iterates), larger ones in a second launch of one block per
-// system that sums the first-level sums in block order. Several systems
-// (channels, batched meshes) share the launches, each with its own blocks.
-// Partials per first-level block: four chunks of 256, summed per lane as the
-// step's own re-reduction sums them (a tree over the first chunk's sixteen,
-// then the other chunks' values in turn), so up to 1024 blocks the one
-// first-level block gives the step's own bits.
-constexpr int kGramChunk = 1024;
+// [256 b, 256 b + 256) of every value (value v by the 16 lanes of one DPP
+// row, partials j, j + 16, ... each: a tree over each lane's sixteen, as in
+// the step's own re-reduction, so a system of up to 256 blocks gets the
+// step's own bits); a system of one such block is done there (totals, and
+// the coefficients when the next launch iterates), larger ones in a second
+// launch of one block per system that sums the first-level sums in block
+// order. Several systems (channels, batched meshes) share the launches, each
+// with its own blocks. Chunks of 256 give a 8192^2 system (47k step blocks)
+// 185 first-level blocks, enough to spread the partials' loads over the chip.
+constexpr int kGramChunk = 256;
 
 struct SsRedSys {
   const float* part;  // NGP rows of partials (value-major, rows of part_stride(grid))
