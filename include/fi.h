@@ -157,8 +157,8 @@ typedef struct fi_mesh_info {
   int64_t cg_block_size; /* threads per block of that launch */
   int64_t large_mode;   /* 1: a separate launch sums the step's partial sums */
   int64_t cg_iters_per_launch; /* CG iterations one FP32 step launch advances:
-                                  3 on the quadtree mesh (blocks of Z-ordered
-                                  rows with 3-hop halos), else 1 */
+                                  3 on the quadtree mesh (blocks of rows in
+                                  Hilbert order with 3-hop halos), else 1 */
   int64_t cg_max_region;  /* rows of the largest block region (3 per launch), or 0 */
   int64_t cg_region_rows; /* region rows over all blocks (own rows included), or 0 */
 } fi_mesh_info;

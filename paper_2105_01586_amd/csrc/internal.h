@@ -139,7 +139,7 @@ class DeviceCache {
 };
 
 // The S-iteration CG launch (sstep.hip): its plan on the device and its
-// vectors, all in the plan's Z-order numbering of the free rows.
+// vectors, all in the plan's Hilbert-order numbering of the free rows.
 struct SsState {
   int grid = 0;             // blocks of one launch (a multiple of 8)
   int max_region = 0;       // largest block region (rows)

@@ -3,10 +3,12 @@
 // The s-step launch advances S iterations of Jacobi PCG per launch. Each
 // block applies the preconditioned operator S times to its rows' vectors, so
 // it needs the rows within S hops of its own in the matrix graph. The free
-// rows are therefore renumbered along a Z-order (Morton) curve of their
-// lattice coordinates (the last lattice row and column clamped onto the one
-// before), so that a block's BS consecutive rows form a compact
-// patch, and each block gets:
+// rows are therefore renumbered along a Hilbert curve over their lattice
+// coordinates (the last lattice row and column clamped onto the one before),
+// so that a block's BS consecutive rows form a compact patch and consecutive
+// blocks are neighbouring patches (a block's halo rows mostly belong to
+// blocks just before or after it, which run at about the same time on the
+// same XCD: its cache still holds them), and each block gets:
 //   - its region: its own rows (local index 0 .. nown-1), then the rows at
 //     graph distance 1, 2, ..., S from them (ascending within each ring),
 //     listed in full (own rows included) so that a region row is one load;
@@ -61,18 +63,26 @@ struct SsPlan {
   HostVec<uint16_t> lmat;        // local matrix rows, kPlanSlots entries each
 };
 
-// Interleaves the bits of x (even positions) and y (odd positions).
-inline uint64_t morton_key(uint32_t x, uint32_t y) {
-  auto spread = [](uint64_t v) {
-    v &= 0xFFFFFFFFull;
-    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
-    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
-    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
-    v = (v | (v << 2)) & 0x3333333333333333ull;
-    v = (v | (v << 1)) & 0x5555555555555555ull;
-    return v;
-  };
-  return spread(x) | (spread(y) << 1);
+// Position of (x, y) along the Hilbert curve over [0, 2^order)^2: the
+// quadrant digits from the top level down, each level's frame rotated or
+// reflected so that consecutive positions are edge neighbours.
+inline uint64_t hilbert_key(uint32_t x, uint32_t y, int order) {
+  const uint32_t side = 1u << order;
+  uint64_t d = 0;
+  for (uint32_t s = side >> 1; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += (uint64_t)s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = side - 1 - x;
+        y = side - 1 - y;
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
 }
 
 // Builds the plan. xy: lattice coordinates of the free rows (natural order,
@@ -89,9 +99,9 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   out.n = n;
   if (n <= 0 || W > kPlanSlots || S < 1 || max_region >= kPlanLocalMax || max_region < BS)
     return false;
-  // Z-order of the free rows. The lattice runs from 0 to N (a power of two),
-  // and its last row and column would take a bit of their own in the key,
-  // which would string them out into blocks that are thin strips with wide
+  // Hilbert order of the free rows. The lattice runs from 0 to N (a power of
+  // two), and its last row and column would take a level of their own in the
+  // key, which would string them out into blocks that are thin strips with wide
   // halos; coordinates are therefore clamped to N - 1, which keeps those
   // vertices next to their neighbours (ties go to the lower natural row).
   int32_t maxc = 0;
@@ -99,6 +109,8 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
   uint32_t top = 1;
   while (maxc > 1 && top * 2 <= (uint32_t)maxc) top *= 2;
   const uint32_t clampc = maxc > 1 ? top - 1 : (uint32_t)maxc;
+  int order = 0;
+  while (order < 31 && (1u << order) <= clampc) ++order;
   const int nthr = std::max(1, threads);
   auto range = [&](int t, int nt) {
     return std::pair<int64_t, int64_t>(n * t / nt, n * (t + 1) / nt);
@@ -111,8 +123,8 @@ inline bool build_ss_plan(int S, int BS, int64_t n, const int32_t* xy, const int
     const auto [i0, i1] = range(t, nt);
     uint64_t m = 0;
     for (int64_t i = i0; i < i1; ++i) {
-      const uint64_t k = morton_key(std::min((uint32_t)xy[2 * i], clampc),
-                                    std::min((uint32_t)xy[2 * i + 1], clampc));
+      const uint64_t k = hilbert_key(std::min((uint32_t)xy[2 * i], clampc),
+                                     std::min((uint32_t)xy[2 * i + 1], clampc), order);
       m = std::max(m, k);
       kr[i] = (k << 32) | (uint64_t)i;
     }

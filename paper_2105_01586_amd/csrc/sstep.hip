@@ -7,8 +7,8 @@
 // (solver.hip) pays one kernel boundary per iteration; on systems that fit
 // in the caches that boundary, not memory traffic, sets the time. Here one
 // launch advances S iterations:
-//   - each block owns BS consecutive rows of a Z-order numbering of the free
-//     rows and reads the basis of the previous launch on its region (its rows
+//   - each block owns BS consecutive rows of a Hilbert-order numbering of the
+//     free rows and reads the basis of the previous launch on its region (its rows
 //     and the rows within S hops, ss_plan.h);
 //   - every block reduces the Gram matrix G = W^T D W of the previous basis
 //     W = [P_0..P_S, Z_0..Z_{S-1}] (28 values; block sums exact or FP64,

@@ -1,7 +1,7 @@
 """Row blocks with halos for the s-step CG launch (csrc/ss_plan.h), compiled
 with g++ and run on the oracle's K_FF (CPU only).
 
-Checks, per block: the own rows are the block's slice of a Z-order numbering
+Checks, per block: the own rows are the block's slice of a Hilbert-order numbering
 of the free rows (last lattice row and column clamped onto the one before); the region holds exactly the rows within S hops of them,
 in rings of increasing distance; every local matrix row decodes to that
 row's entries of K_FF (neighbour slot and weight -1/2 or -1, padding pointing
@@ -78,14 +78,37 @@ def run_plan(exe, tmp_path, xy, ell, n, n_pad, W, S, BS, tasks=4):
     return plan
 
 
-def morton(x, y):
-    def spread(v):
-        v = v.astype(np.uint64)
-        for sh, m in ((16, 0x0000FFFF0000FFFF), (8, 0x00FF00FF00FF00FF), (4, 0x0F0F0F0F0F0F0F0F),
-                      (2, 0x3333333333333333), (1, 0x5555555555555555)):
-            v = (v | (v << np.uint64(sh))) & np.uint64(m)
-        return v
-    return spread(x) | (spread(y) << np.uint64(1))
+def hilbert(x, y, order):
+    """Position along the Hilbert curve over [0, 2^order)^2 (quadrant digits
+    from the top level down, the frame turned at each level)."""
+    x = np.asarray(x, np.int64).copy()
+    y = np.asarray(y, np.int64).copy()
+    side = 1 << order
+    d = np.zeros_like(x)
+    s = side >> 1
+    while s > 0:
+        rx = (x & s) > 0
+        ry = (y & s) > 0
+        d += s * s * ((3 * rx.astype(np.int64)) ^ ry.astype(np.int64))
+        turn = ~ry
+        flip = turn & rx
+        x[flip] = side - 1 - x[flip]
+        y[flip] = side - 1 - y[flip]
+        x[turn], y[turn] = y[turn].copy(), x[turn].copy()
+        s >>= 1
+    return d
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 5])
+def test_hilbert_reference(order):
+    # the test's own curve: every cell once, consecutive cells edge neighbours
+    side = 1 << order
+    xs, ys = np.meshgrid(np.arange(side), np.arange(side), indexing="ij")
+    d = hilbert(xs.ravel(), ys.ravel(), order)
+    assert np.array_equal(np.sort(d), np.arange(side * side))
+    at = np.empty((side * side, 2), np.int64)
+    at[d] = np.stack([xs.ravel(), ys.ravel()], axis=1)
+    assert np.all(np.abs(np.diff(at, axis=0)).sum(axis=1) == 1)
 
 
 def check_plan(plan, K_FF, xy, S, BS):
@@ -95,7 +118,8 @@ def check_plan(plan, K_FF, xy, S, BS):
     assert np.array_equal(np.sort(perm), np.arange(n))
     top = 1 << int(np.floor(np.log2(max(int(xy.max()), 1))))
     c = top - 1 if xy.max() > 1 else int(xy.max())
-    keys = morton(np.minimum(xy[perm, 0], c), np.minimum(xy[perm, 1], c))
+    order = int(c).bit_length()
+    keys = hilbert(np.minimum(xy[perm, 0], c), np.minimum(xy[perm, 1], c), order)
     assert np.all((keys[1:] > keys[:-1]) | ((keys[1:] == keys[:-1]) & (perm[1:] > perm[:-1])))
     inv = np.empty(n, np.int64)
     inv[perm] = np.arange(n)
