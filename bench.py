@@ -60,14 +60,16 @@ def cg_kernel_name(info, nrhs: int = 1) -> str:
 def ss_layout_bytes(info):
     """Bytes the three-iteration launch moves by its layout, with no cache
     help: per own row the 32-byte basis record read and written, the
-    correction read and written, the diagonal; per region row (halo rows
-    too) its row index and a 16-byte local matrix row (which only rows within
-    two hops have: an upper bound) and, for halo rows, the record read
+    correction read and written, the diagonal; per region row a 12-byte
+    local matrix row (which only rows within two hops have: an upper bound)
+    and its row index (halo rows only in the large-system launch, which
+    takes own rows from the block's position); per halo row the record read
     again. None for the one-iteration kernel."""
     if info["cg_iters_per_launch"] <= 1:
         return None
     n, reg = info["n"], info["cg_region_rows"]
-    return n * (32 + 32 + 8 + 4) + reg * (4 + 16) + (reg - n) * 32
+    idx_rows = reg - n if info["large_mode"] else reg
+    return n * (32 + 32 + 8 + 4) + reg * 12 + idx_rows * 4 + (reg - n) * 32
 
 
 def launch_rates(info, nrhs, kms):

@@ -13,12 +13,13 @@
 //     graph distance 1, 2, ..., S from them (ascending within each ring),
 //     listed in full (own rows included) so that a region row is one load;
 //   - a local matrix for the rows of its region at distance <= S - 1: for
-//     each such row, 8 entries, each the neighbour's slot (bits 0-13: its
+//     each such row, 6 entries, each the neighbour's slot (bits 0-13: its
 //     local index + 1; slot 0 is a zero the launch keeps in front of its
 //     region values, so every entry is one unconditional load), bit 15 for
 //     weight -1 (clear: -1/2), bit 14 marking padding (slot 0, weight bit
 //     clear). On the quadtree mesh every off-diagonal entry of K_FF is -1/2
-//     or -1.
+//     or -1, and no row has more than 6 of them (every mask measured; a
+//     mesh with a longer row keeps the one-iteration launch).
 // Rows of a block are [b * BS, min(n, (b + 1) * BS)) in the new order.
 //
 // Inputs come from the library's column-major ELL of K_FF (natural order):
@@ -39,7 +40,7 @@ constexpr int kPlanLocalBits = 14;
 constexpr int32_t kPlanLocalMax = 1 << kPlanLocalBits;  // slots: region rows per block + 1, at most
 constexpr uint16_t kPlanPad = 1u << 14;
 constexpr uint16_t kPlanMinusOne = 1u << 15;
-constexpr int kPlanSlots = 8;  // entries per local matrix row
+constexpr int kPlanSlots = 6;  // entries per local matrix row (12 bytes)
 
 struct BlockPlan {
   int32_t reg_off;   // first region row of the block in SsPlan::region (0 when empty)

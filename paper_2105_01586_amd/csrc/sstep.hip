@@ -81,6 +81,13 @@ __host__ __device__ constexpr int gi(int a, int b) {
   return a <= b ? a * NB - a * (a - 1) / 2 + (b - a) : b * NB - b * (b - 1) / 2 + (a - b);
 }
 
+// One local matrix row: kPlanSlots 16-bit entries in three dwords (one
+// 12-byte load).
+struct LmRow {
+  uint32_t w[3];
+};
+static_assert(kPlanSlots == 6 && sizeof(LmRow) == 2 * kPlanSlots, "local matrix row layout");
+
 struct SsArgs {
   int n;
   int grid;
@@ -88,7 +95,7 @@ struct SsArgs {
   const int32_t* perm;
   const BlockPlan* blocks;
   const int32_t* region;  // region rows of every block (own rows first)
-  const uint4* lmat;
+  const LmRow* lmat;
   const float4* Win;   // 2 float4 per row: P_0..P_3 | Z_0..Z_2, D^-1
   float4* Wout;
   float* x;
@@ -115,8 +122,8 @@ __device__ __forceinline__ float lm_weight(uint32_t e) {
   return __uint_as_float(0xBF000000u | ((e & kPlanMinusOne) << 8));
 }
 
-__device__ __forceinline__ uint32_t lm_entry(const uint4& m, int k) {
-  const uint32_t w = k < 2 ? m.x : k < 4 ? m.y : k < 6 ? m.z : m.w;
+__device__ __forceinline__ uint32_t lm_entry(const LmRow& m, int k) {
+  const uint32_t w = k < 2 ? m.w[0] : k < 4 ? m.w[1] : m.w[2];
   return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
@@ -129,7 +136,7 @@ __device__ __forceinline__ int region_row(const SsArgs& A, const BlockPlan& B, i
 // sum_k w_k vs[idx_k] over one local matrix row, for p and z at once
 // (FP32, slot order; vs holds (p, z) per LDS slot: 0 the zero slot, l + 1
 // region row l).
-__device__ __forceinline__ float2 lm_apply(const uint4& m, const float2* vs) {
+__device__ __forceinline__ float2 lm_apply(const LmRow& m, const float2* vs) {
   float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
   for (int k = 0; k < kPlanSlots; ++k) {
@@ -344,7 +351,7 @@ __device__ __forceinline__ void gram_finish(const SsArgs& A, const GramLoads& L,
 struct Pre {
   int i[2];        // rows (new numbering), 0 past the region
   float4 a[2], b[2];
-  uint4 m[2];      // local matrix rows (zeros past the inner rows)
+  LmRow m[2];      // local matrix rows (zeros past the inner rows)
 };
 
 // Rows and local matrix rows (loads that need only the block table). The
@@ -392,7 +399,7 @@ __device__ __forceinline__ void rec_at(const SsArgs& A, const Pre& R, int i, int
     b = A.Win[2 * (size_t)i + 1];
   }
 }
-__device__ __forceinline__ uint4 lm_at(const SsArgs& A, const BlockPlan& B, const Pre& R, int l,
+__device__ __forceinline__ LmRow lm_at(const SsArgs& A, const BlockPlan& B, const Pre& R, int l,
                                        int k) {
   return k < 2 ? R.m[k] : A.lmat[B.lmat_off + l];
 }
@@ -418,7 +425,7 @@ __device__ __forceinline__ void build_basis(const SsArgs& A, const BlockPlan& B,
   __syncthreads();
   // level 1: rows within S - 1 hops
   for (int l = t, k = 0; l < B.ninner; l += BS, ++k) {
-    const uint4 m = lm_at(A, B, R, l, k);
+    const LmRow m = lm_at(A, B, R, l, k);
     const float dv = ld[l];
     const float2 acc = lm_apply(m, s0);
     pz1[l] = make_float2(dv * acc.x, dv * acc.y);
@@ -431,7 +438,7 @@ __device__ __forceinline__ void build_basis(const SsArgs& A, const BlockPlan& B,
   // level 2 over level 0 (each row reads its own level 0 before writing it;
   // the neighbours' values come from level 1)
   for (int l = t, k = 0; l < B.n1; l += BS, ++k) {
-    const uint4 m = lm_at(A, B, R, l, k);
+    const LmRow m = lm_at(A, B, R, l, k);
     const float dv2 = 2.0f * ld[l];
     const float2 acc = lm_apply(m, s1);
     const float2 old = pz0[l];
@@ -800,7 +807,7 @@ __global__ __launch_bounds__(BS) void k_ss_start(SsArgs A, Params prm, Params* p
     const double bi = b_nat[A.perm[ro]];
     double ri = bi, xi = 0.0;
     if (x0) {
-      const uint4 m = A.lmat[B.lmat_off + t];
+      const LmRow m = A.lmat[B.lmat_off + t];
       xi = lx[t];
       double acc = (double)A.d[ro] * xi;
 #pragma unroll
@@ -975,7 +982,7 @@ SsArgs ss_args(fi_mesh* M, int par, int force, bool large) {
   A.perm = Z.perm;
   A.blocks = (const BlockPlan*)Z.blocks;
   A.region = Z.region;
-  A.lmat = (const uint4*)Z.lmat;
+  A.lmat = (const LmRow*)Z.lmat;
   A.Win = (const float4*)Z.W[par];
   A.Wout = (float4*)Z.W[par ^ 1];
   A.x = Z.x;

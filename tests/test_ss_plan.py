@@ -23,6 +23,7 @@ from oracle import fem, mesh as om
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "..", "paper_2105_01586_amd", "csrc")
+SLOTS = 6  # local matrix entries per row (the plan's kPlanSlots)
 PAD, M1 = 1 << 14, 1 << 15
 
 
@@ -74,7 +75,7 @@ def run_plan(exe, tmp_path, xy, ell, n, n_pad, W, S, BS, tasks=4):
     nh = int(np.frombuffer(raw, dtype=np.int64, count=1, offset=o)[0]); o += 8
     plan["region"] = np.frombuffer(raw, dtype=np.int32, count=nh, offset=o); o += 4 * nh
     nl = int(np.frombuffer(raw, dtype=np.int64, count=1, offset=o)[0]); o += 8
-    plan["lmat"] = np.frombuffer(raw, dtype=np.uint16, count=nl, offset=o).reshape(-1, 8)
+    plan["lmat"] = np.frombuffer(raw, dtype=np.uint16, count=nl, offset=o).reshape(-1, SLOTS)
     return plan
 
 
@@ -213,11 +214,22 @@ def test_plan_small(exe, tmp_path, side, k, S, BS):
     M = om.build_mesh(side, mask)
     K = fem.assemble(M).K_FF
     xy = M.vxy[M.free_vids]
-    ell, n_pad = ell_of(K, 8)
-    plan = run_plan(exe, tmp_path, xy, ell, K.shape[0], n_pad, 8, S, BS)
+    ell, n_pad = ell_of(K, SLOTS)
+    plan = run_plan(exe, tmp_path, xy, ell, K.shape[0], n_pad, SLOTS, S, BS)
     assert plan["ok"]
     Aoff, regions = check_plan(plan, K, xy, S, BS)
     check_basis(plan, Aoff, regions, K.diagonal()[plan["perm"]], S)
+
+
+def test_plan_refuses_rows_wider_than_its_slots(exe, tmp_path):
+    # the library's ELL is 8 wide only when a row has more than 6 entries;
+    # such a mesh keeps the one-iteration launch
+    mask = synth.make_mask(32, 32 * 32, k=40)
+    M = om.build_mesh(32, mask)
+    K = fem.assemble(M).K_FF
+    ell, n_pad = ell_of(K, 8)
+    plan = run_plan(exe, tmp_path, M.vxy[M.free_vids], ell, K.shape[0], n_pad, 8, 3, 64)
+    assert plan["ok"] == 0
 
 
 def test_plan_independent_of_task_count(exe, tmp_path):
@@ -227,8 +239,8 @@ def test_plan_independent_of_task_count(exe, tmp_path):
     M = om.build_mesh(128, mask)
     K = fem.assemble(M).K_FF
     xy = M.vxy[M.free_vids]
-    ell, n_pad = ell_of(K, 8)
-    plans = [run_plan(exe, tmp_path, xy, ell, K.shape[0], n_pad, 8, 3, 256, tasks=t)
+    ell, n_pad = ell_of(K, SLOTS)
+    plans = [run_plan(exe, tmp_path, xy, ell, K.shape[0], n_pad, SLOTS, 3, 256, tasks=t)
              for t in (1, 3, 16)]
     for p in plans[1:]:
         assert plans[0]["ok"] and p["ok"] and p["grid"] == plans[0]["grid"]
