@@ -13,7 +13,9 @@
 // into tasks by the caller, independently of how many threads execute them,
 // so results never depend on the thread count. One caller uses the workers at
 // a time: a call made while another is running (builder threads of the server
-// building meshes side by side) runs its tasks on its own thread.
+// building meshes side by side) runs its tasks on its own thread, and so does
+// a call in a process forked from the one that started the workers (a fork
+// copies no threads).
 #pragma once
 
 #include <algorithm>
@@ -23,6 +25,7 @@
 #include <functional>
 #include <mutex>
 #include <memory>
+#include <unistd.h>
 #include <new>
 #include <thread>
 #include <type_traits>
@@ -69,8 +72,12 @@ class HostPool {
   template <class F>
   void run(int64_t ntasks, F&& body) {
     if (ntasks <= 0) return;
+    if (ntasks == 1 || workers_.empty() || getpid() != pid_) {
+      for (int64_t t = 0; t < ntasks; ++t) body(t, ntasks);
+      return;
+    }
     std::unique_lock<std::mutex> own(run_mu_, std::try_to_lock);
-    if (ntasks == 1 || workers_.empty() || !own.owns_lock()) {
+    if (!own.owns_lock()) {
       for (int64_t t = 0; t < ntasks; ++t) body(t, ntasks);
       return;
     }
@@ -91,7 +98,7 @@ class HostPool {
   }
 
  private:
-  explicit HostPool(int nthreads) {
+  explicit HostPool(int nthreads) : pid_(getpid()) {
     for (int i = 1; i < nthreads; ++i) workers_.emplace_back([this] { loop(); });
     for (auto& w : workers_) w.detach();  // parked until the process ends
   }
@@ -120,6 +127,7 @@ class HostPool {
     }
   }
 
+  const pid_t pid_;  // the process the workers run in
   std::vector<std::thread> workers_;
   std::mutex run_mu_;  // held by the caller that has the workers
   std::mutex mu_;

@@ -67,6 +67,21 @@ def test_host_mesh_bit_exact(N, k, seed):
     assert np.array_equal(h["mask_vids"], o.mask_vids)
 
 
+def _child_tri(N, m):
+    return fi.host_mesh(N, m)["tri"]
+
+
+def test_host_mesh_in_forked_child():
+    # the host builders' worker threads are not copied by fork: a forked
+    # child builds on its own thread and gets the same mesh
+    import multiprocessing as mp
+    m = rand_mask(256, 2621, 8)
+    h = fi.host_mesh(256, m)  # starts the workers in this process
+    with mp.get_context("fork").Pool(1) as pool:
+        tri = pool.apply_async(_child_tri, (256, m)).get(timeout=120)
+    assert np.array_equal(tri, h["tri"])
+
+
 def test_host_mesh_workload_512():
     w = synth.WORKLOADS["tonal512"]
     m = w.mask()
