@@ -211,6 +211,35 @@ def test_three_iterations_per_launch(ctx, monkeypatch):
     assert st3["launches"] > 0 and 1.8 * st3["launches"] <= st1["launches"]
 
 
+def test_kept_device_blocks_give_the_same_bits():
+    """A context keeps a destroyed mesh's device blocks for the meshes built
+    after it; meshes built in turn on such blocks (as a mask-growth loop
+    builds them, each larger than the last) give the same bits as on a fresh
+    context."""
+    side, mask, f = case("c2")
+    rng = np.random.default_rng(11)
+    extra = np.setdiff1d(rng.choice(side * side, 3000, replace=False), mask)
+    masks = [np.asarray(mask), np.union1d(mask, extra[:1000]), np.union1d(mask, extra)]
+    fd = dev(f)
+
+    def run(c, m):
+        M = fi.Mesh(c, side, m.astype(np.int32))
+        u, _ = M.inpaint(f=fd)
+        out = u.cpu().numpy()
+        M.close()
+        return out
+
+    c1 = fi.Context(0)
+    reused = [run(c1, m) for m in masks]
+    c1.close()
+    for k, (m, u) in enumerate(zip(masks, reused)):
+        print(f"  mesh {k}: {m.size} mask pixels", flush=True)
+        c2 = fi.Context(0)
+        fresh = run(c2, m)
+        c2.close()
+        assert np.array_equal(u, fresh)
+
+
 def test_reduction_launch_same_bits_up_to_256_blocks(ctx, monkeypatch):
     """Up to 256 blocks the reduction launch (used by batched and multi-solve
     launches) sums the Gram partials in the order the blocks themselves use,
