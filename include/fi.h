@@ -161,6 +161,8 @@ typedef struct fi_mesh_info {
                                   Hilbert order with 3-hop halos), else 1 */
   int64_t cg_max_region;  /* rows of the largest block region (3 per launch), or 0 */
   int64_t cg_region_rows; /* region rows over all blocks (own rows included), or 0 */
+  int64_t cg_lmat_rows;   /* local matrix rows over all blocks (rows within S - 1
+                             hops), or 0 */
 } fi_mesh_info;
 
 /* Default solve options: FP32 inner PCG with FP64 refinement to 1e-10. */
@@ -359,6 +361,20 @@ int fi_mesh_export_geometry(const fi_mesh* mesh, int32_t* vxy, int32_t* tri, int
  * slots), float64 val[nnz_fd]. Synchronous. */
 int fi_mesh_export_csr(const fi_mesh* mesh, int32_t* ff_rowptr, int32_t* ff_col, double* ff_val,
                        int32_t* fd_rowptr, int32_t* fd_col, double* fd_val);
+
+/* Export of the plan of the S-iteration launch (rows in blocks of 512 with
+ * S-hop halos over a Hilbert-order numbering of the free rows; see
+ * cg_iters_per_launch), for checking it against a builder of its own (host
+ * buffers, each may be NULL): perm int32[n] (new index -> free row);
+ * blocks int32[cg_blocks][8] (region offset, local matrix offset, own rows,
+ * rows within 1 hop, within S - 1 hops, within S hops, the largest region in
+ * block 0's seventh field, 0); region int32[cg_region_rows] (each block's
+ * rows: own rows, then the rings at distance 1..S, ascending within a ring);
+ * lmat uint16[cg_lmat_rows][6] (per local matrix row: neighbour slot = local
+ * index + 1 in bits 0-13, 0 and bit 14 for padding, bit 15 for weight -1).
+ * FI_E_INVALID if the mesh has no such plan. Synchronous. */
+int fi_mesh_export_ss_plan(const fi_mesh* mesh, int32_t* perm, int32_t* blocks, int32_t* region,
+                           uint16_t* lmat);
 
 /* Owner triangle of every pixel, int32[P] device output (the rule of
  * fi_error). */

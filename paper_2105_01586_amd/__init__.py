@@ -39,6 +39,7 @@ EXPORTED_SYMBOLS = (
     "fi_ctx_create", "fi_ctx_set_stream", "fi_ctx_destroy", "fi_mesh_build", "fi_mesh_destroy",
     "fi_mesh_get_info", "fi_assemble", "fi_inpaint", "fi_vertex_values", "fi_error",
     "fi_adjoint", "fi_solve", "fi_error_dev", "fi_tonal_opt", "fi_mesh_export_geometry", "fi_mesh_export_csr",
+    "fi_mesh_export_ss_plan",
     "fi_owner_map", "fi_topk_new_pixels", "fi_time_cg_kernel", "fi_cg_kernel_bytes",
     "fi_host_mesh_build", "fi_host_mesh_info", "fi_host_mesh_export", "fi_host_mesh_destroy",
     "fi_mesh_upload", "fi_grow_mask", "fi_server_opts_default", "fi_server_create",
@@ -101,7 +102,7 @@ class _MeshInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("N", "P", "V", "T", "L", "n", "m", "nnz_ff", "nnz_fd", "device_bytes",
                  "cg_blocks", "cg_block_size", "large_mode", "cg_iters_per_launch",
-                 "cg_max_region", "cg_region_rows")]
+                 "cg_max_region", "cg_region_rows", "cg_lmat_rows")]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -189,6 +190,7 @@ def library() -> ctypes.CDLL:
                                         ctypes.POINTER(_TonalStats)]),
         "fi_mesh_export_geometry": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "fi_mesh_export_csr": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "fi_mesh_export_ss_plan": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fi_owner_map": (ctypes.c_int, [vp, vp]),
         "fi_topk_new_pixels": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp]),
         "fi_topk_new_pixels_noalloc": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp]),
@@ -661,6 +663,19 @@ class Mesh:
         _check(library().fi_mesh_export_csr(self._h, c(a["ff_rowptr"]), c(a["ff_col"]),
                                             c(a["ff_val"]), c(a["fd_rowptr"]), c(a["fd_col"]),
                                             c(a["fd_val"])), "fi_mesh_export_csr")
+        return a
+
+    def export_ss_plan(self) -> dict:
+        """The S-iteration launch's plan (fi_mesh_export_ss_plan) as numpy arrays."""
+        i = self.info
+        a = {"perm": np.empty(self.n, np.int32),
+             "blocks": np.empty((int(i["cg_blocks"]), 8), np.int32),
+             "region": np.empty(int(i["cg_region_rows"]), np.int32),
+             "lmat": np.empty((int(i["cg_lmat_rows"]), 6), np.uint16)}
+        c = lambda x: x.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(library().fi_mesh_export_ss_plan(self._h, c(a["perm"]), c(a["blocks"]),
+                                                c(a["region"]), c(a["lmat"])),
+               "fi_mesh_export_ss_plan")
         return a
 
     def owner_map(self):

@@ -575,6 +575,7 @@ int fi_mesh_get_info(const fi_mesh* M, fi_mesh_info* info) {
   info->cg_iters_per_launch = M->ss ? kSsIters : 1;
   info->cg_max_region = M->ss ? M->ss->max_region : 0;
   info->cg_region_rows = M->ss ? M->ss->region_rows : 0;
+  info->cg_lmat_rows = M->ss ? M->ss->lmat_rows : 0;
   return FI_OK;
 }
 
@@ -774,6 +775,14 @@ int fi_mesh_export_geometry(const fi_mesh* M, int32_t* vxy, int32_t* tri, int32_
   fi_host_mesh view;
   view.mesh = M->host;  // copy: exports are for checking, not the hot path
   return fi_host_mesh_export(&view, vxy, tri, leaves, free_vids, mask_vids);
+}
+
+int fi_mesh_export_ss_plan(const fi_mesh* M, int32_t* perm, int32_t* blocks, int32_t* region,
+                           uint16_t* lmat) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  FI_HIP_TRY(hipSetDevice(M->ctx->device));
+  return ss_export_plan(M, perm, blocks, region, lmat);
 }
 
 int fi_mesh_export_csr(const fi_mesh* Mc, int32_t* ff_rowptr, int32_t* ff_col, double* ff_val,

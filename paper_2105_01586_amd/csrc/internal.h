@@ -397,6 +397,14 @@ int solver_channel_setup(fi_mesh* S, const fi_mesh* M);
 // FI_CG_SSTEP=0) and refreshes the matrix values after later ones.
 constexpr int kSsIters = 3;  // CG iterations per launch
 int ss_setup(fi_mesh* M);
+// The plan built on the device (ss_plan_dev.hip) into Z's plan arrays and
+// shape; *built stays false when a region would exceed max_region rows or a
+// row has more entries than the plan's slots (the mesh keeps the
+// one-iteration launch).
+int ss_plan_on_device(fi_mesh* M, int S, int max_region, SsState& Z, bool* built);
+// Copies the plan to host buffers (fi_mesh_export_ss_plan).
+int ss_export_plan(const fi_mesh* M, int32_t* perm, int32_t* blocks, int32_t* region,
+                   uint16_t* lmat);
 void ss_release(fi_mesh* M);
 // FP32 solve of K_FF x = b64 from x0 (natural order, may be NULL) with the
 // S-iteration launch; the result in d_x64 (natural order).

@@ -40,6 +40,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -1100,10 +1101,68 @@ int large_alloc(fi_mesh* M, SsState& Z) {
 
 int slot_of(const double* x0) { return 0 + (x0 ? 1 : 0); }  // FP32 cold / warm prediction slots
 
+// The host builder's plan (ss_plan.h), from the ELL copied back from the
+// device: what the device builder is checked against, and its stand-in with
+// FI_SS_PLAN=host.
+int plan_on_host(fi_mesh* M, SsState& Z, bool* built) {
+  *built = false;
+  hipStream_t st = M->ctx->stream;
+  const int64_t n = M->n;
+  // the ELL comes back through the context's pinned staging buffer when it
+  // fits there (several times faster than a copy to pageable memory)
+  const size_t ell_words = (size_t)M->ell_w * M->n_pad;
+  std::unique_lock<std::mutex> staging_hold;
+  int32_t* ell = M->cache ? (int32_t*)M->cache->staging(ell_words * 4, staging_hold) : nullptr;
+  std::vector<int32_t> ell_pageable;
+  if (!ell) {
+    ell_pageable.resize(ell_words);
+    ell = ell_pageable.data();
+  }
+  FI_HIP_TRY(hipMemcpyAsync(ell, M->d_ell, ell_words * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  HostVec<int32_t> xy((size_t)2 * n);
+  pool_run(16, [&](int64_t t, int64_t nt) {
+    const auto [i0, i1] = split_range(n, nt, t);
+    for (int64_t i = i0; i < i1; ++i) {
+      const int32_t v = M->host.free_vids[i];
+      xy[2 * i] = M->host.vxy[2 * (size_t)v];
+      xy[2 * i + 1] = M->host.vxy[2 * (size_t)v + 1];
+    }
+  });
+  SsPlan plan;
+  if (!build_ss_plan(S, BS, n, xy.data(), ell, M->n_pad, M->ell_w, 16, kMaxRegion, plan))
+    return FI_OK;  // keep the one-iteration launch
+  if (staging_hold.owns_lock()) staging_hold.unlock();
+  plan.blocks[0].pad0 = plan.max_region;  // the LDS layout size, in the first block's spare field
+  int rc = 0;
+  if ((rc = device_alloc(M, (void**)&Z.perm, (size_t)n * 4)) ||
+      (rc = device_alloc(M, &Z.blocks, plan.blocks.size() * sizeof(BlockPlan))) ||
+      (rc = device_alloc(M, (void**)&Z.region, std::max<size_t>(plan.region.size(), 1) * 4)) ||
+      (rc = device_alloc(M, &Z.lmat, std::max<size_t>(plan.lmat.size(), kPlanSlots) * 2)))
+    return rc;
+  FI_HIP_TRY(hipMemcpyAsync(Z.perm, plan.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+  FI_HIP_TRY(hipMemcpyAsync(Z.blocks, plan.blocks.data(), plan.blocks.size() * sizeof(BlockPlan),
+                            hipMemcpyHostToDevice, st));
+  FI_HIP_TRY(hipMemcpyAsync(Z.region, plan.region.data(), plan.region.size() * 4,
+                            hipMemcpyHostToDevice, st));
+  if (!plan.lmat.empty())
+    FI_HIP_TRY(hipMemcpyAsync(Z.lmat, plan.lmat.data(), plan.lmat.size() * 2,
+                              hipMemcpyHostToDevice, st));
+  // the host copies come from vectors that end with this call
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  Z.grid = plan.grid;
+  Z.max_region = plan.max_region;
+  Z.region_rows = (int64_t)plan.region.size();
+  Z.lmat_rows = (int64_t)plan.lmat.size() / kPlanSlots;
+  *built = true;
+  return FI_OK;
+}
+
 }  // namespace
 
-// Builds the plan after the first assembly of a quadtree mesh; later calls
-// refresh the values that come from the matrix.
+// Builds the plan after the first assembly of a quadtree mesh (on the device,
+// or on the host for server requests and with FI_SS_PLAN=host; both give the
+// same plan); later calls refresh the values that come from the matrix.
 int ss_setup(fi_mesh* M) {
   hipStream_t st = M->ctx->stream;
   if (!M->ss) {
@@ -1111,51 +1170,24 @@ int ss_setup(fi_mesh* M) {
     if (const char* env = std::getenv("FI_CG_SSTEP"))
       if (std::atoi(env) == 0) return FI_OK;
     const int64_t n = M->n;
-    // the ELL comes back through the context's pinned staging buffer when it
-    // fits there (several times faster than a copy to pageable memory)
-    const size_t ell_words = (size_t)M->ell_w * M->n_pad;
-    std::unique_lock<std::mutex> staging_hold;
-    int32_t* ell = M->cache ? (int32_t*)M->cache->staging(ell_words * 4, staging_hold) : nullptr;
-    std::vector<int32_t> ell_pageable;
-    if (!ell) {
-      ell_pageable.resize(ell_words);
-      ell = ell_pageable.data();
-    }
-    FI_HIP_TRY(hipMemcpyAsync(ell, M->d_ell, ell_words * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    FI_HIP_TRY(hipStreamSynchronize(st));
-    HostVec<int32_t> xy((size_t)2 * n);
-    pool_run(16, [&](int64_t t, int64_t nt) {
-      const auto [i0, i1] = split_range(n, nt, t);
-      for (int64_t i = i0; i < i1; ++i) {
-        const int32_t v = M->host.free_vids[i];
-        xy[2 * i] = M->host.vxy[2 * (size_t)v];
-        xy[2 * i + 1] = M->host.vxy[2 * (size_t)v + 1];
-      }
-    });
-    SsPlan plan;
-    if (!build_ss_plan(S, BS, n, xy.data(), ell, M->n_pad, M->ell_w, 16, kMaxRegion,
-                       plan))
-      return FI_OK;  // keep the one-iteration launch
-    if (staging_hold.owns_lock()) staging_hold.unlock();
-    SsState* Z = new SsState();
-    Z->grid = plan.grid;
-    Z->max_region = plan.max_region;
-    Z->region_rows = (int64_t)plan.region.size();
-    Z->lmat_rows = (int64_t)plan.lmat.size() / kPlanSlots;
+    std::unique_ptr<SsState> plan(new SsState());
+    bool built = false;
+    // server requests (meshes carved out of an arena) build it on the host:
+    // their builder threads run beside the device's work, and the device
+    // build's scratch memory is outside a request's footprint bound
+    const char* where = std::getenv("FI_SS_PLAN");
+    const bool on_host = M->arena || (where && std::strcmp(where, "host") == 0);
+    int rc = on_host ? plan_on_host(M, *plan, &built)
+                     : ss_plan_on_device(M, S, kMaxRegion, *plan, &built);
+    if (rc || !built) return rc;  // not built: keep the one-iteration launch
+    SsState* Z = plan.release();
     bool large = Z->grid > kSmallGrid;
     if (const char* env = std::getenv("FI_CG_LARGE"))
       if (std::atoi(env) == 1) large = true;
     Z->large = large;
-    // the LDS layout size travels in the first block's spare field
-    plan.blocks[0].pad0 = plan.max_region;
     M->ss = Z;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
-    int rc = 0;
-    if ((rc = device_alloc(M, (void**)&Z->perm, nn * 4)) ||
-        (rc = device_alloc(M, &Z->blocks, plan.blocks.size() * sizeof(BlockPlan))) ||
-        (rc = device_alloc(M, (void**)&Z->region, std::max<size_t>(plan.region.size(), 1) * 4)) ||
-        (rc = device_alloc(M, &Z->lmat, std::max<size_t>(plan.lmat.size(), 8) * 2)) ||
-        (rc = device_alloc(M, (void**)&Z->W[0], nn * 32)) ||
+    if ((rc = device_alloc(M, (void**)&Z->W[0], nn * 32)) ||
         (rc = device_alloc(M, (void**)&Z->W[1], nn * 32)) ||
         (rc = device_alloc(M, (void**)&Z->x, nn * 4)) ||
         (rc = device_alloc(M, (void**)&Z->d, nn * 4)) ||
@@ -1167,26 +1199,35 @@ int ss_setup(fi_mesh* M) {
         (rc = device_alloc(M, (void**)&Z->red, NGP * 8)) ||
         (rc = large_alloc(M, *Z)))
       return rc;
-    FI_HIP_TRY(hipMemcpyAsync(Z->perm, plan.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
-    FI_HIP_TRY(hipMemcpyAsync(Z->blocks, plan.blocks.data(), plan.blocks.size() * sizeof(BlockPlan),
-                              hipMemcpyHostToDevice, st));
-    if (!plan.region.empty())
-      FI_HIP_TRY(hipMemcpyAsync(Z->region, plan.region.data(), plan.region.size() * 4,
-                                hipMemcpyHostToDevice, st));
-    if (!plan.lmat.empty())
-      FI_HIP_TRY(hipMemcpyAsync(Z->lmat, plan.lmat.data(), plan.lmat.size() * 2,
-                                hipMemcpyHostToDevice, st));
     // every basis slot starts finite (the first launch reads only D^-1)
     FI_HIP_TRY(hipMemsetAsync(Z->W[0], 0, nn * 32, st));
     FI_HIP_TRY(hipMemsetAsync(Z->part, 0, part_bytes(Z->grid), st));  // the padding stays 0
     FI_HIP_TRY(hipMemsetAsync(Z->W[1], 0, nn * 32, st));
-    // the host copies above come from vectors that end with this call
-    FI_HIP_TRY(hipStreamSynchronize(st));
   }
   SsState& Z = *M->ss;
   hipLaunchKernelGGL(k_ss_values, dim3((unsigned)((M->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      st, (int)M->n, Z.perm, M->d_diag64, M->d_dinv32, Z.d, Z.W[0], Z.W[1]);
   FI_HIP_TRY(hipGetLastError());
+  return FI_OK;
+}
+
+int ss_export_plan(const fi_mesh* M, int32_t* perm, int32_t* blocks, int32_t* region,
+                   uint16_t* lmat) {
+  if (!M || !M->ss) return fail(FI_E_INVALID, "the mesh has no S-iteration plan");
+  const SsState& Z = *M->ss;
+  hipStream_t st = M->ctx->stream;
+  if (perm)
+    FI_HIP_TRY(hipMemcpyAsync(perm, Z.perm, (size_t)M->n * 4, hipMemcpyDeviceToHost, st));
+  if (blocks)
+    FI_HIP_TRY(hipMemcpyAsync(blocks, Z.blocks, (size_t)Z.grid * sizeof(BlockPlan),
+                              hipMemcpyDeviceToHost, st));
+  if (region)
+    FI_HIP_TRY(hipMemcpyAsync(region, Z.region, (size_t)Z.region_rows * 4, hipMemcpyDeviceToHost,
+                              st));
+  if (lmat && Z.lmat_rows > 0)
+    FI_HIP_TRY(hipMemcpyAsync(lmat, Z.lmat, (size_t)Z.lmat_rows * kPlanSlots * 2,
+                              hipMemcpyDeviceToHost, st));
+  FI_HIP_TRY(hipStreamSynchronize(st));
   return FI_OK;
 }
 
