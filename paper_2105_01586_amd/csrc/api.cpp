@@ -193,7 +193,8 @@ int alloc_workspace(fi_mesh* M) {
   int rc = 0;
   const int64_t n = M->n, m = M->m, T = M->T;
   TRY(alloc_n(M, &M->d_cnt, std::max(2 * (n + 1), m + 1)));
-  TRY(alloc_n(M, &M->d_scan_tmp, scan_tmp_ints(std::max(std::max(n, m), T) + 1)));
+  // scans over free rows, mask rows, triangles and vertices
+  TRY(alloc_n(M, &M->d_scan_tmp, scan_tmp_ints(std::max({n, m, T, M->V}) + 1)));
   TRY(alloc_n(M, &M->d_ff_rowptr, n + 1));
   TRY(alloc_n(M, &M->d_fd_rowptr, n + 1));
   TRY(alloc_n(M, &M->d_df_rowptr, m + 1));
@@ -531,8 +532,8 @@ int fi::mesh_upload(fi_ctx* ctx, fi_host_mesh** host, Arena* arena, fi_mesh** ou
       (rc = upload(M, &M->d_leaves, H.leaves)) || (rc = upload(M, &M->d_vmap, H.vmap)) ||
       (rc = upload(M, &M->d_free_vids, H.free_vids)) ||
       (rc = upload(M, &M->d_mask_vids, H.mask_vids)) ||
-      (rc = upload(M, &M->d_mask_pix, H.mask_pix)) || (rc = upload(M, &M->d_vt_ptr, H.vt_ptr)) ||
-      (rc = upload(M, &M->d_vt_idx, H.vt_idx)) || (rc = alloc_workspace(M)) ||
+      (rc = upload(M, &M->d_mask_pix, H.mask_pix)) || (rc = alloc_workspace(M)) ||
+      (rc = build_vertex_triangles(M)) ||
       (rc = build_pixel_maps(M)) || (rc = fi_assemble(M))) {
     std::string keep = g_last_error;
     (*host)->mesh = std::move(M->host);

@@ -317,17 +317,11 @@ int build_delaunay_mesh(int N, const int32_t* mask, int64_t m, const int32_t* un
       H.free_vids.push_back(v);
     }
   }
-  // vertex -> (triangle, corner) lists, ascending
-  H.vt_ptr.assign((size_t)V + 1, 0);
-  for (int32_t x : H.tri) ++H.vt_ptr[(size_t)x + 1];
-  for (int v = 0; v < V; ++v) H.vt_ptr[v + 1] += H.vt_ptr[v];
-  H.vt_idx.resize(3 * (size_t)nt);
-  std::vector<int32_t> cur(H.vt_ptr.begin(), H.vt_ptr.end() - 1);
-  for (int t = 0; t < nt; ++t)
-    for (int k = 0; k < 3; ++k) H.vt_idx[cur[H.tri[3 * t + k]]++] = 3 * t + k;
-  H.max_incident = 0;
-  for (int v = 0; v < V; ++v) H.max_incident = std::max(H.max_incident, H.vt_ptr[v + 1] - H.vt_ptr[v]);
-  if (H.max_incident > kMaxIncidentGeneral)
+  // incident triangles per vertex (the lists themselves are built on the
+  // device): the assembly holds at most kMaxIncidentGeneral
+  std::vector<int32_t> inc((size_t)V, 0);
+  for (int32_t x : H.tri) ++inc[(size_t)x];
+  if (V > 0 && *std::max_element(inc.begin(), inc.end()) > kMaxIncidentGeneral)
     return fail(FI_E_INVALID, "a vertex has more incident triangles than the assembly supports");
   return FI_OK;
 }

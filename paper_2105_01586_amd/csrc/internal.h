@@ -40,9 +40,6 @@ struct HostMesh {
   HostVec<int32_t> free_vids;  // n
   HostVec<int32_t> mask_vids;  // m
   HostVec<int32_t> mask_pix;   // m: linear pixel index of each mask slot
-  HostVec<int32_t> vt_ptr;     // V+1: incident (triangle, corner) lists
-  HostVec<int32_t> vt_idx;     // 3T: 3 * triangle + corner, ascending
-  int max_incident = 0;            // largest incident-triangle count
   bool delaunay = false;           // the Delaunay mesh (no quadtree leaves)
 
   int64_t L() const { return (int64_t)leaves.size() / 4 - 1; }
@@ -344,6 +341,9 @@ int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uin
 int raster_blocks(const fi_mesh* M);
 // Owner map and per-triangle pixel lists (geometry only; once per mesh).
 int build_pixel_maps(fi_mesh* M);
+// Vertex -> (triangle, corner) lists on the device from the uploaded
+// triangles (needs the workspace); checks the incident-triangle bounds.
+int build_vertex_triangles(fi_mesh* M);
 // t = R^T r, or R^T (w r) when w is given (weighted least squares).
 int launch_raster_transpose(fi_mesh* M, const double* r, double* tpart,
                             const double* w = nullptr);

@@ -1322,6 +1322,98 @@ int build_pixel_maps_general(fi_mesh* M) {
   return FI_OK;
 }
 
+// Vertex -> (triangle, corner) lists, built on the device from the
+// triangles: counts, their exclusive sum, a fill in any order, then each list
+// put in ascending order (e = 3 * triangle + corner), so the lists do not
+// depend on the order of the atomic additions. The vertex work vector holds
+// the counts and fill positions while they are built.
+__global__ __launch_bounds__(kBlock) void k_vt_count(int64_t E, const int32_t* __restrict__ tri,
+                                                     int32_t* __restrict__ cnt) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < E) atomicAdd(&cnt[tri[e]], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_vt_fill(int64_t E, const int32_t* __restrict__ tri,
+                                                    int32_t* __restrict__ pos,
+                                                    int32_t* __restrict__ vt_idx) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < E) vt_idx[atomicAdd(&pos[tri[e]], 1)] = (int32_t)e;
+}
+
+// Sorts each list (at most `limit` entries; longer lists set bit 0 of flag);
+// with border_limit > 0, a vertex on the square's border with more than that
+// many triangles sets bit 1 (its open fan has one neighbour more than
+// triangles, and a row holds kMaxIncident neighbours).
+__global__ __launch_bounds__(kBlock) void k_vt_sort(int V, int N, const int32_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ vxy,
+                                                    int32_t* __restrict__ vt_idx, int limit,
+                                                    int border_limit, int32_t* __restrict__ flag) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= V) return;
+  const int a = ptr[v], deg = ptr[v + 1] - a;
+  if (deg > limit) {
+    atomicOr(flag, 1);
+    return;
+  }
+  if (border_limit > 0 && deg > border_limit) {
+    const int x = vxy[2 * v], y = vxy[2 * v + 1];
+    if (x == 0 || y == 0 || x == N || y == N) atomicOr(flag, 2);
+  }
+  int32_t l[kMaxIncidentGeneral];
+  for (int i = 0; i < deg; ++i) l[i] = vt_idx[a + i];
+  for (int i = 1; i < deg; ++i) {
+    const int32_t x = l[i];
+    int j = i - 1;
+    while (j >= 0 && l[j] > x) {
+      l[j + 1] = l[j];
+      --j;
+    }
+    l[j + 1] = x;
+  }
+  for (int i = 0; i < deg; ++i) vt_idx[a + i] = l[i];
+}
+
+int build_vertex_triangles(fi_mesh* M) {
+  hipStream_t st = M->ctx->stream;
+  const int64_t V = M->V, E = 3 * M->T;
+  int rc = 0;
+  if ((rc = device_alloc(M, (void**)&M->d_vt_ptr, (size_t)(V + 1) * sizeof(int32_t))) ||
+      (rc = device_alloc(M, (void**)&M->d_vt_idx, (size_t)std::max<int64_t>(E, 1) * sizeof(int32_t))))
+    return rc;
+  int32_t* cnt = (int32_t*)M->d_uvert;  // scratch: V doubles hold V + 1 counts
+  int32_t* flag = M->d_cnt;             // scratch until the assembly counts rows
+  FI_HIP_TRY(hipMemsetAsync(cnt, 0, (size_t)(V + 1) * sizeof(int32_t), st));
+  FI_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  if (E > 0) {
+    hipLaunchKernelGGL(k_vt_count, dim3(grid_for(E)), dim3(kBlock), 0, st, E, M->d_tri, cnt);
+    FI_LAUNCH_CHECK();
+  }
+  int rc2 = scan_exclusive(st, cnt, M->d_vt_ptr, V + 1, M->d_scan_tmp);
+  if (rc2) return rc2;
+  FI_HIP_TRY(hipMemcpyAsync(cnt, M->d_vt_ptr, (size_t)V * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                            st));
+  if (E > 0) {
+    hipLaunchKernelGGL(k_vt_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, E, M->d_tri, cnt,
+                       M->d_vt_idx);
+    FI_LAUNCH_CHECK();
+  }
+  const bool general = M->host.delaunay;
+  hipLaunchKernelGGL(k_vt_sort, dim3(grid_for(V)), dim3(kBlock), 0, st, (int)V, M->N,
+                     M->d_vt_ptr, M->d_vxy, M->d_vt_idx,
+                     general ? kMaxIncidentGeneral : kMaxIncident,
+                     general ? 0 : kMaxIncident - 1, flag);
+  FI_LAUNCH_CHECK();
+  int32_t bad = 0;
+  FI_HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  if (bad & 1)
+    return fail(FI_E_INVALID, general ? "Delaunay mesh: a vertex has more than 31 incident triangles"
+                                      : "internal: vertex with more incident triangles than expected");
+  if (bad & 2)
+    return fail(FI_E_INVALID, "internal: border vertex with more incident triangles than expected");
+  return FI_OK;
+}
+
 int build_pixel_maps(fi_mesh* M) {
   if (M->host.delaunay) return build_pixel_maps_general(M);
   hipStream_t st = M->ctx->stream;

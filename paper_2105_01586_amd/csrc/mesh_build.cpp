@@ -20,10 +20,10 @@
 // ranks in row-major (y, x) order, found with a bitset and popcounts.
 //
 // Every step runs on the host pool in tasks fixed by the data (rows of a
-// level, subtrees, chunks of leaves, vertices or triangle corners), so the
-// mesh is the same whatever the number of threads: per-task pieces are
-// concatenated in order, and the only atomic step (the vertex -> triangle
-// lists) is put in ascending order afterwards.
+// level, subtrees, chunks of leaves or vertices), so the mesh is the same
+// whatever the number of threads: per-task pieces are concatenated in order.
+// The vertex -> triangle lists are built on the device from the triangles
+// (build_vertex_triangles), which also checks the incident-triangle bounds.
 
 #include <algorithm>
 #include <atomic>
@@ -367,76 +367,6 @@ int build_host_mesh(int N, const int32_t* mask, int64_t m, HostMesh& H) {
     }
   });
 
-  // ---- vertex -> (triangle, corner) adjacency ----------------------------
-  H.vt_ptr.resize((size_t)(V + 1));
-  pool_run(vch, [&](int64_t t, int64_t nt) {
-    const auto [v0, v1] = split_range(V + 1, nt, t);
-    std::fill(H.vt_ptr.begin() + v0, H.vt_ptr.begin() + v1, 0);
-  });
-  const int64_t E = 3 * T;
-  const int64_t ech = chunks_for(E);
-  pool_run(ech, [&](int64_t t, int64_t nt) {
-    const auto [e0, e1] = split_range(E, nt, t);
-    for (int64_t e = e0; e < e1; ++e)
-      __atomic_fetch_add(&H.vt_ptr[(size_t)H.tri[(size_t)e] + 1], 1, __ATOMIC_RELAXED);
-  });
-  // A vertex on the square's border has an open fan, one neighbour more than
-  // triangles; the assembly's neighbour slots hold kMaxIncident.
-  std::vector<int64_t> coff((size_t)vch);
-  std::vector<int32_t> cmax((size_t)vch, 0);
-  std::vector<uint8_t> cborder((size_t)vch, 1);
-  pool_run(vch, [&](int64_t t, int64_t nt) {
-    const auto [v0, v1] = split_range(V, nt, t);
-    int64_t c = 0;
-    int32_t mx = 0;
-    bool ok = true;
-    for (int64_t v = v0; v < v1; ++v) {
-      const int32_t inc = H.vt_ptr[(size_t)v + 1];
-      const int32_t x = H.vxy[(size_t)(2 * v)], y = H.vxy[(size_t)(2 * v + 1)];
-      ok &= !(x == 0 || y == 0 || x == N || y == N) || inc <= kMaxIncident - 1;
-      mx = std::max(mx, inc);
-      c += inc;
-    }
-    coff[(size_t)t] = c;
-    cmax[(size_t)t] = mx;
-    cborder[(size_t)t] = ok;
-  });
-  exclusive_scan(coff);
-  for (int64_t t = 0; t < vch; ++t) H.max_incident = std::max(H.max_incident, cmax[(size_t)t]);
-  const bool border_ok = std::all_of(cborder.begin(), cborder.end(), [](uint8_t b) { return b; });
-  if (H.max_incident > kMaxIncident)
-    return fail(FI_E_INVALID, "internal: vertex with more incident triangles than expected");
-  if (!border_ok)
-    return fail(FI_E_INVALID, "internal: border vertex with more incident triangles than expected");
-  // list starts, and a copy of them that the fill below advances
-  HostVec<int32_t> fill((size_t)V);
-  pool_run(vch, [&](int64_t t, int64_t nt) {
-    const auto [v0, v1] = split_range(V, nt, t);
-    int64_t acc = coff[(size_t)t];
-    for (int64_t v = v0; v < v1; ++v) {
-      const int32_t inc = H.vt_ptr[(size_t)v + 1];
-      H.vt_ptr[(size_t)v] = (int32_t)acc;  // slot v is no longer read as a count
-      fill[(size_t)v] = (int32_t)acc;
-      acc += inc;
-    }
-  });
-  H.vt_ptr[(size_t)V] = (int32_t)E;
-  H.vt_idx.resize((size_t)E);
-  {
-    pool_run(ech, [&](int64_t t, int64_t nt) {
-      const auto [e0, e1] = split_range(E, nt, t);
-      for (int64_t e = e0; e < e1; ++e) {
-        const int32_t v = H.tri[(size_t)e];
-        H.vt_idx[(size_t)__atomic_fetch_add(&fill[(size_t)v], 1, __ATOMIC_RELAXED)] = (int32_t)e;
-      }
-    });
-    // each list in ascending order (e = 3 * t + corner)
-    pool_run(vch, [&](int64_t t, int64_t nt) {
-      const auto [v0, v1] = split_range(V, nt, t);
-      for (int64_t v = v0; v < v1; ++v)
-        std::sort(H.vt_idx.begin() + H.vt_ptr[(size_t)v], H.vt_idx.begin() + H.vt_ptr[(size_t)v + 1]);
-    });
-  }
   return FI_OK;
 }
 

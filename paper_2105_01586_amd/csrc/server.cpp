@@ -141,11 +141,11 @@ namespace {
 int64_t footprint_bound(const HostMesh& H, int iters) {
   const int64_t V = H.V(), T = H.T(), L = H.L(), P = (int64_t)H.N * H.N;
   const int64_t m = (int64_t)H.mask_vids.size(), n = (int64_t)H.free_vids.size();
-  int64_t deg_free = 0, deg_mask = 0;
-  for (int64_t v = 0; v < V; ++v) {
-    const int64_t d = (int64_t)H.vt_ptr[v + 1] - H.vt_ptr[v] + 1;
-    if (H.vmap[v] >= 0) deg_free += d;
-    else deg_mask += d;
+  // sum over the free (mask) vertices of incident triangles + 1
+  int64_t deg_free = n, deg_mask = m;
+  for (int64_t e = 0; e < 3 * T; ++e) {
+    if (H.vmap[(size_t)H.tri[(size_t)e]] >= 0) ++deg_free;
+    else ++deg_mask;
   }
   int64_t total = 0;
   auto add = [&](int64_t count, int64_t size) {
@@ -156,7 +156,7 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   add(2 * V, 4); add(3 * T, 4); add(4 * (L + 1), 4); add(V, 4); add(n, 4); add(m, 4); add(m, 4);
   add(V + 1, 4); add(3 * T, 4);
   // workspace
-  add(std::max(2 * (n + 1), m + 1), 4); add(scan_tmp_ints(std::max(std::max(n, m), T) + 1), 4);
+  add(std::max(2 * (n + 1), m + 1), 4); add(scan_tmp_ints(std::max({n, m, T, V}) + 1), 4);
   add(n + 1, 4); add(n + 1, 4); add(m + 1, 4);
   add(n, 8); add(n, 8); add(n, 4); add(n, 8); add(n, 8); add(n, 8); add(n, 8);
   add(n, 4); add(n, 4); add(4 * n, 4); add(4 * n, 4);
