@@ -178,7 +178,13 @@ const char* fi_version(void);
 
 /* Context: binds a device and a HIP stream (hipStream_t passed as void*; NULL
  * means the null stream). The stream is borrowed, not owned. A context must
- * outlive every mesh built on it: destroy the meshes first. */
+ * outlive every mesh built on it: destroy the meshes first.
+ * A context keeps the device blocks of meshes destroyed on it (up to 2 GiB)
+ * for the meshes built after them (a request takes a kept block of at least
+ * its size and at most a quarter plus 1 MiB above it), and one pinned host
+ * staging buffer (up to 256 MiB); fi_ctx_destroy frees them once no mesh
+ * built on the context is left. A failed device allocation frees the kept
+ * blocks and tries again. */
 int fi_ctx_create(int device, void* stream, fi_ctx** out);
 int fi_ctx_set_stream(fi_ctx* ctx, void* stream);
 int fi_ctx_destroy(fi_ctx* ctx);
@@ -190,6 +196,8 @@ int fi_ctx_destroy(fi_ctx* ctx);
  * FI_E_INVALID (shape, ordering, range), FI_E_EMPTY_MASK (m == 0). */
 int fi_mesh_build(fi_ctx* ctx, int width, int height, const int32_t* mask_idx, int64_t m,
                   fi_mesh** out);
+/* Waits for the device, then returns the mesh's device blocks to its
+ * context (see fi_ctx_create) or, for a server request, to its arena. */
 int fi_mesh_destroy(fi_mesh* mesh);
 int fi_mesh_get_info(const fi_mesh* mesh, fi_mesh_info* info);
 
