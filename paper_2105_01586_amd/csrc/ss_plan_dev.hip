@@ -232,7 +232,11 @@ __global__ __launch_bounds__(kRingThreads) void k_plan_rings(RingArgs A) {
 }
 
 // Device memory for the build only: a block the context keeps, else its own
-// allocation; handed back (or freed) once the stream is done with it.
+// allocation; once the stream is done with it, handed to the context (up to
+// kKeepTmp, for the next mesh's build) or freed (a large mesh's scratch
+// would otherwise stay held beside the mesh).
+constexpr size_t kKeepTmp = (size_t)256 << 20;
+
 struct TmpBlock {
   fi_mesh* M;
   void* p = nullptr;
@@ -253,7 +257,7 @@ struct TmpBlock {
   ~TmpBlock() {
     if (!p) return;
     (void)hipStreamSynchronize(M->ctx->stream);
-    if (M->cache) M->cache->give(p, got);
+    if (M->cache && got <= kKeepTmp) M->cache->give(p, got);
     else (void)hipFree(p);
   }
 };
