@@ -76,6 +76,26 @@ void DeviceCache::give(void* p, size_t bytes) {
   (void)hipFree(p);
 }
 
+int TmpBlock::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  got = bytes;
+  if (M->cache && (p = M->cache->take(bytes, &got))) return FI_OK;
+  got = bytes;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return fail(FI_E_NOMEM, "device scratch of a build step");
+  }
+  return FI_OK;
+}
+
+TmpBlock::~TmpBlock() {
+  if (!p) return;
+  (void)hipStreamSynchronize(M->ctx->stream);
+  if (M->cache && got <= kKeepTmp) M->cache->give(p, got);
+  else (void)hipFree(p);
+}
+
 DeviceCache::~DeviceCache() {
   release_all();
   if (staging_) (void)hipHostFree(staging_);
@@ -495,6 +515,13 @@ int fi_mesh_build(fi_ctx* ctx, int width, int height, const int32_t* mask_idx, i
                   fi_mesh** out) {
   if (!ctx || !out) return fail(FI_E_INVALID, "ctx or out is NULL");
   *out = nullptr;
+  // built on the device; with FI_MESH_HOST=1 on the host and uploaded (the
+  // same mesh either way)
+  const char* env = std::getenv("FI_MESH_HOST");
+  if (!(env && std::atoi(env) == 1)) {
+    if (width != height) return fail(FI_E_INVALID, "image must be square");
+    return mesh_build_on_device(ctx, width, mask_idx, m, out);
+  }
   fi_host_mesh* h = nullptr;
   int rc = fi_host_mesh_build(width, height, mask_idx, m, &h);
   if (rc) return rc;
@@ -508,6 +535,42 @@ int fi_mesh_upload(fi_ctx* ctx, fi_host_mesh** host, fi_mesh** out) {
 }
 
 }  // extern "C"
+
+int fi::mesh_build_on_device(fi_ctx* ctx, int N, const int32_t* mask, int64_t m, fi_mesh** out) {
+  FI_HIP_TRY(hipSetDevice(ctx->device));
+  fi_mesh* M = new fi_mesh();
+  M->ctx = ctx;
+  M->device = ctx->device;
+  M->cache = ctx->cache;
+  int rc = FI_OK;
+  if ((rc = mesh_geometry_on_device(M, N, mask, m)) || (rc = alloc_workspace(M)) ||
+      (rc = build_vertex_triangles(M)) || (rc = build_pixel_maps(M)) || (rc = fi_assemble(M))) {
+    std::string keep = g_last_error;
+    free_mesh(M);
+    g_last_error = keep;
+    return rc;
+  }
+  *out = M;
+  return FI_OK;
+}
+
+int fi::mesh_host_coords(const fi_mesh* M, std::vector<int32_t>& vxy,
+                         std::vector<int32_t>& free_vids) {
+  if (!M->host.vxy.empty() || M->V == 0) {
+    vxy.assign(M->host.vxy.begin(), M->host.vxy.end());
+    free_vids.assign(M->host.free_vids.begin(), M->host.free_vids.end());
+    return FI_OK;
+  }
+  vxy.resize((size_t)(2 * M->V));
+  free_vids.resize((size_t)M->n);
+  hipStream_t st = M->ctx->stream;
+  FI_HIP_TRY(hipMemcpyAsync(vxy.data(), M->d_vxy, vxy.size() * 4, hipMemcpyDeviceToHost, st));
+  if (M->n > 0)
+    FI_HIP_TRY(hipMemcpyAsync(free_vids.data(), M->d_free_vids, free_vids.size() * 4,
+                              hipMemcpyDeviceToHost, st));
+  FI_HIP_TRY(hipStreamSynchronize(st));
+  return FI_OK;
+}
 
 int fi::mesh_upload(fi_ctx* ctx, fi_host_mesh** host, Arena* arena, fi_mesh** out) {
   if (!ctx || !out || !host || !*host) return fail(FI_E_INVALID, "NULL argument");
@@ -773,6 +836,24 @@ int fi_mesh_export_geometry(const fi_mesh* M, int32_t* vxy, int32_t* tri, int32_
                             int32_t* free_vids, int32_t* mask_vids) {
   int rc = check_mesh(M);
   if (rc) return rc;
+  if (M->host.vxy.empty() && M->V > 0) {  // built on the device: read the arrays back
+    FI_HIP_TRY(hipSetDevice(M->ctx->device));
+    hipStream_t st = M->ctx->stream;
+    FI_HIP_TRY(hipStreamSynchronize(st));
+    if (vxy) FI_HIP_TRY(hipMemcpy(vxy, M->d_vxy, (size_t)(2 * M->V) * 4, hipMemcpyDeviceToHost));
+    if (tri) FI_HIP_TRY(hipMemcpy(tri, M->d_tri, (size_t)(3 * M->T) * 4, hipMemcpyDeviceToHost));
+    if (leaves) {
+      std::vector<int32_t> lv((size_t)(4 * (M->L + 1)));
+      FI_HIP_TRY(hipMemcpy(lv.data(), M->d_leaves, lv.size() * 4, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < M->L; ++i)
+        for (int k = 0; k < 3; ++k) leaves[3 * i + k] = lv[(size_t)(4 * i + k)];
+    }
+    if (free_vids && M->n > 0)
+      FI_HIP_TRY(hipMemcpy(free_vids, M->d_free_vids, (size_t)M->n * 4, hipMemcpyDeviceToHost));
+    if (mask_vids && M->m > 0)
+      FI_HIP_TRY(hipMemcpy(mask_vids, M->d_mask_vids, (size_t)M->m * 4, hipMemcpyDeviceToHost));
+    return FI_OK;
+  }
   fi_host_mesh view;
   view.mesh = M->host;  // copy: exports are for checking, not the hot path
   return fi_host_mesh_export(&view, vxy, tri, leaves, free_vids, mask_vids);

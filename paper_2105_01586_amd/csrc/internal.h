@@ -135,6 +135,23 @@ class DeviceCache {
   size_t staging_bytes_ = 0;
 };
 
+// Device scratch of one build step (the device mesh builder, the device
+// s-step plan): a block the mesh's context keeps, else its own allocation;
+// once the stream is done with it, handed to the context (up to kKeepTmp,
+// for the next mesh's build) or freed (a large mesh's scratch would
+// otherwise stay held beside the mesh).
+struct TmpBlock {
+  static constexpr size_t kKeepTmp = (size_t)256 << 20;
+  fi_mesh* M;
+  void* p = nullptr;
+  size_t got = 0;
+  explicit TmpBlock(fi_mesh* m) : M(m) {}
+  TmpBlock(const TmpBlock&) = delete;
+  TmpBlock& operator=(const TmpBlock&) = delete;
+  int alloc(size_t bytes);
+  ~TmpBlock();
+};
+
 // The S-iteration CG launch (sstep.hip): its plan on the device and its
 // vectors, all in the plan's Hilbert-order numbering of the free rows.
 struct SsState {
@@ -307,6 +324,16 @@ int device_alloc(fi_mesh* M, void** p, size_t bytes);
 // Uploads a host mesh and assembles it; memory from `arena` when not NULL.
 // On success the host mesh is consumed (*host set to NULL).
 int mesh_upload(fi_ctx* ctx, fi_host_mesh** host, Arena* arena, fi_mesh** out);
+// The quadtree mesh built on the device from the mask (host array), then the
+// same set-up as mesh_upload.
+int mesh_build_on_device(fi_ctx* ctx, int N, const int32_t* mask, int64_t m, fi_mesh** out);
+// The quadtree mesh's geometry built on the device (mesh_build_dev.hip; the
+// host builder's arrays, bit for bit) into M's device arrays and sizes; the
+// host copy keeps N and levels only (its arrays stay empty).
+int mesh_geometry_on_device(fi_mesh* M, int N, const int32_t* mask, int64_t m);
+// Host copies of a mesh's coordinates and free vertex ids: the host mesh's,
+// or read back when the mesh was built on the device.
+int mesh_host_coords(const fi_mesh* M, std::vector<int32_t>& vxy, std::vector<int32_t>& free_vids);
 // Frees a mesh. A mesh without an arena waits for the device first; an arena
 // mesh returns its memory at once (its owner has waited for its last work).
 void free_mesh(fi_mesh* M);

@@ -52,6 +52,19 @@ __device__ __forceinline__ uint32_t hilbert_pos(uint32_t x, uint32_t y, int orde
   return d;
 }
 
+// Largest lattice coordinate of a free row.
+__global__ void k_plan_maxc(int n, const int32_t* __restrict__ free_vids,
+                            const int32_t* __restrict__ vxy, int32_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t v = 0;
+  if (i < n) {
+    const int r = free_vids[i];
+    v = max(vxy[2 * (size_t)r], vxy[2 * (size_t)r + 1]);
+  }
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(out, v);
+}
+
 __global__ void k_plan_keys(int n, const int32_t* __restrict__ free_vids,
                             const int32_t* __restrict__ vxy, uint32_t clampc, int order,
                             uint64_t* __restrict__ keys) {
@@ -231,37 +244,6 @@ __global__ __launch_bounds__(kRingThreads) void k_plan_rings(RingArgs A) {
   }
 }
 
-// Device memory for the build only: a block the context keeps, else its own
-// allocation; once the stream is done with it, handed to the context (up to
-// kKeepTmp, for the next mesh's build) or freed (a large mesh's scratch
-// would otherwise stay held beside the mesh).
-constexpr size_t kKeepTmp = (size_t)256 << 20;
-
-struct TmpBlock {
-  fi_mesh* M;
-  void* p = nullptr;
-  size_t got = 0;
-  explicit TmpBlock(fi_mesh* m) : M(m) {}
-  int alloc(size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    got = bytes;
-    if (M->cache && (p = M->cache->take(bytes, &got))) return FI_OK;
-    got = bytes;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      return fail(FI_E_NOMEM, "s-step plan: temporary device memory");
-    }
-    return FI_OK;
-  }
-  ~TmpBlock() {
-    if (!p) return;
-    (void)hipStreamSynchronize(M->ctx->stream);
-    if (M->cache && got <= kKeepTmp) M->cache->give(p, got);
-    else (void)hipFree(p);
-  }
-};
-
 unsigned grid_of(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -275,17 +257,18 @@ int ss_plan_on_device(fi_mesh* M, int S, int max_region, SsState& Z, bool* built
     return FI_OK;
   // lattice clamp of the host builder: coordinates up to the largest power of
   // two not above the largest coordinate of a free row, minus one
-  std::vector<int32_t> tmax(16, 0);
-  pool_run(16, [&](int64_t t, int64_t nt) {
-    const auto [i0, i1] = split_range(n, nt, t);
-    int32_t mx = 0;
-    for (int64_t i = i0; i < i1; ++i) {
-      const int32_t v = M->host.free_vids[i];
-      mx = std::max({mx, M->host.vxy[2 * (size_t)v], M->host.vxy[2 * (size_t)v + 1]});
-    }
-    tmax[t] = mx;
-  });
-  const int32_t maxc = *std::max_element(tmax.begin(), tmax.end());
+  int32_t maxc = 0;
+  {
+    TmpBlock mx(M);
+    int rc0 = mx.alloc(256);
+    if (rc0) return rc0;
+    FI_HIP_TRY(hipMemsetAsync(mx.p, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_plan_maxc, dim3(grid_of(n, 256)), dim3(256), 0, st, (int)n,
+                       M->d_free_vids, M->d_vxy, (int32_t*)mx.p);
+    FI_HIP_TRY(hipGetLastError());
+    FI_HIP_TRY(hipMemcpyAsync(&maxc, mx.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FI_HIP_TRY(hipStreamSynchronize(st));
+  }
   uint32_t top = 1;
   while (maxc > 1 && top * 2 <= (uint32_t)maxc) top *= 2;
   const uint32_t clampc = maxc > 1 ? top - 1 : (uint32_t)maxc;

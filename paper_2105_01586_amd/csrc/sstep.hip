@@ -1120,13 +1120,16 @@ int plan_on_host(fi_mesh* M, SsState& Z, bool* built) {
   }
   FI_HIP_TRY(hipMemcpyAsync(ell, M->d_ell, ell_words * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   FI_HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int32_t> hv, hf;
+  int rc = mesh_host_coords(M, hv, hf);
+  if (rc) return rc;
   HostVec<int32_t> xy((size_t)2 * n);
   pool_run(16, [&](int64_t t, int64_t nt) {
     const auto [i0, i1] = split_range(n, nt, t);
     for (int64_t i = i0; i < i1; ++i) {
-      const int32_t v = M->host.free_vids[i];
-      xy[2 * i] = M->host.vxy[2 * (size_t)v];
-      xy[2 * i + 1] = M->host.vxy[2 * (size_t)v + 1];
+      const int32_t v = hf[i];
+      xy[2 * i] = hv[2 * (size_t)v];
+      xy[2 * i + 1] = hv[2 * (size_t)v + 1];
     }
   });
   SsPlan plan;
@@ -1134,7 +1137,6 @@ int plan_on_host(fi_mesh* M, SsState& Z, bool* built) {
     return FI_OK;  // keep the one-iteration launch
   if (staging_hold.owns_lock()) staging_hold.unlock();
   plan.blocks[0].pad0 = plan.max_region;  // the LDS layout size, in the first block's spare field
-  int rc = 0;
   if ((rc = device_alloc(M, (void**)&Z.perm, (size_t)n * 4)) ||
       (rc = device_alloc(M, &Z.blocks, plan.blocks.size() * sizeof(BlockPlan))) ||
       (rc = device_alloc(M, (void**)&Z.region, std::max<size_t>(plan.region.size(), 1) * 4)) ||
