@@ -190,10 +190,13 @@ int fi_ctx_set_stream(fi_ctx* ctx, void* stream);
 int fi_ctx_destroy(fi_ctx* ctx);
 
 /* Builds the quadtree mesh for an N x N image (width == height == N) and the
- * mask (host array, strictly ascending, in range), uploads it and assembles
- * the stiffness matrix on the device (fi_assemble). The mesh rules are those
- * of Section 2.2 with the quadtree reading stated above. Errors:
- * FI_E_INVALID (shape, ordering, range), FI_E_EMPTY_MASK (m == 0). */
+ * mask (host array, strictly ascending, in range) on the device (the mask is
+ * checked on the host and uploaded), and assembles the stiffness matrix
+ * (fi_assemble). The mesh rules are those of Section 2.2 with the quadtree
+ * reading stated above; the mesh equals fi_host_mesh_build's array for array
+ * (with the environment variable FI_MESH_HOST=1 it is built by that host
+ * builder and uploaded). Synchronous. Errors: FI_E_INVALID (shape, ordering,
+ * range), FI_E_EMPTY_MASK (m == 0). */
 int fi_mesh_build(fi_ctx* ctx, int width, int height, const int32_t* mask_idx, int64_t m,
                   fi_mesh** out);
 /* Waits for the device, then returns the mesh's device blocks to its
