@@ -36,6 +36,8 @@ def masks():
                     + (300 + rng.integers(-60, 60, 15000)) % 1024)
     out.append(("cluster1024", 1024, pts))
     out.append(("r2048", 2048, synth.make_mask(42, 2048 * 2048, k=2048 * 2048 // 20)))
+    out.append(("dense1024", 1024, synth.make_mask(43, 1024 * 1024, k=1024 * 1024 * 7 // 10)))
+    out.append(("r4096", 4096, synth.make_mask(44, 4096 * 4096, k=4096 * 4096 // 50)))
     return out
 
 
