@@ -76,23 +76,29 @@ void DeviceCache::give(void* p, size_t bytes) {
   (void)hipFree(p);
 }
 
-int TmpBlock::alloc(size_t bytes) {
+bool TmpBlock::take(size_t bytes) {
   bytes = (bytes + 255) & ~(size_t)255;
   got = bytes;
-  if (M->cache && (p = M->cache->take(bytes, &got))) return FI_OK;
+  if (M->arena) return (p = M->arena->alloc(bytes)) != nullptr;
+  if (M->cache && (p = M->cache->take(bytes, &got))) return true;
   got = bytes;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     p = nullptr;
     (void)hipGetLastError();
-    return fail(FI_E_NOMEM, "device scratch of a build step");
+    return false;
   }
-  return FI_OK;
+  return true;
+}
+
+int TmpBlock::alloc(size_t bytes) {
+  return take(bytes) ? FI_OK : fail(FI_E_NOMEM, "device scratch of a build step");
 }
 
 TmpBlock::~TmpBlock() {
   if (!p) return;
   (void)hipStreamSynchronize(M->ctx->stream);
-  if (M->cache && got <= kKeepTmp) M->cache->give(p, got);
+  if (M->arena) M->arena->free(p);
+  else if (M->cache && got <= kKeepTmp) M->cache->give(p, got);
   else (void)hipFree(p);
 }
 

@@ -136,10 +136,11 @@ class DeviceCache {
 };
 
 // Device scratch of one build step (the device mesh builder, the device
-// s-step plan): a block the mesh's context keeps, else its own allocation;
-// once the stream is done with it, handed to the context (up to kKeepTmp,
-// for the next mesh's build) or freed (a large mesh's scratch would
-// otherwise stay held beside the mesh).
+// s-step plan). For a mesh in an arena (a server request) it comes from the
+// arena and goes back to it; otherwise it is a block the mesh's context
+// keeps, else its own allocation, and once the stream is done with it it is
+// handed to the context (up to kKeepTmp, for the next mesh's build) or freed
+// (a large mesh's scratch would otherwise stay held beside the mesh).
 struct TmpBlock {
   static constexpr size_t kKeepTmp = (size_t)256 << 20;
   fi_mesh* M;
@@ -148,7 +149,8 @@ struct TmpBlock {
   explicit TmpBlock(fi_mesh* m) : M(m) {}
   TmpBlock(const TmpBlock&) = delete;
   TmpBlock& operator=(const TmpBlock&) = delete;
-  int alloc(size_t bytes);
+  int alloc(size_t bytes);  // FI_E_NOMEM (with the error message) on failure
+  bool take(size_t bytes);  // false on failure, no error recorded
   ~TmpBlock();
 };
 
@@ -429,6 +431,9 @@ int ss_setup(fi_mesh* M);
 // row has more entries than the plan's slots (the mesh keeps the
 // one-iteration launch).
 int ss_plan_on_device(fi_mesh* M, int S, int max_region, SsState& Z, bool* built);
+// Bound of the device scratch ss_plan_on_device takes for n rows (a server
+// request's footprint reserves it).
+int64_t ss_plan_scratch_bound(int64_t n);
 // Copies the plan to host buffers (fi_mesh_export_ss_plan).
 int ss_export_plan(const fi_mesh* M, int32_t* perm, int32_t* blocks, int32_t* region,
                    uint16_t* lmat);

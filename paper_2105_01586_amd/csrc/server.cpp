@@ -174,8 +174,9 @@ int64_t footprint_bound(const HostMesh& H, int iters) {
   // CGLS workspace and the request's buffers
   add(m, 8); add(m, 8); add(P, 8); add(P, 8); add(n, 8); add(8, 8);
   add(P, 1); add(m, 8);
-  // the S-iteration solver's plan and vectors
+  // the S-iteration solver's plan and vectors, and the plan build's scratch
   total += ss_footprint(n);
+  total += ss_plan_scratch_bound(n);
   (void)iters;
   return total;
 }

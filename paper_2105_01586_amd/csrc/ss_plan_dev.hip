@@ -248,6 +248,16 @@ unsigned grid_of(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
 
+// Device scratch of ss_plan_on_device for n rows, as a bound: the keys in and
+// out, the inverse permutation and neighbour lists (52 bytes per row), the
+// ring counts, and for the radix sort's storage 12 bytes per row plus 4 MiB
+// (a pass over 8-bit digits keeps a second copy of the keys and per-block
+// digit counts); with 256-byte rounding of every piece.
+int64_t ss_plan_scratch_bound(int64_t n) {
+  const int64_t nblk = (n + kRingThreads - 1) / kRingThreads;
+  return 256 + 52 * n + (12 * n + ((int64_t)4 << 20)) + 16 * nblk + 8 * 256;
+}
+
 int ss_plan_on_device(fi_mesh* M, int S, int max_region, SsState& Z, bool* built) {
   *built = false;
   hipStream_t st = M->ctx->stream;
@@ -260,8 +270,7 @@ int ss_plan_on_device(fi_mesh* M, int S, int max_region, SsState& Z, bool* built
   int32_t maxc = 0;
   {
     TmpBlock mx(M);
-    int rc0 = mx.alloc(256);
-    if (rc0) return rc0;
+    if (!mx.take(256)) return M->arena ? FI_OK : fail(FI_E_NOMEM, "s-step plan: scratch");
     FI_HIP_TRY(hipMemsetAsync(mx.p, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_plan_maxc, dim3(grid_of(n, 256)), dim3(256), 0, st, (int)n,
                        M->d_free_vids, M->d_vxy, (int32_t*)mx.p);
@@ -287,9 +296,13 @@ int ss_plan_on_device(fi_mesh* M, int S, int max_region, SsState& Z, bool* built
   const size_t o_nb = (o_inv + (size_t)n * 4 + 255) & ~(size_t)255;
   const size_t o_cnt = (o_nb + (size_t)n * kPlanSlots * 4 + 255) & ~(size_t)255;
   const size_t o_flag = o_cnt + (size_t)nblk * sizeof(int4);
+  if (M->arena && (int64_t)(o_flag + 256) > ss_plan_scratch_bound(n) - 256) return FI_OK;
+  // a server request's scratch comes from its arena region, whose bound
+  // reserves ss_plan_scratch_bound(n); should the sort need more, the
+  // request keeps the host builder
   TmpBlock tmp(M);
-  int rc = tmp.alloc(o_flag + 256);
-  if (rc) return rc;
+  if (!tmp.take(o_flag + 256)) return M->arena ? FI_OK : fail(FI_E_NOMEM, "s-step plan: scratch");
+  int rc = 0;
   char* base = (char*)tmp.p;
   uint64_t* keys = (uint64_t*)base;
   uint64_t* sorted = (uint64_t*)(base + o_keys2);

@@ -1163,8 +1163,8 @@ int plan_on_host(fi_mesh* M, SsState& Z, bool* built) {
 }  // namespace
 
 // Builds the plan after the first assembly of a quadtree mesh (on the device,
-// or on the host for server requests and with FI_SS_PLAN=host; both give the
-// same plan); later calls refresh the values that come from the matrix.
+// or on the host with FI_SS_PLAN=host; both give the same plan); later calls
+// refresh the values that come from the matrix.
 int ss_setup(fi_mesh* M) {
   hipStream_t st = M->ctx->stream;
   if (!M->ss) {
@@ -1174,13 +1174,14 @@ int ss_setup(fi_mesh* M) {
     const int64_t n = M->n;
     std::unique_ptr<SsState> plan(new SsState());
     bool built = false;
-    // server requests (meshes carved out of an arena) build it on the host:
-    // their builder threads run beside the device's work, and the device
-    // build's scratch memory is outside a request's footprint bound
+    // server requests (meshes carved out of an arena) take the device
+    // build's scratch from their arena region; one whose scratch would not
+    // fit the region's reserve falls back to the host builder
     const char* where = std::getenv("FI_SS_PLAN");
-    const bool on_host = M->arena || (where && std::strcmp(where, "host") == 0);
+    const bool on_host = where && std::strcmp(where, "host") == 0;
     int rc = on_host ? plan_on_host(M, *plan, &built)
                      : ss_plan_on_device(M, S, kMaxRegion, *plan, &built);
+    if (!rc && !built && !on_host && M->arena) rc = plan_on_host(M, *plan, &built);
     if (rc || !built) return rc;  // not built: keep the one-iteration launch
     SsState* Z = plan.release();
     bool large = Z->grid > kSmallGrid;
