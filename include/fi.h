@@ -644,7 +644,8 @@ double fi_server_clock(fi_server* server);
 /* Finishes every queued request, then frees the server. */
 int fi_server_destroy(fi_server* server);
 /* Admission bound (bytes) of a request with this mask, computed on the host
- * from its mesh; no device use. */
+ * from its mesh; no device use. It covers every device allocation of the
+ * request, including the scratch of the device build of its s-step plan. */
 int fi_server_footprint(int side, const int32_t* mask, int64_t m, int tonal_iters, int64_t* bytes);
 
 #ifdef __cplusplus
