@@ -44,7 +44,7 @@ constexpr int kPlanSlots = 6;  // entries per local matrix row (12 bytes)
 
 struct BlockPlan {
   int32_t reg_off;   // first region row of the block in SsPlan::region (0 when empty)
-  int32_t lmat_off;  // first local matrix row of the block in SsPlan::lmat (rows of 8; 0 when empty)
+  int32_t lmat_off;  // first local matrix row of the block in SsPlan::lmat (0 when empty)
   int32_t nown;      // own rows
   int32_t n1;        // region rows at distance <= 1
   int32_t ninner;    // region rows at distance <= S - 1 (rows of the local matrix)
