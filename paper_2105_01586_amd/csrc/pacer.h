@@ -17,7 +17,7 @@ namespace fi {
 
 constexpr int kChunk = 8;       // step launches per chunk (even)
 constexpr int kAhead = 2;       // chunks queued at most
-constexpr int kPredMargin = 2;  // launches queued beyond the prediction
+constexpr int kPredMargin = 0;  // launches queued beyond the prediction (rounded up to even)
 
 // Step launches a solve used: one per iteration, the start and the end of
 // every inner solve, and the launch that found the outer tolerance met.
