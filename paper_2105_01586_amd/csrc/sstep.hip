@@ -1245,7 +1245,8 @@ int ss_solve(fi_mesh* M, const fi_solve_opts* o, fi_solve_stats* stats, const do
   int rc = ss_launch_start(M, o, epoch, x0, M->ss->large);
   if (rc) return rc;
   const int slot = slot_of(x0);
-  Pacer pc = make_pacer(o->max_inner, o->max_refine, M->pred_launches[slot]);
+  Pacer pc = make_pacer(o->max_inner, o->max_refine, M->pred_launches[slot],
+                        M->ss->large ? kChunk : kChunkShort);
   for (;;) {
     int drc = FI_OK;
     int64_t nl = 0;

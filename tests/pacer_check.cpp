@@ -8,7 +8,6 @@
 #include "pacer.h"
 
 using fi::kAhead;
-using fi::kChunk;
 using fi::kPredMargin;
 
 static int g_fail = 0;
@@ -23,11 +22,14 @@ static int g_fail = 0;
     }                                                    \
   } while (0)
 
+static int kChunk = fi::kChunk;  // the chunk of the pacers under test
+
 // A solve that needs `end` step launches. The host sees its end once the
 // chunk holding launch `end` has run. Returns the launches queued by then,
 // or -2 when the host stops at the limit without seeing the end.
 static long long run(long long max_inner, long long max_refine, long long pred, long long end) {
-  fi::Pacer p = fi::make_pacer(max_inner, max_refine, pred);
+  fi::Pacer p = fi::make_pacer(max_inner, max_refine, pred, kChunk);
+  CHECK(p.chunk == kChunk, "chunk %d, asked for %d", p.chunk, kChunk);
   std::vector<int> chunks;
   long long executed = 0;
   for (long long step = 0; step < 10000000; ++step) {
@@ -56,7 +58,7 @@ static long long run(long long max_inner, long long max_refine, long long pred, 
   return -1;
 }
 
-int main() {
+static int check_all() {
   const long long mi = 20000, mr = 40;
   for (long long end = 1; end <= 400 && !g_fail; ++end) {
     // no prediction: at most the chunks in flight run idle
@@ -80,7 +82,7 @@ int main() {
   // that needs more as not ended
   for (long long end = 1; end <= 80 && !g_fail; ++end) {
     for (long long pred : {0LL, 5LL, 31LL, 500LL}) {
-      fi::Pacer p = fi::make_pacer(1, 1, pred);
+      fi::Pacer p = fi::make_pacer(1, 1, pred, kChunk);
       const long long q = run(1, 1, pred, end);
       if (end <= p.limit) {
         CHECK(q >= end && q <= p.limit, "cap: end %lld pred %lld queued %lld", end, pred, q);
@@ -89,7 +91,26 @@ int main() {
       }
     }
   }
-  CHECK(fi::launches_used(86, 3) == 93, "launch count");
-  if (!g_fail) std::printf("pacer: all properties hold\n");
-  return g_fail;
+  return 0;
+}
+
+int main() {
+  for (int c : {fi::kChunk, fi::kChunkShort, 2, 6}) {
+    kChunk = c;
+    check_all();
+    if (g_fail) {
+      std::printf("(chunks of %d)\n", c);
+      return 1;
+    }
+  }
+  if (fi::make_pacer(10, 1, 0, 7).chunk != 6 || fi::make_pacer(10, 1, 0, 1).chunk != 2) {
+    std::printf("FAIL: odd chunk sizes are not rounded down to even\n");
+    return 1;
+  }
+  if (fi::launches_used(86, 3) != 93) {
+    std::printf("FAIL: launch count\n");
+    return 1;
+  }
+  std::printf("pacer: all properties hold\n");
+  return 0;
 }
