@@ -368,6 +368,9 @@ int launch_raster(fi_mesh* M, const double* uvert, const double* u_in, const uin
                   double* u_out, double* e_out, double* tri_err_out, int32_t* owner_out,
                   double* partial_out);
 int raster_blocks(const fi_mesh* M);
+// u_out = B u (pixel values from vertex values) and *sq_dev = ||u_out||^2,
+// with the bits of launch_raster followed by launch_dot.
+int launch_interp_sq(fi_mesh* M, const double* uvert, double* u_out, double* sq_dev);
 // Owner map and per-triangle pixel lists (geometry only; once per mesh).
 int build_pixel_maps(fi_mesh* M);
 // Vertex -> (triangle, corner) lists on the device from the uploaded
@@ -388,6 +391,9 @@ int launch_reduce(fi_mesh* M, const double* part, int nparts, int ncomp, double*
 int launch_dot(fi_mesh* M, const double* a, const double* b, int64_t n, double* out_dev);
 // y += sign * (num / den) x and y = x + (num / den) y, the ratio read from
 // device scalars (0 when den <= 0).
+// y1 += (num / den) x1 (length n1) and y2 -= (num / den) x2 (length n2), one launch.
+int launch_axpy2_ratio(fi_mesh* M, int64_t n1, int64_t n2, const double* num, const double* den,
+                       const double* x1, double* y1, const double* x2, double* y2);
 int launch_axpy_ratio(fi_mesh* M, int64_t n, const double* num, const double* den, double sign,
                       const double* x, double* y);
 int launch_xpby_ratio(fi_mesh* M, int64_t n, const double* x, const double* num, const double* den,

@@ -786,14 +786,10 @@ __global__ __launch_bounds__(kBlock) void k_tri_err_list(int64_t T,
 
 // u at every pixel from the vertex values (one thread per pixel; the weights
 // are formed exactly as in the leaf-major pass).
-__global__ __launch_bounds__(kBlock) void k_interp_px(int64_t P, int logN,
-                                                      const int32_t* __restrict__ owner,
-                                                      const int32_t* __restrict__ tri,
-                                                      const int32_t* __restrict__ vxy,
-                                                      const double* __restrict__ uv,
-                                                      double* __restrict__ u_out) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= P) return;
+__device__ __forceinline__ double interp_at(int64_t p, int logN, const int32_t* __restrict__ owner,
+                                            const int32_t* __restrict__ tri,
+                                            const int32_t* __restrict__ vxy,
+                                            const double* __restrict__ uv) {
   const int t = owner[p];
   const int x = (int)(p & ((1 << logN) - 1)), y = (int)(p >> logN);
   const int va = tri[3 * t], vb = tri[3 * t + 1], vc = tri[3 * t + 2];
@@ -805,7 +801,40 @@ __global__ __launch_bounds__(kBlock) void k_interp_px(int64_t P, int logN,
   const int oa = (bx - x) * (cy - y) - (by - y) * (cx - x);
   const int ob = (cx - x) * (ay - y) - (cy - y) * (ax - x);
   const int oc = (ax - x) * (by - y) - (ay - y) * (bx - x);
-  u_out[p] = ((double)oa * ia) * uv[va] + ((double)ob * ia) * uv[vb] + ((double)oc * ia) * uv[vc];
+  return ((double)oa * ia) * uv[va] + ((double)ob * ia) * uv[vb] + ((double)oc * ia) * uv[vc];
+}
+
+__global__ __launch_bounds__(kBlock) void k_interp_px(int64_t P, int logN,
+                                                      const int32_t* __restrict__ owner,
+                                                      const int32_t* __restrict__ tri,
+                                                      const int32_t* __restrict__ vxy,
+                                                      const double* __restrict__ uv,
+                                                      double* __restrict__ u_out) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= P) return;
+  u_out[p] = interp_at(p, logN, owner, tri, vxy, uv);
+}
+
+// k_interp_px with the per-block partial sums of u_out^2 that k_dot_part
+// would take of it (the same grid-stride loop over the same grid), so
+// their sum has the bits of the separate dot product.
+__global__ __launch_bounds__(kBlock) void k_interp_px_sq(int64_t P, int logN,
+                                                         const int32_t* __restrict__ owner,
+                                                         const int32_t* __restrict__ tri,
+                                                         const int32_t* __restrict__ vxy,
+                                                         const double* __restrict__ uv,
+                                                         double* __restrict__ u_out,
+                                                         double* __restrict__ part) {
+  __shared__ double lds[4];
+  double v[1] = {0.0};
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * kBlock) {
+    const double u = interp_at(p, logN, owner, tri, vxy, uv);
+    u_out[p] = u;
+    v[0] += u * u;
+  }
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
 // e = (u - f)^2 per pixel and per-block partial sums; `nblocks` blocks cover
@@ -1000,6 +1029,20 @@ __global__ __launch_bounds__(kBlock) void k_axpy_ratio(int64_t n, const double* 
                                                        double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) y[i] += sign * ratio(num, den) * x[i];
+}
+
+// y1 += (num / den) x1 on [0, n1) and y2 -= (num / den) x2 on [0, n2), the
+// two updates of k_axpy_ratio (signs 1 and -1) in one launch.
+__global__ __launch_bounds__(kBlock) void k_axpy2_ratio(int64_t n1, int64_t n2,
+                                                        const double* __restrict__ num,
+                                                        const double* __restrict__ den,
+                                                        const double* __restrict__ x1,
+                                                        double* __restrict__ y1,
+                                                        const double* __restrict__ x2,
+                                                        double* __restrict__ y2) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n1) y1[i] += 1.0 * ratio(num, den) * x1[i];
+  if (i < n2) y2[i] += -1.0 * ratio(num, den) * x2[i];
 }
 
 // y = x + (num / den) y
@@ -1485,6 +1528,30 @@ int launch_dot(fi_mesh* M, const double* a, const double* b, int64_t n, double* 
   hipLaunchKernelGGL(k_dot_part, dim3(g), dim3(kBlock), 0, M->ctx->stream, a, b, n, M->d_red);
   FI_LAUNCH_CHECK();
   return launch_reduce(M, M->d_red, g, 1, out_dev);
+}
+
+int launch_interp_sq(fi_mesh* M, const double* uvert, double* u_out, double* sq_dev) {
+  if (M->host.delaunay || !M->d_owner) {  // no per-pixel owner map: two passes
+    const int rc =
+        launch_raster(M, uvert, nullptr, nullptr, u_out, nullptr, nullptr, nullptr, nullptr);
+    return rc ? rc : launch_dot(M, u_out, u_out, M->P, sq_dev);
+  }
+  int g = grid_for(M->P);
+  if (g > kMaxGrid) g = kMaxGrid;
+  hipLaunchKernelGGL(k_interp_px_sq, dim3(g), dim3(kBlock), 0, M->ctx->stream, M->P,
+                     M->host.levels, M->d_owner, M->d_tri, M->d_vxy, uvert, u_out, M->d_red);
+  FI_LAUNCH_CHECK();
+  return launch_reduce(M, M->d_red, g, 1, sq_dev);
+}
+
+int launch_axpy2_ratio(fi_mesh* M, int64_t n1, int64_t n2, const double* num, const double* den,
+                       const double* x1, double* y1, const double* x2, double* y2) {
+  const int64_t n = std::max(n1, n2);
+  if (n == 0) return FI_OK;
+  hipLaunchKernelGGL(k_axpy2_ratio, dim3(grid_for(n)), dim3(kBlock), 0, M->ctx->stream, n1, n2,
+                     num, den, x1, y1, x2, y2);
+  FI_LAUNCH_CHECK();
+  return FI_OK;
 }
 
 int launch_axpy_ratio(fi_mesh* M, int64_t n, const double* num, const double* den, double sign,

@@ -86,15 +86,16 @@ int Cgls::post() {
       }
       return launch_xpby_ratio(M, m, s, gamma_slot(M, k), gamma_slot(M, k - 1), p);
     case kApplyP: {  // alpha = gamma / ||q||^2; g += alpha p; r -= alpha q
-      if ((rc = launch_vertex_values(M, M->d_x64, p, M->d_uvert)) ||
-          (rc = launch_raster(M, M->d_uvert, nullptr, nullptr, q, nullptr, nullptr, nullptr,
-                              nullptr)) ||
-          (wsqrt && (rc = launch_scale(M, P, wsqrt, q))) ||
-          (rc = launch_dot(M, q, q, P, sc + kScQQ)))
+      if ((rc = launch_vertex_values(M, M->d_x64, p, M->d_uvert))) return rc;
+      if (wsqrt) {
+        if ((rc = launch_raster(M, M->d_uvert, nullptr, nullptr, q, nullptr, nullptr, nullptr,
+                                nullptr)) ||
+            (rc = launch_scale(M, P, wsqrt, q)) || (rc = launch_dot(M, q, q, P, sc + kScQQ)))
+          return rc;
+      } else if ((rc = launch_interp_sq(M, M->d_uvert, q, sc + kScQQ))) {
         return rc;
-      const double* gam = gamma_slot(M, k);
-      if ((rc = launch_axpy_ratio(M, m, gam, sc + kScQQ, 1.0, p, g)) ||
-          (rc = launch_axpy_ratio(M, P, gam, sc + kScQQ, -1.0, q, r)))
+      }
+      if ((rc = launch_axpy2_ratio(M, m, P, gamma_slot(M, k), sc + kScQQ, p, g, q, r)))
         return rc;
       ++k;
       return FI_OK;
